@@ -1,0 +1,570 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: published
+known-answer vectors, textbook special cases, closed forms, invariants, brute
+force over all periodic images, or exact discrete-time statistics.
+"""
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from inputs import gen
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PI = math.pi
+
+
+def _params(L, **kw):
+    p = O.Params(L=tuple(L))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+# --------------------------------------------------------------------------
+# RNG: Philox4x32-10 and Box-Muller
+# --------------------------------------------------------------------------
+def _kat():
+    rows = []
+    for line in open(os.path.join(HERE, "golden", "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = [int(t, 16) for t in line.split()]
+        rows.append((v[0:4], v[4:6], v[6:10]))
+    return rows
+
+
+def test_philox_known_answers():
+    for ctr, key, out in _kat():
+        assert list(O.philox4x32_10(ctr, key)) == out
+
+
+def test_philox_matches_pytorch_header(tmp_path):
+    """Cross-check against PyTorch's open-source Philox engine header (compiled here, host only)."""
+    import torch.utils.cpp_extension as ce
+    inc = ce.include_paths()[0]
+    hdr = os.path.join(inc, "ATen", "core", "PhiloxRNGEngine.h")
+    if not os.path.exists(hdr):
+        pytest.skip("PyTorch headers not installed")
+    src = tmp_path / "p.cpp"
+    src.write_text(r"""
+#include <ATen/core/PhiloxRNGEngine.h>
+#include <cstdio>
+#include <cstdlib>
+int main(int argc, char** argv) {
+  unsigned long long seed = strtoull(argv[1], 0, 0), sub = strtoull(argv[2], 0, 0), off = strtoull(argv[3], 0, 0);
+  at::philox_engine e(seed, sub, off);
+  for (int q = 0; q < 4; ++q) printf("%u ", e());
+  printf("\n");
+  return 0;
+}
+""")
+    exe = tmp_path / "p"
+    r = subprocess.run(["g++", "-std=c++17", "-O1", "-I", inc, str(src), "-o", str(exe)], capture_output=True)
+    if r.returncode != 0:
+        pytest.skip("could not compile the PyTorch header: " + r.stderr.decode()[-300:])
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        seed, sub, off = (int(t) for t in rng.integers(0, 2 ** 63, size=3))
+        outs = [int(t) for t in subprocess.check_output([str(exe), str(seed), str(sub), str(off)]).split()]
+        ctr = [off & 0xFFFFFFFF, off >> 32, sub & 0xFFFFFFFF, sub >> 32]
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        assert list(O.philox4x32_10(ctr, key)) == outs
+
+
+def test_box_muller_moments():
+    from scipy import stats
+    g = np.array([O.gauss3(12345, k, 7, 0xFFFFFFFF, 2) for k in range(60000)]).reshape(-1)
+    assert abs(g.mean()) < 5 / math.sqrt(g.size)
+    assert abs(g.var() - 1.0) < 5 * math.sqrt(2.0 / g.size)
+    assert abs(stats.kurtosis(g, fisher=False) - 3.0) < 5 * math.sqrt(24.0 / g.size)
+    assert stats.kstest(g, "norm").pvalue > 1e-4
+
+
+def test_noise_streams_uncorrelated():
+    a = np.array([O.gauss3(9, k, 3, 0xFFFFFFFF, 2) for k in range(20000)])
+    b = np.array([O.gauss3(9, k, 3, 0xFFFFFFFF, 3) for k in range(20000)])
+    c = np.array([O.gauss3(9, k, 3, 5, 0) for k in range(20000)])
+    for u, v in ((a, b), (a, c), (b, c)):
+        cc = (u * v).mean(axis=0)
+        assert np.all(np.abs(cc) < 5 / math.sqrt(len(u)))
+
+
+# --------------------------------------------------------------------------
+# Lubrication scalars X^A_11, Y^A_11 (Sec. II.B)
+# --------------------------------------------------------------------------
+def _golden_xa():
+    rows = []
+    for line in open(os.path.join(HERE, "golden", "lubrication_scalars.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        rows.append([float(t) for t in line.split()])
+    return rows
+
+
+def test_lub_equal_spheres_textbook():
+    """beta = 1: X^A/(6 pi eta a) = 1/(4 xi) + 9/40 ln(1/xi), Y^A/(6 pi eta a) = 1/6 ln(1/xi)."""
+    for a in (0.6, 1.0, 1.4):
+        for xi in (1e-3, 1e-2, 0.05):
+            xa, ya = O.lub_scalars(0.1, a, a, xi)
+            s = 6 * PI * 0.1 * a
+            assert xa / s == pytest.approx(1 / (4 * xi) + 0.225 * math.log(1 / xi), rel=1e-14)
+            assert ya / s == pytest.approx(math.log(1 / xi) / 6, rel=1e-14)
+
+
+def test_lub_golden_values():
+    for eta, ai, aj, xi, xa_ref, ya_ref in _golden_xa():
+        xa, ya = O.lub_scalars(eta, ai, aj, xi)
+        assert xa == pytest.approx(xa_ref, rel=2e-4)
+        assert ya == pytest.approx(ya_ref, rel=2e-4)
+
+
+def test_lub_symmetric_and_reynolds_limit():
+    """X^A, Y^A are symmetric in (a_i, a_j); the 1/xi part is Reynolds' 6 pi eta a*^2 / h."""
+    rng = np.random.default_rng(2)
+    for _ in range(200):
+        ai, aj = rng.uniform(0.6, 1.6, 2)
+        xi = 10 ** rng.uniform(-3, math.log10(0.05))
+        x1, y1 = O.lub_scalars(0.1, ai, aj, xi)
+        x2, y2 = O.lub_scalars(0.1, aj, ai, xi)
+        assert x1 == pytest.approx(x2, rel=1e-13)
+        assert y1 == pytest.approx(y2, rel=1e-13)
+    ai, aj = 0.8, 1.5
+    astar = ai * aj / (ai + aj)
+    # X^A(xi) = c1/xi + c2 ln(1/xi): remove the log part using two gaps
+    xs = [1e-3, 2e-3]
+    vals = [O.lub_scalars(0.1, ai, aj, xi)[0] for xi in xs]
+    l1, l2 = (math.log(1 / x) for x in xs)
+    # solve for c1, c2
+    A = np.array([[1 / xs[0], l1], [1 / xs[1], l2]])
+    c1, c2 = np.linalg.solve(A, vals)
+    h_over_xi = (ai + aj) / 2  # h = xi (a_i + a_j) / 2
+    # c1 / xi = c1 (h / xi) / h must equal 6 pi eta a*^2 / h
+    assert c1 * h_over_xi == pytest.approx(6 * PI * 0.1 * astar ** 2, rel=1e-10)
+
+
+# --------------------------------------------------------------------------
+# Two-sphere force law: lubrication, contact, Brownian, stress
+# --------------------------------------------------------------------------
+HEAVY = 1e12   # density making masses so large that velocities stay put
+
+
+def _two(gap_xi, a=(1.0, 1.0), v=((0, 0, 0), (0, 0, 0)), w=((0, 0, 0), (0, 0, 0)), direction=(1, 0, 0),
+         flags=0, L=20.0, **kw):
+    a = np.array(a, float)
+    n = np.array(direction, float)
+    n /= np.linalg.norm(n)
+    sa = a.sum()
+    dist = sa * (1 + gap_xi / 2)
+    c = np.array([L / 2, L / 2, L / 2])
+    # r = x_i - x_j = dist * n, particle 0 is i
+    x = np.array([c + 0.5 * dist * n, c - 0.5 * dist * n])
+    p = _params((L, L, L), flags=flags, **kw)
+    return O.Oracle(p, a, x, np.array(v, float), np.array(w, float)), n, dist
+
+
+def test_lubrication_two_spheres_closed_form():
+    eta = 0.1
+    for xi in (2e-3, 0.01, 0.04):
+        U = np.array([0.3, -0.2, 0.5])
+        o, n, dist = _two(xi, v=((0, 0, 0), U), flags=O.NO_PAIR_BROWN | O.NO_CONTACT | O.NO_ONEBODY, eta=eta)
+        F = o.state()["F"]
+        s = 6 * PI * eta * 1.0
+        XA = s * (1 / (4 * xi) + 0.225 * math.log(1 / xi))
+        YA = s * math.log(1 / xi) / 6
+        un = U @ n
+        expect = XA * un * n + YA * (U - un * n)
+        assert np.allclose(F[0], expect, rtol=1e-12, atol=0)
+        assert np.array_equal(F[1], -F[0])
+
+
+def test_lubrication_resists_approach_and_projects():
+    fl = O.NO_PAIR_BROWN | O.NO_CONTACT | O.NO_ONEBODY
+    # i (particle 0) moves toward j: force on i must point away from j (along +n)
+    o, n, _ = _two(0.01, v=(-0.1 * np.array([1, 0, 0]), (0, 0, 0)), flags=fl)
+    F = o.state()["F"]
+    assert F[0] @ n > 0 and np.allclose(F[0][1:], 0, atol=1e-15)
+    # pure tangential relative motion gives no normal force
+    o, n, _ = _two(0.01, v=((0, 0, 0), (0, 0.2, 0)), flags=fl)
+    F = o.state()["F"]
+    assert abs(F[0] @ n) < 1e-15 and F[0][1] > 0
+
+
+def test_lubrication_regularisation_and_cutoff():
+    fl = O.NO_PAIR_BROWN | O.NO_CONTACT | O.NO_ONEBODY
+    U = ((0, 0, 0), (0.1, 0.1, 0.0))
+    F_min = _two(1e-3, v=U, flags=fl)[0].state()["F"][0]
+    for xi in (5e-4, 1e-5, -0.01):
+        F = _two(xi, v=U, flags=fl)[0].state()["F"][0]
+        assert np.allclose(F, F_min, rtol=1e-12)
+    assert np.all(_two(0.0501, v=U, flags=fl)[0].state()["F"] == 0)
+    assert np.any(_two(0.0499, v=U, flags=fl)[0].state()["F"] != 0)
+
+
+def test_normal_contact_repulsive_hookean():
+    kn = 1e4
+    for delta in (1e-4, 1e-3):
+        xi = -2 * delta / 2.0
+        o, n, _ = _two(xi, flags=O.NO_PAIR_BROWN | O.NO_LUB | O.NO_ONEBODY, kn=kn)
+        F = o.state()["F"]
+        assert np.allclose(F[0], kn * delta * n, rtol=1e-9)
+        assert np.array_equal(F[1], -F[0])
+
+
+def test_tangential_spring_slip_closed_form():
+    """Fixed overlap, constant sliding velocity v: |s| = v t until mu k_n delta / k_t, then constant."""
+    kn, kt, mu, dt = 1e4, 2e4 / 7, 0.5, 1e-4
+    delta = 1e-3
+    vslide = 0.7
+    fl = O.NO_PAIR_BROWN | O.NO_LUB | O.NO_ONEBODY | O.FREEZE_X
+    o, n, _ = _two(-delta, v=((0, vslide, 0), (0, 0, 0)), flags=fl, kn=kn, kt=kt, mu=mu, dt=dt, rho=HEAVY)
+    limit = mu * kn * delta / kt
+    for k in range(1, 80):
+        o.step(1)
+        ij, s, sl = o.contacts()
+        assert len(ij) == 1
+        expect = min(vslide * dt * (k + 1), limit)   # the evaluation at creation already added one increment
+        assert np.linalg.norm(s[0]) == pytest.approx(expect, rel=1e-9)
+        assert bool(sl[0]) == (vslide * dt * (k + 1) > limit)
+        F = o.state()["F"]
+        Ft = F[0] - (F[0] @ n) * n
+        assert np.linalg.norm(Ft) == pytest.approx(kt * expect, rel=1e-9)
+        assert Ft[1] < 0  # opposes the sliding of i along +y
+    # torques: T_i / a_i == T_j / a_j, equal to lever arm x tangential force
+    T = o.state()["T"]
+    assert np.allclose(T[0], T[1], rtol=1e-12)
+    F = o.state()["F"]
+    Ft = F[0] - (F[0] @ n) * n
+    assert np.allclose(T[0], np.cross(-1.0 * n, Ft), rtol=1e-9)
+
+
+def test_frictionless_and_rolling():
+    fl = O.NO_PAIR_BROWN | O.NO_LUB | O.NO_ONEBODY | O.FREEZE_X
+    o, n, _ = _two(-1e-3, v=((0, 0.5, 0), (0, 0, 0)), flags=fl, mu=0.0, rho=HEAVY)
+    o.step(5)
+    F = o.state()["F"]
+    assert np.allclose(F[0] - (F[0] @ n) * n, 0, atol=1e-14)
+    # gears: a_i w_i + a_j w_j = 0 gives zero contact-point slip, s stays zero
+    a = (1.0, 1.4)
+    om = np.array([0, 0, 2.0])
+    o, n, _ = _two(-1e-3, a=a, w=(om, -a[0] / a[1] * om), flags=fl, rho=HEAVY)
+    o.step(3)
+    _, s, _ = o.contacts()
+    assert np.allclose(s, 0, atol=1e-15)
+
+
+def test_spring_rotates_with_pair():
+    """A stored spring is carried into the new tangent plane with its length kept."""
+    fl = O.NO_PAIR_BROWN | O.NO_LUB | O.NO_ONEBODY
+    L = 20.0
+    a = np.array([1.0, 1.0])
+    th = 0.3
+    n = np.array([math.cos(th), math.sin(th), 0.0])
+    dist = 2.0 - 1e-3
+    c = np.full(3, L / 2)
+    x = np.array([c + 0.5 * dist * n, c - 0.5 * dist * n])
+    s0 = np.array([[0.0, 2e-4, 1e-4]])  # tangent to the old normal (1,0,0)
+    o = O.Oracle(_params((L, L, L), flags=fl), a, x, np.zeros((2, 3)), np.zeros((2, 3)),
+                 contacts=(np.array([[0, 1]]), s0))
+    _, s, _ = o.contacts()
+    assert np.linalg.norm(s[0]) == pytest.approx(np.linalg.norm(s0[0]), rel=1e-12)
+    assert abs(s[0] @ n) < 1e-18
+
+
+def test_pair_brownian_covariance_fdt():
+    """<F^B (x) F^B> = (2 kT / dt)(X^A N + Y^A T) for a frozen pair (Sec. II.C)."""
+    kT, dt, eta = 0.7, 1e-3, 0.1
+    xi = 0.01
+    fl = O.NO_LUB | O.NO_CONTACT | O.NO_ONEBODY | O.FREEZE_X
+    o, n, _ = _two(xi, a=(1.0, 1.4), direction=(1, 2, -1), flags=fl, kT=kT, dt=dt, eta=eta, rho=HEAVY, seed=77)
+    ns = 40000
+    Fs = np.empty((ns, 3))
+    for t in range(ns):
+        o.step(1)
+        st = o.state()
+        Fs[t] = st["F"][0]
+        assert np.array_equal(st["F"][1], -st["F"][0])
+    xa, ya = O.lub_scalars(eta, 1.0, 1.4, xi)
+    N = np.outer(n, n)
+    R = (2 * kT / dt) * (xa * N + ya * (np.eye(3) - N))
+    cov = Fs.T @ Fs / ns
+    # compare in the eigenbasis: normal variance and in-plane variances
+    evn = n @ cov @ n
+    assert evn == pytest.approx(n @ R @ n, rel=5 * math.sqrt(2 / ns))
+    t1 = np.cross(n, [0, 0, 1.0]); t1 /= np.linalg.norm(t1)
+    t2 = np.cross(n, t1)
+    for t in (t1, t2):
+        assert t @ cov @ t == pytest.approx(t @ R @ t, rel=5 * math.sqrt(2 / ns))
+    scale = math.sqrt((n @ R @ n) * (t1 @ R @ t1))
+    assert abs(n @ cov @ t1) < 5 * scale / math.sqrt(ns)
+    # no correlation between successive steps
+    lag = (Fs[1:] * Fs[:-1]).sum(axis=1).mean() / np.trace(R)
+    assert abs(lag) < 5 * math.sqrt(3) / math.sqrt(ns)
+
+
+def test_one_body_brownian_covariance():
+    """<F F> = (2kT/dt) 6 pi eta a I and <T T> = (2kT/dt) 8 pi eta a^3 I (Sec. II.C)."""
+    kT, dt, eta, a = 0.3, 1e-3, 0.1, 1.4
+    fl = O.FREEZE_X
+    L = 20.0
+    o = O.Oracle(_params((L, L, L), flags=fl, kT=kT, dt=dt, eta=eta, rho=HEAVY, seed=3), np.array([a]),
+                 np.array([[L / 2, L / 2, 3.0]]), np.zeros((1, 3)), np.zeros((1, 3)))
+    ns = 40000
+    F = np.empty((ns, 3)); T = np.empty((ns, 3))
+    for t in range(ns):
+        o.step(1)
+        st = o.state()
+        F[t] = st["F"][0]; T[t] = st["T"][0]
+    cf = F.T @ F / ns
+    ct = T.T @ T / ns
+    tol = 5 * math.sqrt(2 / ns)
+    assert np.allclose(np.diag(cf), (2 * kT / dt) * 6 * PI * eta * a, rtol=tol)
+    assert np.allclose(np.diag(ct), (2 * kT / dt) * 8 * PI * eta * a ** 3, rtol=tol)
+    assert np.all(np.abs(cf - np.diag(np.diag(cf))) < 5 * np.mean(np.diag(cf)) / math.sqrt(ns))
+
+
+def test_single_pair_stress_closed_form_and_label_swap():
+    L = 20.0
+    rng = np.random.default_rng(4)
+    for trial in range(5):
+        x = np.array([[8.0, 9.0, 10.0], [8.0, 9.0, 10.0]])
+        d = rng.normal(size=3); d /= np.linalg.norm(d)
+        x[1] = x[0] - (2.4 - 3e-3) * d
+        v = rng.normal(size=(2, 3)) * 0.1
+        w = rng.normal(size=(2, 3)) * 0.1
+        a = np.array([1.0, 1.4])
+        o1 = O.Oracle(_params((L, L, L), seed=11, flags=O.NO_ONEBODY), a, x, v, w)
+        o2 = O.Oracle(_params((L, L, L), seed=11, flags=O.NO_ONEBODY), a[::-1].copy(), x[::-1].copy(),
+                      v[::-1].copy(), w[::-1].copy())
+        S1 = o1.stress()
+        S2 = o2.stress()
+        F = o1.state()["F"]
+        r = x[0] - x[1]
+        V = L ** 3
+        assert np.allclose(S1.sum(axis=0), -np.outer(F[0], r) / V, rtol=1e-12, atol=1e-18)
+        # contact and lubrication parts are label independent (noise is keyed by ids, so skip it)
+        assert np.allclose(S1[0], S2[0], rtol=1e-12, atol=1e-18)
+        assert np.allclose(S1[1], S2[1], rtol=1e-12, atol=1e-18)
+
+
+# --------------------------------------------------------------------------
+# Geometry: sheared periodic images and the pair set
+# --------------------------------------------------------------------------
+def _brute_all_images(x, a, L, s, xi_cut):
+    """Pairs whose nearest image among all 27 sheared images is within the cut-off."""
+    n = len(a)
+    out = set()
+    for i in range(n):
+        for j in range(i + 1, n):
+            best = np.inf
+            for kx in (-1, 0, 1):
+                for ky in (-1, 0, 1):
+                    for kz in (-1, 0, 1):
+                        img = x[j] + np.array([kx * L[0] + ky * s, ky * L[1], kz * L[2]])
+                        # also allow the x-shifted neighbours of a sheared row
+                        for kk in (-1, 0, 1):
+                            d = x[i] - (img + np.array([kk * L[0], 0, 0]))
+                            best = min(best, float(np.sqrt(d @ d)))
+            rc = (a[i] + a[j]) * (1 + 0.5 * xi_cut)
+            out.add(((i, j), best - rc))
+    return out
+
+
+@pytest.mark.parametrize("s_frac", [0.0, 1.0 / 3.0, 1.0 - 1e-12])
+def test_pair_set_matches_all_images_and_cells(s_frac):
+    n = 150
+    L = (9.0, 8.0, 10.0)
+    rng = np.random.default_rng(int(s_frac * 1000) + 1)
+    a = rng.choice([1.0, 1.4], size=n)
+    x, v, w = gen.random_state(n, L, a, seed=3)
+    s = s_frac * L[0]
+    o = O.Oracle(_params(L), a, x, v, w, s_le=s)
+    got = {tuple(p) for p in o.pairs()}
+    ref = _brute_all_images(x, a, L, s, 0.05)
+    for (ij, margin) in ref:
+        if margin < -1e-9:
+            assert ij in got
+        elif margin > 1e-9:
+            assert ij not in got
+    oc = O.Oracle(_params(L, flags=O.CELLS), a, x, v, w, s_le=s)
+    assert np.array_equal(oc.pairs(), o.pairs())
+
+
+def test_cells_bit_exact_large():
+    n = 2000
+    L = (30.0, 30.0, 30.0)
+    a = gen.radii_bidisperse(n, 1)
+    x, v, w = gen.random_state(n, L, a, seed=5)
+    for s in (0.0, 11.3, L[0] - 1e-9):
+        o1 = O.Oracle(_params(L, seed=4), a, x, v, w, s_le=s)
+        o2 = O.Oracle(_params(L, seed=4, flags=O.CELLS), a, x, v, w, s_le=s)
+        assert np.array_equal(o1.pairs(), o2.pairs())
+        c1 = o1.contacts(); c2 = o2.contacts()
+        assert np.array_equal(c1[0], c2[0]) and np.array_equal(c1[1], c2[1])
+        assert np.allclose(o1.state()["F"], o2.state()["F"], rtol=1e-12, atol=1e-9)
+
+
+def test_lees_edwards_offset_equivalent_to_flipped_tilt():
+    """Offsets s and s - Lx describe the same image lattice (the remap at strain 0.5 -> -0.5)."""
+    n = 300
+    L = (12.0, 12.0, 12.0)
+    a = gen.radii_bidisperse(n, 2)
+    x, v, w = gen.random_state(n, L, a, seed=9)
+    s = 0.7 * L[0]
+    o1 = O.Oracle(_params(L, seed=2, flags=O.NO_PAIR_BROWN), a, x, v, w, s_le=s)
+    o2 = O.Oracle(_params(L, seed=2, flags=O.NO_PAIR_BROWN), a, x, v, w, s_le=s - L[0])
+    assert np.array_equal(o1.pairs(), o2.pairs())
+    assert np.allclose(o1.state()["F"], o2.state()["F"], rtol=1e-10, atol=1e-9)
+
+
+def test_boundary_crossing_keeps_peculiar_velocity():
+    L = 10.0
+    gd = 0.5
+    x = np.array([[5.0, L - 1e-6, 5.0]])
+    v = np.array([[gd * (L - 1e-6 - L / 2) + 0.01, 0.3, 0.0]])
+    p = _params((L, L, L), gammadot=gd, flags=O.NO_ONEBODY, dt=1e-4)
+    o = O.Oracle(p, np.array([1.0]), x, v, np.zeros((1, 3)))
+    o.step(1)
+    st = o.state()
+    assert st["x"][0, 1] < 1.0  # re-entered at the bottom
+    pec = st["v"][0, 0] - gd * (st["x"][0, 1] - L / 2)
+    assert pec == pytest.approx(0.01, abs=1e-3)
+
+
+# --------------------------------------------------------------------------
+# Conservation and exact discrete-time statistics
+# --------------------------------------------------------------------------
+def test_pair_forces_conserve_momentum():
+    n = 400
+    w_ = gen.Workload("t", n, 0.5, 1.0, kT=1.0)
+    st = gen.make_state(w_)
+    p = O.Params(L=st["L"], **st["params"], flags=O.NO_ONEBODY)
+    o = O.Oracle(p, st["radii"], st["x"], st["v"], st["w"])
+    o.step(20)
+    F = o.state()["F"]
+    Fa, _ = o.norms()
+    assert np.all(np.abs(F.sum(axis=0)) <= 1e-13 * Fa.sum())
+
+
+def test_equipartition_exact_discrete():
+    """Frozen positions, no shear: with forces evaluated at half-step velocities the
+    full-step velocities have covariance exactly kT/m per component, for any stable
+    damping, lubrication pairs included (the lubrication and its noise obey FDT)."""
+    kT, dt, rho = 0.5, 0.1, 1.0
+    L = 12.0
+    # a small cluster with lubrication gaps (xi ~ 0.04) but no contacts; dt is
+    # chosen so that the explicit lubrication damping stays stable
+    x = np.array([[4.0, 4.0, 4.0], [6.04, 4.0, 4.0], [4.0, 6.045, 4.0], [6.045, 6.045, 4.0],
+                  [8.0, 8.0, 8.0], [10.448, 8.0, 8.0]])
+    a = np.array([1.0, 1.0, 1.0, 1.0, 1.0, 1.4])
+    m = 4 / 3 * PI * rho * a ** 3
+    inertia = 0.4 * m * a ** 2
+    p = _params((L, L, L), kT=kT, dt=dt, rho=rho, flags=O.FREEZE_X, seed=21)
+    o = O.Oracle(p, a, x, np.zeros((6, 3)), np.zeros((6, 3)))
+    assert len(o.pairs()) >= 4 and len(o.contacts()[0]) == 0
+    o.step(2000)
+    ns = 60000
+    ev = np.zeros(6); ew = np.zeros(6)
+    for t in range(ns // 200):
+        o.step(200)
+        st = o.state()
+        ev += (m[:, None] * st["v"] ** 2).sum(axis=1) / 3
+        ew += (inertia[:, None] * st["w"] ** 2).sum(axis=1) / 3
+    ev /= ns // 200; ew /= ns // 200
+    # 300 samples x 3 components, decorrelated by 200 steps
+    tol = 5 * math.sqrt(2.0 / (3 * (ns // 200)))
+    assert np.allclose(ev / kT, 1.0, atol=tol)
+    assert np.allclose(ew / kT, 1.0, atol=tol)
+
+
+def test_dilute_msd_closed_form():
+    """Isolated spheres: <x^2> = 2 kT m / gamma^2 (gamma t / m - 1 + exp(-gamma t / m)) (Sec. III.B)."""
+    n = 64
+    L = 400.0
+    kT, dt, rho, eta, a = 1.0, 5e-4, 0.1, 0.1, 1.0
+    rng = np.random.default_rng(8)
+    x = rng.random((n, 3)) * L
+    m = 4 / 3 * PI * rho * a ** 3
+    g = 6 * PI * eta * a
+    v = rng.standard_normal((n, 3)) * math.sqrt(kT / m)
+    p = _params((L, L, L), kT=kT, dt=dt, rho=rho, eta=eta, seed=5)
+    o = O.Oracle(p, np.full(n, a), x, v, np.zeros((n, 3)))
+    x0 = o.state()["x"].copy()
+    disp = np.zeros((n, 3))
+    prev = x0.copy()
+    checkpoints = {200: None, 800: None, 3000: None}
+    t = 0
+    for stop in sorted(checkpoints):
+        while t < stop:
+            o.step(50)
+            t += 50
+            cur = o.state()["x"]
+            d = cur - prev
+            d -= L * np.rint(d / L)
+            disp += d
+            prev = cur.copy()
+        checkpoints[stop] = (disp ** 2).mean()
+    for stop, msd in checkpoints.items():
+        tt = stop * dt
+        ref = 2 * kT * m / g ** 2 * (g * tt / m - 1 + math.exp(-g * tt / m))
+        # 192 independent components: relative sd sqrt(2/192)
+        assert msd == pytest.approx(ref, rel=5 * math.sqrt(2 / (3 * n)))
+
+
+def test_msd_two_printed_forms_agree():
+    """The dimensional and the timescale forms of the MSD in Sec. III.B are the same function."""
+    rho, eta, a, kT = 0.1, 0.1, 1.0, 0.017
+    m = 4 / 3 * PI * rho * a ** 3
+    g = 6 * PI * eta * a
+    tI = rho * a ** 2 / eta
+    tB = eta * a ** 3 / kT
+    for t in (0.01, 0.3, 5.0):
+        f1 = 2 * kT * m / g ** 2 * (g * t / m - 1 + math.exp(-g * t / m))
+        f2 = a ** 2 * 2 / (27 * PI) * tI / tB * (4.5 * t / tI - 1 + math.exp(-4.5 * t / tI))
+        assert f1 == pytest.approx(f2, rel=1e-12)
+
+
+def test_sheared_contact_network_positive_viscosity():
+    """Under shear the contact + lubrication shear stress is positive (eta_r > 0)."""
+    w_ = gen.Workload("t", 300, 0.55, 100.0, steps=0)
+    st = gen.make_state(w_)
+    prm = dict(st["params"])
+    prm["gammadot"] = 0.5
+    p = O.Params(L=st["L"], **prm, flags=O.CELLS)
+    o = O.Oracle(p, st["radii"], st["x"], st["v"], st["w"])
+    ser = o.step(400, series=True).reshape(-1, 3, 3, 3)
+    sxy = ser[100:, 0, 0, 1] + ser[100:, 1, 0, 1]
+    assert sxy.mean() > 0
+
+
+def test_restart_bit_exact():
+    w_ = gen.Workload("t", 200, 0.5, 1.0, kT=1.0)
+    st = gen.make_state(w_)
+    p = O.Params(L=st["L"], **st["params"])
+    o = O.Oracle(p, st["radii"], st["x"], st["v"], st["w"])
+    o.step(30)
+    mid = o.state()
+    ij, s, _ = o.contacts()
+    o.step(30)
+    end = o.state()
+    o2 = O.Oracle(p, st["radii"], mid["x"], mid["v"], mid["w"], s_le=mid["s_le"], step=mid["step"],
+                  contacts=(ij, s), F=mid["F"], T=mid["T"])
+    o2.step(30)
+    end2 = o2.state()
+    for k in ("x", "v", "w", "F", "T"):
+        assert np.array_equal(end[k], end2[k])
+
+
+def test_table1_peclet_numbers():
+    """Sec. II.F: Pe = 6 pi eta a^3 gammadot / kT reproduces Table 1 to its printed precision."""
+    for line in open(os.path.join(HERE, "golden", "table1_parameters.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        pe, gd, kT, a, rho, kn, eta = (float(t) for t in line.split())
+        assert 6 * PI * eta * a ** 3 * gd / kT == pytest.approx(pe, rel=0.05)
+        g2, k2 = gen.pe_to_rates(pe, eta)
+        assert 6 * PI * eta * g2 / k2 == pytest.approx(pe, rel=1e-12)
