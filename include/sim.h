@@ -1,0 +1,236 @@
+/*
+ * sim.h -- C ABI of the MI355X (gfx950) force engine for sheared dense
+ * suspensions: the per-timestep hot path of the pairwise model of Li, Royer &
+ * Ness (arXiv 2307.13802).
+ *
+ * One handle holds R >= 1 independent replicas (systems) that advance
+ * together; every stage of a step is one kernel launch over all replicas.
+ * Per replica and per step the library computes, on the GPU:
+ *   - the Lees-Edwards offset and the wrap of particles into the sheared
+ *     periodic box (Sec. II.E: the tilted box remapped at strain +-1/2 is the
+ *     same image lattice as a Lees-Edwards offset);
+ *   - a Verlet neighbour list from Morton-ordered cells, rebuilt on device when
+ *     the accumulated non-affine displacement can have used up the skin
+ *     (Sec. II, footnote on the skin);
+ *   - per pair: the squeeze and shear lubrication force of eq. (force_lub)
+ *     with X^A_11, Y^A_11 (Sec. II.B), regularised at xi_min and cut off above
+ *     xi_cut; the Hookean normal and frictional tangential contact force and
+ *     torque of eq. (force_contact), (torque_contact) with per-pair spring
+ *     history and Coulomb limit mu (Sec. II.A); the pairwise Brownian force of
+ *     eq. (force_brownian_lub) with amplitude sqrt(2 kT/dt) (Sec. II.C);
+ *   - per particle: Stokes drag force and torque, eq. (force_drag),
+ *     (torque_drag), and one-body Brownian force and torque, eq.
+ *     (force_brownian_drag), (torque_brownian_drag);
+ *   - velocity-Verlet for translation and rotation (Sec. II, I = 2/5 m a^2);
+ *   - the virial stresses -F (x) r / V of contact, lubrication and Brownian
+ *     pair forces (Sec. II.A, II.B, II.D), accumulated in FP64.
+ *
+ * Conventions
+ *   Units are the paper's (Sec. II.E): lengths in a, masses in rho a^3, time
+ *   such that k_n = 1 gives unit frequency.  Particle ids are 0..n-1 in the
+ *   order of the arrays given to sim_create.  x is the flow direction, y the
+ *   gradient direction, z the vorticity direction; U^inf = gammadot (y - Ly/2)
+ *   e_x and Omega^inf = (0, 0, -gammadot/2).  r_ij = x_i - x_j (minimum
+ *   image), so n_ij points from j to i.  Arrays of vectors are particle-major,
+ *   xyz interleaved (x0 y0 z0 x1 ...).  Stress tensors are 3x3 row-major,
+ *   element [a][b] = -(1/V) sum F_a r_b.
+ *
+ * Memory and threading
+ *   The caller owns every host array; inputs are copied, outputs are written
+ *   into caller-sized buffers.  The library owns the handle and all device
+ *   memory (through the allocator set by sim_set_allocator, else hipMalloc).
+ *   All GPU work is ordered on the stream given at creation.  A handle is not
+ *   thread safe; different handles are independent.  The same build, inputs
+ *   and configuration give bit-identical results (no floating-point atomics).
+ *
+ * Errors
+ *   Every function returns an int32 status: 0 = SIM_OK, negative = error.
+ *   sim_strerror gives a static description of a code and sim_last_error the
+ *   message of the last failure on a handle.  No exception crosses the ABI.
+ */
+#ifndef SUSP_SIM_H
+#define SUSP_SIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SIM_OK         0
+#define SIM_EINVAL    -1  /* bad configuration or argument                         */
+#define SIM_ENOMEM    -2  /* device or host allocation failed                       */
+#define SIM_EDEVICE   -3  /* HIP runtime error (text in sim_last_error)              */
+#define SIM_EUNSTABLE -4  /* NaN/Inf force or overlap above the limit (see below)    */
+#define SIM_ECAPACITY -5  /* neighbour list capacity exceeded                        */
+#define SIM_ERANGE    -6  /* replica index out of range or output buffer too small   */
+
+/* precision of the pair arithmetic */
+#define SIM_FP64  0       /* everything in FP64                                      */
+#define SIM_MIXED 1       /* FP64 positions, image offsets, gaps, stress and
+                             integration; FP32 pair forces with compensated sums     */
+
+/* sim_config.flags (test and measurement switches; 0 = the physical model) */
+#define SIM_FREEZE_X          0x001u /* positions are not advanced                   */
+#define SIM_NO_LUB            0x002u /* drop the lubrication force                   */
+#define SIM_NO_PAIR_BROWN     0x004u /* drop the pairwise Brownian force             */
+#define SIM_NO_CONTACT        0x008u /* drop contact force and torque                */
+#define SIM_NO_ONEBODY        0x010u /* drop one-body drag and Brownian terms        */
+#define SIM_REBUILD_EACH_STEP 0x100u /* rebuild the neighbour list every step        */
+#define SIM_NO_GRAPH          0x200u /* launch kernels directly, no HIP graph        */
+
+/* sim_stress components and modes */
+#define SIM_STRESS_CONTACT 0      /* -F^C (x) r / V                     (Sec. II.A) */
+#define SIM_STRESS_LUB     1      /* -F^{H,L} (x) r / V                 (Sec. II.B) */
+#define SIM_STRESS_BROWN   2      /* -F^{B,L} (x) r / V, instantaneous  (Sec. II.D) */
+#define SIM_STRESS_DRAG    3      /* (1/V) sum 20/3 pi eta a^3 E        (Sec. II.B) */
+#define SIM_STRESS_TOTAL   4      /* contact + lubrication + drag       (Sec. IV.D) */
+#define SIM_STRESS_LAST    0      /* value at the last evaluated step               */
+#define SIM_STRESS_MEAN    1      /* mean over steps since sim_reset_stress/create  */
+
+typedef struct sim sim;
+
+/* One replica.  struct_size must equal sizeof(sim_config). */
+typedef struct sim_config {
+    uint32_t struct_size;
+    uint32_t n;             /* particles, 1 <= n < 2^32 - 1                          */
+    double   box[3];        /* Lx, Ly, Lz                                            */
+    double   rho;           /* particle density (mass / length^3), Sec. II.E        */
+    double   eta;           /* fluid viscosity, Sec. II.B                            */
+    double   kn, kt;        /* normal and tangential contact stiffness, Sec. II.A   */
+    double   mu;            /* static friction coefficient, Sec. II.A                */
+    double   kT;            /* thermal energy, Sec. II.C                             */
+    double   gammadot;      /* shear rate (x velocity varying along y)               */
+    double   dt;            /* time step                                             */
+    double   xi_cut;        /* no lubrication for dimensionless gaps xi > xi_cut     */
+    double   xi_min;        /* xi is replaced by xi_min when smaller (Sec. II.B)     */
+    double   skin;          /* Verlet skin, length; <= 0 selects 0.2 * min radius    */
+    double   le_offset0;    /* initial Lees-Edwards offset (x shift of the y image)  */
+    double   max_overlap;   /* health limit on the overlap; <= 0 selects 0.1 * min a */
+    uint64_t seed;          /* key of the counter-based noise generator             */
+    uint64_t step0;         /* step counter of the initial state                     */
+    int32_t  precision;     /* SIM_FP64 or SIM_MIXED, identical for all replicas     */
+    uint32_t flags;         /* SIM_* flags, identical for all replicas               */
+    uint32_t nlist_cap;     /* neighbour list capacity per particle; 0 selects 48    */
+    uint32_t reserved;      /* must be 0                                             */
+} sim_config;
+
+typedef struct sim_stats_t {
+    double  contacts_per_particle;  /* Z = 2 * contacts / n                          */
+    double  sliding_fraction;       /* contacts at the Coulomb limit / contacts       */
+    double  max_overlap;            /* largest overlap at the last evaluation          */
+    double  neighbours_per_particle;/* Verlet list entries per particle              */
+    double  interacting_per_particle; /* pairs with xi <= xi_cut, counted per side     */
+    int64_t contacts;               /* number of contacts (pairs with overlap)         */
+    int64_t rebuilds;               /* neighbour list builds since creation            */
+    int64_t steps;                  /* steps taken since creation                      */
+    uint64_t step;                  /* current step counter                            */
+    double  le_offset;              /* current Lees-Edwards offset                     */
+} sim_stats_t;
+
+/* Checks a configuration and its radii on the host (no GPU needed).
+ * radii: n doubles, host memory.  Returns SIM_EINVAL for n = 0, a <= 0,
+ * dt <= 0, rho/eta <= 0, kn/kt < 0, mu < 0, kT < 0, xi_min <= 0,
+ * xi_min >= xi_cut, a box side not larger than twice the largest
+ * interaction range plus skin (the minimum image must be unique), a wrong
+ * struct_size or a nonzero reserved field. */
+int sim_validate(const sim_config* cfg, const double* radii);
+
+/* Creates a handle with n_replicas systems.  For replica r: radii[r] -> n
+ * doubles; x0[r] -> 3n doubles inside [0, L); v0[r], w0[r] -> 3n doubles of
+ * velocities and angular velocities, or NULL for U^inf(x) and Omega^inf.
+ * hip_stream is a hipStream_t (NULL = the null stream).  Evaluates the forces
+ * of every replica at its initial state (Sec. II force law at step step0,
+ * using v0 and w0), so the first sim_step starts a velocity-Verlet step.
+ * On success *out receives the handle. */
+int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* radii,
+               const double* const* x0, const double* const* v0, const double* const* w0,
+               void* hip_stream, sim** out);
+
+/* Advances every replica by nsteps velocity-Verlet steps (Sec. II): half
+ * kick, drift, Lees-Edwards wrap, neighbour rebuild when needed, forces at
+ * the new positions with the half-step velocities, half kick.  Returns after
+ * the work is complete.  SIM_EUNSTABLE / SIM_ECAPACITY report a step whose
+ * forces are not trustworthy; the state is then that of the failing step. */
+int sim_step(sim* s, int64_t nsteps);
+
+/* Stress of one replica (3x3 row-major, FP64, host memory). */
+int sim_stress(sim* s, int32_t replica, int32_t component, int32_t mode, double out[9]);
+
+/* Restarts the running means used by SIM_STRESS_MEAN for all replicas. */
+int sim_reset_stress(sim* s);
+
+/* Per-step series of the contact, lubrication and Brownian stresses (27
+ * doubles per step: [component][a][b]) recorded since the previous call, at
+ * most the ring capacity (8192 steps); oldest first.  *count receives the
+ * number of steps available; if it exceeds cap, SIM_ERANGE is returned and
+ * nothing is consumed. */
+int sim_stress_series(sim* s, int32_t replica, double* out, int64_t cap, int64_t* count);
+
+/* Positions of one replica in id order, wrapped into [0, L), FP64, 3n doubles. */
+int sim_positions(sim* s, int32_t replica, double* out_3n);
+
+/* Full state of one replica in id order (any pointer may be NULL):
+ * positions, full-step velocities and angular velocities, last force and
+ * torque, Lees-Edwards offset and step counter. */
+int sim_get_state(sim* s, int32_t replica, double* x, double* v, double* w, double* F, double* T,
+                  double* le_offset, uint64_t* step);
+
+/* Replaces the state of one replica.  x, v, w: 3n doubles (required).
+ * c_ij: n_contacts (id_i, id_j) pairs with id_i < id_j and c_s their springs
+ * (3 doubles each); pairs that are not overlapping are ignored.  If F and T
+ * are given they are taken as the forces of the state (a restart); if both
+ * are NULL the forces are evaluated at this state with these velocities at
+ * step counter `step` (forces of the other replicas are left unchanged). */
+int sim_set_state(sim* s, int32_t replica, const double* x, const double* v, const double* w,
+                  const double* F, const double* T, double le_offset, uint64_t step,
+                  const uint32_t* c_ij, const double* c_s, int64_t n_contacts);
+
+/* Last evaluated force and torque of one replica, id order, 3n doubles each. */
+int sim_forces(sim* s, int32_t replica, double* F_3n, double* T_3n);
+
+/* Interaction set of the last evaluation: pairs (id_i < id_j) with
+ * dimensionless gap xi <= xi_cut, sorted.  cap is in pairs. */
+int sim_pairs(sim* s, int32_t replica, uint32_t* ij_2m, int64_t cap, int64_t* count);
+
+/* Verlet set of the current neighbour list (gap within xi_cut plus skin at
+ * the last rebuild), pairs (id_i < id_j), sorted. */
+int sim_nlist(sim* s, int32_t replica, uint32_t* ij_2m, int64_t cap, int64_t* count);
+
+/* Contact history: pairs (id_i < id_j) in contact at the last evaluation,
+ * their springs s_ij (3 doubles) and whether they slid (Coulomb limit). */
+int sim_contacts(sim* s, int32_t replica, uint32_t* ij_2m, double* s_3m, int32_t* sliding,
+                 int64_t cap, int64_t* count);
+
+/* Statistics of one replica at the last evaluation. */
+int sim_stats(sim* s, int32_t replica, sim_stats_t* out);
+
+/* Kernel timing: when enabled, sim_step launches directly (no graph) and
+ * brackets every pair-force launch with HIP events on the library stream.
+ * sim_kernel_time returns the number of timed launches and their total
+ * duration in milliseconds since the last enable. */
+int sim_profile(sim* s, int32_t enable);
+int sim_kernel_time(sim* s, int64_t* launches, double* total_ms);
+
+/* Destroys a handle and frees its device memory. */
+int sim_destroy(sim* s);
+
+/* Static description of a status code. */
+const char* sim_strerror(int32_t code);
+
+/* Copies the message of the last error on the handle (or the last
+ * handle-less error if s is NULL) into buf (NUL-terminated). */
+int sim_last_error(const sim* s, char* buf, size_t len);
+
+/* Routes device allocations of handles created afterwards through alloc/free
+ * (e.g. a framework's caching allocator); NULL restores hipMalloc/hipFree. */
+int sim_set_allocator(void* (*alloc_fn)(size_t bytes, void* ctx), void (*free_fn)(void* p, void* ctx),
+                      void* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SUSP_SIM_H */

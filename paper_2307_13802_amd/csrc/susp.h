@@ -1,0 +1,134 @@
+// Internal declarations of the gfx950 force engine: per-replica parameter
+// tables, device buffers and kernel launchers.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace susp {
+
+constexpr int kTile = 256;               // replicas are padded to multiples of this many particles
+constexpr uint32_t kNoId = 0xFFFFFFFFu;  // id of a padding slot
+constexpr double kPi = 3.14159265358979323846;
+
+enum : uint32_t {
+    F_FREEZE_X = 0x001u, F_NO_LUB = 0x002u, F_NO_PAIR_BROWN = 0x004u, F_NO_CONTACT = 0x008u,
+    F_NO_ONEBODY = 0x010u, F_REBUILD_EACH_STEP = 0x100u, F_NO_GRAPH = 0x200u,
+};
+
+enum : uint32_t { H_NAN = 1u, H_OVERLAP = 2u, H_NLIST = 4u };
+
+// Constant per-replica parameters (host-written, read-only on device).
+struct RepParams {
+    double L[3];
+    double gd, gdLy;          // shear rate, shear rate * Ly
+    double dt, half_dt;
+    double rho, eta, kn, kt, mu;
+    double bamp;              // sqrt(2 kT / dt)
+    double c1;                // 1 + xi_cut / 2
+    double xi_min;
+    double skin;
+    double rc_max;            // largest interaction range (2 a_max c1)
+    double rl_max;            // rc_max + skin
+    double invV;
+    double cw[3];             // cell widths
+    double max_overlap;
+    int32_t nc[3];            // cells per dimension (1 or >= 3)
+    int32_t mbits;            // Morton bits per dimension
+    uint32_t key_off;         // first cell key of this replica
+    uint32_t nkeys;           // Morton cells + 1 padding cell
+    uint32_t p_begin, n, n_pad;
+    uint32_t flags;
+    uint32_t blk_begin, nblk; // pair-kernel blocks of this replica
+    uint64_t seed;
+};
+
+// Per-replica values the device updates every step.
+struct RepDyn {
+    double s_le;              // Lees-Edwards offset
+    double dmax;              // bound on the non-affine displacement since the last build
+    double t_since;           // time since the last build
+    uint64_t step;            // step counter of the last force evaluation
+    uint32_t stepmax_bits;    // float bits: largest displacement in the current step
+    uint32_t maxov_bits;      // float bits: largest overlap at the last evaluation
+    uint32_t health;          // H_* bits, sticky until read by the host
+    uint32_t ring_head;       // number of series entries written (mod ring size)
+    double stress_sum[27];    // running sum for means
+    uint64_t stress_count;
+};
+
+struct SysDyn {
+    uint32_t rebuild;         // 1: this step rebuilds cells and lists
+    uint32_t pad0;
+    uint64_t rebuilds;
+    uint64_t steps;
+};
+
+// Device buffers of one handle.  Particle arrays have npad entries, in
+// Morton-cell order; replicas are contiguous and padded to kTile.
+struct Bufs {
+    uint32_t npad, nrep, nkeys_total, cap;   // cap = neighbour slots per particle
+    int mixed;
+
+    double4* pos;     // x, y, z, a
+    double4* vh;      // half-step velocity (after kick 1) -- read by the pair kernel
+    double4* wh;      // half-step angular velocity
+    double4* vf;      // full-step velocity (after kick 2)
+    double4* wf;
+    void* F;          // double4 (FP64) or float4 (mixed)
+    void* T;
+    float4* vsh;      // mixed: FP32 copies of vh and wh used by pair gathers
+    float4* wsh;
+    uint32_t* id;
+
+    // neighbour list, slot-major: nbr[e * npad + i]
+    uint32_t* nbr;
+    uint32_t* ncnt;
+    // contact history per list entry, slot-major, canonical orientation (lower id first)
+    void* hs[3];      // double or float per component
+    uint64_t* cmask;  // bit e: entry e holds a live contact
+    uint64_t* smask;  // bit e: that contact slid at its last update
+
+    // rebuild scratch
+    uint32_t* key;        // cell key per particle
+    uint32_t* cell_cnt;   // nkeys_total
+    uint32_t* cell_fill;
+    uint32_t* cell_start; // nkeys_total + 1
+    uint32_t* scan_blk;   // block sums of the scan
+    uint32_t* src;        // new slot -> old slot
+    // carry of contact history across a rebuild: compact table per particle
+    uint32_t* ct_id;      // [c * npad + i] partner id
+    double* ct_s;         // [(c * 3 + d) * npad + i]
+    uint8_t* ct_sl;       // sliding flag
+    uint32_t* ct_n;
+    // staging copies for the reorder
+    double4* alt4[7];
+    uint32_t* alt_id;
+
+    // stress: per pair-kernel block partial sums, ring of per-step values
+    double* partial;      // [blk][27]
+    double* ring;         // [rep][kRing][27]
+    double* last;         // [rep][27]
+
+    uint32_t* blk_rep;    // replica of each kTile-block of particles
+    RepParams* reps;
+    RepDyn* dyn;
+    SysDyn* sys;
+};
+
+constexpr int kRing = 8192;
+constexpr int kCtCap = 16;   // contacts per particle carried across a rebuild
+
+// kernel launchers (susp_kernels.hip)
+void launch_step_begin(const Bufs& b, hipStream_t st);
+void launch_integrate(const Bufs& b, hipStream_t st);
+void launch_rebuild_decision(const Bufs& b, hipStream_t st, int force);
+// ct_input_rep: 0xFFFFFFFF = carry history from the current lists; 0xFFFFFFFE =
+// every replica takes the host-written compact table; else that replica does
+void launch_rebuild(const Bufs& b, hipStream_t st, int ct_input_rep);
+void launch_pair_force(const Bufs& b, hipStream_t st, int kick, uint32_t only_rep);
+void launch_reduce_stress(const Bufs& b, hipStream_t st, int record, uint32_t only_rep);
+void launch_diag(const Bufs& b, hipStream_t st, uint32_t rep, uint32_t n, uint32_t* out_ij, double* out_s,
+                 int32_t* out_sl, uint32_t* count, uint32_t cap, int mode);
+
+}  // namespace susp

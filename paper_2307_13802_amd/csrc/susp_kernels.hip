@@ -1,0 +1,999 @@
+// gfx950 kernels of the sheared-suspension force engine.
+//
+// One step of every replica is: step_begin (Lees-Edwards offset, counters) ->
+// integrate (kick 1, drift, wrap, displacement bound) -> rebuild decision ->
+// [rebuild: cell keys, scan, scatter, in-cell ordering, reorder, neighbour
+// list with history carry-over; each early-exits unless a rebuild is due] ->
+// pair force (all pair and one-body terms, kick 2, per-block stress) ->
+// stress reduction.  Paper references are to Li, Royer & Ness, arXiv
+// 2307.13802.
+//
+// Compiled with -ffp-contract=off: the geometry, the neighbour predicate and
+// the contact-history update are evaluated operation by operation in the
+// same order as the plain FP64 definition, so neighbour sets and springs are
+// bit-reproducible; FP64 division and square root are IEEE correctly rounded.
+#include "susp.h"
+
+namespace susp {
+
+// ---------------------------------------------------------------------------
+// Counter-based noise: Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw,
+// SC'11), Box-Muller normals.  Counter words: (step_lo, id_a, id_b,
+// step_hi << 8 | stream); stream 0 = pair force (id_a < id_b), 2 and 3 =
+// one-body force and torque (id_b = 0xFFFFFFFF).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                          uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c0 = n0;
+        c1 = (uint32_t)p1;
+        c2 = n2;
+        c3 = (uint32_t)p0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ void normals3(uint4 w, double g[3]) {
+    const double s = 2.3283064365386963e-10;  // 2^-32
+    const double u0 = ((double)w.x + 0.5) * s, u1 = ((double)w.y + 0.5) * s;
+    const double u2 = ((double)w.z + 0.5) * s, u3 = ((double)w.w + 0.5) * s;
+    const double r0 = sqrt(-2.0 * log(u0));
+    const double r1 = sqrt(-2.0 * log(u2));
+    const double a1 = (2.0 * kPi) * u1, a3 = (2.0 * kPi) * u3;
+    g[0] = r0 * cos(a1);
+    g[1] = r0 * sin(a1);
+    g[2] = r1 * cos(a3);
+}
+
+__device__ __forceinline__ void normals3(uint4 w, float g[3]) {
+    const float s = 2.3283064365386963e-10f;
+    const float u0 = ((float)w.x + 0.5f) * s, u1 = ((float)w.y + 0.5f) * s;
+    const float u2 = ((float)w.z + 0.5f) * s, u3 = ((float)w.w + 0.5f) * s;
+    // hardware log2 and sin/cos of 2*pi*x (argument in revolutions)
+    const float r0 = __fsqrt_rn(-2.0f * 0.69314718055994531f * __builtin_amdgcn_logf(u0));
+    const float r1 = __fsqrt_rn(-2.0f * 0.69314718055994531f * __builtin_amdgcn_logf(u2));
+    g[0] = r0 * __builtin_amdgcn_cosf(u1);
+    g[1] = r0 * __builtin_amdgcn_sinf(u1);
+    g[2] = r1 * __builtin_amdgcn_cosf(u3);
+}
+
+// ---------------------------------------------------------------------------
+// Geometry in the sheared periodic box (Sec. II.E as a Lees-Edwards offset s:
+// the image of a particle shifted by +Ly in y is shifted by +s in x).
+// d = x_a - x_b over the nearest image; returns k_y, the number of Ly periods
+// between a and the image of b.  Pairs within the interaction range are far
+// from the half-box points where the rounding of t/L could matter.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int min_image(const RepParams& P, double s_le, const double4& pa, const double4& pb,
+                                         double& dx, double& dy, double& dz) {
+    dy = pa.y - pb.y;
+    const double ky = rint(dy / P.L[1]);
+    dy = dy - ky * P.L[1];
+    dx = (pa.x - pb.x) - ky * s_le;
+    dx = dx - P.L[0] * rint(dx / P.L[0]);
+    dz = pa.z - pb.z;
+    dz = dz - P.L[2] * rint(dz / P.L[2]);
+    return (int)ky;
+}
+
+__device__ __forceinline__ uint32_t part1by2(uint32_t v) {
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+    return part1by2(x) | (part1by2(y) << 1) | (part1by2(z) << 2);
+}
+
+__device__ __forceinline__ int cell_coord(double x, double w, int n) {
+    int c = (int)floor(x / w);
+    return c < 0 ? 0 : (c >= n ? n - 1 : c);
+}
+
+__device__ __forceinline__ float as_posf(uint32_t b) { return __uint_as_float(b); }
+
+// block-wide max of a non-negative float, then one atomic per block
+__device__ __forceinline__ void block_atomic_max(float v, uint32_t* target) {
+    __shared__ float red[16];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = red[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, red[w]);
+        if (m > 0.0f) atomicMax(target, __float_as_uint(m));
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Step begin: advance the Lees-Edwards offset and the step counter.
+// ---------------------------------------------------------------------------
+__global__ void k_step_begin(Bufs b) {
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= b.nrep) return;
+    const RepParams& P = b.reps[r];
+    RepDyn& D = b.dyn[r];
+    double s = D.s_le + P.gdLy * P.dt;
+    s = s - P.L[0] * floor(s / P.L[0]);
+    D.s_le = s;
+    D.step = D.step + 1;
+    D.stepmax_bits = 0u;
+    D.maxov_bits = 0u;
+    if (r == 0) b.sys->steps += 1;
+}
+
+// ---------------------------------------------------------------------------
+// Kick 1, drift and wrap (velocity-Verlet, Sec. II; sheared box, Sec. II.E).
+// Also bounds this step's non-affine displacement |dx - U^inf dt| for the
+// neighbour-list validity test.
+// ---------------------------------------------------------------------------
+template <bool MIX>
+__global__ __launch_bounds__(256) void k_integrate(Bufs b) {
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t r = b.blk_rep[q / kTile];
+    const RepParams& P = b.reps[r];
+    float disp = 0.0f;
+    if (q - P.p_begin < P.n) {
+        double4 x = b.pos[q];
+        double4 v = b.vf[q];
+        double4 w = b.wf[q];
+        double Fx, Fy, Fz, Tx, Ty, Tz;
+        if (MIX) {
+            const float4 f = ((const float4*)b.F)[q], t = ((const float4*)b.T)[q];
+            Fx = f.x; Fy = f.y; Fz = f.z; Tx = t.x; Ty = t.y; Tz = t.z;
+        } else {
+            const double4 f = ((const double4*)b.F)[q], t = ((const double4*)b.T)[q];
+            Fx = f.x; Fy = f.y; Fz = f.z; Tx = t.x; Ty = t.y; Tz = t.z;
+        }
+        const double a = x.w;
+        const double m = (4.0 / 3.0) * kPi * P.rho * a * a * a;
+        const double I = 0.4 * m * a * a;
+        const double hm = P.half_dt / m, hI = P.half_dt / I;
+        v.x += hm * Fx; v.y += hm * Fy; v.z += hm * Fz;
+        w.x += hI * Tx; w.y += hI * Ty; w.z += hI * Tz;
+        if (!(P.flags & F_FREEZE_X)) {
+            const double yold = x.y;
+            const double vdx = v.x, vdy = v.y, vdz = v.z;  // drift velocity
+            x.x += P.dt * v.x;
+            x.y += P.dt * v.y;
+            x.z += P.dt * v.z;
+            const double s = b.dyn[r].s_le;
+            const double Lx = P.L[0], Ly = P.L[1], Lz = P.L[2];
+            if (x.y >= Ly) {
+                x.y -= Ly; x.x -= s; v.x -= P.gdLy;
+            } else if (x.y < 0.0) {
+                x.y += Ly; x.x += s; v.x += P.gdLy;
+                if (x.y >= Ly) x.y = 0.0;
+            }
+            x.x -= Lx * floor(x.x / Lx);
+            x.z -= Lz * floor(x.z / Lz);
+            if (x.x >= Lx) x.x -= Lx;
+            if (x.z >= Lz) x.z -= Lz;
+            // non-affine displacement of this step: drift minus the imposed flow
+            // integrated along the path, gammadot (y(t) - Ly/2) with y(t) = yold + vdy t
+            const double ux = P.gd * (yold - 0.5 * Ly) + 0.5 * P.gd * P.dt * vdy;
+            const double ex = P.dt * (vdx - ux), ey = P.dt * vdy, ez = P.dt * vdz;
+            disp = (float)(sqrt(ex * ex + ey * ey + ez * ez) * (1.0 + 1e-6)) + 1e-30f;
+            b.pos[q] = x;
+        }
+        b.vh[q] = v;
+        b.wh[q] = w;
+        if (MIX) {
+            b.vsh[q] = make_float4((float)v.x, (float)v.y, (float)v.z, 0.0f);
+            b.wsh[q] = make_float4((float)w.x, (float)w.y, (float)w.z, 0.0f);
+        }
+    }
+    block_atomic_max(disp, &b.dyn[r].stepmax_bits);
+}
+
+// ---------------------------------------------------------------------------
+// Rebuild decision.  A pair outside the list at the last build (|r| > r_c +
+// skin) can have come within r_c only if 2 D + |gammadot| t (r_c + 4 D) >
+// skin, where D bounds every particle's non-affine displacement since the
+// build and t is the time since the build (the affine part of the relative
+// motion is gammadot r_y t along x, with |r_y| <= r_c + 4 D).  With
+// 2 D <= skin this is implied by 2 D + |gammadot| t (r_c + 2 skin) > skin.
+// ---------------------------------------------------------------------------
+__global__ void k_rebuild_decision(Bufs b, int force) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = force;
+    __syncthreads();
+    for (uint32_t r = threadIdx.x; r < b.nrep; r += blockDim.x) {
+        const RepParams& P = b.reps[r];
+        RepDyn& D = b.dyn[r];
+        D.dmax += (double)as_posf(D.stepmax_bits);
+        D.t_since += P.dt;
+        const double gd = fabs(P.gd);
+        const bool trig = 2.0 * D.dmax + gd * D.t_since * (P.rc_max + 2.0 * P.skin) > P.skin;
+        if (trig || (P.flags & F_REBUILD_EACH_STEP)) any = 1;  // benign race: all writers store 1
+    }
+    __syncthreads();
+    if (any) {
+        for (uint32_t r = threadIdx.x; r < b.nrep; r += blockDim.x) {
+            b.dyn[r].dmax = 0.0;
+            b.dyn[r].t_since = 0.0;
+        }
+    }
+    if (threadIdx.x == 0) {
+        b.sys->rebuild = any ? 1u : 0u;
+        if (any) b.sys->rebuilds += 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Rebuild: Morton-ordered cells, deterministic order inside a cell (by id),
+// reorder of all particle data, neighbour list with history carry-over.
+// ---------------------------------------------------------------------------
+__global__ void k_rb_zero(Bufs b) {
+    if (!b.sys->rebuild) return;
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < b.nkeys_total) {
+        b.cell_cnt[k] = 0u;
+        b.cell_fill[k] = 0u;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rb_keys(Bufs b) {
+    if (!b.sys->rebuild) return;
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t r = b.blk_rep[q / kTile];
+    const RepParams& P = b.reps[r];
+    const uint32_t lq = q - P.p_begin;
+    if (lq < P.n) {
+        const double4 x = b.pos[q];
+        const int cx = cell_coord(x.x, P.cw[0], P.nc[0]);
+        const int cy = cell_coord(x.y, P.cw[1], P.nc[1]);
+        const int cz = cell_coord(x.z, P.cw[2], P.nc[2]);
+        const uint32_t key = P.key_off + morton3((uint32_t)cx, (uint32_t)cy, (uint32_t)cz);
+        b.key[q] = key;
+        atomicAdd(&b.cell_cnt[key], 1u);
+    } else if (lq == P.n && P.n_pad > P.n) {
+        // the padding slots of the replica form one extra cell at its end
+        atomicAdd(&b.cell_cnt[P.key_off + P.nkeys - 1], P.n_pad - P.n);
+    }
+}
+
+// exclusive scan of cell counts: per-block sums, scan of the sums, down-sweep
+constexpr int kScanPer = 4;
+constexpr int kScanBlock = 256;
+constexpr int kScanTile = kScanPer * kScanBlock;
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total) {
+    __shared__ uint32_t wsum[kScanBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (int w = 0; w < kScanBlock / 64; ++w) {
+        if (w < wave) base += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + x - v;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_reduce(Bufs b) {
+    if (!b.sys->rebuild) return;
+    const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+    uint32_t s = 0;
+#pragma unroll
+    for (int t = 0; t < kScanPer; ++t) s += (base + t < b.nkeys_total) ? b.cell_cnt[base + t] : 0u;
+    uint32_t tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) b.scan_blk[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_top(Bufs b, uint32_t nblk) {
+    if (!b.sys->rebuild) return;
+    // single block: scan nblk block sums in chunks of kScanBlock
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < nblk; c0 += kScanBlock) {
+        const uint32_t k = c0 + threadIdx.x;
+        const uint32_t v = k < nblk ? b.scan_blk[k] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_excl_scan(v, &tot);
+        if (k < nblk) b.scan_blk[k] = carry + ex;
+        carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) b.cell_start[b.nkeys_total] = carry;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_down(Bufs b) {
+    if (!b.sys->rebuild) return;
+    const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+    uint32_t v[kScanPer];
+    uint32_t s = 0;
+#pragma unroll
+    for (int t = 0; t < kScanPer; ++t) {
+        v[t] = (base + t < b.nkeys_total) ? b.cell_cnt[base + t] : 0u;
+        s += v[t];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(s, &tot) + b.scan_blk[blockIdx.x];
+#pragma unroll
+    for (int t = 0; t < kScanPer; ++t) {
+        if (base + t < b.nkeys_total) b.cell_start[base + t] = ex;
+        ex += v[t];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rb_scatter(Bufs b) {
+    if (!b.sys->rebuild) return;
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t r = b.blk_rep[q / kTile];
+    const RepParams& P = b.reps[r];
+    if (q - P.p_begin < P.n) {
+        const uint32_t key = b.key[q];
+        const uint32_t slot = b.cell_start[key] + atomicAdd(&b.cell_fill[key], 1u);
+        b.src[slot] = q;
+    }
+}
+
+// order the members of each cell by particle id (makes the layout independent of atomic order)
+__global__ void k_rb_cellsort(Bufs b) {
+    if (!b.sys->rebuild) return;
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= b.nkeys_total) return;
+    const uint32_t cnt = b.cell_fill[k];
+    if (cnt < 2 || cnt != b.cell_cnt[k]) return;  // padding cells have fill 0
+    const uint32_t s0 = b.cell_start[k];
+    for (uint32_t a = 1; a < cnt; ++a) {
+        const uint32_t v = b.src[s0 + a];
+        const uint32_t idv = b.id[v];
+        int c = (int)a - 1;
+        while (c >= 0 && b.id[b.src[s0 + c]] > idv) {
+            b.src[s0 + c + 1] = b.src[s0 + c];
+            --c;
+        }
+        b.src[s0 + c + 1] = v;
+    }
+}
+
+// gather every particle array into its new slot (staging copies), and turn
+// the per-entry contact history of the old list into a compact per-particle
+// table keyed by partner id
+__global__ __launch_bounds__(256) void k_rb_gather(Bufs b, uint32_t ct_input_rep) {
+    if (!b.sys->rebuild) return;
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t r = b.blk_rep[q / kTile];
+    const RepParams& P = b.reps[r];
+    const uint32_t npad = b.npad;
+    if (q - P.p_begin >= P.n) {
+        b.alt_id[q] = kNoId;
+        for (int a = 0; a < 7; ++a) b.alt4[a][q] = make_double4(0.0, 0.0, 0.0, 0.0);
+        b.ct_n[q] = 0u;
+        return;
+    }
+    const uint32_t s = b.src[q];
+    b.alt_id[q] = b.id[s];
+    b.alt4[0][q] = b.pos[s];
+    b.alt4[1][q] = b.vh[s];
+    b.alt4[2][q] = b.wh[s];
+    b.alt4[3][q] = b.vf[s];
+    b.alt4[4][q] = b.wf[s];
+    if (b.mixed) {
+        const float4 f = ((const float4*)b.F)[s], t = ((const float4*)b.T)[s];
+        b.alt4[5][q] = make_double4(f.x, f.y, f.z, 0.0);
+        b.alt4[6][q] = make_double4(t.x, t.y, t.z, 0.0);
+    } else {
+        b.alt4[5][q] = ((const double4*)b.F)[s];
+        b.alt4[6][q] = ((const double4*)b.T)[s];
+    }
+    uint32_t c = 0;
+    if (ct_input_rep == 0xFFFFFFFEu || r == ct_input_rep) {
+        // history given by the host in compact form at the old slot (second table)
+        const uint32_t nin = b.ct_n[npad + s];
+        for (uint32_t e = 0; e < nin && c < (uint32_t)kCtCap; ++e, ++c) {
+            b.ct_id[c * npad + q] = b.ct_id[(kCtCap + e) * npad + s];
+            for (int d = 0; d < 3; ++d) b.ct_s[(c * 3 + d) * npad + q] = b.ct_s[((kCtCap + e) * 3 + d) * npad + s];
+            b.ct_sl[c * npad + q] = 0;
+        }
+    } else {
+        const uint64_t cm = b.cmask[s], sm = b.smask[s];
+        const uint32_t cnt = b.ncnt[s];
+        for (uint32_t e = 0; e < cnt; ++e) {
+            if (!((cm >> e) & 1ull)) continue;
+            if (c >= (uint32_t)kCtCap) {
+                atomicOr(&b.dyn[r].health, H_NLIST);
+                break;
+            }
+            b.ct_id[c * npad + q] = b.id[b.nbr[e * npad + s]];
+            for (int d = 0; d < 3; ++d) {
+                const double hv = b.mixed ? (double)((const float*)b.hs[d])[e * npad + s]
+                                          : ((const double*)b.hs[d])[e * npad + s];
+                b.ct_s[(c * 3 + d) * npad + q] = hv;
+            }
+            b.ct_sl[c * npad + q] = (uint8_t)((sm >> e) & 1ull);
+            ++c;
+        }
+    }
+    b.ct_n[q] = c;
+}
+
+__global__ __launch_bounds__(256) void k_rb_copyback(Bufs b) {
+    if (!b.sys->rebuild) return;
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    b.id[q] = b.alt_id[q];
+    b.pos[q] = b.alt4[0][q];
+    const double4 vh = b.alt4[1][q], wh = b.alt4[2][q];
+    b.vh[q] = vh;
+    b.wh[q] = wh;
+    b.vf[q] = b.alt4[3][q];
+    b.wf[q] = b.alt4[4][q];
+    if (b.mixed) {
+        const double4 f = b.alt4[5][q], t = b.alt4[6][q];
+        ((float4*)b.F)[q] = make_float4((float)f.x, (float)f.y, (float)f.z, 0.0f);
+        ((float4*)b.T)[q] = make_float4((float)t.x, (float)t.y, (float)t.z, 0.0f);
+        b.vsh[q] = make_float4((float)vh.x, (float)vh.y, (float)vh.z, 0.0f);
+        b.wsh[q] = make_float4((float)wh.x, (float)wh.y, (float)wh.z, 0.0f);
+    } else {
+        ((double4*)b.F)[q] = b.alt4[5][q];
+        ((double4*)b.T)[q] = b.alt4[6][q];
+    }
+}
+
+// Verlet list: every j with |r| <= (a_i + a_j)(1 + xi_cut/2) + skin, sorted by
+// partner id (so force sums do not depend on the cell layout), then the
+// carried contact history is attached to its list entry.
+__global__ __launch_bounds__(256) void k_rb_nlist(Bufs b) {
+    if (!b.sys->rebuild) return;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t r = b.blk_rep[i / kTile];
+    const RepParams& P = b.reps[r];
+    const uint32_t npad = b.npad, cap = b.cap;
+    if (i - P.p_begin >= P.n) {
+        b.ncnt[i] = 0u;
+        b.cmask[i] = 0ull;
+        b.smask[i] = 0ull;
+        return;
+    }
+    const double4 pi = b.pos[i];
+    const double s_le = b.dyn[r].s_le;
+    const double amax = P.rc_max / (2.0 * P.c1);
+    const double rli = (pi.w + amax) * P.c1 + P.skin;           // largest list radius of i
+    const double margin = rli * (1.0 + 1e-12) + 1e-12 * P.L[0];
+    const int cy = cell_coord(pi.y, P.cw[1], P.nc[1]);
+    const int cz = cell_coord(pi.z, P.cw[2], P.nc[2]);
+    uint32_t cnt = 0;
+    const int oy0 = P.nc[1] == 1 ? 0 : -1, oy1 = P.nc[1] == 1 ? 0 : 1;
+    const int oz0 = P.nc[2] == 1 ? 0 : -1, oz1 = P.nc[2] == 1 ? 0 : 1;
+    for (int oz = oz0; oz <= oz1; ++oz) {
+        const int zz = (cz + oz + P.nc[2]) % P.nc[2];
+        for (int oy = oy0; oy <= oy1; ++oy) {
+            int yy = cy + oy;
+            double shift = 0.0;
+            bool all_x = (P.nc[0] == 1) || (P.nc[1] == 1);
+            if (yy < 0) { yy += P.nc[1]; shift = s_le; }          // j's image sits at y - Ly, x - s
+            else if (yy >= P.nc[1]) { yy -= P.nc[1]; shift = -s_le; }
+            const double xs = pi.x + shift;
+            int xlo = (int)floor((xs - margin) / P.cw[0]);
+            int xhi = (int)floor((xs + margin) / P.cw[0]);
+            if (all_x || xhi - xlo + 1 >= P.nc[0]) { xlo = 0; xhi = P.nc[0] - 1; }
+            for (int xc = xlo; xc <= xhi; ++xc) {
+                const int xx = ((xc % P.nc[0]) + P.nc[0]) % P.nc[0];
+                const uint32_t key = P.key_off + morton3((uint32_t)xx, (uint32_t)yy, (uint32_t)zz);
+                const uint32_t st = b.cell_start[key], en = st + b.cell_cnt[key];
+                for (uint32_t j = st; j < en; ++j) {
+                    if (j == i) continue;
+                    const double4 pj = b.pos[j];
+                    double dx, dy, dz;
+                    min_image(P, s_le, pi, pj, dx, dy, dz);
+                    const double d2 = (dx * dx + dy * dy) + dz * dz;
+                    const double rl = (pi.w + pj.w) * P.c1 + P.skin;
+                    if (d2 <= rl * rl) {
+                        if (cnt < cap) b.nbr[cnt * npad + i] = j;
+                        ++cnt;
+                    }
+                }
+            }
+        }
+    }
+    if (cnt > cap) {
+        atomicOr(&b.dyn[r].health, H_NLIST);
+        cnt = cap;
+    }
+    // insertion sort of the entries by partner id
+    for (uint32_t a = 1; a < cnt; ++a) {
+        const uint32_t v = b.nbr[a * npad + i];
+        const uint32_t idv = b.id[v];
+        int c = (int)a - 1;
+        while (c >= 0 && b.id[b.nbr[c * npad + i]] > idv) {
+            b.nbr[(c + 1) * npad + i] = b.nbr[c * npad + i];
+            --c;
+        }
+        b.nbr[(c + 1) * npad + i] = v;
+    }
+    b.ncnt[i] = cnt;
+    // attach carried contact history
+    uint64_t cm = 0ull, sm = 0ull;
+    const uint32_t nct = b.ct_n[i];
+    for (uint32_t c = 0; c < nct; ++c) {
+        const uint32_t pid = b.ct_id[c * npad + i];
+        for (uint32_t e = 0; e < cnt; ++e) {
+            if (b.id[b.nbr[e * npad + i]] == pid) {
+                for (int d = 0; d < 3; ++d) {
+                    const double v = b.ct_s[(c * 3 + d) * npad + i];
+                    if (b.mixed) ((float*)b.hs[d])[e * npad + i] = (float)v;
+                    else ((double*)b.hs[d])[e * npad + i] = v;
+                }
+                cm |= 1ull << e;
+                if (b.ct_sl[c * npad + i]) sm |= 1ull << e;
+                break;
+            }
+        }
+    }
+    b.cmask[i] = cm;
+    b.smask[i] = sm;
+}
+
+// ---------------------------------------------------------------------------
+// Pair forces (Sec. II.A-II.D), one-body terms (Sec. II.B-II.C), kick 2.
+// One lane per particle i walks its Verlet list.  Every pair is evaluated in
+// canonical orientation (lower id = "a", higher id = "b", r = x_a - x_b), so
+// both sides compute bit-identical pair terms and the pair forces are
+// exactly antisymmetric; the stress of a pair is added on the lower-id side.
+// ---------------------------------------------------------------------------
+template <class R> struct Acc;
+template <> struct Acc<double> {
+    double v[3] = {0.0, 0.0, 0.0};
+    __device__ __forceinline__ void add(int d, double x) { v[d] += x; }
+    __device__ __forceinline__ double get(int d) const { return v[d]; }
+};
+// FP32 with Neumaier compensation
+template <> struct Acc<float> {
+    float s[3] = {0.f, 0.f, 0.f}, c[3] = {0.f, 0.f, 0.f};
+    __device__ __forceinline__ void add(int d, float x) {
+        const float t = s[d] + x;
+        const float e = fabsf(s[d]) >= fabsf(x) ? (s[d] - t) + x : (x - t) + s[d];
+        c[d] += e;
+        s[d] = t;
+    }
+    __device__ __forceinline__ double get(int d) const { return (double)s[d] + (double)c[d]; }
+};
+
+template <class R> __device__ __forceinline__ R rlog(R x);
+template <> __device__ __forceinline__ double rlog<double>(double x) { return log(x); }
+template <> __device__ __forceinline__ float rlog<float>(float x) {
+    return 0.69314718055994531f * __builtin_amdgcn_logf(x);
+}
+template <class R> __device__ __forceinline__ R rsqrt_(R x);
+template <> __device__ __forceinline__ double rsqrt_<double>(double x) { return sqrt(x); }
+template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return __fsqrt_rn(x); }
+
+template <bool MIX>
+__global__ __launch_bounds__(256) void k_pair(Bufs b, int kick, uint32_t only_rep) {
+    using R = typename std::conditional<MIX, float, double>::type;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t r = b.blk_rep[i / kTile];
+    if (only_rep != 0xFFFFFFFFu && r != only_rep) return;  // whole block belongs to one replica
+    const RepParams& P = b.reps[r];
+    const RepDyn& D = b.dyn[r];
+    const uint32_t npad = b.npad;
+    const bool valid = (i - P.p_begin) < P.n;
+
+    double sC[9], sL[9], sB[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) { sC[t] = 0.0; sL[t] = 0.0; sB[t] = 0.0; }
+    float maxov = 0.0f;
+    bool bad = false;
+
+    if (valid) {
+        const double4 pi = b.pos[i];
+        const uint32_t idi = b.id[i];
+        const double s_le = D.s_le;
+        const uint64_t step = D.step;
+        const uint32_t k0 = (uint32_t)P.seed, k1 = (uint32_t)(P.seed >> 32);
+        const uint32_t ctr_lo = (uint32_t)step, ctr_hi = (uint32_t)(step >> 32) << 8;
+        const double4 vhi = b.vh[i];
+        const double4 whi = b.wh[i];
+        R vi[3], wi[3];
+        if (MIX) {
+            const float4 v4 = b.vsh[i], w4 = b.wsh[i];
+            vi[0] = v4.x; vi[1] = v4.y; vi[2] = v4.z;
+            wi[0] = w4.x; wi[1] = w4.y; wi[2] = w4.z;
+        } else {
+            vi[0] = (R)vhi.x; vi[1] = (R)vhi.y; vi[2] = (R)vhi.z;
+            wi[0] = (R)whi.x; wi[1] = (R)whi.y; wi[2] = (R)whi.z;
+        }
+        const R ai = (R)pi.w;
+        const double c1 = P.c1;
+        const R bamp = (R)P.bamp;
+        const R eta6pi = (R)(6.0 * kPi * P.eta);
+        const R xi_min = (R)P.xi_min;
+        const R kn = (R)P.kn, kt = (R)P.kt, mukn = (R)(P.mu * P.kn), dtR = (R)P.dt;
+        const bool do_lub = !(P.flags & F_NO_LUB), do_br = !(P.flags & F_NO_PAIR_BROWN);
+        const bool do_ct = !(P.flags & F_NO_CONTACT);
+
+        Acc<R> F, T;
+        const uint32_t cnt = b.ncnt[i];
+        const uint64_t cm_old = b.cmask[i], sm_old = b.smask[i];
+        uint64_t cm = 0ull, sm = 0ull;
+
+        for (uint32_t e = 0; e < cnt; ++e) {
+            const uint32_t j = b.nbr[e * npad + i];
+            const double4 pj = b.pos[j];
+            const uint32_t idj = b.id[j];
+            const bool lo = idi < idj;  // this lane holds the lower id
+            double dx, dy, dz;
+            const int ky = lo ? min_image(P, s_le, pi, pj, dx, dy, dz) : min_image(P, s_le, pj, pi, dx, dy, dz);
+            const double d2 = (dx * dx + dy * dy) + dz * dz;
+            const double sa = pi.w + pj.w;
+            const double rc = sa * c1;
+            if (!(d2 <= rc * rc)) continue;
+
+            // geometry (FP64): distance, unit normal a <- b, gap
+            const double dist = sqrt(d2);
+            const double h = dist - sa;
+            R n[3];
+            if (MIX) {
+                const float inv = 1.0f / (float)dist;
+                n[0] = (float)dx * inv; n[1] = (float)dy * inv; n[2] = (float)dz * inv;
+            } else {
+                n[0] = (R)(dx / dist); n[1] = (R)(dy / dist); n[2] = (R)(dz / dist);
+            }
+            const R aj = (R)pj.w;
+            const R aa = lo ? ai : aj, ab = lo ? aj : ai;  // canonical radii
+            R xi = (R)((2.0 * h) / sa);
+            const R xie = xi < xi_min ? xi_min : xi;
+
+            // resistance scalars X^A_11, Y^A_11 (Sec. II.B) in the symmetric form
+            const R pab = aa * ab, qab = aa * aa + ab * ab;
+            const R sR = aa + ab;
+            const R pre = eta6pi / (sR * sR * sR);
+            const R lg = -rlog<R>(xie);
+            const R XA = pre * ((R)2 * pab * pab / xie + pab * (qab + (R)7 * pab) / (R)5 * lg);
+            const R YA = pre * ((R)4 * pab * ((R)2 * qab + pab) / (R)15 * lg);
+
+            // velocities in canonical orientation; image of b moves with +k_y gammadot Ly
+            R va[3], vb[3];
+            const R shiftv = (R)((double)ky * P.gdLy);
+            R vj[3];
+            if (MIX) {
+                const float4 v4 = b.vsh[j];
+                vj[0] = v4.x; vj[1] = v4.y; vj[2] = v4.z;
+            } else {
+                const double4 v4 = b.vh[j];
+                vj[0] = (R)v4.x; vj[1] = (R)v4.y; vj[2] = (R)v4.z;
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) { va[d] = lo ? vi[d] : vj[d]; vb[d] = lo ? vj[d] : vi[d]; }
+            vb[0] = vb[0] + shiftv;
+
+            R f[3] = {(R)0, (R)0, (R)0};   // total pair force on a
+            R fl[3] = {(R)0, (R)0, (R)0}, fb[3] = {(R)0, (R)0, (R)0}, fc[3] = {(R)0, (R)0, (R)0};
+            if (do_lub) {
+                // eq. (force_lub): (X^A N + Y^A T)(U_b - U_a)
+                R ur[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) ur[d] = vb[d] - va[d];
+                const R un = (n[0] * ur[0] + n[1] * ur[1]) + n[2] * ur[2];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) fl[d] = XA * (un * n[d]) + YA * (ur[d] - un * n[d]);
+            }
+            if (do_br) {
+                // eq. (force_brownian_lub): sqrt(2kT/dt) (sqrt(X^A) N + sqrt(Y^A) T) theta
+                const uint32_t ida = lo ? idi : idj, idb = lo ? idj : idi;
+                const uint4 w = philox10(ctr_lo, ida, idb, ctr_hi, k0, k1);
+                R th[3];
+                normals3(w, th);
+                const R tn = (n[0] * th[0] + n[1] * th[1]) + n[2] * th[2];
+                const R sx = rsqrt_<R>(XA), sy = rsqrt_<R>(YA);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) fb[d] = bamp * (sx * (tn * n[d]) + sy * (th[d] - tn * n[d]));
+            }
+            if (h < 0.0 && do_ct) {
+                // eq. (force_contact), (torque_contact); the spring s lives in canonical orientation
+                const R delta = (R)(-h);
+                if ((float)(-h) > maxov) maxov = (float)(-h);
+                R s[3] = {(R)0, (R)0, (R)0};
+                if ((cm_old >> e) & 1ull) {
+                    if (MIX) {
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) s[d] = ((const float*)b.hs[d])[e * npad + i];
+                    } else {
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) s[d] = ((const double*)b.hs[d])[e * npad + i];
+                    }
+                }
+                R wj[3];
+                if (MIX) {
+                    const float4 w4 = b.wsh[j];
+                    wj[0] = w4.x; wj[1] = w4.y; wj[2] = w4.z;
+                } else {
+                    const double4 w4 = b.wh[j];
+                    wj[0] = (R)w4.x; wj[1] = (R)w4.y; wj[2] = (R)w4.z;
+                }
+                R aw[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const R wa = lo ? wi[d] : wj[d], wb = lo ? wj[d] : wi[d];
+                    aw[d] = aa * wa + ab * wb;
+                }
+                const R awn[3] = {aw[1] * n[2] - aw[2] * n[1], aw[2] * n[0] - aw[0] * n[2],
+                                  aw[0] * n[1] - aw[1] * n[0]};
+                R vc[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) vc[d] = (va[d] - vb[d]) - awn[d];
+                const R vcn = (n[0] * vc[0] + n[1] * vc[1]) + n[2] * vc[2];
+                R vt[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) vt[d] = vc[d] - vcn * n[d];
+                const R sn = (n[0] * s[0] + n[1] * s[1]) + n[2] * s[2];
+                R pr[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) pr[d] = s[d] - sn * n[d];
+                const R ps = rsqrt_<R>((pr[0] * pr[0] + pr[1] * pr[1]) + pr[2] * pr[2]);
+                if (ps > (R)0) {
+                    const R ss = rsqrt_<R>((s[0] * s[0] + s[1] * s[1]) + s[2] * s[2]);
+                    const R fac = ss / ps;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) s[d] = pr[d] * fac;
+                } else {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) s[d] = pr[d];
+                }
+#pragma unroll
+                for (int d = 0; d < 3; ++d) s[d] = s[d] + dtR * vt[d];
+                const R ftmax = mukn * delta;
+                const R sl = rsqrt_<R>((s[0] * s[0] + s[1] * s[1]) + s[2] * s[2]);
+                if (kt * sl > ftmax) {
+                    const R fac = ftmax / (kt * sl);
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) s[d] = s[d] * fac;
+                    sm |= 1ull << e;
+                }
+                if (MIX) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) ((float*)b.hs[d])[e * npad + i] = (float)s[d];
+                } else {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) ((double*)b.hs[d])[e * npad + i] = (double)s[d];
+                }
+                cm |= 1ull << e;
+                const R ks[3] = {kt * s[0], kt * s[1], kt * s[2]};
+#pragma unroll
+                for (int d = 0; d < 3; ++d) fc[d] = (kn * delta) * n[d] - ks[d];
+                const R nks[3] = {n[1] * ks[2] - n[2] * ks[1], n[2] * ks[0] - n[0] * ks[2],
+                                  n[0] * ks[1] - n[1] * ks[0]};
+#pragma unroll
+                for (int d = 0; d < 3; ++d) T.add(d, ai * nks[d]);
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                f[d] = fl[d] + fb[d] + fc[d];
+                F.add(d, lo ? f[d] : -f[d]);
+            }
+            if (lo) {
+                // Sec. II.A, II.B, II.D: Sigma^X_ab -= F^X_a r_b / V, FP64
+                const double rr[3] = {dx, dy, dz};
+#pragma unroll
+                for (int al = 0; al < 3; ++al)
+#pragma unroll
+                    for (int be = 0; be < 3; ++be) {
+                        sC[3 * al + be] -= (double)fc[al] * rr[be] * P.invV;
+                        sL[3 * al + be] -= (double)fl[al] * rr[be] * P.invV;
+                        sB[3 * al + be] -= (double)fb[al] * rr[be] * P.invV;
+                    }
+            }
+        }
+
+        // one-body terms: eq. (force_drag), (torque_drag), (force_brownian_drag), (torque_brownian_drag)
+        double Ft[3], Tt[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) { Ft[d] = F.get(d); Tt[d] = T.get(d); }
+        if (!(P.flags & F_NO_ONEBODY)) {
+            const double a = pi.w;
+            const R zeta = (R)(6.0 * kPi * P.eta * a);
+            const R zr = (R)(8.0 * kPi * P.eta * a * a * a);
+            const R uinf[3] = {(R)(P.gd * (pi.y - 0.5 * P.L[1])), (R)0, (R)0};
+            const R oinf[3] = {(R)0, (R)0, (R)(-0.5 * P.gd)};
+            const uint4 wf = philox10(ctr_lo, idi, 0xFFFFFFFFu, ctr_hi | 2u, k0, k1);
+            const uint4 wt = philox10(ctr_lo, idi, 0xFFFFFFFFu, ctr_hi | 3u, k0, k1);
+            R psi[3], phi[3];
+            normals3(wf, psi);
+            normals3(wt, phi);
+            const R sz = rsqrt_<R>(zeta), szr = rsqrt_<R>(zr);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                Ft[d] += (double)(zeta * (uinf[d] - vi[d]) + bamp * sz * psi[d]);
+                Tt[d] += (double)(zr * (oinf[d] - wi[d]) + bamp * szr * phi[d]);
+            }
+        }
+        bad = !(isfinite(Ft[0]) && isfinite(Ft[1]) && isfinite(Ft[2]) && isfinite(Tt[0]) && isfinite(Tt[1]) &&
+                isfinite(Tt[2]));
+        b.cmask[i] = cm;
+        b.smask[i] = sm;
+        if (MIX) {
+            ((float4*)b.F)[i] = make_float4((float)Ft[0], (float)Ft[1], (float)Ft[2], 0.0f);
+            ((float4*)b.T)[i] = make_float4((float)Tt[0], (float)Tt[1], (float)Tt[2], 0.0f);
+        } else {
+            ((double4*)b.F)[i] = make_double4(Ft[0], Ft[1], Ft[2], 0.0);
+            ((double4*)b.T)[i] = make_double4(Tt[0], Tt[1], Tt[2], 0.0);
+        }
+        // kick 2 of velocity-Verlet
+        double4 vf = vhi, wf = whi;
+        if (kick) {
+            const double a = pi.w;
+            const double m = (4.0 / 3.0) * kPi * P.rho * a * a * a;
+            const double I = 0.4 * m * a * a;
+            const double hm = P.half_dt / m, hI = P.half_dt / I;
+            vf.x += hm * Ft[0]; vf.y += hm * Ft[1]; vf.z += hm * Ft[2];
+            wf.x += hI * Tt[0]; wf.y += hI * Tt[1]; wf.z += hI * Tt[2];
+        }
+        b.vf[i] = vf;
+        b.wf[i] = wf;
+        (void)sm_old;
+    }
+
+    // health: overlap above the limit, non-finite forces
+    if (bad) atomicOr(&b.dyn[r].health, H_NAN);
+    block_atomic_max(maxov, &b.dyn[r].maxov_bits);
+
+    // block partial sums of the 27 stress components, fixed order
+    __shared__ double red[4][27];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 27; ++c) {
+        double v = c < 9 ? sC[c] : (c < 18 ? sL[c - 9] : sB[c - 18]);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) red[wave][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 27) {
+        const int c = threadIdx.x;
+        b.partial[(size_t)blockIdx.x * 27 + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+    }
+}
+
+// per-replica stress: fixed-order sum of the block partials
+__global__ __launch_bounds__(256) void k_reduce_stress(Bufs b, int record, uint32_t only_rep) {
+    const uint32_t r = blockIdx.x;
+    if (only_rep != 0xFFFFFFFFu && r != only_rep) return;
+    const RepParams& P = b.reps[r];
+    __shared__ double acc[256];
+    __shared__ double out[27];
+    for (int c = 0; c < 27; ++c) {
+        double s = 0.0;
+        for (uint32_t k = threadIdx.x; k < P.nblk; k += blockDim.x) s += b.partial[(size_t)(P.blk_begin + k) * 27 + c];
+        acc[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) acc[threadIdx.x] += acc[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[c] = acc[0];
+        __syncthreads();
+    }
+    RepDyn& D = b.dyn[r];
+    if (threadIdx.x < 27) {
+        const int c = threadIdx.x;
+        b.last[r * 27 + c] = out[c];
+        if (record) {
+            b.ring[((size_t)r * kRing + (D.ring_head % kRing)) * 27 + c] = out[c];
+            D.stress_sum[c] += out[c];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (record) {
+            D.ring_head += 1;
+            D.stress_count += 1;
+        }
+        if ((double)__uint_as_float(D.maxov_bits) > P.max_overlap) D.health |= H_OVERLAP;
+    }
+}
+
+// diagnostics: mode 0 = interaction set, 1 = Verlet list, 2 = contacts (with springs)
+__global__ void k_diag(Bufs b, uint32_t rep, uint32_t* out_ij, double* out_s, int32_t* out_sl, uint32_t* count,
+                       uint32_t cap, int mode) {
+    const RepParams& P = b.reps[rep];
+    const uint32_t i = P.p_begin + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i - P.p_begin >= P.n) return;
+    const double4 pi = b.pos[i];
+    const uint32_t idi = b.id[i];
+    const uint32_t cnt = b.ncnt[i];
+    const uint64_t cm = b.cmask[i], sm = b.smask[i];
+    const double s_le = b.dyn[rep].s_le;
+    for (uint32_t e = 0; e < cnt; ++e) {
+        const uint32_t j = b.nbr[e * b.npad + i];
+        const uint32_t idj = b.id[j];
+        if (!(idi < idj)) continue;
+        bool take;
+        if (mode == 1) {
+            take = true;
+        } else if (mode == 2) {
+            take = (cm >> e) & 1ull;
+        } else {
+            double dx, dy, dz;
+            min_image(P, s_le, pi, b.pos[j], dx, dy, dz);
+            const double d2 = (dx * dx + dy * dy) + dz * dz;
+            const double rc = (pi.w + b.pos[j].w) * P.c1;
+            take = d2 <= rc * rc;
+        }
+        if (!take) continue;
+        const uint32_t k = atomicAdd(count, 1u);
+        if (k < cap) {
+            out_ij[2 * k] = idi;
+            out_ij[2 * k + 1] = idj;
+            if (mode == 2) {
+                for (int d = 0; d < 3; ++d)
+                    out_s[3 * k + d] = b.mixed ? (double)((const float*)b.hs[d])[e * b.npad + i]
+                                               : ((const double*)b.hs[d])[e * b.npad + i];
+                out_sl[k] = (int32_t)((sm >> e) & 1ull);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline uint32_t nblocks(uint32_t n, uint32_t bs) { return (n + bs - 1) / bs; }
+
+void launch_step_begin(const Bufs& b, hipStream_t st) {
+    hipLaunchKernelGGL(k_step_begin, dim3(nblocks(b.nrep, 64)), dim3(64), 0, st, b);
+}
+
+void launch_integrate(const Bufs& b, hipStream_t st) {
+    if (b.mixed) hipLaunchKernelGGL(k_integrate<true>, dim3(b.npad / 256), dim3(256), 0, st, b);
+    else hipLaunchKernelGGL(k_integrate<false>, dim3(b.npad / 256), dim3(256), 0, st, b);
+}
+
+void launch_rebuild_decision(const Bufs& b, hipStream_t st, int force) {
+    hipLaunchKernelGGL(k_rebuild_decision, dim3(1), dim3(256), 0, st, b, force);
+}
+
+void launch_rebuild(const Bufs& b, hipStream_t st, int ct_input_rep) {
+    const uint32_t np = b.npad / 256;
+    hipLaunchKernelGGL(k_rb_zero, dim3(nblocks(b.nkeys_total, 256)), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_rb_keys, dim3(np), dim3(256), 0, st, b);
+    const uint32_t nsb = nblocks(b.nkeys_total, kScanTile);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nsb), dim3(kScanBlock), 0, st, b);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanBlock), 0, st, b, nsb);
+    hipLaunchKernelGGL(k_scan_down, dim3(nsb), dim3(kScanBlock), 0, st, b);
+    hipLaunchKernelGGL(k_rb_scatter, dim3(np), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_rb_cellsort, dim3(nblocks(b.nkeys_total, 256)), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_rb_gather, dim3(np), dim3(256), 0, st, b, (uint32_t)ct_input_rep);
+    hipLaunchKernelGGL(k_rb_copyback, dim3(np), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_rb_nlist, dim3(np), dim3(256), 0, st, b);
+}
+
+void launch_pair_force(const Bufs& b, hipStream_t st, int kick, uint32_t only_rep) {
+    if (b.mixed) hipLaunchKernelGGL(k_pair<true>, dim3(b.npad / 256), dim3(256), 0, st, b, kick, only_rep);
+    else hipLaunchKernelGGL(k_pair<false>, dim3(b.npad / 256), dim3(256), 0, st, b, kick, only_rep);
+}
+
+void launch_reduce_stress(const Bufs& b, hipStream_t st, int record, uint32_t only_rep) {
+    hipLaunchKernelGGL(k_reduce_stress, dim3(b.nrep), dim3(256), 0, st, b, record, only_rep);
+}
+
+void launch_diag(const Bufs& b, hipStream_t st, uint32_t rep, uint32_t n, uint32_t* out_ij, double* out_s,
+                 int32_t* out_sl, uint32_t* count, uint32_t cap, int mode) {
+    hipLaunchKernelGGL(k_diag, dim3(nblocks(n, 256)), dim3(256), 0, st, b, rep, out_ij, out_s, out_sl, count, cap,
+                       mode);
+}
+
+}  // namespace susp

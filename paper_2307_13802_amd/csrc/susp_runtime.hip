@@ -1,0 +1,856 @@
+// Host runtime and C ABI of the force engine (declared in include/sim.h):
+// configuration checks, device memory, the per-step launch sequence captured
+// in HIP graphs, state transfer in particle-id order and diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sim.h"
+#include "susp.h"
+
+using namespace susp;
+
+namespace {
+
+std::mutex g_mu;
+std::string g_err;  // message of the last failure not tied to a handle
+void* (*g_alloc)(size_t, void*) = nullptr;
+void (*g_free)(void*, void*) = nullptr;
+void* g_alloc_ctx = nullptr;
+
+constexpr uint32_t kDefaultCap = 48;
+constexpr int kGraphSteps = 8;
+
+struct HipError {
+    hipError_t e;
+    const char* what;
+};
+
+#define HIPCHK(x)                                        \
+    do {                                                 \
+        hipError_t e__ = (x);                            \
+        if (e__ != hipSuccess) throw HipError{e__, #x};  \
+    } while (0)
+
+void set_global_error(const std::string& m) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_err = m;
+}
+
+std::string fmt(const char* f, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, f);
+    vsnprintf(buf, sizeof buf, f, ap);
+    va_end(ap);
+    return buf;
+}
+
+}  // namespace
+
+struct sim {
+    int nrep = 0;
+    int mixed = 0;
+    uint32_t flags = 0;
+    std::vector<sim_config> cfg;
+    std::vector<std::vector<double>> radii;  // id order
+    std::vector<RepParams> P;
+    std::vector<double> drag_xy;             // drag stresslet sigma_xy = sigma_yx per replica
+    std::vector<uint32_t> ring_tail;
+    Bufs b{};
+    hipStream_t st = nullptr;
+    hipStream_t cap_st = nullptr;            // stream used only to capture graphs
+    hipGraphExec_t g1 = nullptr, gk = nullptr;
+    std::vector<std::pair<void*, size_t>> allocs;
+    void* (*afn)(size_t, void*) = nullptr;
+    void (*ffn)(void*, void*) = nullptr;
+    void* actx = nullptr;
+    std::string err;
+    int profile = 0;
+    std::vector<hipEvent_t> ev;
+    int64_t prof_launches = 0;
+    double prof_ms = 0.0;
+    int64_t steps_total = 0;
+
+    void* dalloc(size_t bytes) {
+        if (bytes == 0) bytes = 256;
+        void* p = nullptr;
+        if (afn) {
+            p = afn(bytes, actx);
+            if (!p) throw HipError{hipErrorOutOfMemory, "allocator hook"};
+        } else {
+            HIPCHK(hipMalloc(&p, bytes));
+        }
+        allocs.push_back({p, bytes});
+        HIPCHK(hipMemsetAsync(p, 0, bytes, st));
+        return p;
+    }
+    template <class T> T* alloc(size_t count) { return (T*)dalloc(count * sizeof(T)); }
+
+    ~sim() {
+        if (g1) (void)hipGraphExecDestroy(g1);
+        if (gk) (void)hipGraphExecDestroy(gk);
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        (void)hipStreamSynchronize(st);
+        for (auto& a : allocs) {
+            if (ffn) ffn(a.first, actx);
+            else (void)hipFree(a.first);
+        }
+        if (cap_st) (void)hipStreamDestroy(cap_st);
+    }
+};
+
+namespace {
+
+int fail(sim* s, int code, const std::string& m) {
+    if (s) s->err = m;
+    else set_global_error(m);
+    return code;
+}
+
+int hip_fail(sim* s, const HipError& e) {
+    return fail(s, SIM_EDEVICE, fmt("%s failed: %s", e.what, hipGetErrorString(e.e)));
+}
+
+double min_radius(const double* a, uint32_t n) {
+    double m = a[0];
+    for (uint32_t i = 1; i < n; ++i) m = std::min(m, a[i]);
+    return m;
+}
+
+double max_radius(const double* a, uint32_t n) {
+    double m = a[0];
+    for (uint32_t i = 1; i < n; ++i) m = std::max(m, a[i]);
+    return m;
+}
+
+double eff_skin(const sim_config& c, const double* radii) {
+    return c.skin > 0.0 ? c.skin : 0.2 * min_radius(radii, c.n);
+}
+
+int validate(const sim_config* c, const double* radii, std::string& why) {
+    if (!c) { why = "null config"; return SIM_EINVAL; }
+    if (c->struct_size != sizeof(sim_config)) {
+        why = fmt("struct_size %u != sizeof(sim_config) %zu", c->struct_size, sizeof(sim_config));
+        return SIM_EINVAL;
+    }
+    if (c->reserved != 0) { why = "reserved field must be 0"; return SIM_EINVAL; }
+    if (c->n == 0 || c->n >= 0xFFFFFFFFu) { why = "n must be in [1, 2^32-2]"; return SIM_EINVAL; }
+    if (!radii) { why = "null radii"; return SIM_EINVAL; }
+    for (uint32_t i = 0; i < c->n; ++i)
+        if (!(radii[i] > 0.0) || !std::isfinite(radii[i])) { why = fmt("radius %u is not positive", i); return SIM_EINVAL; }
+    for (int d = 0; d < 3; ++d)
+        if (!(c->box[d] > 0.0) || !std::isfinite(c->box[d])) { why = "box sides must be positive"; return SIM_EINVAL; }
+    if (!(c->dt > 0.0)) { why = "dt must be positive"; return SIM_EINVAL; }
+    if (!(c->rho > 0.0) || !(c->eta > 0.0)) { why = "rho and eta must be positive"; return SIM_EINVAL; }
+    if (c->kn < 0.0 || c->kt < 0.0 || c->mu < 0.0 || c->kT < 0.0) {
+        why = "kn, kt, mu and kT must be non-negative";
+        return SIM_EINVAL;
+    }
+    if (!std::isfinite(c->gammadot)) { why = "gammadot must be finite"; return SIM_EINVAL; }
+    if (!(c->xi_min > 0.0) || !(c->xi_min < c->xi_cut)) { why = "need 0 < xi_min < xi_cut"; return SIM_EINVAL; }
+    if (c->precision != SIM_FP64 && c->precision != SIM_MIXED) { why = "unknown precision"; return SIM_EINVAL; }
+    if (c->nlist_cap > 64) { why = "nlist_cap must be <= 64"; return SIM_EINVAL; }
+    const double amax = max_radius(radii, c->n);
+    const double rl = 2.0 * amax * (1.0 + 0.5 * c->xi_cut) + eff_skin(*c, radii);
+    for (int d = 0; d < 3; ++d)
+        if (!(c->box[d] > 2.0 * rl)) {
+            why = fmt("box side %d (%g) must exceed twice the list range %g", d, c->box[d], rl);
+            return SIM_EINVAL;
+        }
+    return SIM_OK;
+}
+
+int morton_bits(int n) {
+    int b = 0;
+    while ((1 << b) < n) ++b;
+    return b;
+}
+
+// host copy of one replica's slots [p_begin, p_begin + n_pad)
+template <class T> std::vector<T> d2h(sim* s, const T* dev, size_t off, size_t count) {
+    std::vector<T> h(count);
+    HIPCHK(hipMemcpyAsync(h.data(), dev + off, count * sizeof(T), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return h;
+}
+
+void enqueue_step(sim* s, hipStream_t st) {
+    launch_step_begin(s->b, st);
+    launch_integrate(s->b, st);
+    launch_rebuild_decision(s->b, st, 0);
+    launch_rebuild(s->b, st, (int)0xFFFFFFFFu);
+    launch_pair_force(s->b, st, 1, 0xFFFFFFFFu);
+    launch_reduce_stress(s->b, st, 1, 0xFFFFFFFFu);
+}
+
+hipGraphExec_t capture(sim* s, int nsteps) {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    HIPCHK(hipStreamBeginCapture(s->cap_st, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < nsteps; ++k) enqueue_step(s, s->cap_st);
+    HIPCHK(hipStreamEndCapture(s->cap_st, &g));
+    HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    HIPCHK(hipGraphDestroy(g));
+    return ge;
+}
+
+// Reads and clears the health flags; returns a status.
+int check_health(sim* s) {
+    std::vector<RepDyn> dyn(s->nrep);
+    HIPCHK(hipMemcpyAsync(dyn.data(), s->b.dyn, sizeof(RepDyn) * s->nrep, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    int code = SIM_OK;
+    std::string msg;
+    for (int r = 0; r < s->nrep; ++r) {
+        const uint32_t h = dyn[r].health;
+        if (!h) continue;
+        if (h & H_NLIST) {
+            code = SIM_ECAPACITY;
+            msg = fmt("replica %d: neighbour list or contact capacity exceeded at step %llu", r,
+                      (unsigned long long)dyn[r].step);
+        } else if (code == SIM_OK) {
+            code = SIM_EUNSTABLE;
+            msg = fmt("replica %d: %s at step %llu", r, (h & H_NAN) ? "non-finite force" : "overlap above the limit",
+                      (unsigned long long)dyn[r].step);
+        }
+        const uint32_t zero = 0;
+        HIPCHK(hipMemcpyAsync((char*)(s->b.dyn + r) + offsetof(RepDyn, health), &zero, sizeof zero,
+                              hipMemcpyHostToDevice, s->st));
+    }
+    HIPCHK(hipStreamSynchronize(s->st));
+    if (code != SIM_OK) s->err = msg;
+    return code;
+}
+
+// Writes the state of replica r (id order) into its slots, and its contact
+// history into the host-input half of the compact table.
+void upload_state(sim* s, int r, const double* x, const double* v, const double* w, const double* F,
+                  const double* T, const uint32_t* cij, const double* cs, int64_t nc) {
+    const RepParams& P = s->P[r];
+    const uint32_t n = P.n, np = P.n_pad, p0 = P.p_begin, npad = s->b.npad;
+    const std::vector<double>& a = s->radii[r];
+    std::vector<double4> pos(np), vv(np), ww(np), FF(np), TT(np);
+    std::vector<float4> vs(np), ws(np), Ff(np), Tf(np);
+    std::vector<uint32_t> id(np, kNoId);
+    for (uint32_t i = 0; i < n; ++i) {
+        pos[i] = make_double4(x[3 * i], x[3 * i + 1], x[3 * i + 2], a[i]);
+        const double* vi = v ? v + 3 * i : nullptr;
+        double vx = vi ? vi[0] : P.gd * (x[3 * i + 1] - 0.5 * P.L[1]);
+        vv[i] = make_double4(vx, vi ? vi[1] : 0.0, vi ? vi[2] : 0.0, 0.0);
+        ww[i] = w ? make_double4(w[3 * i], w[3 * i + 1], w[3 * i + 2], 0.0) : make_double4(0.0, 0.0, -0.5 * P.gd, 0.0);
+        FF[i] = F ? make_double4(F[3 * i], F[3 * i + 1], F[3 * i + 2], 0.0) : make_double4(0, 0, 0, 0);
+        TT[i] = T ? make_double4(T[3 * i], T[3 * i + 1], T[3 * i + 2], 0.0) : make_double4(0, 0, 0, 0);
+        vs[i] = make_float4((float)vv[i].x, (float)vv[i].y, (float)vv[i].z, 0.f);
+        ws[i] = make_float4((float)ww[i].x, (float)ww[i].y, (float)ww[i].z, 0.f);
+        Ff[i] = make_float4((float)FF[i].x, (float)FF[i].y, (float)FF[i].z, 0.f);
+        Tf[i] = make_float4((float)TT[i].x, (float)TT[i].y, (float)TT[i].z, 0.f);
+        id[i] = i;
+    }
+    hipStream_t st = s->st;
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    };
+    up(s->b.pos + p0, pos.data(), np * sizeof(double4));
+    up(s->b.vh + p0, vv.data(), np * sizeof(double4));
+    up(s->b.vf + p0, vv.data(), np * sizeof(double4));
+    up(s->b.wh + p0, ww.data(), np * sizeof(double4));
+    up(s->b.wf + p0, ww.data(), np * sizeof(double4));
+    up(s->b.id + p0, id.data(), np * sizeof(uint32_t));
+    if (s->mixed) {
+        up(s->b.vsh + p0, vs.data(), np * sizeof(float4));
+        up(s->b.wsh + p0, ws.data(), np * sizeof(float4));
+        up((float4*)s->b.F + p0, Ff.data(), np * sizeof(float4));
+        up((float4*)s->b.T + p0, Tf.data(), np * sizeof(float4));
+    } else {
+        up((double4*)s->b.F + p0, FF.data(), np * sizeof(double4));
+        up((double4*)s->b.T + p0, TT.data(), np * sizeof(double4));
+    }
+    // compact contact table (both sides of each contact), host-input half
+    std::vector<uint32_t> cnt(np, 0), cid((size_t)kCtCap * np, 0);
+    std::vector<double> cvs((size_t)kCtCap * 3 * np, 0.0);
+    for (int64_t k = 0; k < nc; ++k) {
+        const uint32_t i = cij[2 * k], j = cij[2 * k + 1];
+        if (i >= n || j >= n || i == j) throw std::string(fmt("contact %lld has invalid ids (%u, %u)", (long long)k, i, j));
+        if (!(i < j)) throw std::string(fmt("contact %lld must list the lower id first", (long long)k));
+        for (int side = 0; side < 2; ++side) {
+            const uint32_t me = side ? j : i, other = side ? i : j;
+            if (cnt[me] >= (uint32_t)kCtCap) throw std::string(fmt("particle %u has more than %d contacts", me, kCtCap));
+            const uint32_t c = cnt[me]++;
+            cid[(size_t)c * np + me] = other;
+            for (int d = 0; d < 3; ++d) cvs[((size_t)c * 3 + d) * np + me] = cs[3 * k + d];
+        }
+    }
+    up(s->b.ct_n + npad + p0, cnt.data(), np * sizeof(uint32_t));
+    for (int c = 0; c < kCtCap; ++c) {
+        up(s->b.ct_id + (size_t)(kCtCap + c) * npad + p0, cid.data() + (size_t)c * np, np * sizeof(uint32_t));
+        for (int d = 0; d < 3; ++d)
+            up(s->b.ct_s + ((size_t)(kCtCap + c) * 3 + d) * npad + p0, cvs.data() + ((size_t)c * 3 + d) * np,
+               np * sizeof(double));
+    }
+    // list of this replica becomes invalid; its history now comes from the table
+    HIPCHK(hipMemsetAsync(s->b.ncnt + p0, 0, np * sizeof(uint32_t), st));
+    HIPCHK(hipMemsetAsync(s->b.cmask + p0, 0, np * sizeof(uint64_t), st));
+    HIPCHK(hipMemsetAsync(s->b.smask + p0, 0, np * sizeof(uint64_t), st));
+}
+
+void set_dyn(sim* s, int r, double s_le, uint64_t step) {
+    RepDyn d{};
+    d.s_le = s_le;
+    d.step = step;
+    HIPCHK(hipMemcpyAsync(s->b.dyn + r, &d, sizeof d, hipMemcpyHostToDevice, s->st));
+    s->ring_tail[r] = 0;
+}
+
+int check_rep(sim* s, int32_t r) {
+    if (!s) return fail(nullptr, SIM_EINVAL, "null handle");
+    if (r < 0 || r >= s->nrep) return fail(s, SIM_ERANGE, fmt("replica %d out of range [0, %d)", r, s->nrep));
+    return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_validate(const sim_config* cfg, const double* radii) {
+    std::string why;
+    const int rc = validate(cfg, radii, why);
+    if (rc != SIM_OK) set_global_error(why);
+    return rc;
+}
+
+int sim_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, void*), void* ctx) {
+    if ((alloc_fn == nullptr) != (free_fn == nullptr)) return fail(nullptr, SIM_EINVAL, "give both or neither");
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_alloc = alloc_fn;
+    g_free = free_fn;
+    g_alloc_ctx = ctx;
+    return SIM_OK;
+}
+
+int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* radii, const double* const* x0,
+               const double* const* v0, const double* const* w0, void* hip_stream, sim** out) {
+    if (!out) return fail(nullptr, SIM_EINVAL, "null output handle");
+    *out = nullptr;
+    if (!cfgs || n_replicas <= 0 || !radii || !x0) return fail(nullptr, SIM_EINVAL, "missing replicas");
+    for (int r = 0; r < n_replicas; ++r) {
+        std::string why;
+        if (validate(&cfgs[r], radii[r], why) != SIM_OK) return fail(nullptr, SIM_EINVAL, fmt("replica %d: %s", r, why.c_str()));
+        if (cfgs[r].precision != cfgs[0].precision || cfgs[r].flags != cfgs[0].flags)
+            return fail(nullptr, SIM_EINVAL, "precision and flags must be equal for all replicas");
+        if (!x0[r]) return fail(nullptr, SIM_EINVAL, fmt("replica %d: null positions", r));
+        for (uint32_t i = 0; i < 3 * cfgs[r].n; ++i) {
+            const double L = cfgs[r].box[i % 3];
+            if (!(x0[r][i] >= 0.0 && x0[r][i] < L))
+                return fail(nullptr, SIM_EINVAL, fmt("replica %d: coordinate %u outside [0, L)", r, i));
+        }
+    }
+    sim* s = new sim();
+    try {
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            s->afn = g_alloc;
+            s->ffn = g_free;
+            s->actx = g_alloc_ctx;
+        }
+        s->st = (hipStream_t)hip_stream;
+        HIPCHK(hipStreamCreateWithFlags(&s->cap_st, hipStreamNonBlocking));
+        s->nrep = n_replicas;
+        s->mixed = cfgs[0].precision == SIM_MIXED;
+        s->flags = cfgs[0].flags;
+        s->cfg.assign(cfgs, cfgs + n_replicas);
+        s->ring_tail.assign(n_replicas, 0);
+        uint32_t cap = cfgs[0].nlist_cap ? cfgs[0].nlist_cap : kDefaultCap;
+        for (int r = 1; r < n_replicas; ++r) cap = std::max(cap, cfgs[r].nlist_cap ? cfgs[r].nlist_cap : kDefaultCap);
+        uint32_t p = 0, key = 0;
+        std::vector<uint32_t> blk_rep;
+        for (int r = 0; r < n_replicas; ++r) {
+            const sim_config& c = cfgs[r];
+            s->radii.emplace_back(radii[r], radii[r] + c.n);
+            RepParams P{};
+            for (int d = 0; d < 3; ++d) P.L[d] = c.box[d];
+            P.gd = c.gammadot;
+            P.gdLy = c.gammadot * c.box[1];
+            P.dt = c.dt;
+            P.half_dt = 0.5 * c.dt;
+            P.rho = c.rho; P.eta = c.eta; P.kn = c.kn; P.kt = c.kt; P.mu = c.mu;
+            P.bamp = std::sqrt(2.0 * c.kT / c.dt);
+            P.c1 = 1.0 + 0.5 * c.xi_cut;
+            P.xi_min = c.xi_min;
+            P.skin = eff_skin(c, radii[r]);
+            const double amax = max_radius(radii[r], c.n), amin = min_radius(radii[r], c.n);
+            P.rc_max = 2.0 * amax * P.c1;
+            P.rl_max = P.rc_max + P.skin;
+            P.invV = 1.0 / (c.box[0] * c.box[1] * c.box[2]);
+            int mx = 1;
+            for (int d = 0; d < 3; ++d) {
+                int nc = (int)std::floor(c.box[d] / P.rl_max);
+                if (nc < 3) nc = 1;
+                if (nc > 1024) nc = 1024;
+                P.nc[d] = nc;
+                P.cw[d] = c.box[d] / nc;
+                mx = std::max(mx, nc);
+            }
+            P.mbits = morton_bits(mx);
+            P.key_off = key;
+            P.nkeys = (1u << (3 * P.mbits)) + 1u;
+            key += P.nkeys;
+            P.max_overlap = c.max_overlap > 0.0 ? c.max_overlap : 0.1 * amin;
+            P.p_begin = p;
+            P.n = c.n;
+            P.n_pad = (c.n + kTile - 1) / kTile * kTile;
+            P.flags = c.flags;
+            P.blk_begin = p / kTile;
+            P.nblk = P.n_pad / kTile;
+            P.seed = c.seed;
+            for (uint32_t k = 0; k < P.nblk; ++k) blk_rep.push_back((uint32_t)r);
+            p += P.n_pad;
+            s->P.push_back(P);
+            double sa3 = 0.0;
+            for (uint32_t i = 0; i < c.n; ++i) sa3 += radii[r][i] * radii[r][i] * radii[r][i];
+            // Sec. II.B: per-particle drag stresslet 20/3 pi eta a^3 E, E_xy = gammadot / 2
+            s->drag_xy.push_back(P.invV * (20.0 / 3.0) * kPi * c.eta * sa3 * 0.5 * c.gammadot);
+        }
+        Bufs& b = s->b;
+        b.npad = p;
+        b.nrep = (uint32_t)n_replicas;
+        b.nkeys_total = key;
+        b.cap = cap;
+        b.mixed = s->mixed;
+        const size_t np = p;
+        b.pos = s->alloc<double4>(np);
+        b.vh = s->alloc<double4>(np);
+        b.wh = s->alloc<double4>(np);
+        b.vf = s->alloc<double4>(np);
+        b.wf = s->alloc<double4>(np);
+        b.F = s->dalloc(np * (s->mixed ? sizeof(float4) : sizeof(double4)));
+        b.T = s->dalloc(np * (s->mixed ? sizeof(float4) : sizeof(double4)));
+        b.vsh = s->mixed ? s->alloc<float4>(np) : nullptr;
+        b.wsh = s->mixed ? s->alloc<float4>(np) : nullptr;
+        b.id = s->alloc<uint32_t>(np);
+        b.nbr = s->alloc<uint32_t>(np * cap);
+        b.ncnt = s->alloc<uint32_t>(np);
+        for (int d = 0; d < 3; ++d) b.hs[d] = s->dalloc(np * cap * (s->mixed ? sizeof(float) : sizeof(double)));
+        b.cmask = s->alloc<uint64_t>(np);
+        b.smask = s->alloc<uint64_t>(np);
+        b.key = s->alloc<uint32_t>(np);
+        b.cell_cnt = s->alloc<uint32_t>(key);
+        b.cell_fill = s->alloc<uint32_t>(key);
+        b.cell_start = s->alloc<uint32_t>(key + 1);
+        b.scan_blk = s->alloc<uint32_t>((key + 1023) / 1024 + 1);
+        b.src = s->alloc<uint32_t>(np);
+        b.ct_id = s->alloc<uint32_t>(np * 2 * kCtCap);
+        b.ct_s = s->alloc<double>(np * 2 * kCtCap * 3);
+        b.ct_sl = s->alloc<uint8_t>(np * kCtCap);
+        b.ct_n = s->alloc<uint32_t>(np * 2);
+        for (int a = 0; a < 7; ++a) b.alt4[a] = s->alloc<double4>(np);
+        b.alt_id = s->alloc<uint32_t>(np);
+        b.partial = s->alloc<double>(np / kTile * 27);
+        b.ring = s->alloc<double>((size_t)n_replicas * kRing * 27);
+        b.last = s->alloc<double>((size_t)n_replicas * 27);
+        b.blk_rep = s->alloc<uint32_t>(blk_rep.size());
+        b.reps = s->alloc<RepParams>(n_replicas);
+        b.dyn = s->alloc<RepDyn>(n_replicas);
+        b.sys = s->alloc<SysDyn>(1);
+        HIPCHK(hipMemcpyAsync(b.blk_rep, blk_rep.data(), blk_rep.size() * 4, hipMemcpyHostToDevice, s->st));
+        HIPCHK(hipMemcpyAsync(b.reps, s->P.data(), sizeof(RepParams) * n_replicas, hipMemcpyHostToDevice, s->st));
+        for (int r = 0; r < n_replicas; ++r) {
+            upload_state(s, r, x0[r], v0 ? v0[r] : nullptr, w0 ? w0[r] : nullptr, nullptr, nullptr, nullptr, nullptr, 0);
+            set_dyn(s, r, cfgs[r].le_offset0, cfgs[r].step0);
+        }
+        launch_rebuild_decision(b, s->st, 1);
+        launch_rebuild(b, s->st, (int)0xFFFFFFFEu);
+        launch_pair_force(b, s->st, 0, 0xFFFFFFFFu);
+        launch_reduce_stress(b, s->st, 0, 0xFFFFFFFFu);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s->st));
+        const int hc = check_health(s);
+        if (hc != SIM_OK) {
+            std::string m = s->err;
+            delete s;
+            return fail(nullptr, hc, m);
+        }
+    } catch (const HipError& e) {
+        std::string m = fmt("%s failed: %s", e.what, hipGetErrorString(e.e));
+        delete s;
+        return fail(nullptr, e.e == hipErrorOutOfMemory ? SIM_ENOMEM : SIM_EDEVICE, m);
+    } catch (const std::string& m) {
+        delete s;
+        return fail(nullptr, SIM_EINVAL, m);
+    }
+    *out = s;
+    return SIM_OK;
+}
+
+int sim_step(sim* s, int64_t nsteps) {
+    if (!s) return fail(nullptr, SIM_EINVAL, "null handle");
+    if (nsteps < 0) return fail(s, SIM_EINVAL, "nsteps < 0");
+    try {
+        const bool graph = !(s->flags & SIM_NO_GRAPH) && !s->profile;
+        int64_t left = nsteps;
+        if (graph) {
+            if (!s->g1) s->g1 = capture(s, 1);
+            if (!s->gk && left >= kGraphSteps) s->gk = capture(s, kGraphSteps);
+            while (left >= kGraphSteps) {
+                HIPCHK(hipGraphLaunch(s->gk, s->st));
+                left -= kGraphSteps;
+            }
+            while (left > 0) {
+                HIPCHK(hipGraphLaunch(s->g1, s->st));
+                --left;
+            }
+        } else {
+            for (; left > 0; --left) {
+                launch_step_begin(s->b, s->st);
+                launch_integrate(s->b, s->st);
+                launch_rebuild_decision(s->b, s->st, 0);
+                launch_rebuild(s->b, s->st, (int)0xFFFFFFFFu);
+                if (s->profile) {
+                    if (s->ev.size() < 2) {
+                        for (int k = 0; k < 2; ++k) {
+                            hipEvent_t e;
+                            HIPCHK(hipEventCreate(&e));
+                            s->ev.push_back(e);
+                        }
+                    }
+                    HIPCHK(hipEventRecord(s->ev[0], s->st));
+                    launch_pair_force(s->b, s->st, 1, 0xFFFFFFFFu);
+                    HIPCHK(hipEventRecord(s->ev[1], s->st));
+                    launch_reduce_stress(s->b, s->st, 1, 0xFFFFFFFFu);
+                    HIPCHK(hipEventSynchronize(s->ev[1]));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, s->ev[0], s->ev[1]));
+                    s->prof_ms += ms;
+                    s->prof_launches += 1;
+                } else {
+                    launch_pair_force(s->b, s->st, 1, 0xFFFFFFFFu);
+                    launch_reduce_stress(s->b, s->st, 1, 0xFFFFFFFFu);
+                }
+            }
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s->st));
+        s->steps_total += nsteps;
+        return check_health(s);
+    } catch (const HipError& e) {
+        return hip_fail(s, e);
+    }
+}
+
+int sim_profile(sim* s, int32_t enable) {
+    if (!s) return fail(nullptr, SIM_EINVAL, "null handle");
+    s->profile = enable ? 1 : 0;
+    s->prof_launches = 0;
+    s->prof_ms = 0.0;
+    return SIM_OK;
+}
+
+int sim_kernel_time(sim* s, int64_t* launches, double* total_ms) {
+    if (!s) return fail(nullptr, SIM_EINVAL, "null handle");
+    if (launches) *launches = s->prof_launches;
+    if (total_ms) *total_ms = s->prof_ms;
+    return SIM_OK;
+}
+
+int sim_stress(sim* s, int32_t r, int32_t component, int32_t mode, double out[9]) {
+    if (int rc = check_rep(s, r)) return rc;
+    if (!out || component < 0 || component > SIM_STRESS_TOTAL || (mode != SIM_STRESS_LAST && mode != SIM_STRESS_MEAN))
+        return fail(s, SIM_EINVAL, "bad component, mode or output");
+    try {
+        double v[27];
+        if (mode == SIM_STRESS_LAST) {
+            auto h = d2h(s, s->b.last, (size_t)r * 27, 27);
+            std::copy(h.begin(), h.end(), v);
+        } else {
+            auto d = d2h(s, s->b.dyn, (size_t)r, 1);
+            const double c = d[0].stress_count ? (double)d[0].stress_count : 1.0;
+            for (int k = 0; k < 27; ++k) v[k] = d[0].stress_sum[k] / c;
+        }
+        double drag[9] = {0, s->drag_xy[r], 0, s->drag_xy[r], 0, 0, 0, 0, 0};
+        for (int k = 0; k < 9; ++k) {
+            switch (component) {
+                case SIM_STRESS_CONTACT: out[k] = v[k]; break;
+                case SIM_STRESS_LUB: out[k] = v[9 + k]; break;
+                case SIM_STRESS_BROWN: out[k] = v[18 + k]; break;
+                case SIM_STRESS_DRAG: out[k] = drag[k]; break;
+                default: out[k] = v[k] + v[9 + k] + drag[k]; break;
+            }
+        }
+        return SIM_OK;
+    } catch (const HipError& e) {
+        return hip_fail(s, e);
+    }
+}
+
+int sim_reset_stress(sim* s) {
+    if (!s) return fail(nullptr, SIM_EINVAL, "null handle");
+    try {
+        for (int r = 0; r < s->nrep; ++r) {
+            std::vector<char> z(sizeof(double) * 27 + sizeof(uint64_t), 0);
+            HIPCHK(hipMemcpyAsync((char*)(s->b.dyn + r) + offsetof(RepDyn, stress_sum), z.data(), z.size(),
+                                  hipMemcpyHostToDevice, s->st));
+        }
+        HIPCHK(hipStreamSynchronize(s->st));
+        return SIM_OK;
+    } catch (const HipError& e) {
+        return hip_fail(s, e);
+    }
+}
+
+int sim_stress_series(sim* s, int32_t r, double* out, int64_t cap, int64_t* count) {
+    if (int rc = check_rep(s, r)) return rc;
+    if (!count) return fail(s, SIM_EINVAL, "null count");
+    try {
+        auto d = d2h(s, s->b.dyn, (size_t)r, 1);
+        const uint32_t head = d[0].ring_head;
+        uint32_t tail = s->ring_tail[r];
+        if (head - tail > (uint32_t)kRing) tail = head - kRing;
+        const int64_t n = (int64_t)(head - tail);
+        *count = n;
+        if (n > cap || (!out && n > 0)) return fail(s, SIM_ERANGE, fmt("series holds %lld steps", (long long)n));
+        auto ring = d2h(s, s->b.ring, (size_t)r * kRing * 27, (size_t)kRing * 27);
+        for (int64_t k = 0; k < n; ++k) {
+            const uint32_t slot = (tail + (uint32_t)k) % kRing;
+            std::memcpy(out + 27 * k, ring.data() + (size_t)slot * 27, 27 * sizeof(double));
+        }
+        s->ring_tail[r] = head;
+        return SIM_OK;
+    } catch (const HipError& e) {
+        return hip_fail(s, e);
+    }
+}
+
+int sim_get_state(sim* s, int32_t r, double* x, double* v, double* w, double* F, double* T, double* le_offset,
+                  uint64_t* step) {
+    if (int rc = check_rep(s, r)) return rc;
+    try {
+        const RepParams& P = s->P[r];
+        const size_t p0 = P.p_begin, np = P.n_pad;
+        auto id = d2h(s, s->b.id, p0, np);
+        auto scatter4 = [&](const double4* dev, double* outp) {
+            if (!outp) return;
+            auto h = d2h(s, dev, p0, np);
+            for (size_t q = 0; q < np; ++q) {
+                if (id[q] == kNoId) continue;
+                outp[3 * id[q]] = h[q].x; outp[3 * id[q] + 1] = h[q].y; outp[3 * id[q] + 2] = h[q].z;
+            }
+        };
+        auto scatterF = [&](void* dev, double* outp) {
+            if (!outp) return;
+            if (s->mixed) {
+                auto h = d2h(s, (const float4*)dev, p0, np);
+                for (size_t q = 0; q < np; ++q) {
+                    if (id[q] == kNoId) continue;
+                    outp[3 * id[q]] = h[q].x; outp[3 * id[q] + 1] = h[q].y; outp[3 * id[q] + 2] = h[q].z;
+                }
+            } else {
+                scatter4((const double4*)dev, outp);
+            }
+        };
+        scatter4(s->b.pos, x);
+        scatter4(s->b.vf, v);
+        scatter4(s->b.wf, w);
+        scatterF(s->b.F, F);
+        scatterF(s->b.T, T);
+        if (le_offset || step) {
+            auto d = d2h(s, s->b.dyn, (size_t)r, 1);
+            if (le_offset) *le_offset = d[0].s_le;
+            if (step) *step = d[0].step;
+        }
+        return SIM_OK;
+    } catch (const HipError& e) {
+        return hip_fail(s, e);
+    }
+}
+
+int sim_positions(sim* s, int32_t r, double* out_3n) {
+    if (!out_3n) return fail(s, SIM_EINVAL, "null output");
+    return sim_get_state(s, r, out_3n, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+int sim_forces(sim* s, int32_t r, double* F_3n, double* T_3n) {
+    return sim_get_state(s, r, nullptr, nullptr, nullptr, F_3n, T_3n, nullptr, nullptr);
+}
+
+int sim_set_state(sim* s, int32_t r, const double* x, const double* v, const double* w, const double* F,
+                  const double* T, double le_offset, uint64_t step, const uint32_t* c_ij, const double* c_s,
+                  int64_t n_contacts) {
+    if (int rc = check_rep(s, r)) return rc;
+    if (!x || !v || !w) return fail(s, SIM_EINVAL, "x, v and w are required");
+    if ((F == nullptr) != (T == nullptr)) return fail(s, SIM_EINVAL, "give both F and T or neither");
+    if (n_contacts < 0 || (n_contacts > 0 && (!c_ij || !c_s))) return fail(s, SIM_EINVAL, "bad contact arrays");
+    const RepParams& P = s->P[r];
+    for (uint32_t i = 0; i < 3 * P.n; ++i)
+        if (!(x[i] >= 0.0 && x[i] < P.L[i % 3])) return fail(s, SIM_EINVAL, fmt("coordinate %u outside [0, L)", i));
+    try {
+        upload_state(s, r, x, v, w, F, T, c_ij, c_s, n_contacts);
+        set_dyn(s, r, le_offset, step);
+        launch_rebuild_decision(s->b, s->st, 1);
+        launch_rebuild(s->b, s->st, r);
+        if (!F) {
+            launch_pair_force(s->b, s->st, 0, (uint32_t)r);
+            launch_reduce_stress(s->b, s->st, 0, (uint32_t)r);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s->st));
+        return check_health(s);
+    } catch (const HipError& e) {
+        return hip_fail(s, e);
+    } catch (const std::string& m) {
+        return fail(s, SIM_EINVAL, m);
+    }
+}
+
+namespace {
+// Lists pairs of one replica from the device (mode 0 interaction set, 1
+// Verlet list, 2 contacts), sorted by (id_i, id_j).
+int diag_pairs(sim* s, int32_t r, int mode, std::vector<uint32_t>& ij, std::vector<double>& sv,
+               std::vector<int32_t>& sl) {
+    const RepParams& P = s->P[r];
+    uint32_t* dcount = nullptr;
+    HIPCHK(hipMalloc(&dcount, sizeof(uint32_t)));
+    HIPCHK(hipMemsetAsync(dcount, 0, sizeof(uint32_t), s->st));
+    launch_diag(s->b, s->st, (uint32_t)r, P.n, nullptr, nullptr, nullptr, dcount, 0, mode);
+    uint32_t cnt = 0;
+    HIPCHK(hipMemcpyAsync(&cnt, dcount, 4, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    uint32_t* dij = nullptr;
+    double* ds = nullptr;
+    int32_t* dsl = nullptr;
+    HIPCHK(hipMalloc(&dij, sizeof(uint32_t) * 2 * (cnt + 1)));
+    HIPCHK(hipMalloc(&ds, sizeof(double) * 3 * (cnt + 1)));
+    HIPCHK(hipMalloc(&dsl, sizeof(int32_t) * (cnt + 1)));
+    HIPCHK(hipMemsetAsync(dcount, 0, sizeof(uint32_t), s->st));
+    launch_diag(s->b, s->st, (uint32_t)r, P.n, dij, ds, dsl, dcount, cnt, mode);
+    std::vector<uint32_t> hij(2 * (size_t)cnt);
+    std::vector<double> hs(3 * (size_t)cnt);
+    std::vector<int32_t> hsl(cnt);
+    HIPCHK(hipMemcpyAsync(hij.data(), dij, hij.size() * 4, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(hs.data(), ds, hs.size() * 8, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(hsl.data(), dsl, hsl.size() * 4, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    (void)hipFree(dcount); (void)hipFree(dij); (void)hipFree(ds); (void)hipFree(dsl);
+    std::vector<uint32_t> order(cnt);
+    for (uint32_t k = 0; k < cnt; ++k) order[k] = k;
+    std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        return hij[2 * a] != hij[2 * b] ? hij[2 * a] < hij[2 * b] : hij[2 * a + 1] < hij[2 * b + 1];
+    });
+    ij.resize(2 * (size_t)cnt);
+    sv.resize(3 * (size_t)cnt);
+    sl.resize(cnt);
+    for (uint32_t k = 0; k < cnt; ++k) {
+        const uint32_t o = order[k];
+        ij[2 * k] = hij[2 * o];
+        ij[2 * k + 1] = hij[2 * o + 1];
+        for (int d = 0; d < 3; ++d) sv[3 * k + d] = hs[3 * o + d];
+        sl[k] = hsl[o];
+    }
+    return SIM_OK;
+}
+
+int copy_pairs(sim* s, int32_t r, int mode, uint32_t* ij_2m, double* s_3m, int32_t* sliding, int64_t cap,
+               int64_t* count) {
+    if (int rc = check_rep(s, r)) return rc;
+    if (!count) return fail(s, SIM_EINVAL, "null count");
+    try {
+        std::vector<uint32_t> ij;
+        std::vector<double> sv;
+        std::vector<int32_t> sl;
+        diag_pairs(s, r, mode, ij, sv, sl);
+        const int64_t n = (int64_t)sl.size();
+        *count = n;
+        if (n > cap) return fail(s, SIM_ERANGE, fmt("%lld pairs do not fit in %lld", (long long)n, (long long)cap));
+        if (n && !ij_2m) return fail(s, SIM_EINVAL, "null output");
+        std::memcpy(ij_2m, ij.data(), ij.size() * 4);
+        if (s_3m) std::memcpy(s_3m, sv.data(), sv.size() * 8);
+        if (sliding) std::memcpy(sliding, sl.data(), sl.size() * 4);
+        return SIM_OK;
+    } catch (const HipError& e) {
+        return hip_fail(s, e);
+    }
+}
+}  // namespace
+
+int sim_pairs(sim* s, int32_t r, uint32_t* ij_2m, int64_t cap, int64_t* count) {
+    return copy_pairs(s, r, 0, ij_2m, nullptr, nullptr, cap, count);
+}
+
+int sim_nlist(sim* s, int32_t r, uint32_t* ij_2m, int64_t cap, int64_t* count) {
+    return copy_pairs(s, r, 1, ij_2m, nullptr, nullptr, cap, count);
+}
+
+int sim_contacts(sim* s, int32_t r, uint32_t* ij_2m, double* s_3m, int32_t* sliding, int64_t cap, int64_t* count) {
+    return copy_pairs(s, r, 2, ij_2m, s_3m, sliding, cap, count);
+}
+
+int sim_stats(sim* s, int32_t r, sim_stats_t* out) {
+    if (int rc = check_rep(s, r)) return rc;
+    if (!out) return fail(s, SIM_EINVAL, "null output");
+    try {
+        std::vector<uint32_t> ij;
+        std::vector<double> sv;
+        std::vector<int32_t> sl;
+        const double n = (double)s->P[r].n;
+        diag_pairs(s, r, 2, ij, sv, sl);
+        int64_t nsl = 0;
+        for (int32_t v : sl) nsl += v;
+        out->contacts = (int64_t)sl.size();
+        out->contacts_per_particle = 2.0 * (double)sl.size() / n;
+        out->sliding_fraction = sl.empty() ? 0.0 : (double)nsl / (double)sl.size();
+        diag_pairs(s, r, 1, ij, sv, sl);
+        out->neighbours_per_particle = 2.0 * (double)sl.size() / n;
+        diag_pairs(s, r, 0, ij, sv, sl);
+        out->interacting_per_particle = 2.0 * (double)sl.size() / n;
+        auto d = d2h(s, s->b.dyn, (size_t)r, 1);
+        auto sy = d2h(s, s->b.sys, 0, 1);
+        float mo;
+        std::memcpy(&mo, &d[0].maxov_bits, sizeof mo);
+        out->max_overlap = (double)mo;
+        out->rebuilds = (int64_t)sy[0].rebuilds;
+        out->steps = s->steps_total;
+        out->step = d[0].step;
+        out->le_offset = d[0].s_le;
+        return SIM_OK;
+    } catch (const HipError& e) {
+        return hip_fail(s, e);
+    }
+}
+
+int sim_destroy(sim* s) {
+    delete s;
+    return SIM_OK;
+}
+
+const char* sim_strerror(int32_t code) {
+    switch (code) {
+        case SIM_OK: return "ok";
+        case SIM_EINVAL: return "invalid configuration or argument";
+        case SIM_ENOMEM: return "out of memory";
+        case SIM_EDEVICE: return "HIP runtime error";
+        case SIM_EUNSTABLE: return "unstable step (non-finite force or overlap above the limit)";
+        case SIM_ECAPACITY: return "neighbour list or contact capacity exceeded";
+        case SIM_ERANGE: return "index or output capacity out of range";
+        default: return "unknown status";
+    }
+}
+
+int sim_last_error(const sim* s, char* buf, size_t len) {
+    if (!buf || len == 0) return SIM_EINVAL;
+    std::string m;
+    if (s) m = s->err;
+    else {
+        std::lock_guard<std::mutex> lk(g_mu);
+        m = g_err;
+    }
+    std::snprintf(buf, len, "%s", m.c_str());
+    return SIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,243 @@
+"""GPU parity: the HIP path, called through the C ABI, against the FP64 CPU oracle.
+
+Bars: neighbour sets and contact springs bit-exact (FP64); forces and torques
+within 1e-10 relative to the per-particle sum of pair-force norms; stresses
+within 1e-10 relative; mixed precision within its FP32 bound.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from inputs import gen
+
+pytestmark = pytest.mark.gpu
+
+TOL_F64 = 1e-10
+# mixed: FP32 pair arithmetic (unit roundoff 6e-8) with hardware log/sin/cos;
+# forces carry ~1e-6 relative error per pair, Brownian terms a few 1e-6
+TOL_MIX = 5e-5
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2307_13802_amd as P
+    P.lib()
+    return P
+
+
+def _cfg(P, st, precision=0, flags=0, **kw):
+    p = dict(st["params"])
+    p.update(kw)
+    return P.Config(box=st["L"], precision=precision, flags=flags, **p)
+
+
+def _state(n=500, phi=0.5, pe=1.0, kT=1.0, seed=0, mu=0.5):
+    w = gen.Workload("t", n, phi, pe, kT=kT, seed=seed, mu=mu)
+    return gen.make_state(w)
+
+
+def _force_err(Fg, Fo, norm):
+    e = np.linalg.norm(Fg - Fo, axis=1) / np.maximum(norm, 1e-300)
+    return float(e.max())
+
+
+def _stress_err(Sg, So):
+    Sg = np.asarray(Sg).reshape(3, 9)
+    So = np.asarray(So).reshape(3, 9)
+    out = []
+    for c in range(3):
+        scale = max(np.abs(So[c]).max(), 1e-300)
+        out.append(float(np.abs(Sg[c] - So[c]).max() / scale))
+    return max(out)
+
+
+def _gpu_stress27(sim, r=0):
+    import paper_2307_13802_amd as P
+    return np.stack([sim.stress(r, c, P.STRESS_LAST) for c in (P.STRESS_CONTACT, P.STRESS_LUB, P.STRESS_BROWN)])
+
+
+def _compare_eval(P, sim, orc, tol, exact=True, r=0):
+    Fg, Tg = sim.forces(r)
+    so = orc.state()
+    Fa, Ta = orc.norms()
+    ef = _force_err(Fg, so["F"], Fa)
+    et = _force_err(Tg, so["T"], np.maximum(Ta, 1e-300))
+    pg, po = sim.pairs(r), orc.pairs()
+    cg, co = sim.contacts(r), orc.contacts()
+    es = _stress_err(_gpu_stress27(sim, r), orc.stress())
+    _say(f"  F err {ef:.2e}  T err {et:.2e}  stress err {es:.2e}  pairs {len(pg)}/{len(po)}  contacts {len(cg[0])}/{len(co[0])}")
+    assert np.array_equal(pg, po)
+    assert np.array_equal(cg[0], co[0])
+    if exact:
+        assert np.array_equal(cg[1], co[1]), np.abs(cg[1] - co[1]).max()
+        assert np.array_equal(cg[2], co[2])
+    else:
+        scale = max(np.abs(co[1]).max(), 1e-30)
+        assert np.abs(cg[1] - co[1]).max() <= 1e-4 * scale
+    assert ef <= tol and et <= tol and es <= tol
+    return ef, et, es
+
+
+def test_create_fp64_matches_oracle(P):
+    _say("case: create N=500 phi=0.5 FP64, forces at the initial state")
+    st = _state()
+    sim = P.Sim(_cfg(P, st), st["radii"], st["x"], st["v"], st["w"])
+    orc = O.Oracle(O.Params(L=st["L"], **st["params"]), st["radii"], st["x"], st["v"], st["w"])
+    _compare_eval(P, sim, orc, TOL_F64)
+    # Verlet set at the same positions with the same skin, bit-exact
+    assert np.array_equal(sim.nlist(), orc.verlet_pairs(0.2))
+
+
+def test_injected_contacts_and_offset(P):
+    """Random stored springs on every overlapping pair, Lees-Edwards offset, shear: one evaluation."""
+    rng = np.random.default_rng(3)
+    n = 200
+    L = (14.0, 13.0, 15.0)
+    a = gen.radii_bidisperse(n, 4)
+    x, v, w = gen.random_state(n, L, a, seed=11, kT=0.5, gammadot=0.4)
+    for s_le in (0.0, L[0] / 3.0, L[0] - 1e-9):
+        _say(f"case: random overlapping state n={n} s_le={s_le:.6f}")
+        prm = dict(rho=0.1, eta=0.1, kn=1e4, kt=2e4 / 7, mu=0.5, kT=0.5, gammadot=0.4, dt=1e-4, xi_cut=0.05,
+                   xi_min=1e-3, seed=99)
+        probe = O.Oracle(O.Params(L=L, **prm), a, x, v, w, s_le=s_le)
+        # overlapping pairs (the oracle's contact list after its evaluation) get random springs
+        cij = probe.contacts()[0]
+        cs = rng.normal(size=(len(cij), 3)) * 1e-3
+        orc = O.Oracle(O.Params(L=L, **prm), a, x, v, w, s_le=s_le, contacts=(cij, cs))
+        cfg = P.Config(box=L, **prm, max_overlap=10.0)
+        sim = P.Sim(cfg, a, x, v, w)
+        sim.set_state(0, x, v, w, s_le=s_le, step=0, contacts=(cij, cs))
+        _compare_eval(P, sim, orc, TOL_F64)
+
+
+def test_step_trajectory_fp64(P):
+    """Short trajectory: the same state after each step (chaos sets in only later)."""
+    st = _state(n=500, phi=0.5)
+    for flags in (0, P.REBUILD_EACH_STEP | P.NO_GRAPH):
+        _say(f"case: trajectory N=500 flags={flags:#x}")
+        sim = P.Sim(_cfg(P, st, flags=flags), st["radii"], st["x"], st["v"], st["w"])
+        orc = O.Oracle(O.Params(L=st["L"], **st["params"]), st["radii"], st["x"], st["v"], st["w"])
+        for k in range(4):
+            sim.step(5)
+            series = sim.stress_series()
+            oser = orc.step(5, series=True)
+            gs = sim.get_state()
+            os_ = orc.state()
+            dx = np.abs(gs["x"] - os_["x"]).max()
+            dv = np.abs(gs["v"] - os_["v"]).max() / np.abs(os_["v"]).max()
+            _say(f"  after {5 * (k + 1)} steps: |dx| {dx:.2e} |dv|/|v| {dv:.2e}")
+            assert gs["step"] == os_["step"] and gs["s_le"] == os_["s_le"]
+            assert dx < 1e-11 and dv < 1e-9
+            assert series.shape[0] == 5
+            assert _stress_err(series[-1], oser[-1].reshape(3, 3, 3)) < 1e-8
+            assert np.array_equal(sim.contacts()[0], orc.contacts()[0])
+
+
+def test_mixed_precision_create(P):
+    _say("case: create N=500 mixed precision")
+    st = _state()
+    sim = P.Sim(_cfg(P, st, precision=P.MIXED), st["radii"], st["x"], st["v"], st["w"])
+    orc = O.Oracle(O.Params(L=st["L"], **st["params"]), st["radii"], st["x"], st["v"], st["w"])
+    _compare_eval(P, sim, orc, TOL_MIX, exact=False)
+
+
+def test_ragged_and_tiny_systems(P):
+    for n, phi in ((2, 0.001), (37, 0.3), (257, 0.45), (1000, 0.55)):
+        _say(f"case: ragged n={n} phi={phi}")
+        w = gen.Workload("t", n, phi, 1.0, kT=1.0, seed=n)
+        a = gen.radii_bidisperse(n, n)
+        L = max(gen.box_length(a, phi), 2.0 * (2 * 1.4 * 1.025 + 0.2) + 0.1)
+        x = gen.relaxed_positions(a, L, n)
+        if n == 2:  # put the pair into contact
+            x[1] = x[0] + np.array([a[0] + a[1] - 1e-3, 0.0, 0.0])
+            x %= L
+        _, v, om = gen.random_state(n, (L, L, L), a, seed=1)
+        st = dict(radii=a, x=x, v=v, w=om, L=(L, L, L), params=w.params())
+        sim = P.Sim(_cfg(P, st), a, x, v, om)
+        orc = O.Oracle(O.Params(L=st["L"], **st["params"]), a, x, v, om)
+        _compare_eval(P, sim, orc, TOL_F64)
+
+
+def test_batched_replicas_match_single(P):
+    """Replicas of uneven size in one handle: each bit-identical to the same replica run alone."""
+    sts = [_state(n=n, phi=phi, seed=s) for n, phi, s in ((300, 0.45, 1), (777, 0.55, 2), (512, 0.5, 3))]
+    cfgs = [_cfg(P, st, seed=10 + k) for k, st in enumerate(sts)]
+    _say("case: 3 replicas batched vs alone, 30 steps")
+    multi = P.Sim(cfgs, [s["radii"] for s in sts], [s["x"] for s in sts], [s["v"] for s in sts],
+                  [s["w"] for s in sts])
+    multi.step(30)
+    for k, st in enumerate(sts):
+        one = P.Sim(cfgs[k], st["radii"], st["x"], st["v"], st["w"])
+        one.step(30)
+        a, b = multi.get_state(k), one.get_state()
+        _say(f"  replica {k}: max |dx| {np.abs(a['x'] - b['x']).max():.2e}")
+        for key in ("x", "v", "w", "F", "T"):
+            assert np.array_equal(a[key], b[key]), key
+
+
+def test_deterministic_and_restart(P):
+    st = _state(n=600, phi=0.55, seed=5)
+    cfg = _cfg(P, st)
+    _say("case: determinism and restart, 40 steps")
+    s1 = P.Sim(cfg, st["radii"], st["x"], st["v"], st["w"])
+    s2 = P.Sim(cfg, st["radii"], st["x"], st["v"], st["w"])
+    s1.step(40)
+    s2.step(20)
+    mid = s2.get_state()
+    ij, cs, _ = s2.contacts()
+    s2.step(20)
+    s3 = P.Sim(cfg, st["radii"], st["x"], st["v"], st["w"])
+    s3.set_state(0, mid["x"], mid["v"], mid["w"], F=mid["F"], T=mid["T"], s_le=mid["s_le"], step=mid["step"],
+                 contacts=(ij, cs))
+    s3.step(20)
+    a, b, c = s1.get_state(), s2.get_state(), s3.get_state()
+    for key in ("x", "v", "w", "F", "T"):
+        assert np.array_equal(a[key], b[key]), key
+        assert np.array_equal(a[key], c[key]), key
+
+
+def test_health_errors(P):
+    st = _state(n=300, phi=0.5)
+    x = st["x"].copy()
+    x[1] = (x[0] + np.array([0.5, 0.0, 0.0])) % st["L"][0]   # deep overlap
+    _say("case: deep overlap rejected at creation")
+    with pytest.raises(P.SimError) as e:
+        P.Sim(_cfg(P, st), st["radii"], x, st["v"], st["w"])
+    assert e.value.code == -4
+    _say("case: list capacity 2 rejected")
+    with pytest.raises(P.SimError) as e:
+        P.Sim(_cfg(P, st, nlist_cap=2), st["radii"], st["x"], st["v"], st["w"])
+    assert e.value.code == -5
+
+
+def test_large_sampled_fp64(P):
+    """50,000 spheres at phi = 0.55: forces on sampled particles against the oracle one by one."""
+    w = gen.C2
+    st = gen.make_state(w)
+    _say("case: N=50000 phi=0.55 FP64 sampled")
+    sim = P.Sim(_cfg(P, st), st["radii"], st["x"], st["v"], st["w"])
+    orc = O.Oracle(O.Params(L=st["L"], **st["params"], flags=O.CELLS), st["radii"], st["x"], st["v"], st["w"])
+    _compare_eval(P, sim, orc, TOL_F64)
+    # the one-by-one oracle used for spot checks of larger systems, on the same input
+    Fg, Tg = sim.forces()
+    zero = np.zeros((w.n, 3))
+    one = O.Oracle(O.Params(L=st["L"], **st["params"]), st["radii"], st["x"], st["v"], st["w"], F=zero, T=zero)
+    rng = np.random.default_rng(0)
+    worst = 0.0
+    for i in rng.choice(w.n, 40, replace=False):
+        F, T, fa, ta = one.particle_force(int(i))
+        worst = max(worst, np.linalg.norm(Fg[i] - F) / fa, np.linalg.norm(Tg[i] - T) / max(ta, 1e-300))
+    _say(f"  worst sampled error {worst:.2e}")
+    assert worst <= TOL_F64
