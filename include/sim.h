@@ -114,7 +114,8 @@ typedef struct sim_config {
     int32_t  precision;     /* SIM_FP64 or SIM_MIXED, identical for all replicas     */
     uint32_t flags;         /* SIM_* flags, identical for all replicas               */
     uint32_t nlist_cap;     /* neighbour list capacity per particle; 0 selects 48    */
-    uint32_t reserved;      /* must be 0                                             */
+    uint32_t lanes;         /* lanes sharing one particle's list in the pair kernel:
+                               1, 2, 4 or 8; 0 = chosen by timing at creation        */
 } sim_config;
 
 typedef struct sim_stats_t {
@@ -128,6 +129,8 @@ typedef struct sim_stats_t {
     int64_t steps;                  /* steps taken since creation                      */
     uint64_t step;                  /* current step counter                            */
     double  le_offset;              /* current Lees-Edwards offset                     */
+    int32_t lanes;                  /* lanes per particle used by the pair kernel       */
+    int32_t pad;
 } sim_stats_t;
 
 /* Checks a configuration and its radii on the host (no GPU needed).
@@ -135,7 +138,7 @@ typedef struct sim_stats_t {
  * dt <= 0, rho/eta <= 0, kn/kt < 0, mu < 0, kT < 0, xi_min <= 0,
  * xi_min >= xi_cut, a box side not larger than twice the largest
  * interaction range plus skin (the minimum image must be unique), a wrong
- * struct_size or a nonzero reserved field. */
+ * struct_size, nlist_cap > 64 or lanes not in {0, 1, 2, 4, 8}. */
 int sim_validate(const sim_config* cfg, const double* radii);
 
 /* Creates a handle with n_replicas systems.  For replica r: radii[r] -> n

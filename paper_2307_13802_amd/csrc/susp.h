@@ -45,23 +45,24 @@ struct RepParams {
 
 // Per-replica values the device updates every step.
 struct RepDyn {
-    double s_le;              // Lees-Edwards offset
+    double s_le;              // Lees-Edwards offset of the last force evaluation
     double dmax;              // bound on the non-affine displacement since the last build
     double t_since;           // time since the last build
     uint64_t step;            // step counter of the last force evaluation
     uint32_t stepmax_bits;    // float bits: largest displacement in the current step
-    uint32_t maxov_bits;      // float bits: largest overlap at the last evaluation
+    uint32_t maxov_bits;      // float bits: largest overlap in the current evaluation
     uint32_t health;          // H_* bits, sticky until read by the host
     uint32_t ring_head;       // number of series entries written (mod ring size)
+    uint32_t blk_done;        // pair-kernel blocks of this replica finished in the current launch
+    uint32_t maxov_last_bits; // float bits: largest overlap of the last completed evaluation
     double stress_sum[27];    // running sum for means
     uint64_t stress_count;
 };
 
 struct SysDyn {
-    uint32_t rebuild;         // 1: this step rebuilds cells and lists
-    uint32_t pad0;
+    uint32_t halted;          // 1: some list may have expired; the remaining launches of the chunk do nothing
+    uint32_t int_done;        // integrate blocks finished in the current launch
     uint64_t rebuilds;
-    uint64_t steps;
 };
 
 // Device buffers of one handle.  Particle arrays have npad entries, in
@@ -109,6 +110,7 @@ struct Bufs {
     double* partial;      // [blk][27]
     double* ring;         // [rep][kRing][27]
     double* last;         // [rep][27]
+    int lanes;            // pair kernel: lanes per particle (1, 2, 4, 8)
 
     uint32_t* blk_rep;    // replica of each kTile-block of particles
     RepParams* reps;
@@ -120,14 +122,16 @@ constexpr int kRing = 8192;
 constexpr int kCtCap = 16;   // contacts per particle carried across a rebuild
 
 // kernel launchers (susp_kernels.hip)
-void launch_step_begin(const Bufs& b, hipStream_t st);
+// one time step without a list rebuild: kick 1 + drift + wrap + list-expiry test, then forces + kick 2
 void launch_integrate(const Bufs& b, hipStream_t st);
-void launch_rebuild_decision(const Bufs& b, hipStream_t st, int force);
-// ct_input_rep: 0xFFFFFFFF = carry history from the current lists; 0xFFFFFFFE =
-// every replica takes the host-written compact table; else that replica does
-void launch_rebuild(const Bufs& b, hipStream_t st, int ct_input_rep);
-void launch_pair_force(const Bufs& b, hipStream_t st, int kick, uint32_t only_rep);
-void launch_reduce_stress(const Bufs& b, hipStream_t st, int record, uint32_t only_rep);
+// kick: apply kick 2; advance: evaluate at the next step counter and offset (a time step) rather
+// than at the current ones (creation / state injection); only_rep: one replica or 0xFFFFFFFF
+void launch_pair_force(const Bufs& b, hipStream_t st, int kick, int advance, uint32_t only_rep);
+// Rebuild of cells and neighbour lists from the current positions.  in_step: called between kick 1
+// and the force evaluation of a step (the offset of that step is used).  ct_input_rep:
+// 0xFFFFFFFF = carry contact history from the current lists; 0xFFFFFFFE = every replica takes
+// the host-written compact table; else that replica does.
+void launch_rebuild(const Bufs& b, hipStream_t st, int in_step, uint32_t ct_input_rep);
 void launch_diag(const Bufs& b, hipStream_t st, uint32_t rep, uint32_t n, uint32_t* out_ij, double* out_s,
                  int32_t* out_sl, uint32_t* count, uint32_t cap, int mode);
 

@@ -1,12 +1,13 @@
 // gfx950 kernels of the sheared-suspension force engine.
 //
-// One step of every replica is: step_begin (Lees-Edwards offset, counters) ->
-// integrate (kick 1, drift, wrap, displacement bound) -> rebuild decision ->
-// [rebuild: cell keys, scan, scatter, in-cell ordering, reorder, neighbour
-// list with history carry-over; each early-exits unless a rebuild is due] ->
-// pair force (all pair and one-body terms, kick 2, per-block stress) ->
-// stress reduction.  Paper references are to Li, Royer & Ness, arXiv
-// 2307.13802.
+// A time step is two launches over all replicas: integrate (kick 1, drift,
+// Lees-Edwards wrap, bound on the displacement since the last list build,
+// list-expiry test) and pair force (all pair and one-body terms, kick 2,
+// stress with a fixed-order reduction, advance of the step counter).  The
+// cell/list rebuild (Morton cell keys, scan, scatter, in-cell ordering,
+// reorder, Verlet list with contact-history carry-over) is launched by the
+// host only when its displacement budget is used up, or when the expiry test
+// halted a step.  Paper references are to Li, Royer & Ness, arXiv 2307.13802.
 //
 // Compiled with -ffp-contract=off: the geometry, the neighbour predicate and
 // the contact-history update are evaluated operation by operation in the
@@ -103,6 +104,47 @@ __device__ __forceinline__ int cell_coord(double x, double w, int n) {
 
 __device__ __forceinline__ float as_posf(uint32_t b) { return __uint_as_float(b); }
 
+// Lees-Edwards offset one step after the stored one (same arithmetic everywhere)
+__device__ __forceinline__ double next_offset(const RepParams& P, double s_le) {
+    double s = s_le + P.gdLy * P.dt;
+    return s - P.L[0] * floor(s / P.L[0]);
+}
+
+// block-wide sum of 27 doubles per thread, fixed order (blockDim = 256); result in out (LDS)
+__device__ __forceinline__ void block_sum27(const double* acc, double* out) {
+    __shared__ double red[4][27];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 27; ++c) {
+        double v = acc[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) red[wave][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 27) {
+        const int c = threadIdx.x;
+        out[c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+    }
+    __syncthreads();
+}
+
+// true in every thread of the block that finished last among `total` blocks
+// counted on *ctr (which it resets); publishes this block's global writes
+__device__ __forceinline__ bool last_block(uint32_t* ctr, uint32_t total) {
+    __shared__ int last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t prev = atomicAdd(ctr, 1u);
+        last = (prev == total - 1);
+        if (last) *ctr = 0u;
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last != 0;
+}
+
 // block-wide max of a non-negative float, then one atomic per block
 __device__ __forceinline__ void block_atomic_max(float v, uint32_t* target) {
     __shared__ float red[16];
@@ -120,29 +162,13 @@ __device__ __forceinline__ void block_atomic_max(float v, uint32_t* target) {
 }
 
 // ---------------------------------------------------------------------------
-// Step begin: advance the Lees-Edwards offset and the step counter.
-// ---------------------------------------------------------------------------
-__global__ void k_step_begin(Bufs b) {
-    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= b.nrep) return;
-    const RepParams& P = b.reps[r];
-    RepDyn& D = b.dyn[r];
-    double s = D.s_le + P.gdLy * P.dt;
-    s = s - P.L[0] * floor(s / P.L[0]);
-    D.s_le = s;
-    D.step = D.step + 1;
-    D.stepmax_bits = 0u;
-    D.maxov_bits = 0u;
-    if (r == 0) b.sys->steps += 1;
-}
-
-// ---------------------------------------------------------------------------
 // Kick 1, drift and wrap (velocity-Verlet, Sec. II; sheared box, Sec. II.E).
 // Also bounds this step's non-affine displacement |dx - U^inf dt| for the
 // neighbour-list validity test.
 // ---------------------------------------------------------------------------
 template <bool MIX>
 __global__ __launch_bounds__(256) void k_integrate(Bufs b) {
+    if (b.sys->halted) return;  // uniform: set only by the last block of an earlier launch
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t r = b.blk_rep[q / kTile];
     const RepParams& P = b.reps[r];
@@ -171,7 +197,7 @@ __global__ __launch_bounds__(256) void k_integrate(Bufs b) {
             x.x += P.dt * v.x;
             x.y += P.dt * v.y;
             x.z += P.dt * v.z;
-            const double s = b.dyn[r].s_le;
+            const double s = next_offset(P, b.dyn[r].s_le);
             const double Lx = P.L[0], Ly = P.L[1], Lz = P.L[2];
             if (x.y >= Ly) {
                 x.y -= Ly; x.x -= s; v.x -= P.gdLy;
@@ -198,48 +224,38 @@ __global__ __launch_bounds__(256) void k_integrate(Bufs b) {
         }
     }
     block_atomic_max(disp, &b.dyn[r].stepmax_bits);
+    if (!last_block(&b.sys->int_done, gridDim.x)) return;
+    // all particles have moved: fold this step into the displacement bound and test
+    // whether every list still holds all pairs within the interaction range
+    __shared__ int expired;
+    if (threadIdx.x == 0) expired = 0;
+    __syncthreads();
+    for (uint32_t rr = threadIdx.x; rr < b.nrep; rr += blockDim.x) {
+        const RepParams& Q = b.reps[rr];
+        RepDyn& D = b.dyn[rr];
+        D.dmax += (double)as_posf(D.stepmax_bits);
+        D.t_since += Q.dt;
+        D.stepmax_bits = 0u;
+        const bool ex = 2.0 * D.dmax + fabs(Q.gd) * D.t_since * (Q.rc_max + 2.0 * Q.skin) > Q.skin;
+        if (ex || (Q.flags & F_REBUILD_EACH_STEP)) expired = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && expired) b.sys->halted = 1u;
 }
 
 // ---------------------------------------------------------------------------
-// Rebuild decision.  A pair outside the list at the last build (|r| > r_c +
+// List validity (the expiry test of k_integrate).  A pair outside the list at the last build (|r| > r_c +
 // skin) can have come within r_c only if 2 D + |gammadot| t (r_c + 4 D) >
 // skin, where D bounds every particle's non-affine displacement since the
 // build and t is the time since the build (the affine part of the relative
 // motion is gammadot r_y t along x, with |r_y| <= r_c + 4 D).  With
 // 2 D <= skin this is implied by 2 D + |gammadot| t (r_c + 2 skin) > skin.
 // ---------------------------------------------------------------------------
-__global__ void k_rebuild_decision(Bufs b, int force) {
-    __shared__ int any;
-    if (threadIdx.x == 0) any = force;
-    __syncthreads();
-    for (uint32_t r = threadIdx.x; r < b.nrep; r += blockDim.x) {
-        const RepParams& P = b.reps[r];
-        RepDyn& D = b.dyn[r];
-        D.dmax += (double)as_posf(D.stepmax_bits);
-        D.t_since += P.dt;
-        const double gd = fabs(P.gd);
-        const bool trig = 2.0 * D.dmax + gd * D.t_since * (P.rc_max + 2.0 * P.skin) > P.skin;
-        if (trig || (P.flags & F_REBUILD_EACH_STEP)) any = 1;  // benign race: all writers store 1
-    }
-    __syncthreads();
-    if (any) {
-        for (uint32_t r = threadIdx.x; r < b.nrep; r += blockDim.x) {
-            b.dyn[r].dmax = 0.0;
-            b.dyn[r].t_since = 0.0;
-        }
-    }
-    if (threadIdx.x == 0) {
-        b.sys->rebuild = any ? 1u : 0u;
-        if (any) b.sys->rebuilds += 1;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Rebuild: Morton-ordered cells, deterministic order inside a cell (by id),
 // reorder of all particle data, neighbour list with history carry-over.
 // ---------------------------------------------------------------------------
 __global__ void k_rb_zero(Bufs b) {
-    if (!b.sys->rebuild) return;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < b.nkeys_total) {
         b.cell_cnt[k] = 0u;
@@ -248,7 +264,6 @@ __global__ void k_rb_zero(Bufs b) {
 }
 
 __global__ __launch_bounds__(256) void k_rb_keys(Bufs b) {
-    if (!b.sys->rebuild) return;
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t r = b.blk_rep[q / kTile];
     const RepParams& P = b.reps[r];
@@ -294,7 +309,6 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total)
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(Bufs b) {
-    if (!b.sys->rebuild) return;
     const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
     uint32_t s = 0;
 #pragma unroll
@@ -305,7 +319,6 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(Bufs b) {
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_top(Bufs b, uint32_t nblk) {
-    if (!b.sys->rebuild) return;
     // single block: scan nblk block sums in chunks of kScanBlock
     uint32_t carry = 0;
     for (uint32_t c0 = 0; c0 < nblk; c0 += kScanBlock) {
@@ -321,7 +334,6 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_top(Bufs b, uint32_t nblk) 
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_down(Bufs b) {
-    if (!b.sys->rebuild) return;
     const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
     uint32_t v[kScanPer];
     uint32_t s = 0;
@@ -340,7 +352,6 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(Bufs b) {
 }
 
 __global__ __launch_bounds__(256) void k_rb_scatter(Bufs b) {
-    if (!b.sys->rebuild) return;
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t r = b.blk_rep[q / kTile];
     const RepParams& P = b.reps[r];
@@ -353,7 +364,6 @@ __global__ __launch_bounds__(256) void k_rb_scatter(Bufs b) {
 
 // order the members of each cell by particle id (makes the layout independent of atomic order)
 __global__ void k_rb_cellsort(Bufs b) {
-    if (!b.sys->rebuild) return;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= b.nkeys_total) return;
     const uint32_t cnt = b.cell_fill[k];
@@ -375,7 +385,6 @@ __global__ void k_rb_cellsort(Bufs b) {
 // the per-entry contact history of the old list into a compact per-particle
 // table keyed by partner id
 __global__ __launch_bounds__(256) void k_rb_gather(Bufs b, uint32_t ct_input_rep) {
-    if (!b.sys->rebuild) return;
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t r = b.blk_rep[q / kTile];
     const RepParams& P = b.reps[r];
@@ -433,7 +442,6 @@ __global__ __launch_bounds__(256) void k_rb_gather(Bufs b, uint32_t ct_input_rep
 }
 
 __global__ __launch_bounds__(256) void k_rb_copyback(Bufs b) {
-    if (!b.sys->rebuild) return;
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     b.id[q] = b.alt_id[q];
     b.pos[q] = b.alt4[0][q];
@@ -457,8 +465,7 @@ __global__ __launch_bounds__(256) void k_rb_copyback(Bufs b) {
 // Verlet list: every j with |r| <= (a_i + a_j)(1 + xi_cut/2) + skin, sorted by
 // partner id (so force sums do not depend on the cell layout), then the
 // carried contact history is attached to its list entry.
-__global__ __launch_bounds__(256) void k_rb_nlist(Bufs b) {
-    if (!b.sys->rebuild) return;
+__global__ __launch_bounds__(256) void k_rb_nlist(Bufs b, int in_step) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t r = b.blk_rep[i / kTile];
     const RepParams& P = b.reps[r];
@@ -470,7 +477,7 @@ __global__ __launch_bounds__(256) void k_rb_nlist(Bufs b) {
         return;
     }
     const double4 pi = b.pos[i];
-    const double s_le = b.dyn[r].s_le;
+    const double s_le = in_step ? next_offset(P, b.dyn[r].s_le) : b.dyn[r].s_le;
     const double amax = P.rc_max / (2.0 * P.c1);
     const double rli = (pi.w + amax) * P.c1 + P.skin;           // largest list radius of i
     const double margin = rli * (1.0 + 1e-12) + 1e-12 * P.L[0];
@@ -548,6 +555,19 @@ __global__ __launch_bounds__(256) void k_rb_nlist(Bufs b) {
     b.smask[i] = sm;
 }
 
+// after a build every list holds all pairs within range plus the full skin
+__global__ void k_rb_reset(Bufs b) {
+    for (uint32_t r = threadIdx.x; r < b.nrep; r += blockDim.x) {
+        b.dyn[r].dmax = 0.0;
+        b.dyn[r].t_since = 0.0;
+        b.dyn[r].stepmax_bits = 0u;
+    }
+    if (threadIdx.x == 0) {
+        b.sys->halted = 0u;
+        b.sys->rebuilds += 1;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Pair forces (Sec. II.A-II.D), one-body terms (Sec. II.B-II.C), kick 2.
 // One lane per particle i walks its Verlet list.  Every pair is evaluated in
@@ -582,40 +602,42 @@ template <class R> __device__ __forceinline__ R rsqrt_(R x);
 template <> __device__ __forceinline__ double rsqrt_<double>(double x) { return sqrt(x); }
 template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return __fsqrt_rn(x); }
 
-template <bool MIX>
-__global__ __launch_bounds__(256) void k_pair(Bufs b, int kick, uint32_t only_rep) {
+template <bool MIX, int LN>
+__global__ __launch_bounds__(256) void k_pair(Bufs b, int kick, int advance, uint32_t only_rep) {
     using R = typename std::conditional<MIX, float, double>::type;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b.sys->halted) return;  // a list may have expired: the host rebuilds and repeats this launch
+    // LN consecutive lanes share one particle and split its list (entries e = sub, sub + LN, ...)
+    const uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / LN;
+    const uint32_t sub = threadIdx.x % LN;
     const uint32_t r = b.blk_rep[i / kTile];
     if (only_rep != 0xFFFFFFFFu && r != only_rep) return;  // whole block belongs to one replica
     const RepParams& P = b.reps[r];
-    const RepDyn& D = b.dyn[r];
+    RepDyn& D = b.dyn[r];
     const uint32_t npad = b.npad;
     const bool valid = (i - P.p_begin) < P.n;
 
-    double sC[9], sL[9], sB[9];
+    double acc[27];  // stress: contact, lubrication, Brownian; lower-id side of each pair
 #pragma unroll
-    for (int t = 0; t < 9; ++t) { sC[t] = 0.0; sL[t] = 0.0; sB[t] = 0.0; }
+    for (int t = 0; t < 27; ++t) acc[t] = 0.0;
     float maxov = 0.0f;
     bool bad = false;
+    const double s_le = advance ? next_offset(P, D.s_le) : D.s_le;
+    const uint64_t step = advance ? D.step + 1 : D.step;
 
     if (valid) {
         const double4 pi = b.pos[i];
         const uint32_t idi = b.id[i];
-        const double s_le = D.s_le;
-        const uint64_t step = D.step;
         const uint32_t k0 = (uint32_t)P.seed, k1 = (uint32_t)(P.seed >> 32);
         const uint32_t ctr_lo = (uint32_t)step, ctr_hi = (uint32_t)(step >> 32) << 8;
-        const double4 vhi = b.vh[i];
-        const double4 whi = b.wh[i];
         R vi[3], wi[3];
         if (MIX) {
             const float4 v4 = b.vsh[i], w4 = b.wsh[i];
             vi[0] = v4.x; vi[1] = v4.y; vi[2] = v4.z;
             wi[0] = w4.x; wi[1] = w4.y; wi[2] = w4.z;
         } else {
-            vi[0] = (R)vhi.x; vi[1] = (R)vhi.y; vi[2] = (R)vhi.z;
-            wi[0] = (R)whi.x; wi[1] = (R)whi.y; wi[2] = (R)whi.z;
+            const double4 v4 = b.vh[i], w4 = b.wh[i];
+            vi[0] = (R)v4.x; vi[1] = (R)v4.y; vi[2] = (R)v4.z;
+            wi[0] = (R)w4.x; wi[1] = (R)w4.y; wi[2] = (R)w4.z;
         }
         const R ai = (R)pi.w;
         const double c1 = P.c1;
@@ -628,10 +650,10 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int kick, uint32_t only_re
 
         Acc<R> F, T;
         const uint32_t cnt = b.ncnt[i];
-        const uint64_t cm_old = b.cmask[i], sm_old = b.smask[i];
+        const uint64_t cm_old = b.cmask[i];
         uint64_t cm = 0ull, sm = 0ull;
 
-        for (uint32_t e = 0; e < cnt; ++e) {
+        for (uint32_t e = sub; e < cnt; e += LN) {
             const uint32_t j = b.nbr[e * npad + i];
             const double4 pj = b.pos[j];
             const uint32_t idj = b.id[j];
@@ -655,7 +677,7 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int kick, uint32_t only_re
             }
             const R aj = (R)pj.w;
             const R aa = lo ? ai : aj, ab = lo ? aj : ai;  // canonical radii
-            R xi = (R)((2.0 * h) / sa);
+            const R xi = (R)((2.0 * h) / sa);
             const R xie = xi < xi_min ? xi_min : xi;
 
             // resistance scalars X^A_11, Y^A_11 (Sec. II.B) in the symmetric form
@@ -666,10 +688,9 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int kick, uint32_t only_re
             const R XA = pre * ((R)2 * pab * pab / xie + pab * (qab + (R)7 * pab) / (R)5 * lg);
             const R YA = pre * ((R)4 * pab * ((R)2 * qab + pab) / (R)15 * lg);
 
-            // velocities in canonical orientation; image of b moves with +k_y gammadot Ly
-            R va[3], vb[3];
+            // velocities in canonical orientation; the image of b moves with +k_y gammadot Ly
+            R va[3], vb[3], vj[3];
             const R shiftv = (R)((double)ky * P.gdLy);
-            R vj[3];
             if (MIX) {
                 const float4 v4 = b.vsh[j];
                 vj[0] = v4.x; vj[1] = v4.y; vj[2] = v4.z;
@@ -681,7 +702,6 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int kick, uint32_t only_re
             for (int d = 0; d < 3; ++d) { va[d] = lo ? vi[d] : vj[d]; vb[d] = lo ? vj[d] : vi[d]; }
             vb[0] = vb[0] + shiftv;
 
-            R f[3] = {(R)0, (R)0, (R)0};   // total pair force on a
             R fl[3] = {(R)0, (R)0, (R)0}, fb[3] = {(R)0, (R)0, (R)0}, fc[3] = {(R)0, (R)0, (R)0};
             if (do_lub) {
                 // eq. (force_lub): (X^A N + Y^A T)(U_b - U_a)
@@ -782,8 +802,8 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int kick, uint32_t only_re
             }
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                f[d] = fl[d] + fb[d] + fc[d];
-                F.add(d, lo ? f[d] : -f[d]);
+                const R f = fl[d] + fb[d] + fc[d];
+                F.add(d, lo ? f : -f);
             }
             if (lo) {
                 // Sec. II.A, II.B, II.D: Sigma^X_ab -= F^X_a r_b / V, FP64
@@ -792,117 +812,112 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int kick, uint32_t only_re
                 for (int al = 0; al < 3; ++al)
 #pragma unroll
                     for (int be = 0; be < 3; ++be) {
-                        sC[3 * al + be] -= (double)fc[al] * rr[be] * P.invV;
-                        sL[3 * al + be] -= (double)fl[al] * rr[be] * P.invV;
-                        sB[3 * al + be] -= (double)fb[al] * rr[be] * P.invV;
+                        acc[3 * al + be] -= (double)fc[al] * rr[be] * P.invV;
+                        acc[9 + 3 * al + be] -= (double)fl[al] * rr[be] * P.invV;
+                        acc[18 + 3 * al + be] -= (double)fb[al] * rr[be] * P.invV;
                     }
             }
         }
 
-        // one-body terms: eq. (force_drag), (torque_drag), (force_brownian_drag), (torque_brownian_drag)
+        // combine the LN lanes of the particle (fixed butterfly order)
         double Ft[3], Tt[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) { Ft[d] = F.get(d); Tt[d] = T.get(d); }
-        if (!(P.flags & F_NO_ONEBODY)) {
-            const double a = pi.w;
-            const R zeta = (R)(6.0 * kPi * P.eta * a);
-            const R zr = (R)(8.0 * kPi * P.eta * a * a * a);
-            const R uinf[3] = {(R)(P.gd * (pi.y - 0.5 * P.L[1])), (R)0, (R)0};
-            const R oinf[3] = {(R)0, (R)0, (R)(-0.5 * P.gd)};
-            const uint4 wf = philox10(ctr_lo, idi, 0xFFFFFFFFu, ctr_hi | 2u, k0, k1);
-            const uint4 wt = philox10(ctr_lo, idi, 0xFFFFFFFFu, ctr_hi | 3u, k0, k1);
-            R psi[3], phi[3];
-            normals3(wf, psi);
-            normals3(wt, phi);
-            const R sz = rsqrt_<R>(zeta), szr = rsqrt_<R>(zr);
+#pragma unroll
+        for (int off = 1; off < LN; off <<= 1) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                Ft[d] += (double)(zeta * (uinf[d] - vi[d]) + bamp * sz * psi[d]);
-                Tt[d] += (double)(zr * (oinf[d] - wi[d]) + bamp * szr * phi[d]);
+                Ft[d] += __shfl_xor(Ft[d], off);
+                Tt[d] += __shfl_xor(Tt[d], off);
             }
+            cm |= __shfl_xor(cm, off);
+            sm |= __shfl_xor(sm, off);
         }
-        bad = !(isfinite(Ft[0]) && isfinite(Ft[1]) && isfinite(Ft[2]) && isfinite(Tt[0]) && isfinite(Tt[1]) &&
-                isfinite(Tt[2]));
-        b.cmask[i] = cm;
-        b.smask[i] = sm;
-        if (MIX) {
-            ((float4*)b.F)[i] = make_float4((float)Ft[0], (float)Ft[1], (float)Ft[2], 0.0f);
-            ((float4*)b.T)[i] = make_float4((float)Tt[0], (float)Tt[1], (float)Tt[2], 0.0f);
-        } else {
-            ((double4*)b.F)[i] = make_double4(Ft[0], Ft[1], Ft[2], 0.0);
-            ((double4*)b.T)[i] = make_double4(Tt[0], Tt[1], Tt[2], 0.0);
+
+        if (sub == 0) {
+            // one-body terms: eq. (force_drag), (torque_drag), (force_brownian_drag), (torque_brownian_drag)
+            if (!(P.flags & F_NO_ONEBODY)) {
+                const double a = pi.w;
+                const R zeta = (R)(6.0 * kPi * P.eta * a);
+                const R zr = (R)(8.0 * kPi * P.eta * a * a * a);
+                const R uinf[3] = {(R)(P.gd * (pi.y - 0.5 * P.L[1])), (R)0, (R)0};
+                const R oinf[3] = {(R)0, (R)0, (R)(-0.5 * P.gd)};
+                const uint4 wf = philox10(ctr_lo, idi, 0xFFFFFFFFu, ctr_hi | 2u, k0, k1);
+                const uint4 wt = philox10(ctr_lo, idi, 0xFFFFFFFFu, ctr_hi | 3u, k0, k1);
+                R psi[3], phi[3];
+                normals3(wf, psi);
+                normals3(wt, phi);
+                const R sz = rsqrt_<R>(zeta), szr = rsqrt_<R>(zr);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    Ft[d] += (double)(zeta * (uinf[d] - vi[d]) + bamp * sz * psi[d]);
+                    Tt[d] += (double)(zr * (oinf[d] - wi[d]) + bamp * szr * phi[d]);
+                }
+            }
+            bad = !(isfinite(Ft[0]) && isfinite(Ft[1]) && isfinite(Ft[2]) && isfinite(Tt[0]) && isfinite(Tt[1]) &&
+                    isfinite(Tt[2]));
+            b.cmask[i] = cm;
+            b.smask[i] = sm;
+            if (MIX) {
+                ((float4*)b.F)[i] = make_float4((float)Ft[0], (float)Ft[1], (float)Ft[2], 0.0f);
+                ((float4*)b.T)[i] = make_float4((float)Tt[0], (float)Tt[1], (float)Tt[2], 0.0f);
+            } else {
+                ((double4*)b.F)[i] = make_double4(Ft[0], Ft[1], Ft[2], 0.0);
+                ((double4*)b.T)[i] = make_double4(Tt[0], Tt[1], Tt[2], 0.0);
+            }
+            // kick 2 of velocity-Verlet
+            double4 vf = b.vh[i], wf = b.wh[i];
+            if (kick) {
+                const double a = pi.w;
+                const double m = (4.0 / 3.0) * kPi * P.rho * a * a * a;
+                const double I = 0.4 * m * a * a;
+                const double hm = P.half_dt / m, hI = P.half_dt / I;
+                vf.x += hm * Ft[0]; vf.y += hm * Ft[1]; vf.z += hm * Ft[2];
+                wf.x += hI * Tt[0]; wf.y += hI * Tt[1]; wf.z += hI * Tt[2];
+            }
+            b.vf[i] = vf;
+            b.wf[i] = wf;
         }
-        // kick 2 of velocity-Verlet
-        double4 vf = vhi, wf = whi;
-        if (kick) {
-            const double a = pi.w;
-            const double m = (4.0 / 3.0) * kPi * P.rho * a * a * a;
-            const double I = 0.4 * m * a * a;
-            const double hm = P.half_dt / m, hI = P.half_dt / I;
-            vf.x += hm * Ft[0]; vf.y += hm * Ft[1]; vf.z += hm * Ft[2];
-            wf.x += hI * Tt[0]; wf.y += hI * Tt[1]; wf.z += hI * Tt[2];
-        }
-        b.vf[i] = vf;
-        b.wf[i] = wf;
-        (void)sm_old;
     }
 
-    // health: overlap above the limit, non-finite forces
-    if (bad) atomicOr(&b.dyn[r].health, H_NAN);
-    block_atomic_max(maxov, &b.dyn[r].maxov_bits);
+    // health: non-finite forces, largest overlap
+    if (bad) atomicOr(&D.health, H_NAN);
+    block_atomic_max(maxov, &D.maxov_bits);
 
-    // block partial sums of the 27 stress components, fixed order
-    __shared__ double red[4][27];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // block partial of the 27 stress sums, fixed order
+    __shared__ double tot[27];
+    block_sum27(acc, tot);
+    if (threadIdx.x < 27) b.partial[(size_t)blockIdx.x * 27 + threadIdx.x] = tot[threadIdx.x];
+    const uint32_t blk0 = P.blk_begin * LN, nblk = P.nblk * LN;
+    if (!last_block(&D.blk_done, nblk)) return;
+
+    // last block of the replica: fixed-order sum of all its partials
 #pragma unroll
-    for (int c = 0; c < 27; ++c) {
-        double v = c < 9 ? sC[c] : (c < 18 ? sL[c - 9] : sB[c - 18]);
+    for (int c = 0; c < 27; ++c) acc[c] = 0.0;
+    for (uint32_t k = threadIdx.x; k < nblk; k += blockDim.x) {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) red[wave][c] = v;
+        for (int c = 0; c < 27; ++c) acc[c] += b.partial[(size_t)(blk0 + k) * 27 + c];
     }
-    __syncthreads();
+    block_sum27(acc, tot);
     if (threadIdx.x < 27) {
         const int c = threadIdx.x;
-        b.partial[(size_t)blockIdx.x * 27 + c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
-    }
-}
-
-// per-replica stress: fixed-order sum of the block partials
-__global__ __launch_bounds__(256) void k_reduce_stress(Bufs b, int record, uint32_t only_rep) {
-    const uint32_t r = blockIdx.x;
-    if (only_rep != 0xFFFFFFFFu && r != only_rep) return;
-    const RepParams& P = b.reps[r];
-    __shared__ double acc[256];
-    __shared__ double out[27];
-    for (int c = 0; c < 27; ++c) {
-        double s = 0.0;
-        for (uint32_t k = threadIdx.x; k < P.nblk; k += blockDim.x) s += b.partial[(size_t)(P.blk_begin + k) * 27 + c];
-        acc[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) acc[threadIdx.x] += acc[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[c] = acc[0];
-        __syncthreads();
-    }
-    RepDyn& D = b.dyn[r];
-    if (threadIdx.x < 27) {
-        const int c = threadIdx.x;
-        b.last[r * 27 + c] = out[c];
-        if (record) {
-            b.ring[((size_t)r * kRing + (D.ring_head % kRing)) * 27 + c] = out[c];
-            D.stress_sum[c] += out[c];
+        b.last[r * 27 + c] = tot[c];
+        if (advance) {
+            b.ring[((size_t)r * kRing + (D.ring_head % kRing)) * 27 + c] = tot[c];
+            D.stress_sum[c] += tot[c];
         }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (record) {
+        if ((double)__uint_as_float(D.maxov_bits) > P.max_overlap) D.health |= H_OVERLAP;
+        D.maxov_last_bits = D.maxov_bits;
+        D.maxov_bits = 0u;
+        if (advance) {
             D.ring_head += 1;
             D.stress_count += 1;
+            D.s_le = s_le;
+            D.step = step;
         }
-        if ((double)__uint_as_float(D.maxov_bits) > P.max_overlap) D.health |= H_OVERLAP;
     }
 }
 
@@ -953,20 +968,12 @@ __global__ void k_diag(Bufs b, uint32_t rep, uint32_t* out_ij, double* out_s, in
 // ---------------------------------------------------------------------------
 static inline uint32_t nblocks(uint32_t n, uint32_t bs) { return (n + bs - 1) / bs; }
 
-void launch_step_begin(const Bufs& b, hipStream_t st) {
-    hipLaunchKernelGGL(k_step_begin, dim3(nblocks(b.nrep, 64)), dim3(64), 0, st, b);
-}
-
 void launch_integrate(const Bufs& b, hipStream_t st) {
     if (b.mixed) hipLaunchKernelGGL(k_integrate<true>, dim3(b.npad / 256), dim3(256), 0, st, b);
     else hipLaunchKernelGGL(k_integrate<false>, dim3(b.npad / 256), dim3(256), 0, st, b);
 }
 
-void launch_rebuild_decision(const Bufs& b, hipStream_t st, int force) {
-    hipLaunchKernelGGL(k_rebuild_decision, dim3(1), dim3(256), 0, st, b, force);
-}
-
-void launch_rebuild(const Bufs& b, hipStream_t st, int ct_input_rep) {
+void launch_rebuild(const Bufs& b, hipStream_t st, int in_step, uint32_t ct_input_rep) {
     const uint32_t np = b.npad / 256;
     hipLaunchKernelGGL(k_rb_zero, dim3(nblocks(b.nkeys_total, 256)), dim3(256), 0, st, b);
     hipLaunchKernelGGL(k_rb_keys, dim3(np), dim3(256), 0, st, b);
@@ -976,18 +983,26 @@ void launch_rebuild(const Bufs& b, hipStream_t st, int ct_input_rep) {
     hipLaunchKernelGGL(k_scan_down, dim3(nsb), dim3(kScanBlock), 0, st, b);
     hipLaunchKernelGGL(k_rb_scatter, dim3(np), dim3(256), 0, st, b);
     hipLaunchKernelGGL(k_rb_cellsort, dim3(nblocks(b.nkeys_total, 256)), dim3(256), 0, st, b);
-    hipLaunchKernelGGL(k_rb_gather, dim3(np), dim3(256), 0, st, b, (uint32_t)ct_input_rep);
+    hipLaunchKernelGGL(k_rb_gather, dim3(np), dim3(256), 0, st, b, ct_input_rep);
     hipLaunchKernelGGL(k_rb_copyback, dim3(np), dim3(256), 0, st, b);
-    hipLaunchKernelGGL(k_rb_nlist, dim3(np), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_rb_nlist, dim3(np), dim3(256), 0, st, b, in_step);
+    hipLaunchKernelGGL(k_rb_reset, dim3(1), dim3(256), 0, st, b);
 }
 
-void launch_pair_force(const Bufs& b, hipStream_t st, int kick, uint32_t only_rep) {
-    if (b.mixed) hipLaunchKernelGGL(k_pair<true>, dim3(b.npad / 256), dim3(256), 0, st, b, kick, only_rep);
-    else hipLaunchKernelGGL(k_pair<false>, dim3(b.npad / 256), dim3(256), 0, st, b, kick, only_rep);
+template <bool MIX>
+static void launch_pair_t(const Bufs& b, hipStream_t st, int kick, int advance, uint32_t only_rep) {
+    const dim3 blk(256);
+    switch (b.lanes) {
+        case 1: hipLaunchKernelGGL((k_pair<MIX, 1>), dim3(b.npad / 256), blk, 0, st, b, kick, advance, only_rep); break;
+        case 2: hipLaunchKernelGGL((k_pair<MIX, 2>), dim3(b.npad / 128), blk, 0, st, b, kick, advance, only_rep); break;
+        case 4: hipLaunchKernelGGL((k_pair<MIX, 4>), dim3(b.npad / 64), blk, 0, st, b, kick, advance, only_rep); break;
+        default: hipLaunchKernelGGL((k_pair<MIX, 8>), dim3(b.npad / 32), blk, 0, st, b, kick, advance, only_rep); break;
+    }
 }
 
-void launch_reduce_stress(const Bufs& b, hipStream_t st, int record, uint32_t only_rep) {
-    hipLaunchKernelGGL(k_reduce_stress, dim3(b.nrep), dim3(256), 0, st, b, record, only_rep);
+void launch_pair_force(const Bufs& b, hipStream_t st, int kick, int advance, uint32_t only_rep) {
+    if (b.mixed) launch_pair_t<true>(b, st, kick, advance, only_rep);
+    else launch_pair_t<false>(b, st, kick, advance, only_rep);
 }
 
 void launch_diag(const Bufs& b, hipStream_t st, uint32_t rep, uint32_t n, uint32_t* out_ij, double* out_s,

@@ -78,6 +78,10 @@ struct sim {
     int64_t prof_launches = 0;
     double prof_ms = 0.0;
     int64_t steps_total = 0;
+    uint64_t step_now = 0;       // step counter of replica 0 (all replicas advance together)
+    int64_t since_build = 0;     // steps since the last list build
+    int64_t plan = 16;           // rebuild when since_build reaches this
+    int64_t plan_hint = 16;      // first chunk after a build
 
     void* dalloc(size_t bytes) {
         if (bytes == 0) bytes = 256;
@@ -141,7 +145,10 @@ int validate(const sim_config* c, const double* radii, std::string& why) {
         why = fmt("struct_size %u != sizeof(sim_config) %zu", c->struct_size, sizeof(sim_config));
         return SIM_EINVAL;
     }
-    if (c->reserved != 0) { why = "reserved field must be 0"; return SIM_EINVAL; }
+    if (c->lanes != 0 && c->lanes != 1 && c->lanes != 2 && c->lanes != 4 && c->lanes != 8) {
+        why = "lanes must be 0, 1, 2, 4 or 8";
+        return SIM_EINVAL;
+    }
     if (c->n == 0 || c->n >= 0xFFFFFFFFu) { why = "n must be in [1, 2^32-2]"; return SIM_EINVAL; }
     if (!radii) { why = "null radii"; return SIM_EINVAL; }
     for (uint32_t i = 0; i < c->n; ++i)
@@ -182,13 +189,11 @@ template <class T> std::vector<T> d2h(sim* s, const T* dev, size_t off, size_t c
     return h;
 }
 
+// one time step without a list rebuild; both kernels do nothing once the
+// expiry test of an earlier integrate has halted the chunk
 void enqueue_step(sim* s, hipStream_t st) {
-    launch_step_begin(s->b, st);
     launch_integrate(s->b, st);
-    launch_rebuild_decision(s->b, st, 0);
-    launch_rebuild(s->b, st, (int)0xFFFFFFFFu);
-    launch_pair_force(s->b, st, 1, 0xFFFFFFFFu);
-    launch_reduce_stress(s->b, st, 1, 0xFFFFFFFFu);
+    launch_pair_force(s->b, st, 1, 1, 0xFFFFFFFFu);
 }
 
 hipGraphExec_t capture(sim* s, int nsteps) {
@@ -309,6 +314,34 @@ void set_dyn(sim* s, int r, double s_le, uint64_t step) {
     s->ring_tail[r] = 0;
 }
 
+// Lanes per particle for the pair kernel: the fastest of 1, 2, 4, 8 over a few
+// evaluations of the actual system (few lanes suit large systems, more lanes
+// hide gather latency when particles are too few to fill the GPU).
+void tune_lanes(sim* s) {
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_l = 1;
+    for (int L : {1, 2, 4, 8}) {
+        s->b.lanes = L;
+        launch_pair_force(s->b, s->st, 0, 0, 0xFFFFFFFFu);
+        HIPCHK(hipEventRecord(e0, s->st));
+        for (int k = 0; k < 4; ++k) launch_pair_force(s->b, s->st, 0, 0, 0xFFFFFFFFu);
+        HIPCHK(hipEventRecord(e1, s->st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            best_l = L;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    s->b.lanes = best_l;
+}
+
 int check_rep(sim* s, int32_t r) {
     if (!s) return fail(nullptr, SIM_EINVAL, "null handle");
     if (r < 0 || r >= s->nrep) return fail(s, SIM_ERANGE, fmt("replica %d out of range [0, %d)", r, s->nrep));
@@ -343,8 +376,9 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
     for (int r = 0; r < n_replicas; ++r) {
         std::string why;
         if (validate(&cfgs[r], radii[r], why) != SIM_OK) return fail(nullptr, SIM_EINVAL, fmt("replica %d: %s", r, why.c_str()));
-        if (cfgs[r].precision != cfgs[0].precision || cfgs[r].flags != cfgs[0].flags)
-            return fail(nullptr, SIM_EINVAL, "precision and flags must be equal for all replicas");
+        if (cfgs[r].precision != cfgs[0].precision || cfgs[r].flags != cfgs[0].flags ||
+            cfgs[r].lanes != cfgs[0].lanes)
+            return fail(nullptr, SIM_EINVAL, "precision, flags and lanes must be equal for all replicas");
         if (!x0[r]) return fail(nullptr, SIM_EINVAL, fmt("replica %d: null positions", r));
         for (uint32_t i = 0; i < 3 * cfgs[r].n; ++i) {
             const double L = cfgs[r].box[i % 3];
@@ -465,10 +499,18 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
             upload_state(s, r, x0[r], v0 ? v0[r] : nullptr, w0 ? w0[r] : nullptr, nullptr, nullptr, nullptr, nullptr, 0);
             set_dyn(s, r, cfgs[r].le_offset0, cfgs[r].step0);
         }
-        launch_rebuild_decision(b, s->st, 1);
-        launch_rebuild(b, s->st, (int)0xFFFFFFFEu);
-        launch_pair_force(b, s->st, 0, 0xFFFFFFFFu);
-        launch_reduce_stress(b, s->st, 0, 0xFFFFFFFFu);
+        s->step_now = cfgs[0].step0;
+        launch_rebuild(b, s->st, 0, 0xFFFFFFFEu);
+        b.lanes = 1;
+        if (cfgs[0].lanes == 0) {
+            tune_lanes(s);
+            // the trial evaluations created springs: start again from an empty history
+            HIPCHK(hipMemsetAsync(b.cmask, 0, sizeof(uint64_t) * b.npad, s->st));
+            HIPCHK(hipMemsetAsync(b.smask, 0, sizeof(uint64_t) * b.npad, s->st));
+        } else {
+            b.lanes = (int)cfgs[0].lanes;
+        }
+        launch_pair_force(b, s->st, 0, 0, 0xFFFFFFFFu);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s->st));
         const int hc = check_health(s);
@@ -489,54 +531,108 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
     return SIM_OK;
 }
 
+namespace {
+
+// Launches m steps on the library stream (graphs of kGraphSteps and 1 step, or
+// direct launches), then waits.
+void launch_steps(sim* s, int64_t m) {
+    const bool graph = !(s->flags & SIM_NO_GRAPH) && !s->profile;
+    if (graph) {
+        if (!s->g1) s->g1 = capture(s, 1);
+        if (!s->gk && m >= kGraphSteps) s->gk = capture(s, kGraphSteps);
+        for (; m >= kGraphSteps; m -= kGraphSteps) HIPCHK(hipGraphLaunch(s->gk, s->st));
+        for (; m > 0; --m) HIPCHK(hipGraphLaunch(s->g1, s->st));
+    } else if (s->profile) {
+        if (s->ev.size() < 2) {
+            for (int k = 0; k < 2; ++k) {
+                hipEvent_t e;
+                HIPCHK(hipEventCreate(&e));
+                s->ev.push_back(e);
+            }
+        }
+        for (; m > 0; --m) {
+            launch_integrate(s->b, s->st);
+            HIPCHK(hipEventRecord(s->ev[0], s->st));
+            launch_pair_force(s->b, s->st, 1, 1, 0xFFFFFFFFu);
+            HIPCHK(hipEventRecord(s->ev[1], s->st));
+            HIPCHK(hipEventSynchronize(s->ev[1]));
+            SysDyn sy;
+            HIPCHK(hipMemcpy(&sy, s->b.sys, sizeof sy, hipMemcpyDeviceToHost));
+            if (sy.halted) break;  // that launch did nothing; the caller completes the step
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, s->ev[0], s->ev[1]));
+            s->prof_ms += ms;
+            s->prof_launches += 1;
+        }
+    } else {
+        for (; m > 0; --m) enqueue_step(s, s->st);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s->st));
+}
+
+// Steps affordable before the displacement bound can use up the skin, from its
+// growth since the last build (the bound grows at most linearly per step).
+int64_t plan_steps(sim* s, const std::vector<RepDyn>& dyn) {
+    if (s->since_build <= 0) return s->plan_hint;
+    double worst = 0.0;  // fraction of the skin used per step
+    for (int r = 0; r < s->nrep; ++r) {
+        const RepParams& P = s->P[r];
+        const double used = 2.0 * dyn[r].dmax + std::fabs(P.gd) * dyn[r].t_since * (P.rc_max + 2.0 * P.skin);
+        worst = std::max(worst, used / P.skin / (double)s->since_build);
+    }
+    if (!(worst > 0.0)) return 1 << 20;
+    return (int64_t)(0.8 / worst);
+}
+
+}  // namespace
+
 int sim_step(sim* s, int64_t nsteps) {
     if (!s) return fail(nullptr, SIM_EINVAL, "null handle");
     if (nsteps < 0) return fail(s, SIM_EINVAL, "nsteps < 0");
     try {
-        const bool graph = !(s->flags & SIM_NO_GRAPH) && !s->profile;
         int64_t left = nsteps;
-        if (graph) {
-            if (!s->g1) s->g1 = capture(s, 1);
-            if (!s->gk && left >= kGraphSteps) s->gk = capture(s, kGraphSteps);
-            while (left >= kGraphSteps) {
-                HIPCHK(hipGraphLaunch(s->gk, s->st));
-                left -= kGraphSteps;
+        std::vector<RepDyn> dyn(s->nrep);
+        while (left > 0) {
+            int64_t budget = s->plan - s->since_build;
+            if (budget < 1) {
+                // displacement budget used up: rebuild between steps, from the current positions
+                launch_rebuild(s->b, s->st, 0, 0xFFFFFFFFu);
+                s->since_build = 0;
+                s->plan = s->plan_hint;
+                budget = s->plan;
             }
-            while (left > 0) {
-                HIPCHK(hipGraphLaunch(s->g1, s->st));
-                --left;
-            }
-        } else {
-            for (; left > 0; --left) {
-                launch_step_begin(s->b, s->st);
-                launch_integrate(s->b, s->st);
-                launch_rebuild_decision(s->b, s->st, 0);
-                launch_rebuild(s->b, s->st, (int)0xFFFFFFFFu);
-                if (s->profile) {
-                    if (s->ev.size() < 2) {
-                        for (int k = 0; k < 2; ++k) {
-                            hipEvent_t e;
-                            HIPCHK(hipEventCreate(&e));
-                            s->ev.push_back(e);
-                        }
-                    }
-                    HIPCHK(hipEventRecord(s->ev[0], s->st));
-                    launch_pair_force(s->b, s->st, 1, 0xFFFFFFFFu);
-                    HIPCHK(hipEventRecord(s->ev[1], s->st));
-                    launch_reduce_stress(s->b, s->st, 1, 0xFFFFFFFFu);
-                    HIPCHK(hipEventSynchronize(s->ev[1]));
-                    float ms = 0.f;
-                    HIPCHK(hipEventElapsedTime(&ms, s->ev[0], s->ev[1]));
-                    s->prof_ms += ms;
-                    s->prof_launches += 1;
-                } else {
-                    launch_pair_force(s->b, s->st, 1, 0xFFFFFFFFu);
-                    launch_reduce_stress(s->b, s->st, 1, 0xFFFFFFFFu);
-                }
+            const int64_t m = std::min(left, std::max<int64_t>(budget, 1));
+            const uint64_t step0 = s->step_now;
+            launch_steps(s, m);
+            HIPCHK(hipMemcpyAsync(dyn.data(), s->b.dyn, sizeof(RepDyn) * s->nrep, hipMemcpyDeviceToHost, s->st));
+            SysDyn sy;
+            HIPCHK(hipMemcpyAsync(&sy, s->b.sys, sizeof sy, hipMemcpyDeviceToHost, s->st));
+            HIPCHK(hipStreamSynchronize(s->st));
+            const int64_t done = (int64_t)(dyn[0].step - step0);
+            s->step_now = dyn[0].step;
+            s->since_build += done;
+            left -= done;
+            if (sy.halted) {
+                // the step after `done` ran its integrate but the expiry test stopped its
+                // forces: rebuild from the moved positions and evaluate that step
+                const int64_t grown = plan_steps(s, dyn);
+                launch_rebuild(s->b, s->st, 1, 0xFFFFFFFFu);
+                launch_pair_force(s->b, s->st, 1, 1, 0xFFFFFFFFu);
+                HIPCHK(hipGetLastError());
+                HIPCHK(hipStreamSynchronize(s->st));
+                s->step_now += 1;
+                left -= 1;
+                s->plan_hint = std::max<int64_t>(1, std::min<int64_t>(grown, s->since_build + 1) / 2);
+                s->since_build = 0;
+                s->plan = s->plan_hint;
+            } else {
+                const int64_t p = plan_steps(s, dyn);
+                s->plan = std::max<int64_t>(s->since_build + 1, std::min<int64_t>(p, 1 << 20));
+                if (p <= s->since_build) s->plan = s->since_build;  // rebuild before the next chunk
+                s->plan_hint = std::max<int64_t>(16, std::min<int64_t>(p, 1 << 20));
             }
         }
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipStreamSynchronize(s->st));
         s->steps_total += nsteps;
         return check_health(s);
     } catch (const HipError& e) {
@@ -692,12 +788,10 @@ int sim_set_state(sim* s, int32_t r, const double* x, const double* v, const dou
     try {
         upload_state(s, r, x, v, w, F, T, c_ij, c_s, n_contacts);
         set_dyn(s, r, le_offset, step);
-        launch_rebuild_decision(s->b, s->st, 1);
-        launch_rebuild(s->b, s->st, r);
-        if (!F) {
-            launch_pair_force(s->b, s->st, 0, (uint32_t)r);
-            launch_reduce_stress(s->b, s->st, 0, (uint32_t)r);
-        }
+        if (r == 0) s->step_now = step;
+        launch_rebuild(s->b, s->st, 0, (uint32_t)r);
+        s->since_build = 0;
+        if (!F) launch_pair_force(s->b, s->st, 0, 0, (uint32_t)r);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s->st));
         return check_health(s);
@@ -811,12 +905,14 @@ int sim_stats(sim* s, int32_t r, sim_stats_t* out) {
         auto d = d2h(s, s->b.dyn, (size_t)r, 1);
         auto sy = d2h(s, s->b.sys, 0, 1);
         float mo;
-        std::memcpy(&mo, &d[0].maxov_bits, sizeof mo);
+        std::memcpy(&mo, &d[0].maxov_last_bits, sizeof mo);
         out->max_overlap = (double)mo;
         out->rebuilds = (int64_t)sy[0].rebuilds;
         out->steps = s->steps_total;
         out->step = d[0].step;
         out->le_offset = d[0].s_le;
+        out->lanes = s->b.lanes;
+        out->pad = 0;
         return SIM_OK;
     } catch (const HipError& e) {
         return hip_fail(s, e);

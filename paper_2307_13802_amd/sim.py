@@ -41,14 +41,15 @@ class _Config(C.Structure):
                 ("xi_min", C.c_double), ("skin", C.c_double), ("le_offset0", C.c_double),
                 ("max_overlap", C.c_double), ("seed", C.c_uint64), ("step0", C.c_uint64),
                 ("precision", C.c_int32), ("flags", C.c_uint32), ("nlist_cap", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("lanes", C.c_uint32)]
 
 
 class _Stats(C.Structure):
     _fields_ = [("contacts_per_particle", C.c_double), ("sliding_fraction", C.c_double),
                 ("max_overlap", C.c_double), ("neighbours_per_particle", C.c_double),
                 ("interacting_per_particle", C.c_double), ("contacts", C.c_int64), ("rebuilds", C.c_int64),
-                ("steps", C.c_int64), ("step", C.c_uint64), ("le_offset", C.c_double)]
+                ("steps", C.c_int64), ("step", C.c_uint64), ("le_offset", C.c_double), ("lanes", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 class SimError(RuntimeError):
@@ -147,6 +148,7 @@ class Config:
     precision: int = FP64
     flags: int = 0
     nlist_cap: int = 0
+    lanes: int = 0
 
     def c(self, n) -> _Config:
         c = _Config()
@@ -159,7 +161,7 @@ class Config:
             setattr(c, f, float(getattr(self, f)))
         c.seed, c.step0 = int(self.seed), int(self.step0)
         c.precision, c.flags, c.nlist_cap = int(self.precision), int(self.flags), int(self.nlist_cap)
-        c.reserved = 0
+        c.lanes = int(self.lanes)
         return c
 
 

@@ -145,6 +145,36 @@ def test_step_trajectory_fp64(P):
             assert np.array_equal(sim.contacts()[0], orc.contacts()[0])
 
 
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
+def test_lanes_per_particle(P, lanes):
+    """Every split of the neighbour list over lanes gives the oracle's forces and exact springs."""
+    st = _state(n=1500, phi=0.55, seed=7)
+    for prec, tol, exact in ((P.FP64, TOL_F64, True), (P.MIXED, TOL_MIX, False)):
+        _say(f"case: lanes={lanes} precision={prec} N=1500 phi=0.55, 3 steps")
+        sim = P.Sim(_cfg(P, st, precision=prec, lanes=lanes), st["radii"], st["x"], st["v"], st["w"])
+        assert sim.stats()["lanes"] == lanes
+        orc = O.Oracle(O.Params(L=st["L"], **st["params"]), st["radii"], st["x"], st["v"], st["w"])
+        _compare_eval(P, sim, orc, tol, exact=exact)
+
+
+def test_planned_rebuilds_match_rebuild_every_step(P):
+    """Host-planned list builds (with device-side expiry halts) give bit-identical trajectories
+    to building the list at every step: no interacting pair is ever missing from a list."""
+    st = _state(n=500, phi=0.5, kT=1.0)
+    runs = []
+    for flags in (0, P.REBUILD_EACH_STEP):
+        _say(f"case: 400 steps N=500 kT=1 flags={flags:#x}")
+        sim = P.Sim(_cfg(P, st, flags=flags, lanes=1), st["radii"], st["x"], st["v"], st["w"])
+        for _ in range(4):
+            sim.step(100)
+        runs.append((sim.get_state(), sim.stats()))
+    (a, sa), (b, sb) = runs
+    _say(f"  rebuilds planned {sa['rebuilds']} vs every step {sb['rebuilds']}")
+    assert sa["rebuilds"] < sb["rebuilds"]
+    for key in ("x", "v", "w", "F", "T"):
+        assert np.array_equal(a[key], b[key]), key
+
+
 def test_mixed_precision_create(P):
     _say("case: create N=500 mixed precision")
     st = _state()
@@ -173,7 +203,7 @@ def test_ragged_and_tiny_systems(P):
 def test_batched_replicas_match_single(P):
     """Replicas of uneven size in one handle: each bit-identical to the same replica run alone."""
     sts = [_state(n=n, phi=phi, seed=s) for n, phi, s in ((300, 0.45, 1), (777, 0.55, 2), (512, 0.5, 3))]
-    cfgs = [_cfg(P, st, seed=10 + k) for k, st in enumerate(sts)]
+    cfgs = [_cfg(P, st, seed=10 + k, lanes=4) for k, st in enumerate(sts)]
     _say("case: 3 replicas batched vs alone, 30 steps")
     multi = P.Sim(cfgs, [s["radii"] for s in sts], [s["x"] for s in sts], [s["v"] for s in sts],
                   [s["w"] for s in sts])
@@ -189,7 +219,7 @@ def test_batched_replicas_match_single(P):
 
 def test_deterministic_and_restart(P):
     st = _state(n=600, phi=0.55, seed=5)
-    cfg = _cfg(P, st)
+    cfg = _cfg(P, st, lanes=2)
     _say("case: determinism and restart, 40 steps")
     s1 = P.Sim(cfg, st["radii"], st["x"], st["v"], st["w"])
     s2 = P.Sim(cfg, st["radii"], st["x"], st["v"], st["w"])
