@@ -486,7 +486,7 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         b.ct_n = s->alloc<uint32_t>(np * 2);
         for (int a = 0; a < 7; ++a) b.alt4[a] = s->alloc<double4>(np);
         b.alt_id = s->alloc<uint32_t>(np);
-        b.partial = s->alloc<double>(np / kTile * 27);
+        b.partial = s->alloc<double>(np / kTile * 8 * 27);  // up to 8 lanes per particle
         b.ring = s->alloc<double>((size_t)n_replicas * kRing * 27);
         b.last = s->alloc<double>((size_t)n_replicas * 27);
         b.blk_rep = s->alloc<uint32_t>(blk_rep.size());
