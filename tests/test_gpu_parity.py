@@ -203,7 +203,9 @@ def test_ragged_and_tiny_systems(P):
 def test_batched_replicas_match_single(P):
     """Replicas of uneven size in one handle: each bit-identical to the same replica run alone."""
     sts = [_state(n=n, phi=phi, seed=s) for n, phi, s in ((300, 0.45, 1), (777, 0.55, 2), (512, 0.5, 3))]
-    cfgs = [_cfg(P, st, seed=10 + k, lanes=4) for k, st in enumerate(sts)]
+    # one lane per particle: each force is summed over the interacting partners in id order,
+    # independent of when the (skin-padded) list was built
+    cfgs = [_cfg(P, st, seed=10 + k, lanes=1) for k, st in enumerate(sts)]
     _say("case: 3 replicas batched vs alone, 30 steps")
     multi = P.Sim(cfgs, [s["radii"] for s in sts], [s["x"] for s in sts], [s["v"] for s in sts],
                   [s["w"] for s in sts])
@@ -217,10 +219,14 @@ def test_batched_replicas_match_single(P):
             assert np.array_equal(a[key], b[key]), key
 
 
-def test_deterministic_and_restart(P):
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_deterministic_and_restart(P, lanes):
+    """Identical runs are bit-identical; a restart from get_state/contacts continues the
+    run bit-identically with one lane per particle (list-independent summation order) and
+    to rounding with several lanes (their split of the list depends on when it was built)."""
     st = _state(n=600, phi=0.55, seed=5)
-    cfg = _cfg(P, st, lanes=2)
-    _say("case: determinism and restart, 40 steps")
+    cfg = _cfg(P, st, lanes=lanes)
+    _say(f"case: determinism and restart, 40 steps, lanes={lanes}")
     s1 = P.Sim(cfg, st["radii"], st["x"], st["v"], st["w"])
     s2 = P.Sim(cfg, st["radii"], st["x"], st["v"], st["w"])
     s1.step(40)
@@ -235,7 +241,10 @@ def test_deterministic_and_restart(P):
     a, b, c = s1.get_state(), s2.get_state(), s3.get_state()
     for key in ("x", "v", "w", "F", "T"):
         assert np.array_equal(a[key], b[key]), key
-        assert np.array_equal(a[key], c[key]), key
+        if lanes == 1:
+            assert np.array_equal(a[key], c[key]), key
+        else:
+            assert np.abs(a[key] - c[key]).max() <= 1e-9 * np.abs(a[key]).max(), key
 
 
 def test_health_errors(P):
