@@ -43,25 +43,29 @@ struct RepParams {
     uint64_t seed;
 };
 
-// Per-replica values the device updates every step.
+// Per-replica values the device updates every step.  Step-dependent values
+// are double-buffered by the parity q of the step: a step with parity q reads
+// slot 1 - q (the previous step) and writes slot q, so no kernel reads a value
+// another block of the same kernel may be writing.
 struct RepDyn {
-    double s_le;              // Lees-Edwards offset of the last force evaluation
-    double dmax;              // bound on the non-affine displacement since the last build
-    double t_since;           // time since the last build
-    uint64_t step;            // step counter of the last force evaluation
-    uint32_t stepmax_bits;    // float bits: largest displacement in the current step
-    uint32_t maxov_bits;      // float bits: largest overlap in the current evaluation
+    double s_slot[2];         // Lees-Edwards offset of the evaluation with that parity
+    uint64_t step_slot[2];    // step counter of that evaluation
+    double dmax_slot[2];      // bound on the non-affine displacement since the last build
+    double t_slot[2];         // time since the last build
+    uint32_t stepmax_bits[2]; // float bits: largest displacement of the step with that parity
+    uint32_t maxov_bits[2];   // float bits: largest overlap of that evaluation
+    uint32_t pend[2];         // stress partials of that parity await reduction: 1 record, 2 do not
     uint32_t health;          // H_* bits, sticky until read by the host
     uint32_t ring_head;       // number of series entries written (mod ring size)
-    uint32_t blk_done;        // pair-kernel blocks of this replica finished in the current launch
-    uint32_t maxov_last_bits; // float bits: largest overlap of the last completed evaluation
+    uint32_t maxov_last_bits; // float bits: largest overlap of the last reduced evaluation
+    uint32_t pad;
     double stress_sum[27];    // running sum for means
     uint64_t stress_count;
 };
 
 struct SysDyn {
     uint32_t halted;          // 1: some list may have expired; the remaining launches of the chunk do nothing
-    uint32_t int_done;        // integrate blocks finished in the current launch
+    uint32_t pad;
     uint64_t rebuilds;
 };
 
@@ -106,8 +110,9 @@ struct Bufs {
     double4* alt4[7];
     uint32_t* alt_id;
 
-    // stress: per pair-kernel block partial sums, ring of per-step values
-    double* partial;      // [blk][27]
+    // stress: per pair-kernel block partial sums (two parities), ring of per-step values
+    double* partial;      // [parity][blk][27]
+    uint32_t nblk_max;    // pair-kernel blocks at 8 lanes per particle (partials per parity)
     double* ring;         // [rep][kRing][27]
     double* last;         // [rep][27]
     int lanes;            // pair kernel: lanes per particle (1, 2, 4, 8)
@@ -121,18 +126,23 @@ struct Bufs {
 constexpr int kRing = 8192;
 constexpr int kCtCap = 16;   // contacts per particle carried across a rebuild
 
-// kernel launchers (susp_kernels.hip)
-// one time step without a list rebuild: kick 1 + drift + wrap + list-expiry test, then forces + kick 2
-void launch_integrate(const Bufs& b, hipStream_t st);
-// kick: apply kick 2; advance: evaluate at the next step counter and offset (a time step) rather
-// than at the current ones (creation / state injection); only_rep: one replica or 0xFFFFFFFF
-void launch_pair_force(const Bufs& b, hipStream_t st, int kick, int advance, uint32_t only_rep);
-// Rebuild of cells and neighbour lists from the current positions.  in_step: called between kick 1
-// and the force evaluation of a step (the offset of that step is used).  ct_input_rep:
-// 0xFFFFFFFF = carry contact history from the current lists; 0xFFFFFFFE = every replica takes
-// the host-written compact table; else that replica does.
-void launch_rebuild(const Bufs& b, hipStream_t st, int in_step, uint32_t ct_input_rep);
-void launch_diag(const Bufs& b, hipStream_t st, uint32_t rep, uint32_t n, uint32_t* out_ij, double* out_s,
+// kernel launchers (susp_kernels.hip).  q is the parity of the step being taken
+// (or, for an evaluation without a step, of the current step).
+// kick 1 + drift + wrap of a step; also reduces the stress of the previous step
+void launch_integrate(const Bufs& b, hipStream_t st, int q);
+// forces of a step (advance = 1: next step counter and offset, list-expiry test,
+// kick 2 if kick) or of the current state (advance = 0); only_rep: one replica
+// or 0xFFFFFFFF
+void launch_pair_force(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep);
+// reduces pending stress partials of parity q
+void launch_finalize(const Bufs& b, hipStream_t st, int q);
+// Rebuild of cells and neighbour lists from the current positions; q is the
+// parity of the next force evaluation.  in_step: called between kick 1 and the
+// force evaluation of a step.  ct_input_rep: 0xFFFFFFFF = carry contact
+// history from the current lists; 0xFFFFFFFE = every replica takes the
+// host-written compact table; else that replica does.
+void launch_rebuild(const Bufs& b, hipStream_t st, int q, int in_step, uint32_t ct_input_rep);
+void launch_diag(const Bufs& b, hipStream_t st, int p, uint32_t rep, uint32_t n, uint32_t* out_ij, double* out_s,
                  int32_t* out_sl, uint32_t* count, uint32_t cap, int mode);
 
 }  // namespace susp

@@ -129,22 +129,6 @@ __device__ __forceinline__ void block_sum27(const double* acc, double* out) {
     __syncthreads();
 }
 
-// true in every thread of the block that finished last among `total` blocks
-// counted on *ctr (which it resets); publishes this block's global writes
-__device__ __forceinline__ bool last_block(uint32_t* ctr, uint32_t total) {
-    __shared__ int last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t prev = atomicAdd(ctr, 1u);
-        last = (prev == total - 1);
-        if (last) *ctr = 0u;
-    }
-    __syncthreads();
-    if (last) __threadfence();
-    return last != 0;
-}
-
 // block-wide max of a non-negative float, then one atomic per block
 __device__ __forceinline__ void block_atomic_max(float v, uint32_t* target) {
     __shared__ float red[16];
@@ -161,28 +145,73 @@ __device__ __forceinline__ void block_atomic_max(float v, uint32_t* target) {
     __syncthreads();
 }
 
+// Fixed-order reduction of the stress partials of replica r with parity x
+// (one block); pushes the per-step value to the series when it was a step.
+__device__ void finalize_replica(const Bufs& b, uint32_t r, int x) {
+    RepDyn& D = b.dyn[r];
+    const uint32_t mode = D.pend[x];
+    if (mode == 0u) return;  // uniform across the block
+    const RepParams& P = b.reps[r];
+    const uint32_t blk0 = P.blk_begin * (uint32_t)b.lanes, nblk = P.nblk * (uint32_t)b.lanes;
+    const double* part = b.partial + (size_t)x * b.nblk_max * 27;
+    double acc[27];
+#pragma unroll
+    for (int c = 0; c < 27; ++c) acc[c] = 0.0;
+    for (uint32_t k = threadIdx.x; k < nblk; k += blockDim.x) {
+#pragma unroll
+        for (int c = 0; c < 27; ++c) acc[c] += part[(size_t)(blk0 + k) * 27 + c];
+    }
+    __shared__ double tot[27];
+    block_sum27(acc, tot);
+    if (threadIdx.x < 27) {
+        const int c = threadIdx.x;
+        b.last[r * 27 + c] = tot[c];
+        if (mode == 1u) {
+            b.ring[((size_t)r * kRing + (D.ring_head % kRing)) * 27 + c] = tot[c];
+            D.stress_sum[c] += tot[c];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if ((double)__uint_as_float(D.maxov_bits[x]) > P.max_overlap) D.health |= H_OVERLAP;
+        D.maxov_last_bits = D.maxov_bits[x];
+        D.maxov_bits[x] = 0u;
+        if (mode == 1u) {
+            D.ring_head += 1;
+            D.stress_count += 1;
+        }
+        D.pend[x] = 0u;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_finalize(Bufs b, int x) {
+    finalize_replica(b, blockIdx.x, x);
+}
+
 // ---------------------------------------------------------------------------
-// Kick 1, drift and wrap (velocity-Verlet, Sec. II; sheared box, Sec. II.E).
-// Also bounds this step's non-affine displacement |dx - U^inf dt| for the
-// neighbour-list validity test.
+// Kick 1, drift and wrap of a step with parity q (velocity-Verlet, Sec. II;
+// sheared box, Sec. II.E).  Also bounds the step's non-affine displacement
+// |dx - U^inf dt| for the list-expiry test, and (blocks r < replicas) reduces
+// the stress of the previous step.
 // ---------------------------------------------------------------------------
 template <bool MIX>
-__global__ __launch_bounds__(256) void k_integrate(Bufs b) {
-    if (b.sys->halted) return;  // uniform: set only by the last block of an earlier launch
-    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t r = b.blk_rep[q / kTile];
+__global__ __launch_bounds__(256) void k_integrate(Bufs b, int q) {
+    if (b.sys->halted) return;  // uniform: set by an earlier launch
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t r = b.blk_rep[i / kTile];
     const RepParams& P = b.reps[r];
+    RepDyn& D = b.dyn[r];
     float disp = 0.0f;
-    if (q - P.p_begin < P.n) {
-        double4 x = b.pos[q];
-        double4 v = b.vf[q];
-        double4 w = b.wf[q];
+    if (i - P.p_begin < P.n) {
+        double4 x = b.pos[i];
+        double4 v = b.vf[i];
+        double4 w = b.wf[i];
         double Fx, Fy, Fz, Tx, Ty, Tz;
         if (MIX) {
-            const float4 f = ((const float4*)b.F)[q], t = ((const float4*)b.T)[q];
+            const float4 f = ((const float4*)b.F)[i], t = ((const float4*)b.T)[i];
             Fx = f.x; Fy = f.y; Fz = f.z; Tx = t.x; Ty = t.y; Tz = t.z;
         } else {
-            const double4 f = ((const double4*)b.F)[q], t = ((const double4*)b.T)[q];
+            const double4 f = ((const double4*)b.F)[i], t = ((const double4*)b.T)[i];
             Fx = f.x; Fy = f.y; Fz = f.z; Tx = t.x; Ty = t.y; Tz = t.z;
         }
         const double a = x.w;
@@ -197,7 +226,7 @@ __global__ __launch_bounds__(256) void k_integrate(Bufs b) {
             x.x += P.dt * v.x;
             x.y += P.dt * v.y;
             x.z += P.dt * v.z;
-            const double s = next_offset(P, b.dyn[r].s_le);
+            const double s = next_offset(P, D.s_slot[1 - q]);
             const double Lx = P.L[0], Ly = P.L[1], Lz = P.L[2];
             if (x.y >= Ly) {
                 x.y -= Ly; x.x -= s; v.x -= P.gdLy;
@@ -214,37 +243,21 @@ __global__ __launch_bounds__(256) void k_integrate(Bufs b) {
             const double ux = P.gd * (yold - 0.5 * Ly) + 0.5 * P.gd * P.dt * vdy;
             const double ex = P.dt * (vdx - ux), ey = P.dt * vdy, ez = P.dt * vdz;
             disp = (float)(sqrt(ex * ex + ey * ey + ez * ez) * (1.0 + 1e-6)) + 1e-30f;
-            b.pos[q] = x;
+            b.pos[i] = x;
         }
-        b.vh[q] = v;
-        b.wh[q] = w;
+        b.vh[i] = v;
+        b.wh[i] = w;
         if (MIX) {
-            b.vsh[q] = make_float4((float)v.x, (float)v.y, (float)v.z, 0.0f);
-            b.wsh[q] = make_float4((float)w.x, (float)w.y, (float)w.z, 0.0f);
+            b.vsh[i] = make_float4((float)v.x, (float)v.y, (float)v.z, 0.0f);
+            b.wsh[i] = make_float4((float)w.x, (float)w.y, (float)w.z, 0.0f);
         }
     }
-    block_atomic_max(disp, &b.dyn[r].stepmax_bits);
-    if (!last_block(&b.sys->int_done, gridDim.x)) return;
-    // all particles have moved: fold this step into the displacement bound and test
-    // whether every list still holds all pairs within the interaction range
-    __shared__ int expired;
-    if (threadIdx.x == 0) expired = 0;
-    __syncthreads();
-    for (uint32_t rr = threadIdx.x; rr < b.nrep; rr += blockDim.x) {
-        const RepParams& Q = b.reps[rr];
-        RepDyn& D = b.dyn[rr];
-        D.dmax += (double)as_posf(D.stepmax_bits);
-        D.t_since += Q.dt;
-        D.stepmax_bits = 0u;
-        const bool ex = 2.0 * D.dmax + fabs(Q.gd) * D.t_since * (Q.rc_max + 2.0 * Q.skin) > Q.skin;
-        if (ex || (Q.flags & F_REBUILD_EACH_STEP)) expired = 1;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0 && expired) b.sys->halted = 1u;
+    block_atomic_max(disp, &D.stepmax_bits[q]);
+    if (blockIdx.x < b.nrep) finalize_replica(b, blockIdx.x, 1 - q);
 }
 
 // ---------------------------------------------------------------------------
-// List validity (the expiry test of k_integrate).  A pair outside the list at the last build (|r| > r_c +
+// List validity (the expiry test of the pair kernel).  A pair outside the list at the last build (|r| > r_c +
 // skin) can have come within r_c only if 2 D + |gammadot| t (r_c + 4 D) >
 // skin, where D bounds every particle's non-affine displacement since the
 // build and t is the time since the build (the affine part of the relative
@@ -465,7 +478,7 @@ __global__ __launch_bounds__(256) void k_rb_copyback(Bufs b) {
 // Verlet list: every j with |r| <= (a_i + a_j)(1 + xi_cut/2) + skin, sorted by
 // partner id (so force sums do not depend on the cell layout), then the
 // carried contact history is attached to its list entry.
-__global__ __launch_bounds__(256) void k_rb_nlist(Bufs b, int in_step) {
+__global__ __launch_bounds__(256) void k_rb_nlist(Bufs b, int q, int in_step) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t r = b.blk_rep[i / kTile];
     const RepParams& P = b.reps[r];
@@ -477,7 +490,8 @@ __global__ __launch_bounds__(256) void k_rb_nlist(Bufs b, int in_step) {
         return;
     }
     const double4 pi = b.pos[i];
-    const double s_le = in_step ? next_offset(P, b.dyn[r].s_le) : b.dyn[r].s_le;
+    const double s_base = b.dyn[r].s_slot[1 - q];
+    const double s_le = in_step ? next_offset(P, s_base) : s_base;
     const double amax = P.rc_max / (2.0 * P.c1);
     const double rli = (pi.w + amax) * P.c1 + P.skin;           // largest list radius of i
     const double margin = rli * (1.0 + 1e-12) + 1e-12 * P.L[0];
@@ -555,12 +569,13 @@ __global__ __launch_bounds__(256) void k_rb_nlist(Bufs b, int in_step) {
     b.smask[i] = sm;
 }
 
-// after a build every list holds all pairs within range plus the full skin
-__global__ void k_rb_reset(Bufs b) {
+// after a build every list holds all pairs within range plus the full skin;
+// q is the parity of the next force evaluation
+__global__ void k_rb_reset(Bufs b, int q) {
     for (uint32_t r = threadIdx.x; r < b.nrep; r += blockDim.x) {
-        b.dyn[r].dmax = 0.0;
-        b.dyn[r].t_since = 0.0;
-        b.dyn[r].stepmax_bits = 0u;
+        b.dyn[r].dmax_slot[1 - q] = 0.0;
+        b.dyn[r].t_slot[1 - q] = 0.0;
+        b.dyn[r].stepmax_bits[q] = 0u;
     }
     if (threadIdx.x == 0) {
         b.sys->halted = 0u;
@@ -568,13 +583,6 @@ __global__ void k_rb_reset(Bufs b) {
     }
 }
 
-// ---------------------------------------------------------------------------
-// Pair forces (Sec. II.A-II.D), one-body terms (Sec. II.B-II.C), kick 2.
-// One lane per particle i walks its Verlet list.  Every pair is evaluated in
-// canonical orientation (lower id = "a", higher id = "b", r = x_a - x_b), so
-// both sides compute bit-identical pair terms and the pair forces are
-// exactly antisymmetric; the stress of a pair is added on the lower-id side.
-// ---------------------------------------------------------------------------
 template <class R> struct Acc;
 template <> struct Acc<double> {
     double v[3] = {0.0, 0.0, 0.0};
@@ -602,11 +610,22 @@ template <class R> __device__ __forceinline__ R rsqrt_(R x);
 template <> __device__ __forceinline__ double rsqrt_<double>(double x) { return sqrt(x); }
 template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return __fsqrt_rn(x); }
 
+// ---------------------------------------------------------------------------
+// Forces of a step with parity q (Sec. II.A-II.D pair terms, Sec. II.B-II.C
+// one-body terms), kick 2.  LN consecutive lanes share one particle i and
+// split its work items: the list entries (pairs) and two one-body items (drag
+// + noise force, drag + noise torque).  Every item draws one Philox block and
+// three normals through the same code, so lanes doing pair and one-body items
+// in the same iteration do not diverge on the costly part.  Pairs are
+// evaluated in canonical orientation (lower id = "a", higher id = "b",
+// r = x_a - x_b), so both sides compute bit-identical pair terms and the pair
+// forces are exactly antisymmetric; the stress of a pair is added on the
+// lower-id side.
+// ---------------------------------------------------------------------------
 template <bool MIX, int LN>
-__global__ __launch_bounds__(256) void k_pair(Bufs b, int kick, int advance, uint32_t only_rep) {
+__global__ __launch_bounds__(256) void k_pair(Bufs b, int q, int kick, int advance, uint32_t only_rep) {
     using R = typename std::conditional<MIX, float, double>::type;
-    if (b.sys->halted) return;  // a list may have expired: the host rebuilds and repeats this launch
-    // LN consecutive lanes share one particle and split its list (entries e = sub, sub + LN, ...)
+    if (b.sys->halted) return;  // the host rebuilds the lists and repeats this launch
     const uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / LN;
     const uint32_t sub = threadIdx.x % LN;
     const uint32_t r = b.blk_rep[i / kTile];
@@ -614,17 +633,47 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int kick, int advance, uin
     const RepParams& P = b.reps[r];
     RepDyn& D = b.dyn[r];
     const uint32_t npad = b.npad;
-    const bool valid = (i - P.p_begin) < P.n;
+
+    double s_le;
+    uint64_t step;
+    if (advance) {
+        // list-expiry test (the validity bound in the comment above), for every replica:
+        // one expired list halts the whole launch sequence until the host rebuilt
+        bool expired = false;
+        for (uint32_t rr = 0; rr < b.nrep; ++rr) {
+            const RepParams& Q = b.reps[rr];
+            const RepDyn& E = b.dyn[rr];
+            const double dm = E.dmax_slot[1 - q] + (double)as_posf(E.stepmax_bits[q]);
+            const double tt = E.t_slot[1 - q] + Q.dt;
+            expired |= 2.0 * dm + fabs(Q.gd) * tt * (Q.rc_max + 2.0 * Q.skin) > Q.skin;
+        }
+        if (expired) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) b.sys->halted = 1u;
+            return;
+        }
+        s_le = next_offset(P, D.s_slot[1 - q]);
+        step = D.step_slot[1 - q] + 1;
+        if (blockIdx.x == P.blk_begin * LN && threadIdx.x == 0) {
+            D.s_slot[q] = s_le;
+            D.step_slot[q] = step;
+            D.dmax_slot[q] = D.dmax_slot[1 - q] + (double)as_posf(D.stepmax_bits[q]);
+            D.t_slot[q] = D.t_slot[1 - q] + P.dt;
+            D.stepmax_bits[1 - q] = 0u;  // for the next step's integrate
+            D.pend[q] = 1u;
+        }
+    } else {
+        s_le = D.s_slot[q];
+        step = D.step_slot[q];
+        if (blockIdx.x == P.blk_begin * LN && threadIdx.x == 0) D.pend[q] = 2u;
+    }
 
     double acc[27];  // stress: contact, lubrication, Brownian; lower-id side of each pair
 #pragma unroll
     for (int t = 0; t < 27; ++t) acc[t] = 0.0;
     float maxov = 0.0f;
     bool bad = false;
-    const double s_le = advance ? next_offset(P, D.s_le) : D.s_le;
-    const uint64_t step = advance ? D.step + 1 : D.step;
 
-    if (valid) {
+    if (i - P.p_begin < P.n) {
         const double4 pi = b.pos[i];
         const uint32_t idi = b.id[i];
         const uint32_t k0 = (uint32_t)P.seed, k1 = (uint32_t)(P.seed >> 32);
@@ -650,45 +699,79 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int kick, int advance, uin
 
         Acc<R> F, T;
         const uint32_t cnt = b.ncnt[i];
+        const uint32_t items = cnt + ((P.flags & F_NO_ONEBODY) ? 0u : 2u);
         const uint64_t cm_old = b.cmask[i];
         uint64_t cm = 0ull, sm = 0ull;
 
-        for (uint32_t e = sub; e < cnt; e += LN) {
-            const uint32_t j = b.nbr[e * npad + i];
-            const double4 pj = b.pos[j];
-            const uint32_t idj = b.id[j];
-            const bool lo = idi < idj;  // this lane holds the lower id
-            double dx, dy, dz;
-            const int ky = lo ? min_image(P, s_le, pi, pj, dx, dy, dz) : min_image(P, s_le, pj, pi, dx, dy, dz);
-            const double d2 = (dx * dx + dy * dy) + dz * dz;
-            const double sa = pi.w + pj.w;
-            const double rc = sa * c1;
-            if (!(d2 <= rc * rc)) continue;
-
-            // geometry (FP64): distance, unit normal a <- b, gap
-            const double dist = sqrt(d2);
-            const double h = dist - sa;
-            R n[3];
-            if (MIX) {
-                const float inv = 1.0f / (float)dist;
-                n[0] = (float)dx * inv; n[1] = (float)dy * inv; n[2] = (float)dz * inv;
-            } else {
-                n[0] = (R)(dx / dist); n[1] = (R)(dy / dist); n[2] = (R)(dz / dist);
+        for (uint32_t e = sub; e < items; e += LN) {
+            const bool pair = e < cnt;
+            // ---- geometry of a pair item (FP64), or nothing for a one-body item
+            uint32_t j = 0, idj = 0;
+            double4 pj = make_double4(0.0, 0.0, 0.0, 0.0);
+            bool lo = true;
+            double dx = 0.0, dy = 0.0, dz = 0.0, h = 0.0;
+            int ky = 0;
+            R n[3] = {(R)0, (R)0, (R)0}, XA = (R)0, YA = (R)0;
+            if (pair) {
+                j = b.nbr[e * npad + i];
+                pj = b.pos[j];
+                idj = b.id[j];
+                lo = idi < idj;  // this lane holds the lower id
+                ky = lo ? min_image(P, s_le, pi, pj, dx, dy, dz) : min_image(P, s_le, pj, pi, dx, dy, dz);
+                const double d2 = (dx * dx + dy * dy) + dz * dz;
+                const double sa = pi.w + pj.w;
+                const double rc = sa * c1;
+                if (!(d2 <= rc * rc)) continue;
+                const double dist = sqrt(d2);
+                h = dist - sa;
+                if (MIX) {
+                    const float inv = 1.0f / (float)dist;
+                    n[0] = (float)dx * inv; n[1] = (float)dy * inv; n[2] = (float)dz * inv;
+                } else {
+                    n[0] = (R)(dx / dist); n[1] = (R)(dy / dist); n[2] = (R)(dz / dist);
+                }
+                const R aj = (R)pj.w;
+                const R aa = lo ? ai : aj, ab = lo ? aj : ai;
+                const R xi = (R)((2.0 * h) / sa);
+                const R xie = xi < xi_min ? xi_min : xi;
+                // resistance scalars X^A_11, Y^A_11 (Sec. II.B) in the symmetric form
+                const R pab = aa * ab, qab = aa * aa + ab * ab;
+                const R sR = aa + ab;
+                const R pre = eta6pi / (sR * sR * sR);
+                const R lg = -rlog<R>(xie);
+                XA = pre * ((R)2 * pab * pab / xie + pab * (qab + (R)7 * pab) / (R)5 * lg);
+                YA = pre * ((R)4 * pab * ((R)2 * qab + pab) / (R)15 * lg);
             }
-            const R aj = (R)pj.w;
-            const R aa = lo ? ai : aj, ab = lo ? aj : ai;  // canonical radii
-            const R xi = (R)((2.0 * h) / sa);
-            const R xie = xi < xi_min ? xi_min : xi;
+            // ---- one Philox block -> three normals (shared by both kinds of item)
+            R th[3] = {(R)0, (R)0, (R)0};
+            const bool noise = pair ? do_br : true;
+            if (noise) {
+                const uint32_t ida = pair ? (lo ? idi : idj) : idi;
+                const uint32_t idb = pair ? (lo ? idj : idi) : 0xFFFFFFFFu;
+                const uint32_t stream = pair ? 0u : (e - cnt == 0 ? 2u : 3u);
+                const uint4 w = philox10(ctr_lo, ida, idb, ctr_hi | stream, k0, k1);
+                normals3(w, th);
+            }
+            if (!pair) {
+                // eq. (force_drag) + (force_brownian_drag), or (torque_drag) + (torque_brownian_drag)
+                const double a = pi.w;
+                if (e - cnt == 0) {
+                    const R zeta = (R)(6.0 * kPi * P.eta * a);
+                    const R sz = rsqrt_<R>(zeta);
+                    const R uinf[3] = {(R)(P.gd * (pi.y - 0.5 * P.L[1])), (R)0, (R)0};
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) F.add(d, zeta * (uinf[d] - vi[d]) + bamp * sz * th[d]);
+                } else {
+                    const R zr = (R)(8.0 * kPi * P.eta * a * a * a);
+                    const R szr = rsqrt_<R>(zr);
+                    const R oinf[3] = {(R)0, (R)0, (R)(-0.5 * P.gd)};
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) T.add(d, zr * (oinf[d] - wi[d]) + bamp * szr * th[d]);
+                }
+                continue;
+            }
 
-            // resistance scalars X^A_11, Y^A_11 (Sec. II.B) in the symmetric form
-            const R pab = aa * ab, qab = aa * aa + ab * ab;
-            const R sR = aa + ab;
-            const R pre = eta6pi / (sR * sR * sR);
-            const R lg = -rlog<R>(xie);
-            const R XA = pre * ((R)2 * pab * pab / xie + pab * (qab + (R)7 * pab) / (R)5 * lg);
-            const R YA = pre * ((R)4 * pab * ((R)2 * qab + pab) / (R)15 * lg);
-
-            // velocities in canonical orientation; the image of b moves with +k_y gammadot Ly
+            // ---- pair item: velocities in canonical orientation; b's image moves with +k_y gammadot Ly
             R va[3], vb[3], vj[3];
             const R shiftv = (R)((double)ky * P.gdLy);
             if (MIX) {
@@ -714,10 +797,6 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int kick, int advance, uin
             }
             if (do_br) {
                 // eq. (force_brownian_lub): sqrt(2kT/dt) (sqrt(X^A) N + sqrt(Y^A) T) theta
-                const uint32_t ida = lo ? idi : idj, idb = lo ? idj : idi;
-                const uint4 w = philox10(ctr_lo, ida, idb, ctr_hi, k0, k1);
-                R th[3];
-                normals3(w, th);
                 const R tn = (n[0] * th[0] + n[1] * th[1]) + n[2] * th[2];
                 const R sx = rsqrt_<R>(XA), sy = rsqrt_<R>(YA);
 #pragma unroll
@@ -725,6 +804,8 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int kick, int advance, uin
             }
             if (h < 0.0 && do_ct) {
                 // eq. (force_contact), (torque_contact); the spring s lives in canonical orientation
+                const R aj = (R)pj.w;
+                const R aa = lo ? ai : aj, ab = lo ? aj : ai;
                 const R delta = (R)(-h);
                 if ((float)(-h) > maxov) maxov = (float)(-h);
                 R s[3] = {(R)0, (R)0, (R)0};
@@ -835,25 +916,6 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int kick, int advance, uin
         }
 
         if (sub == 0) {
-            // one-body terms: eq. (force_drag), (torque_drag), (force_brownian_drag), (torque_brownian_drag)
-            if (!(P.flags & F_NO_ONEBODY)) {
-                const double a = pi.w;
-                const R zeta = (R)(6.0 * kPi * P.eta * a);
-                const R zr = (R)(8.0 * kPi * P.eta * a * a * a);
-                const R uinf[3] = {(R)(P.gd * (pi.y - 0.5 * P.L[1])), (R)0, (R)0};
-                const R oinf[3] = {(R)0, (R)0, (R)(-0.5 * P.gd)};
-                const uint4 wf = philox10(ctr_lo, idi, 0xFFFFFFFFu, ctr_hi | 2u, k0, k1);
-                const uint4 wt = philox10(ctr_lo, idi, 0xFFFFFFFFu, ctr_hi | 3u, k0, k1);
-                R psi[3], phi[3];
-                normals3(wf, psi);
-                normals3(wt, phi);
-                const R sz = rsqrt_<R>(zeta), szr = rsqrt_<R>(zr);
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    Ft[d] += (double)(zeta * (uinf[d] - vi[d]) + bamp * sz * psi[d]);
-                    Tt[d] += (double)(zr * (oinf[d] - wi[d]) + bamp * szr * phi[d]);
-                }
-            }
             bad = !(isfinite(Ft[0]) && isfinite(Ft[1]) && isfinite(Ft[2]) && isfinite(Tt[0]) && isfinite(Tt[1]) &&
                     isfinite(Tt[2]));
             b.cmask[i] = cm;
@@ -880,50 +942,20 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int kick, int advance, uin
         }
     }
 
-    // health: non-finite forces, largest overlap
+    // health: non-finite forces, largest overlap (relaxed atomics; read after the launch)
     if (bad) atomicOr(&D.health, H_NAN);
-    block_atomic_max(maxov, &D.maxov_bits);
+    block_atomic_max(maxov, &D.maxov_bits[q]);
 
-    // block partial of the 27 stress sums, fixed order
+    // block partial of the 27 stress sums, fixed order; reduced by a later launch
     __shared__ double tot[27];
     block_sum27(acc, tot);
-    if (threadIdx.x < 27) b.partial[(size_t)blockIdx.x * 27 + threadIdx.x] = tot[threadIdx.x];
-    const uint32_t blk0 = P.blk_begin * LN, nblk = P.nblk * LN;
-    if (!last_block(&D.blk_done, nblk)) return;
-
-    // last block of the replica: fixed-order sum of all its partials
-#pragma unroll
-    for (int c = 0; c < 27; ++c) acc[c] = 0.0;
-    for (uint32_t k = threadIdx.x; k < nblk; k += blockDim.x) {
-#pragma unroll
-        for (int c = 0; c < 27; ++c) acc[c] += b.partial[(size_t)(blk0 + k) * 27 + c];
-    }
-    block_sum27(acc, tot);
-    if (threadIdx.x < 27) {
-        const int c = threadIdx.x;
-        b.last[r * 27 + c] = tot[c];
-        if (advance) {
-            b.ring[((size_t)r * kRing + (D.ring_head % kRing)) * 27 + c] = tot[c];
-            D.stress_sum[c] += tot[c];
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if ((double)__uint_as_float(D.maxov_bits) > P.max_overlap) D.health |= H_OVERLAP;
-        D.maxov_last_bits = D.maxov_bits;
-        D.maxov_bits = 0u;
-        if (advance) {
-            D.ring_head += 1;
-            D.stress_count += 1;
-            D.s_le = s_le;
-            D.step = step;
-        }
-    }
+    if (threadIdx.x < 27)
+        b.partial[((size_t)q * b.nblk_max + blockIdx.x) * 27 + threadIdx.x] = tot[threadIdx.x];
 }
 
 // diagnostics: mode 0 = interaction set, 1 = Verlet list, 2 = contacts (with springs)
-__global__ void k_diag(Bufs b, uint32_t rep, uint32_t* out_ij, double* out_s, int32_t* out_sl, uint32_t* count,
-                       uint32_t cap, int mode) {
+__global__ void k_diag(Bufs b, int p, uint32_t rep, uint32_t* out_ij, double* out_s, int32_t* out_sl,
+                       uint32_t* count, uint32_t cap, int mode) {
     const RepParams& P = b.reps[rep];
     const uint32_t i = P.p_begin + blockIdx.x * blockDim.x + threadIdx.x;
     if (i - P.p_begin >= P.n) return;
@@ -931,7 +963,7 @@ __global__ void k_diag(Bufs b, uint32_t rep, uint32_t* out_ij, double* out_s, in
     const uint32_t idi = b.id[i];
     const uint32_t cnt = b.ncnt[i];
     const uint64_t cm = b.cmask[i], sm = b.smask[i];
-    const double s_le = b.dyn[rep].s_le;
+    const double s_le = b.dyn[rep].s_slot[p];
     for (uint32_t e = 0; e < cnt; ++e) {
         const uint32_t j = b.nbr[e * b.npad + i];
         const uint32_t idj = b.id[j];
@@ -968,12 +1000,16 @@ __global__ void k_diag(Bufs b, uint32_t rep, uint32_t* out_ij, double* out_s, in
 // ---------------------------------------------------------------------------
 static inline uint32_t nblocks(uint32_t n, uint32_t bs) { return (n + bs - 1) / bs; }
 
-void launch_integrate(const Bufs& b, hipStream_t st) {
-    if (b.mixed) hipLaunchKernelGGL(k_integrate<true>, dim3(b.npad / 256), dim3(256), 0, st, b);
-    else hipLaunchKernelGGL(k_integrate<false>, dim3(b.npad / 256), dim3(256), 0, st, b);
+void launch_integrate(const Bufs& b, hipStream_t st, int q) {
+    if (b.mixed) hipLaunchKernelGGL(k_integrate<true>, dim3(b.npad / 256), dim3(256), 0, st, b, q);
+    else hipLaunchKernelGGL(k_integrate<false>, dim3(b.npad / 256), dim3(256), 0, st, b, q);
 }
 
-void launch_rebuild(const Bufs& b, hipStream_t st, int in_step, uint32_t ct_input_rep) {
+void launch_finalize(const Bufs& b, hipStream_t st, int q) {
+    hipLaunchKernelGGL(k_finalize, dim3(b.nrep), dim3(256), 0, st, b, q);
+}
+
+void launch_rebuild(const Bufs& b, hipStream_t st, int q, int in_step, uint32_t ct_input_rep) {
     const uint32_t np = b.npad / 256;
     hipLaunchKernelGGL(k_rb_zero, dim3(nblocks(b.nkeys_total, 256)), dim3(256), 0, st, b);
     hipLaunchKernelGGL(k_rb_keys, dim3(np), dim3(256), 0, st, b);
@@ -985,29 +1021,29 @@ void launch_rebuild(const Bufs& b, hipStream_t st, int in_step, uint32_t ct_inpu
     hipLaunchKernelGGL(k_rb_cellsort, dim3(nblocks(b.nkeys_total, 256)), dim3(256), 0, st, b);
     hipLaunchKernelGGL(k_rb_gather, dim3(np), dim3(256), 0, st, b, ct_input_rep);
     hipLaunchKernelGGL(k_rb_copyback, dim3(np), dim3(256), 0, st, b);
-    hipLaunchKernelGGL(k_rb_nlist, dim3(np), dim3(256), 0, st, b, in_step);
-    hipLaunchKernelGGL(k_rb_reset, dim3(1), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_rb_nlist, dim3(np), dim3(256), 0, st, b, q, in_step);
+    hipLaunchKernelGGL(k_rb_reset, dim3(1), dim3(256), 0, st, b, q);
 }
 
 template <bool MIX>
-static void launch_pair_t(const Bufs& b, hipStream_t st, int kick, int advance, uint32_t only_rep) {
+static void launch_pair_t(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep) {
     const dim3 blk(256);
     switch (b.lanes) {
-        case 1: hipLaunchKernelGGL((k_pair<MIX, 1>), dim3(b.npad / 256), blk, 0, st, b, kick, advance, only_rep); break;
-        case 2: hipLaunchKernelGGL((k_pair<MIX, 2>), dim3(b.npad / 128), blk, 0, st, b, kick, advance, only_rep); break;
-        case 4: hipLaunchKernelGGL((k_pair<MIX, 4>), dim3(b.npad / 64), blk, 0, st, b, kick, advance, only_rep); break;
-        default: hipLaunchKernelGGL((k_pair<MIX, 8>), dim3(b.npad / 32), blk, 0, st, b, kick, advance, only_rep); break;
+        case 1: hipLaunchKernelGGL((k_pair<MIX, 1>), dim3(b.npad / 256), blk, 0, st, b, q, kick, advance, only_rep); break;
+        case 2: hipLaunchKernelGGL((k_pair<MIX, 2>), dim3(b.npad / 128), blk, 0, st, b, q, kick, advance, only_rep); break;
+        case 4: hipLaunchKernelGGL((k_pair<MIX, 4>), dim3(b.npad / 64), blk, 0, st, b, q, kick, advance, only_rep); break;
+        default: hipLaunchKernelGGL((k_pair<MIX, 8>), dim3(b.npad / 32), blk, 0, st, b, q, kick, advance, only_rep); break;
     }
 }
 
-void launch_pair_force(const Bufs& b, hipStream_t st, int kick, int advance, uint32_t only_rep) {
-    if (b.mixed) launch_pair_t<true>(b, st, kick, advance, only_rep);
-    else launch_pair_t<false>(b, st, kick, advance, only_rep);
+void launch_pair_force(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep) {
+    if (b.mixed) launch_pair_t<true>(b, st, q, kick, advance, only_rep);
+    else launch_pair_t<false>(b, st, q, kick, advance, only_rep);
 }
 
-void launch_diag(const Bufs& b, hipStream_t st, uint32_t rep, uint32_t n, uint32_t* out_ij, double* out_s,
+void launch_diag(const Bufs& b, hipStream_t st, int p, uint32_t rep, uint32_t n, uint32_t* out_ij, double* out_s,
                  int32_t* out_sl, uint32_t* count, uint32_t cap, int mode) {
-    hipLaunchKernelGGL(k_diag, dim3(nblocks(n, 256)), dim3(256), 0, st, b, rep, out_ij, out_s, out_sl, count, cap,
+    hipLaunchKernelGGL(k_diag, dim3(nblocks(n, 256)), dim3(256), 0, st, b, p, rep, out_ij, out_s, out_sl, count, cap,
                        mode);
 }
 

@@ -67,7 +67,7 @@ struct sim {
     Bufs b{};
     hipStream_t st = nullptr;
     hipStream_t cap_st = nullptr;            // stream used only to capture graphs
-    hipGraphExec_t g1 = nullptr, gk = nullptr;
+    hipGraphExec_t g1[2] = {nullptr, nullptr}, gk[2] = {nullptr, nullptr};  // by parity of the first step
     std::vector<std::pair<void*, size_t>> allocs;
     void* (*afn)(size_t, void*) = nullptr;
     void (*ffn)(void*, void*) = nullptr;
@@ -79,6 +79,7 @@ struct sim {
     double prof_ms = 0.0;
     int64_t steps_total = 0;
     uint64_t step_now = 0;       // step counter of replica 0 (all replicas advance together)
+    int par = 0;                 // parity of the current state (slot of the last evaluation)
     int64_t since_build = 0;     // steps since the last list build
     int64_t plan = 16;           // rebuild when since_build reaches this
     int64_t plan_hint = 16;      // first chunk after a build
@@ -99,8 +100,10 @@ struct sim {
     template <class T> T* alloc(size_t count) { return (T*)dalloc(count * sizeof(T)); }
 
     ~sim() {
-        if (g1) (void)hipGraphExecDestroy(g1);
-        if (gk) (void)hipGraphExecDestroy(gk);
+        for (int k = 0; k < 2; ++k) {
+            if (g1[k]) (void)hipGraphExecDestroy(g1[k]);
+            if (gk[k]) (void)hipGraphExecDestroy(gk[k]);
+        }
         for (auto& e : ev) (void)hipEventDestroy(e);
         (void)hipStreamSynchronize(st);
         for (auto& a : allocs) {
@@ -189,18 +192,18 @@ template <class T> std::vector<T> d2h(sim* s, const T* dev, size_t off, size_t c
     return h;
 }
 
-// one time step without a list rebuild; both kernels do nothing once the
-// expiry test of an earlier integrate has halted the chunk
-void enqueue_step(sim* s, hipStream_t st) {
-    launch_integrate(s->b, st);
-    launch_pair_force(s->b, st, 1, 1, 0xFFFFFFFFu);
+// one time step with parity q, without a list rebuild; both kernels do nothing
+// once the expiry test of an earlier pair kernel has halted the chunk
+void enqueue_step(sim* s, hipStream_t st, int q) {
+    launch_integrate(s->b, st, q);
+    launch_pair_force(s->b, st, q, 1, 1, 0xFFFFFFFFu);
 }
 
-hipGraphExec_t capture(sim* s, int nsteps) {
+hipGraphExec_t capture(sim* s, int nsteps, int q0) {
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
     HIPCHK(hipStreamBeginCapture(s->cap_st, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < nsteps; ++k) enqueue_step(s, s->cap_st);
+    for (int k = 0; k < nsteps; ++k) enqueue_step(s, s->cap_st, q0 ^ (k & 1));
     HIPCHK(hipStreamEndCapture(s->cap_st, &g));
     HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
     HIPCHK(hipGraphDestroy(g));
@@ -220,11 +223,11 @@ int check_health(sim* s) {
         if (h & H_NLIST) {
             code = SIM_ECAPACITY;
             msg = fmt("replica %d: neighbour list or contact capacity exceeded at step %llu", r,
-                      (unsigned long long)dyn[r].step);
+                      (unsigned long long)std::max(dyn[r].step_slot[0], dyn[r].step_slot[1]));
         } else if (code == SIM_OK) {
             code = SIM_EUNSTABLE;
             msg = fmt("replica %d: %s at step %llu", r, (h & H_NAN) ? "non-finite force" : "overlap above the limit",
-                      (unsigned long long)dyn[r].step);
+                      (unsigned long long)std::max(dyn[r].step_slot[0], dyn[r].step_slot[1]));
         }
         const uint32_t zero = 0;
         HIPCHK(hipMemcpyAsync((char*)(s->b.dyn + r) + offsetof(RepDyn, health), &zero, sizeof zero,
@@ -308,8 +311,8 @@ void upload_state(sim* s, int r, const double* x, const double* v, const double*
 
 void set_dyn(sim* s, int r, double s_le, uint64_t step) {
     RepDyn d{};
-    d.s_le = s_le;
-    d.step = step;
+    d.s_slot[0] = d.s_slot[1] = s_le;
+    d.step_slot[0] = d.step_slot[1] = step;
     HIPCHK(hipMemcpyAsync(s->b.dyn + r, &d, sizeof d, hipMemcpyHostToDevice, s->st));
     s->ring_tail[r] = 0;
 }
@@ -325,9 +328,9 @@ void tune_lanes(sim* s) {
     int best_l = 1;
     for (int L : {1, 2, 4, 8}) {
         s->b.lanes = L;
-        launch_pair_force(s->b, s->st, 0, 0, 0xFFFFFFFFu);
+        launch_pair_force(s->b, s->st, s->par, 0, 0, 0xFFFFFFFFu);
         HIPCHK(hipEventRecord(e0, s->st));
-        for (int k = 0; k < 4; ++k) launch_pair_force(s->b, s->st, 0, 0, 0xFFFFFFFFu);
+        for (int k = 0; k < 4; ++k) launch_pair_force(s->b, s->st, s->par, 0, 0, 0xFFFFFFFFu);
         HIPCHK(hipEventRecord(e1, s->st));
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0.f;
@@ -486,7 +489,8 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         b.ct_n = s->alloc<uint32_t>(np * 2);
         for (int a = 0; a < 7; ++a) b.alt4[a] = s->alloc<double4>(np);
         b.alt_id = s->alloc<uint32_t>(np);
-        b.partial = s->alloc<double>(np / kTile * 8 * 27);  // up to 8 lanes per particle
+        b.nblk_max = (uint32_t)(np / kTile * 8);             // up to 8 lanes per particle
+        b.partial = s->alloc<double>((size_t)2 * b.nblk_max * 27);
         b.ring = s->alloc<double>((size_t)n_replicas * kRing * 27);
         b.last = s->alloc<double>((size_t)n_replicas * 27);
         b.blk_rep = s->alloc<uint32_t>(blk_rep.size());
@@ -500,7 +504,7 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
             set_dyn(s, r, cfgs[r].le_offset0, cfgs[r].step0);
         }
         s->step_now = cfgs[0].step0;
-        launch_rebuild(b, s->st, 0, 0xFFFFFFFEu);
+        launch_rebuild(b, s->st, 1 - s->par, 0, 0xFFFFFFFEu);
         b.lanes = 1;
         if (cfgs[0].lanes == 0) {
             tune_lanes(s);
@@ -510,7 +514,8 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         } else {
             b.lanes = (int)cfgs[0].lanes;
         }
-        launch_pair_force(b, s->st, 0, 0, 0xFFFFFFFFu);
+        launch_pair_force(b, s->st, s->par, 0, 0, 0xFFFFFFFFu);
+        launch_finalize(b, s->st, s->par);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s->st));
         const int hc = check_health(s);
@@ -533,15 +538,18 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
 
 namespace {
 
-// Launches m steps on the library stream (graphs of kGraphSteps and 1 step, or
-// direct launches), then waits.
+// Launches m steps on the library stream (graphs of kGraphSteps and of 1 step,
+// or direct launches), then waits.  Step k of the chunk has parity par^1^(k&1).
 void launch_steps(sim* s, int64_t m) {
+    int q = 1 - s->par;
     const bool graph = !(s->flags & SIM_NO_GRAPH) && !s->profile;
     if (graph) {
-        if (!s->g1) s->g1 = capture(s, 1);
-        if (!s->gk && m >= kGraphSteps) s->gk = capture(s, kGraphSteps);
-        for (; m >= kGraphSteps; m -= kGraphSteps) HIPCHK(hipGraphLaunch(s->gk, s->st));
-        for (; m > 0; --m) HIPCHK(hipGraphLaunch(s->g1, s->st));
+        if (m >= kGraphSteps && !s->gk[q]) s->gk[q] = capture(s, kGraphSteps, q);
+        for (; m >= kGraphSteps; m -= kGraphSteps) HIPCHK(hipGraphLaunch(s->gk[q], s->st));
+        for (; m > 0; --m, q ^= 1) {
+            if (!s->g1[q]) s->g1[q] = capture(s, 1, q);
+            HIPCHK(hipGraphLaunch(s->g1[q], s->st));
+        }
     } else if (s->profile) {
         if (s->ev.size() < 2) {
             for (int k = 0; k < 2; ++k) {
@@ -550,10 +558,10 @@ void launch_steps(sim* s, int64_t m) {
                 s->ev.push_back(e);
             }
         }
-        for (; m > 0; --m) {
-            launch_integrate(s->b, s->st);
+        for (; m > 0; --m, q ^= 1) {
+            launch_integrate(s->b, s->st, q);
             HIPCHK(hipEventRecord(s->ev[0], s->st));
-            launch_pair_force(s->b, s->st, 1, 1, 0xFFFFFFFFu);
+            launch_pair_force(s->b, s->st, q, 1, 1, 0xFFFFFFFFu);
             HIPCHK(hipEventRecord(s->ev[1], s->st));
             HIPCHK(hipEventSynchronize(s->ev[1]));
             SysDyn sy;
@@ -565,7 +573,7 @@ void launch_steps(sim* s, int64_t m) {
             s->prof_launches += 1;
         }
     } else {
-        for (; m > 0; --m) enqueue_step(s, s->st);
+        for (; m > 0; --m, q ^= 1) enqueue_step(s, s->st, q);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s->st));
@@ -578,7 +586,8 @@ int64_t plan_steps(sim* s, const std::vector<RepDyn>& dyn) {
     double worst = 0.0;  // fraction of the skin used per step
     for (int r = 0; r < s->nrep; ++r) {
         const RepParams& P = s->P[r];
-        const double used = 2.0 * dyn[r].dmax + std::fabs(P.gd) * dyn[r].t_since * (P.rc_max + 2.0 * P.skin);
+        const double used = 2.0 * dyn[r].dmax_slot[s->par] +
+                            std::fabs(P.gd) * dyn[r].t_slot[s->par] * (P.rc_max + 2.0 * P.skin);
         worst = std::max(worst, used / P.skin / (double)s->since_build);
     }
     if (!(worst > 0.0)) return 1 << 20;
@@ -593,34 +602,38 @@ int sim_step(sim* s, int64_t nsteps) {
     try {
         int64_t left = nsteps;
         std::vector<RepDyn> dyn(s->nrep);
+        const bool every = (s->flags & SIM_REBUILD_EACH_STEP) != 0;
         while (left > 0) {
-            int64_t budget = s->plan - s->since_build;
+            int64_t budget = every ? 0 : s->plan - s->since_build;
             if (budget < 1) {
                 // displacement budget used up: rebuild between steps, from the current positions
-                launch_rebuild(s->b, s->st, 0, 0xFFFFFFFFu);
+                launch_rebuild(s->b, s->st, 1 - s->par, 0, 0xFFFFFFFFu);
                 s->since_build = 0;
                 s->plan = s->plan_hint;
-                budget = s->plan;
+                budget = every ? 1 : s->plan;
             }
             const int64_t m = std::min(left, std::max<int64_t>(budget, 1));
-            const uint64_t step0 = s->step_now;
             launch_steps(s, m);
             HIPCHK(hipMemcpyAsync(dyn.data(), s->b.dyn, sizeof(RepDyn) * s->nrep, hipMemcpyDeviceToHost, s->st));
             SysDyn sy;
             HIPCHK(hipMemcpyAsync(&sy, s->b.sys, sizeof sy, hipMemcpyDeviceToHost, s->st));
             HIPCHK(hipStreamSynchronize(s->st));
-            const int64_t done = (int64_t)(dyn[0].step - step0);
-            s->step_now = dyn[0].step;
+            const uint64_t cur = std::max(dyn[0].step_slot[0], dyn[0].step_slot[1]);
+            const int64_t done = (int64_t)(cur - s->step_now);
+            s->step_now = cur;
+            s->par ^= (int)(done & 1);
             s->since_build += done;
             left -= done;
             if (sy.halted) {
-                // the step after `done` ran its integrate but the expiry test stopped its
-                // forces: rebuild from the moved positions and evaluate that step
+                // the next step ran its integrate but the expiry test stopped its forces:
+                // rebuild from the moved positions and evaluate that step
                 const int64_t grown = plan_steps(s, dyn);
-                launch_rebuild(s->b, s->st, 1, 0xFFFFFFFFu);
-                launch_pair_force(s->b, s->st, 1, 1, 0xFFFFFFFFu);
+                const int q = 1 - s->par;
+                launch_rebuild(s->b, s->st, q, 1, 0xFFFFFFFFu);
+                launch_pair_force(s->b, s->st, q, 1, 1, 0xFFFFFFFFu);
                 HIPCHK(hipGetLastError());
                 HIPCHK(hipStreamSynchronize(s->st));
+                s->par = q;
                 s->step_now += 1;
                 left -= 1;
                 s->plan_hint = std::max<int64_t>(1, std::min<int64_t>(grown, s->since_build + 1) / 2);
@@ -633,6 +646,10 @@ int sim_step(sim* s, int64_t nsteps) {
                 s->plan_hint = std::max<int64_t>(16, std::min<int64_t>(p, 1 << 20));
             }
         }
+        // reduce the stress of the last step (earlier steps were reduced by the next integrate)
+        launch_finalize(s->b, s->st, s->par);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s->st));
         s->steps_total += nsteps;
         return check_health(s);
     } catch (const HipError& e) {
@@ -757,8 +774,8 @@ int sim_get_state(sim* s, int32_t r, double* x, double* v, double* w, double* F,
         scatterF(s->b.T, T);
         if (le_offset || step) {
             auto d = d2h(s, s->b.dyn, (size_t)r, 1);
-            if (le_offset) *le_offset = d[0].s_le;
-            if (step) *step = d[0].step;
+            if (le_offset) *le_offset = d[0].s_slot[s->par];
+            if (step) *step = d[0].step_slot[s->par];
         }
         return SIM_OK;
     } catch (const HipError& e) {
@@ -789,9 +806,12 @@ int sim_set_state(sim* s, int32_t r, const double* x, const double* v, const dou
         upload_state(s, r, x, v, w, F, T, c_ij, c_s, n_contacts);
         set_dyn(s, r, le_offset, step);
         if (r == 0) s->step_now = step;
-        launch_rebuild(s->b, s->st, 0, (uint32_t)r);
+        launch_rebuild(s->b, s->st, 1 - s->par, 0, (uint32_t)r);
         s->since_build = 0;
-        if (!F) launch_pair_force(s->b, s->st, 0, 0, (uint32_t)r);
+        if (!F) {
+            launch_pair_force(s->b, s->st, s->par, 0, 0, (uint32_t)r);
+            launch_finalize(s->b, s->st, s->par);
+        }
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(s->st));
         return check_health(s);
@@ -811,7 +831,7 @@ int diag_pairs(sim* s, int32_t r, int mode, std::vector<uint32_t>& ij, std::vect
     uint32_t* dcount = nullptr;
     HIPCHK(hipMalloc(&dcount, sizeof(uint32_t)));
     HIPCHK(hipMemsetAsync(dcount, 0, sizeof(uint32_t), s->st));
-    launch_diag(s->b, s->st, (uint32_t)r, P.n, nullptr, nullptr, nullptr, dcount, 0, mode);
+    launch_diag(s->b, s->st, s->par, (uint32_t)r, P.n, nullptr, nullptr, nullptr, dcount, 0, mode);
     uint32_t cnt = 0;
     HIPCHK(hipMemcpyAsync(&cnt, dcount, 4, hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
@@ -822,7 +842,7 @@ int diag_pairs(sim* s, int32_t r, int mode, std::vector<uint32_t>& ij, std::vect
     HIPCHK(hipMalloc(&ds, sizeof(double) * 3 * (cnt + 1)));
     HIPCHK(hipMalloc(&dsl, sizeof(int32_t) * (cnt + 1)));
     HIPCHK(hipMemsetAsync(dcount, 0, sizeof(uint32_t), s->st));
-    launch_diag(s->b, s->st, (uint32_t)r, P.n, dij, ds, dsl, dcount, cnt, mode);
+    launch_diag(s->b, s->st, s->par, (uint32_t)r, P.n, dij, ds, dsl, dcount, cnt, mode);
     std::vector<uint32_t> hij(2 * (size_t)cnt);
     std::vector<double> hs(3 * (size_t)cnt);
     std::vector<int32_t> hsl(cnt);
@@ -909,8 +929,8 @@ int sim_stats(sim* s, int32_t r, sim_stats_t* out) {
         out->max_overlap = (double)mo;
         out->rebuilds = (int64_t)sy[0].rebuilds;
         out->steps = s->steps_total;
-        out->step = d[0].step;
-        out->le_offset = d[0].s_le;
+        out->step = d[0].step_slot[s->par];
+        out->le_offset = d[0].s_slot[s->par];
         out->lanes = s->b.lanes;
         out->pad = 0;
         return SIM_OK;
