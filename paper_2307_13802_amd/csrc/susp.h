@@ -8,6 +8,7 @@
 namespace susp {
 
 constexpr int kTile = 256;               // replicas are padded to multiples of this many particles
+constexpr int kSpread = 16;              // slots per replica for block-level atomic maxima
 constexpr uint32_t kNoId = 0xFFFFFFFFu;  // id of a padding slot
 constexpr double kPi = 3.14159265358979323846;
 
@@ -21,6 +22,7 @@ enum : uint32_t { H_NAN = 1u, H_OVERLAP = 2u, H_NLIST = 4u };
 // Constant per-replica parameters (host-written, read-only on device).
 struct RepParams {
     double L[3];
+    double invL[3];
     double gd, gdLy;          // shear rate, shear rate * Ly
     double dt, half_dt;
     double rho, eta, kn, kt, mu;
@@ -52,15 +54,19 @@ struct RepDyn {
     uint64_t step_slot[2];    // step counter of that evaluation
     double dmax_slot[2];      // bound on the non-affine displacement since the last build
     double t_slot[2];         // time since the last build
-    uint32_t stepmax_bits[2]; // float bits: largest displacement of the step with that parity
-    uint32_t maxov_bits[2];   // float bits: largest overlap of that evaluation
-    uint32_t pend[2];         // stress partials of that parity await reduction: 1 record, 2 do not
+    uint32_t stepmax_bits[2][kSpread];  // float bits: largest displacement of the step, spread
+                                        // over slots to keep atomic contention low
+    uint32_t maxov_bits[2][kSpread];    // float bits: largest overlap of that evaluation
+    uint32_t eval_id[2];      // serial number of the evaluation whose partials have that parity
+    uint32_t rec[2];          // its series record number (1-based), 0 = not recorded
+    uint32_t done_id[2][27];  // per stress component: evaluation already reduced
+    uint32_t eval_seq;        // evaluations so far
+    uint32_t nrec;            // series records so far
+    uint32_t rec_base;        // nrec at the last reset of the means
     uint32_t health;          // H_* bits, sticky until read by the host
-    uint32_t ring_head;       // number of series entries written (mod ring size)
     uint32_t maxov_last_bits; // float bits: largest overlap of the last reduced evaluation
     uint32_t pad;
-    double stress_sum[27];    // running sum for means
-    uint64_t stress_count;
+    double stress_sum[27];    // running sums for means
 };
 
 struct SysDyn {
@@ -111,7 +117,7 @@ struct Bufs {
     uint32_t* alt_id;
 
     // stress: per pair-kernel block partial sums (two parities), ring of per-step values
-    double* partial;      // [parity][blk][27]
+    double* partial;      // [parity][27][blk]
     uint32_t nblk_max;    // pair-kernel blocks at 8 lanes per particle (partials per parity)
     double* ring;         // [rep][kRing][27]
     double* last;         // [rep][27]

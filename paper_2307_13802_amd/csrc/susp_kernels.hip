@@ -17,6 +17,8 @@
 
 namespace susp {
 
+constexpr int kPairBlock = 128;  // threads per pair-force block
+
 // ---------------------------------------------------------------------------
 // Counter-based noise: Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw,
 // SC'11), Box-Muller normals.  Counter words: (step_lo, id_a, id_b,
@@ -47,10 +49,11 @@ __device__ __forceinline__ void normals3(uint4 w, double g[3]) {
     const double u2 = ((double)w.z + 0.5) * s, u3 = ((double)w.w + 0.5) * s;
     const double r0 = sqrt(-2.0 * log(u0));
     const double r1 = sqrt(-2.0 * log(u2));
-    const double a1 = (2.0 * kPi) * u1, a3 = (2.0 * kPi) * u3;
-    g[0] = r0 * cos(a1);
-    g[1] = r0 * sin(a1);
-    g[2] = r1 * cos(a3);
+    double s1, c1;
+    sincospi(2.0 * u1, &s1, &c1);  // sin, cos of 2 pi u1 (the doubling is exact)
+    g[0] = r0 * c1;
+    g[1] = r0 * s1;
+    g[2] = r1 * cospi(2.0 * u3);
 }
 
 __device__ __forceinline__ void normals3(uint4 w, float g[3]) {
@@ -58,8 +61,8 @@ __device__ __forceinline__ void normals3(uint4 w, float g[3]) {
     const float u0 = ((float)w.x + 0.5f) * s, u1 = ((float)w.y + 0.5f) * s;
     const float u2 = ((float)w.z + 0.5f) * s, u3 = ((float)w.w + 0.5f) * s;
     // hardware log2 and sin/cos of 2*pi*x (argument in revolutions)
-    const float r0 = __fsqrt_rn(-2.0f * 0.69314718055994531f * __builtin_amdgcn_logf(u0));
-    const float r1 = __fsqrt_rn(-2.0f * 0.69314718055994531f * __builtin_amdgcn_logf(u2));
+    const float r0 = __builtin_amdgcn_sqrtf(-2.0f * 0.69314718055994531f * __builtin_amdgcn_logf(u0));
+    const float r1 = __builtin_amdgcn_sqrtf(-2.0f * 0.69314718055994531f * __builtin_amdgcn_logf(u2));
     g[0] = r0 * __builtin_amdgcn_cosf(u1);
     g[1] = r0 * __builtin_amdgcn_sinf(u1);
     g[2] = r1 * __builtin_amdgcn_cosf(u3);
@@ -72,15 +75,17 @@ __device__ __forceinline__ void normals3(uint4 w, float g[3]) {
 // between a and the image of b.  Pairs within the interaction range are far
 // from the half-box points where the rounding of t/L could matter.
 // ---------------------------------------------------------------------------
+// (t * (1/L) rounds to the same integer as t / L except within an ulp of a
+// half-integer, i.e. for separations of half a box, far outside any list range.)
 __device__ __forceinline__ int min_image(const RepParams& P, double s_le, const double4& pa, const double4& pb,
                                          double& dx, double& dy, double& dz) {
     dy = pa.y - pb.y;
-    const double ky = rint(dy / P.L[1]);
+    const double ky = rint(dy * P.invL[1]);
     dy = dy - ky * P.L[1];
     dx = (pa.x - pb.x) - ky * s_le;
-    dx = dx - P.L[0] * rint(dx / P.L[0]);
+    dx = dx - P.L[0] * rint(dx * P.invL[0]);
     dz = pa.z - pb.z;
-    dz = dz - P.L[2] * rint(dz / P.L[2]);
+    dz = dz - P.L[2] * rint(dz * P.invL[2]);
     return (int)ky;
 }
 
@@ -110,83 +115,105 @@ __device__ __forceinline__ double next_offset(const RepParams& P, double s_le) {
     return s - P.L[0] * floor(s / P.L[0]);
 }
 
-// block-wide sum of 27 doubles per thread, fixed order (blockDim = 256); result in out (LDS)
-__device__ __forceinline__ void block_sum27(const double* acc, double* out) {
-    __shared__ double red[4][27];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int c = 0; c < 27; ++c) {
-        double v = acc[c];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) red[wave][c] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 27) {
-        const int c = threadIdx.x;
-        out[c] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
-    }
-    __syncthreads();
+// Cross-lane moves on the DPP network (no LDS traffic).  CTRL: 0x111..0x118 =
+// row_shr:1..8 (lanes past the row edge read 0), 0xB1 / 0x4E = quad_perm swaps
+// of neighbouring lanes / lane pairs.
+template <int CTRL> __device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL> __device__ __forceinline__ unsigned long long dpp_u64(unsigned long long u) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, true);
+    return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+template <int CTRL> __device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-// block-wide max of a non-negative float, then one atomic per block
-__device__ __forceinline__ void block_atomic_max(float v, uint32_t* target) {
-    __shared__ float red[16];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) red[wave] = v;
+// thread-private accumulation in LDS (each slot has one writer)
+__device__ __forceinline__ void lds_add(double* p, double v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// inclusive sum over each 16-lane row; lane 15 of a row then holds the row total
+__device__ __forceinline__ double row_sum_f64(double x) {
+    x += dpp_f64<0x111>(x);
+    x += dpp_f64<0x112>(x);
+    x += dpp_f64<0x114>(x);
+    x += dpp_f64<0x118>(x);
+    return x;
+}
+
+// block-wide max of a non-negative float, then one atomic per block into one
+// of kSpread slots (readers take the max over the slots)
+__device__ __forceinline__ void block_atomic_max(float v, uint32_t* slots) {
+    __shared__ float rows[16];
+    v = fmaxf(v, dpp_f32<0x111>(v));
+    v = fmaxf(v, dpp_f32<0x112>(v));
+    v = fmaxf(v, dpp_f32<0x114>(v));
+    v = fmaxf(v, dpp_f32<0x118>(v));
+    if ((threadIdx.x & 15) == 15) rows[threadIdx.x >> 4] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
-        float m = red[0];
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, red[w]);
-        if (m > 0.0f) atomicMax(target, __float_as_uint(m));
+        float m = rows[0];
+        for (int k = 1; k < (int)(blockDim.x >> 4); ++k) m = fmaxf(m, rows[k]);
+        if (m > 0.0f) atomicMax(&slots[blockIdx.x % kSpread], __float_as_uint(m));
     }
     __syncthreads();
 }
 
-// Fixed-order reduction of the stress partials of replica r with parity x
-// (one block); pushes the per-step value to the series when it was a step.
-__device__ void finalize_replica(const Bufs& b, uint32_t r, int x) {
+__device__ __forceinline__ float slots_max(const uint32_t* slots) {
+    float m = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kSpread; ++k) m = fmaxf(m, __uint_as_float(slots[k]));
+    return m;
+}
+
+// Reduction of one stress component c of replica r from the partials of
+// parity x, in a fixed order (one block), unless already done; component 0
+// also checks the overlap limit.
+__device__ void finalize_unit(const Bufs& b, uint32_t r, int c, int x) {
     RepDyn& D = b.dyn[r];
-    const uint32_t mode = D.pend[x];
-    if (mode == 0u) return;  // uniform across the block
+    const uint32_t id = D.eval_id[x];
+    if (id == D.done_id[x][c]) return;  // uniform across the block
     const RepParams& P = b.reps[r];
-    const uint32_t blk0 = P.blk_begin * (uint32_t)b.lanes, nblk = P.nblk * (uint32_t)b.lanes;
-    const double* part = b.partial + (size_t)x * b.nblk_max * 27;
-    double acc[27];
-#pragma unroll
-    for (int c = 0; c < 27; ++c) acc[c] = 0.0;
-    for (uint32_t k = threadIdx.x; k < nblk; k += blockDim.x) {
-#pragma unroll
-        for (int c = 0; c < 27; ++c) acc[c] += part[(size_t)(blk0 + k) * 27 + c];
-    }
-    __shared__ double tot[27];
-    block_sum27(acc, tot);
-    if (threadIdx.x < 27) {
-        const int c = threadIdx.x;
-        b.last[r * 27 + c] = tot[c];
-        if (mode == 1u) {
-            b.ring[((size_t)r * kRing + (D.ring_head % kRing)) * 27 + c] = tot[c];
-            D.stress_sum[c] += tot[c];
-        }
-    }
+    const uint32_t blk0 = P.p_begin * (uint32_t)b.lanes / kPairBlock, nblk = P.n_pad * (uint32_t)b.lanes / kPairBlock;
+    const double* part = b.partial + ((size_t)x * 27 + c) * b.nblk_max + blk0;
+    double v = 0.0;
+    for (uint32_t k = threadIdx.x; k < nblk; k += blockDim.x) v += part[k];
+    __shared__ double rows[16];
+    v = row_sum_f64(v);
+    if ((threadIdx.x & 15) == 15) rows[threadIdx.x >> 4] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
-        if ((double)__uint_as_float(D.maxov_bits[x]) > P.max_overlap) D.health |= H_OVERLAP;
-        D.maxov_last_bits = D.maxov_bits[x];
-        D.maxov_bits[x] = 0u;
-        if (mode == 1u) {
-            D.ring_head += 1;
-            D.stress_count += 1;
+        double t = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 4); ++k) t += rows[k];
+        b.last[r * 27 + c] = t;
+        const uint32_t rec = D.rec[x];
+        if (rec) {
+            b.ring[((size_t)r * kRing + (rec - 1) % kRing) * 27 + c] = t;
+            D.stress_sum[c] += t;
         }
-        D.pend[x] = 0u;
+        if (c == 0) {
+            const float mo = slots_max(D.maxov_bits[x]);
+            if ((double)mo > P.max_overlap) D.health |= H_OVERLAP;
+            D.maxov_last_bits = __float_as_uint(mo);
+            for (int k = 0; k < kSpread; ++k) D.maxov_bits[x][k] = 0u;
+        }
+        D.done_id[x][c] = id;
     }
+    __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_finalize(Bufs b, int x) {
-    finalize_replica(b, blockIdx.x, x);
+// units (replica, component) handled by the blocks of a grid, in turn
+__device__ void finalize_all(const Bufs& b, int x) {
+    for (uint32_t u = blockIdx.x; u < 27u * b.nrep; u += gridDim.x) finalize_unit(b, u / 27u, (int)(u % 27u), x);
 }
+
+__global__ __launch_bounds__(256) void k_finalize(Bufs b, int x) { finalize_all(b, x); }
 
 // ---------------------------------------------------------------------------
 // Kick 1, drift and wrap of a step with parity q (velocity-Verlet, Sec. II;
@@ -252,8 +279,8 @@ __global__ __launch_bounds__(256) void k_integrate(Bufs b, int q) {
             b.wsh[i] = make_float4((float)w.x, (float)w.y, (float)w.z, 0.0f);
         }
     }
-    block_atomic_max(disp, &D.stepmax_bits[q]);
-    if (blockIdx.x < b.nrep) finalize_replica(b, blockIdx.x, 1 - q);
+    block_atomic_max(disp, D.stepmax_bits[q]);
+    finalize_all(b, 1 - q);  // stress of the previous step
 }
 
 // ---------------------------------------------------------------------------
@@ -575,7 +602,7 @@ __global__ void k_rb_reset(Bufs b, int q) {
     for (uint32_t r = threadIdx.x; r < b.nrep; r += blockDim.x) {
         b.dyn[r].dmax_slot[1 - q] = 0.0;
         b.dyn[r].t_slot[1 - q] = 0.0;
-        b.dyn[r].stepmax_bits[q] = 0u;
+        for (int k = 0; k < kSpread; ++k) b.dyn[r].stepmax_bits[q][k] = 0u;
     }
     if (threadIdx.x == 0) {
         b.sys->halted = 0u;
@@ -601,6 +628,8 @@ template <> struct Acc<float> {
     __device__ __forceinline__ double get(int d) const { return (double)s[d] + (double)c[d]; }
 };
 
+// Precision policy: FP64 uses correctly rounded library operations; mixed
+// precision uses the hardware FP32 log2, sqrt and reciprocal (about 1 ulp).
 template <class R> __device__ __forceinline__ R rlog(R x);
 template <> __device__ __forceinline__ double rlog<double>(double x) { return log(x); }
 template <> __device__ __forceinline__ float rlog<float>(float x) {
@@ -608,7 +637,10 @@ template <> __device__ __forceinline__ float rlog<float>(float x) {
 }
 template <class R> __device__ __forceinline__ R rsqrt_(R x);
 template <> __device__ __forceinline__ double rsqrt_<double>(double x) { return sqrt(x); }
-template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return __fsqrt_rn(x); }
+template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <class R> __device__ __forceinline__ R rrcp(R x);
+template <> __device__ __forceinline__ double rrcp<double>(double x) { return 1.0 / x; }
+template <> __device__ __forceinline__ float rrcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ---------------------------------------------------------------------------
 // Forces of a step with parity q (Sec. II.A-II.D pair terms, Sec. II.B-II.C
@@ -623,10 +655,10 @@ template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return __f
 // lower-id side.
 // ---------------------------------------------------------------------------
 template <bool MIX, int LN>
-__global__ __launch_bounds__(256) void k_pair(Bufs b, int q, int kick, int advance, uint32_t only_rep) {
+__global__ __launch_bounds__(kPairBlock) void k_pair(Bufs b, int q, int kick, int advance, uint32_t only_rep) {
     using R = typename std::conditional<MIX, float, double>::type;
     if (b.sys->halted) return;  // the host rebuilds the lists and repeats this launch
-    const uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / LN;
+    const uint32_t i = (blockIdx.x * kPairBlock + threadIdx.x) / LN;
     const uint32_t sub = threadIdx.x % LN;
     const uint32_t r = b.blk_rep[i / kTile];
     if (only_rep != 0xFFFFFFFFu && r != only_rep) return;  // whole block belongs to one replica
@@ -643,7 +675,7 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int q, int kick, int advan
         for (uint32_t rr = 0; rr < b.nrep; ++rr) {
             const RepParams& Q = b.reps[rr];
             const RepDyn& E = b.dyn[rr];
-            const double dm = E.dmax_slot[1 - q] + (double)as_posf(E.stepmax_bits[q]);
+            const double dm = E.dmax_slot[1 - q] + (double)slots_max(E.stepmax_bits[q]);
             const double tt = E.t_slot[1 - q] + Q.dt;
             expired |= 2.0 * dm + fabs(Q.gd) * tt * (Q.rc_max + 2.0 * Q.skin) > Q.skin;
         }
@@ -653,23 +685,32 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int q, int kick, int advan
         }
         s_le = next_offset(P, D.s_slot[1 - q]);
         step = D.step_slot[1 - q] + 1;
-        if (blockIdx.x == P.blk_begin * LN && threadIdx.x == 0) {
+        if (blockIdx.x == P.p_begin * LN / kPairBlock && threadIdx.x == 0) {
             D.s_slot[q] = s_le;
             D.step_slot[q] = step;
-            D.dmax_slot[q] = D.dmax_slot[1 - q] + (double)as_posf(D.stepmax_bits[q]);
+            D.dmax_slot[q] = D.dmax_slot[1 - q] + (double)slots_max(D.stepmax_bits[q]);
             D.t_slot[q] = D.t_slot[1 - q] + P.dt;
-            D.stepmax_bits[1 - q] = 0u;  // for the next step's integrate
-            D.pend[q] = 1u;
+            for (int k = 0; k < kSpread; ++k) D.stepmax_bits[1 - q][k] = 0u;  // for the next step
+            D.eval_seq += 1;
+            D.eval_id[q] = D.eval_seq;
+            D.nrec += 1;
+            D.rec[q] = D.nrec;
         }
     } else {
         s_le = D.s_slot[q];
         step = D.step_slot[q];
-        if (blockIdx.x == P.blk_begin * LN && threadIdx.x == 0) D.pend[q] = 2u;
+        if (blockIdx.x == P.p_begin * LN / kPairBlock && threadIdx.x == 0) {
+            D.eval_seq += 1;
+            D.eval_id[q] = D.eval_seq;
+            D.rec[q] = 0u;
+        }
     }
 
-    double acc[27];  // stress: contact, lubrication, Brownian; lower-id side of each pair
+    // stress sums (contact, lubrication, Brownian; lower-id side of each pair) in
+    // thread-private LDS slots, so they take no registers across the pair loop
+    __shared__ double sacc[27][kPairBlock];
 #pragma unroll
-    for (int t = 0; t < 27; ++t) acc[t] = 0.0;
+    for (int t = 0; t < 27; ++t) sacc[t][threadIdx.x] = 0.0;
     float maxov = 0.0f;
     bool bad = false;
 
@@ -724,23 +765,19 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int q, int kick, int advan
                 if (!(d2 <= rc * rc)) continue;
                 const double dist = sqrt(d2);
                 h = dist - sa;
-                if (MIX) {
-                    const float inv = 1.0f / (float)dist;
-                    n[0] = (float)dx * inv; n[1] = (float)dy * inv; n[2] = (float)dz * inv;
-                } else {
-                    n[0] = (R)(dx / dist); n[1] = (R)(dy / dist); n[2] = (R)(dz / dist);
-                }
+                const R inv = rrcp<R>((R)dist);
+                n[0] = (R)dx * inv; n[1] = (R)dy * inv; n[2] = (R)dz * inv;
                 const R aj = (R)pj.w;
                 const R aa = lo ? ai : aj, ab = lo ? aj : ai;
-                const R xi = (R)((2.0 * h) / sa);
+                const R xi = (R)(2.0 * h) * rrcp<R>((R)sa);
                 const R xie = xi < xi_min ? xi_min : xi;
                 // resistance scalars X^A_11, Y^A_11 (Sec. II.B) in the symmetric form
                 const R pab = aa * ab, qab = aa * aa + ab * ab;
                 const R sR = aa + ab;
-                const R pre = eta6pi / (sR * sR * sR);
+                const R pre = eta6pi * rrcp<R>(sR * sR * sR);
                 const R lg = -rlog<R>(xie);
-                XA = pre * ((R)2 * pab * pab / xie + pab * (qab + (R)7 * pab) / (R)5 * lg);
-                YA = pre * ((R)4 * pab * ((R)2 * qab + pab) / (R)15 * lg);
+                XA = pre * ((R)2 * pab * pab * rrcp<R>(xie) + pab * (qab + (R)7 * pab) * (R)0.2 * lg);
+                YA = pre * ((R)4 * pab * ((R)2 * qab + pab) * (R)(1.0 / 15.0) * lg);
             }
             // ---- one Philox block -> three normals (shared by both kinds of item)
             R th[3] = {(R)0, (R)0, (R)0};
@@ -808,6 +845,11 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int q, int kick, int advan
                 const R aa = lo ? ai : aj, ab = lo ? aj : ai;
                 const R delta = (R)(-h);
                 if ((float)(-h) > maxov) maxov = (float)(-h);
+                if (!MIX) {
+                    // the spring is updated with the correctly rounded normal (bit-reproducible history)
+                    const double dist = sqrt((dx * dx + dy * dy) + dz * dz);
+                    n[0] = (R)(dx / dist); n[1] = (R)(dy / dist); n[2] = (R)(dz / dist);
+                }
                 R s[3] = {(R)0, (R)0, (R)0};
                 if ((cm_old >> e) & 1ull) {
                     if (MIX) {
@@ -848,7 +890,7 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int q, int kick, int advan
                 const R ps = rsqrt_<R>((pr[0] * pr[0] + pr[1] * pr[1]) + pr[2] * pr[2]);
                 if (ps > (R)0) {
                     const R ss = rsqrt_<R>((s[0] * s[0] + s[1] * s[1]) + s[2] * s[2]);
-                    const R fac = ss / ps;
+                    const R fac = MIX ? ss * rrcp<R>(ps) : ss / ps;
 #pragma unroll
                     for (int d = 0; d < 3; ++d) s[d] = pr[d] * fac;
                 } else {
@@ -860,7 +902,7 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int q, int kick, int advan
                 const R ftmax = mukn * delta;
                 const R sl = rsqrt_<R>((s[0] * s[0] + s[1] * s[1]) + s[2] * s[2]);
                 if (kt * sl > ftmax) {
-                    const R fac = ftmax / (kt * sl);
+                    const R fac = MIX ? ftmax * rrcp<R>(kt * sl) : ftmax / (kt * sl);
 #pragma unroll
                     for (int d = 0; d < 3; ++d) s[d] = s[d] * fac;
                     sm |= 1ull << e;
@@ -888,14 +930,14 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int q, int kick, int advan
             }
             if (lo) {
                 // Sec. II.A, II.B, II.D: Sigma^X_ab -= F^X_a r_b / V, FP64
-                const double rr[3] = {dx, dy, dz};
+                const double rr[3] = {dx * P.invV, dy * P.invV, dz * P.invV};
 #pragma unroll
                 for (int al = 0; al < 3; ++al)
 #pragma unroll
                     for (int be = 0; be < 3; ++be) {
-                        acc[3 * al + be] -= (double)fc[al] * rr[be] * P.invV;
-                        acc[9 + 3 * al + be] -= (double)fl[al] * rr[be] * P.invV;
-                        acc[18 + 3 * al + be] -= (double)fb[al] * rr[be] * P.invV;
+                        lds_add(&sacc[3 * al + be][threadIdx.x], -(double)fc[al] * rr[be]);
+                        lds_add(&sacc[9 + 3 * al + be][threadIdx.x], -(double)fl[al] * rr[be]);
+                        lds_add(&sacc[18 + 3 * al + be][threadIdx.x], -(double)fb[al] * rr[be]);
                     }
             }
         }
@@ -904,15 +946,32 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int q, int kick, int advan
         double Ft[3], Tt[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) { Ft[d] = F.get(d); Tt[d] = T.get(d); }
-#pragma unroll
-        for (int off = 1; off < LN; off <<= 1) {
+        if (LN >= 2) {  // neighbouring lanes (quad_perm 1,0,3,2)
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                Ft[d] += __shfl_xor(Ft[d], off);
-                Tt[d] += __shfl_xor(Tt[d], off);
+                Ft[d] += dpp_f64<0xB1>(Ft[d]);
+                Tt[d] += dpp_f64<0xB1>(Tt[d]);
             }
-            cm |= __shfl_xor(cm, off);
-            sm |= __shfl_xor(sm, off);
+            cm |= dpp_u64<0xB1>(cm);
+            sm |= dpp_u64<0xB1>(sm);
+        }
+        if (LN >= 4) {  // lane pairs (quad_perm 2,3,0,1)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                Ft[d] += dpp_f64<0x4E>(Ft[d]);
+                Tt[d] += dpp_f64<0x4E>(Tt[d]);
+            }
+            cm |= dpp_u64<0x4E>(cm);
+            sm |= dpp_u64<0x4E>(sm);
+        }
+        if (LN >= 8) {  // quads
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                Ft[d] += __shfl_xor(Ft[d], 4);
+                Tt[d] += __shfl_xor(Tt[d], 4);
+            }
+            cm |= __shfl_xor(cm, 4);
+            sm |= __shfl_xor(sm, 4);
         }
 
         if (sub == 0) {
@@ -944,13 +1003,24 @@ __global__ __launch_bounds__(256) void k_pair(Bufs b, int q, int kick, int advan
 
     // health: non-finite forces, largest overlap (relaxed atomics; read after the launch)
     if (bad) atomicOr(&D.health, H_NAN);
-    block_atomic_max(maxov, &D.maxov_bits[q]);
+    block_atomic_max(maxov, D.maxov_bits[q]);
 
-    // block partial of the 27 stress sums, fixed order; reduced by a later launch
-    __shared__ double tot[27];
-    block_sum27(acc, tot);
-    if (threadIdx.x < 27)
-        b.partial[((size_t)q * b.nblk_max + blockIdx.x) * 27 + threadIdx.x] = tot[threadIdx.x];
+    // block partial of the 27 stress sums in a fixed order; reduced by a later launch.
+    // Thread t < 108 sums a quarter (32 slots) of component t / 4.
+    __syncthreads();
+    __shared__ double quarter[108];
+    if (threadIdx.x < 108) {
+        const int c = threadIdx.x >> 2, k0 = (threadIdx.x & 3) * (kPairBlock / 4);
+        double t = 0.0;
+        for (int k = 0; k < kPairBlock / 4; ++k) t += sacc[c][k0 + k];
+        quarter[threadIdx.x] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 27) {
+        const int c = threadIdx.x;
+        const double t = ((quarter[4 * c] + quarter[4 * c + 1]) + quarter[4 * c + 2]) + quarter[4 * c + 3];
+        b.partial[((size_t)q * 27 + c) * b.nblk_max + blockIdx.x] = t;
+    }
 }
 
 // diagnostics: mode 0 = interaction set, 1 = Verlet list, 2 = contacts (with springs)
@@ -1006,7 +1076,7 @@ void launch_integrate(const Bufs& b, hipStream_t st, int q) {
 }
 
 void launch_finalize(const Bufs& b, hipStream_t st, int q) {
-    hipLaunchKernelGGL(k_finalize, dim3(b.nrep), dim3(256), 0, st, b, q);
+    hipLaunchKernelGGL(k_finalize, dim3(27 * b.nrep), dim3(256), 0, st, b, q);
 }
 
 void launch_rebuild(const Bufs& b, hipStream_t st, int q, int in_step, uint32_t ct_input_rep) {
@@ -1027,12 +1097,13 @@ void launch_rebuild(const Bufs& b, hipStream_t st, int q, int in_step, uint32_t 
 
 template <bool MIX>
 static void launch_pair_t(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep) {
-    const dim3 blk(256);
+    const dim3 blk(kPairBlock);
+    const uint32_t g = b.npad / kPairBlock;
     switch (b.lanes) {
-        case 1: hipLaunchKernelGGL((k_pair<MIX, 1>), dim3(b.npad / 256), blk, 0, st, b, q, kick, advance, only_rep); break;
-        case 2: hipLaunchKernelGGL((k_pair<MIX, 2>), dim3(b.npad / 128), blk, 0, st, b, q, kick, advance, only_rep); break;
-        case 4: hipLaunchKernelGGL((k_pair<MIX, 4>), dim3(b.npad / 64), blk, 0, st, b, q, kick, advance, only_rep); break;
-        default: hipLaunchKernelGGL((k_pair<MIX, 8>), dim3(b.npad / 32), blk, 0, st, b, q, kick, advance, only_rep); break;
+        case 1: hipLaunchKernelGGL((k_pair<MIX, 1>), dim3(g), blk, 0, st, b, q, kick, advance, only_rep); break;
+        case 2: hipLaunchKernelGGL((k_pair<MIX, 2>), dim3(2 * g), blk, 0, st, b, q, kick, advance, only_rep); break;
+        case 4: hipLaunchKernelGGL((k_pair<MIX, 4>), dim3(4 * g), blk, 0, st, b, q, kick, advance, only_rep); break;
+        default: hipLaunchKernelGGL((k_pair<MIX, 8>), dim3(8 * g), blk, 0, st, b, q, kick, advance, only_rep); break;
     }
 }
 

@@ -412,7 +412,10 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
             const sim_config& c = cfgs[r];
             s->radii.emplace_back(radii[r], radii[r] + c.n);
             RepParams P{};
-            for (int d = 0; d < 3; ++d) P.L[d] = c.box[d];
+            for (int d = 0; d < 3; ++d) {
+                P.L[d] = c.box[d];
+                P.invL[d] = 1.0 / c.box[d];
+            }
             P.gd = c.gammadot;
             P.gdLy = c.gammadot * c.box[1];
             P.dt = c.dt;
@@ -489,7 +492,7 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         b.ct_n = s->alloc<uint32_t>(np * 2);
         for (int a = 0; a < 7; ++a) b.alt4[a] = s->alloc<double4>(np);
         b.alt_id = s->alloc<uint32_t>(np);
-        b.nblk_max = (uint32_t)(np / kTile * 8);             // up to 8 lanes per particle
+        b.nblk_max = (uint32_t)(np / 128 * 8);               // 128-thread pair blocks, up to 8 lanes
         b.partial = s->alloc<double>((size_t)2 * b.nblk_max * 27);
         b.ring = s->alloc<double>((size_t)n_replicas * kRing * 27);
         b.last = s->alloc<double>((size_t)n_replicas * 27);
@@ -683,7 +686,8 @@ int sim_stress(sim* s, int32_t r, int32_t component, int32_t mode, double out[9]
             std::copy(h.begin(), h.end(), v);
         } else {
             auto d = d2h(s, s->b.dyn, (size_t)r, 1);
-            const double c = d[0].stress_count ? (double)d[0].stress_count : 1.0;
+            const uint32_t n = d[0].nrec - d[0].rec_base;
+            const double c = n ? (double)n : 1.0;
             for (int k = 0; k < 27; ++k) v[k] = d[0].stress_sum[k] / c;
         }
         double drag[9] = {0, s->drag_xy[r], 0, s->drag_xy[r], 0, 0, 0, 0, 0};
@@ -705,9 +709,14 @@ int sim_stress(sim* s, int32_t r, int32_t component, int32_t mode, double out[9]
 int sim_reset_stress(sim* s) {
     if (!s) return fail(nullptr, SIM_EINVAL, "null handle");
     try {
+        std::vector<RepDyn> dyn(s->nrep);
+        HIPCHK(hipMemcpyAsync(dyn.data(), s->b.dyn, sizeof(RepDyn) * s->nrep, hipMemcpyDeviceToHost, s->st));
+        HIPCHK(hipStreamSynchronize(s->st));
+        const double z[27] = {0};
         for (int r = 0; r < s->nrep; ++r) {
-            std::vector<char> z(sizeof(double) * 27 + sizeof(uint64_t), 0);
-            HIPCHK(hipMemcpyAsync((char*)(s->b.dyn + r) + offsetof(RepDyn, stress_sum), z.data(), z.size(),
+            HIPCHK(hipMemcpyAsync((char*)(s->b.dyn + r) + offsetof(RepDyn, stress_sum), z, sizeof z,
+                                  hipMemcpyHostToDevice, s->st));
+            HIPCHK(hipMemcpyAsync((char*)(s->b.dyn + r) + offsetof(RepDyn, rec_base), &dyn[r].nrec, sizeof(uint32_t),
                                   hipMemcpyHostToDevice, s->st));
         }
         HIPCHK(hipStreamSynchronize(s->st));
@@ -722,7 +731,7 @@ int sim_stress_series(sim* s, int32_t r, double* out, int64_t cap, int64_t* coun
     if (!count) return fail(s, SIM_EINVAL, "null count");
     try {
         auto d = d2h(s, s->b.dyn, (size_t)r, 1);
-        const uint32_t head = d[0].ring_head;
+        const uint32_t head = d[0].nrec;  // records 1..head; record k sits in slot (k - 1) % kRing
         uint32_t tail = s->ring_tail[r];
         if (head - tail > (uint32_t)kRing) tail = head - kRing;
         const int64_t n = (int64_t)(head - tail);
