@@ -114,9 +114,19 @@ typedef struct sim_config {
     int32_t  precision;     /* SIM_FP64 or SIM_MIXED, identical for all replicas     */
     uint32_t flags;         /* SIM_* flags, identical for all replicas               */
     uint32_t nlist_cap;     /* neighbour list capacity per particle; 0 selects 48    */
-    uint32_t lanes;         /* lanes sharing one particle's list in the pair kernel:
-                               1, 2, 4 or 8; 0 = chosen by timing at creation        */
+    uint32_t lanes;         /* lanes sharing one particle in the pair kernel: 1, 2, 4
+                               or 8 (at most 4 for SIM_KERNEL_WAVE); 0 = chosen by
+                               timing at creation                                     */
+    uint32_t pair_kernel;   /* SIM_KERNEL_AUTO, SIM_KERNEL_LANES or SIM_KERNEL_WAVE   */
+    uint32_t reserved;      /* must be 0                                             */
 } sim_config;
+
+/* sim_config.pair_kernel: both evaluate the same items in the same order and
+ * give bit-identical forces; they differ only in how lanes share the work */
+#define SIM_KERNEL_AUTO  0  /* the faster of the two at creation (timed)              */
+#define SIM_KERNEL_LANES 1  /* each particle's items split over `lanes` lanes         */
+#define SIM_KERNEL_WAVE  2  /* a wave tests its particles' list entries, then packs
+                               their interacting pairs into full 64-lane batches      */
 
 typedef struct sim_stats_t {
     double  contacts_per_particle;  /* Z = 2 * contacts / n                          */
@@ -130,7 +140,7 @@ typedef struct sim_stats_t {
     uint64_t step;                  /* current step counter                            */
     double  le_offset;              /* current Lees-Edwards offset                     */
     int32_t lanes;                  /* lanes per particle used by the pair kernel       */
-    int32_t pad;
+    int32_t pair_kernel;            /* SIM_KERNEL_LANES or SIM_KERNEL_WAVE in use         */
 } sim_stats_t;
 
 /* Checks a configuration and its radii on the host (no GPU needed).
@@ -138,7 +148,9 @@ typedef struct sim_stats_t {
  * dt <= 0, rho/eta <= 0, kn/kt < 0, mu < 0, kT < 0, xi_min <= 0,
  * xi_min >= xi_cut, a box side not larger than twice the largest
  * interaction range plus skin (the minimum image must be unique), a wrong
- * struct_size, nlist_cap > 64 or lanes not in {0, 1, 2, 4, 8}. */
+ * struct_size, nlist_cap > 64, lanes not in {0, 1, 2, 4, 8}, an unknown
+ * pair_kernel, SIM_KERNEL_WAVE with lanes 8 or nlist_cap > 62, or a nonzero
+ * reserved field. */
 int sim_validate(const sim_config* cfg, const double* radii);
 
 /* Creates a handle with n_replicas systems.  For replica r: radii[r] -> n

@@ -122,6 +122,8 @@ struct Bufs {
     double* ring;         // [rep][kRing][27]
     double* last;         // [rep][27]
     int lanes;            // pair kernel: lanes per particle (1, 2, 4, 8)
+    int kern;             // pair kernel: 0 = lanes split each particle's items, 1 = wave-cooperative
+    int ppb;              // particles per pair-kernel block (for the stress partials)
 
     uint32_t* blk_rep;    // replica of each kTile-block of particles
     RepParams* reps;

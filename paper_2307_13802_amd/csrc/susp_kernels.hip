@@ -180,7 +180,7 @@ __device__ void finalize_unit(const Bufs& b, uint32_t r, int c, int x) {
     const uint32_t id = D.eval_id[x];
     if (id == D.done_id[x][c]) return;  // uniform across the block
     const RepParams& P = b.reps[r];
-    const uint32_t blk0 = P.p_begin * (uint32_t)b.lanes / kPairBlock, nblk = P.n_pad * (uint32_t)b.lanes / kPairBlock;
+    const uint32_t blk0 = P.p_begin / (uint32_t)b.ppb, nblk = P.n_pad / (uint32_t)b.ppb;
     const double* part = b.partial + ((size_t)x * 27 + c) * b.nblk_max + blk0;
     double v = 0.0;
     for (uint32_t k = threadIdx.x; k < nblk; k += blockDim.x) v += part[k];
@@ -218,8 +218,7 @@ __global__ __launch_bounds__(256) void k_finalize(Bufs b, int x) { finalize_all(
 // ---------------------------------------------------------------------------
 // Kick 1, drift and wrap of a step with parity q (velocity-Verlet, Sec. II;
 // sheared box, Sec. II.E).  Also bounds the step's non-affine displacement
-// |dx - U^inf dt| for the list-expiry test, and (blocks r < replicas) reduces
-// the stress of the previous step.
+// |dx - U^inf dt| for the list-expiry test.
 // ---------------------------------------------------------------------------
 template <bool MIX>
 __global__ __launch_bounds__(256) void k_integrate(Bufs b, int q) {
@@ -280,7 +279,6 @@ __global__ __launch_bounds__(256) void k_integrate(Bufs b, int q) {
         }
     }
     block_atomic_max(disp, D.stepmax_bits[q]);
-    finalize_all(b, 1 - q);  // stress of the previous step
 }
 
 // ---------------------------------------------------------------------------
@@ -643,34 +641,37 @@ template <> __device__ __forceinline__ double rrcp<double>(double x) { return 1.
 template <> __device__ __forceinline__ float rrcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ---------------------------------------------------------------------------
-// Forces of a step with parity q (Sec. II.A-II.D pair terms, Sec. II.B-II.C
-// one-body terms), kick 2.  LN consecutive lanes share one particle i and
-// split its work items: the list entries (pairs) and two one-body items (drag
-// + noise force, drag + noise torque).  Every item draws one Philox block and
-// three normals through the same code, so lanes doing pair and one-body items
-// in the same iteration do not diverge on the costly part.  Pairs are
+// Forces of a step with parity q: Sec. II.A-II.D pair terms, Sec. II.B-II.C
+// one-body terms, kick 2.  The work of particle i is a list of items: its
+// interacting list entries in entry order (partner ids ascending), then a
+// one-body force item (drag + noise) and a one-body torque item.  Every item
+// draws one Philox block and three normals through the same code.  Pairs are
 // evaluated in canonical orientation (lower id = "a", higher id = "b",
 // r = x_a - x_b), so both sides compute bit-identical pair terms and the pair
 // forces are exactly antisymmetric; the stress of a pair is added on the
-// lower-id side.
+// lower-id side.  The force and torque on i are summed over its items in item
+// order (FP64, or FP32 with Neumaier compensation), so every kernel variant
+// below gives the same bits.
 // ---------------------------------------------------------------------------
-template <bool MIX, int LN>
-__global__ __launch_bounds__(kPairBlock) void k_pair(Bufs b, int q, int kick, int advance, uint32_t only_rep) {
-    using R = typename std::conditional<MIX, float, double>::type;
-    if (b.sys->halted) return;  // the host rebuilds the lists and repeats this launch
-    const uint32_t i = (blockIdx.x * kPairBlock + threadIdx.x) / LN;
-    const uint32_t sub = threadIdx.x % LN;
-    const uint32_t r = b.blk_rep[i / kTile];
-    if (only_rep != 0xFFFFFFFFu && r != only_rep) return;  // whole block belongs to one replica
-    const RepParams& P = b.reps[r];
-    RepDyn& D = b.dyn[r];
-    const uint32_t npad = b.npad;
+constexpr uint32_t kItemForce = 64u;   // item code of the one-body force (list entries are < 64)
+constexpr uint32_t kItemTorque = 65u;  // item code of the one-body torque
 
-    double s_le;
-    uint64_t step;
+template <bool MIX> struct EvalCtx {
+    using R = typename std::conditional<MIX, float, double>::type;
+    double s_le, c1, invV;
+    uint32_t k0, k1, ctr_lo, ctr_hi;
+    R bamp, eta6pi, xi_min, kn, kt, mukn, dtR;
+    bool do_lub, do_br, do_ct, do_one;
+};
+
+// Step bookkeeping shared by the pair kernels.  Returns false when the launch
+// must do nothing (a list may have expired).  first: this block is the first
+// of its replica (it records the step's offset, counter and bound).
+__device__ __forceinline__ bool eval_begin(const Bufs& b, int q, int advance, const RepParams& P, RepDyn& D,
+                                           bool first, double& s_le, uint64_t& step) {
     if (advance) {
-        // list-expiry test (the validity bound in the comment above), for every replica:
-        // one expired list halts the whole launch sequence until the host rebuilt
+        // list-expiry test (the validity bound above) for every replica: one expired
+        // list halts the whole launch sequence until the host has rebuilt
         bool expired = false;
         for (uint32_t rr = 0; rr < b.nrep; ++rr) {
             const RepParams& Q = b.reps[rr];
@@ -681,11 +682,11 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(Bufs b, int q, int kick, in
         }
         if (expired) {
             if (blockIdx.x == 0 && threadIdx.x == 0) b.sys->halted = 1u;
-            return;
+            return false;
         }
         s_le = next_offset(P, D.s_slot[1 - q]);
         step = D.step_slot[1 - q] + 1;
-        if (blockIdx.x == P.p_begin * LN / kPairBlock && threadIdx.x == 0) {
+        if (first && threadIdx.x == 0) {
             D.s_slot[q] = s_le;
             D.step_slot[q] = step;
             D.dmax_slot[q] = D.dmax_slot[1 - q] + (double)slots_max(D.stepmax_bits[q]);
@@ -699,249 +700,395 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(Bufs b, int q, int kick, in
     } else {
         s_le = D.s_slot[q];
         step = D.step_slot[q];
-        if (blockIdx.x == P.p_begin * LN / kPairBlock && threadIdx.x == 0) {
+        if (first && threadIdx.x == 0) {
             D.eval_seq += 1;
             D.eval_id[q] = D.eval_seq;
             D.rec[q] = 0u;
         }
     }
+    return true;
+}
 
-    // stress sums (contact, lubrication, Brownian; lower-id side of each pair) in
-    // thread-private LDS slots, so they take no registers across the pair loop
+template <bool MIX>
+__device__ __forceinline__ void make_ctx(EvalCtx<MIX>& C, const RepParams& P, double s_le, uint64_t step) {
+    using R = typename EvalCtx<MIX>::R;
+    C.s_le = s_le;
+    C.c1 = P.c1;
+    C.invV = P.invV;
+    C.k0 = (uint32_t)P.seed;
+    C.k1 = (uint32_t)(P.seed >> 32);
+    C.ctr_lo = (uint32_t)step;
+    C.ctr_hi = (uint32_t)(step >> 32) << 8;
+    C.bamp = (R)P.bamp;
+    C.eta6pi = (R)(6.0 * kPi * P.eta);
+    C.xi_min = (R)P.xi_min;
+    C.kn = (R)P.kn;
+    C.kt = (R)P.kt;
+    C.mukn = (R)(P.mu * P.kn);
+    C.dtR = (R)P.dt;
+    C.do_lub = !(P.flags & F_NO_LUB);
+    C.do_br = !(P.flags & F_NO_PAIR_BROWN);
+    C.do_ct = !(P.flags & F_NO_CONTACT);
+    C.do_one = !(P.flags & F_NO_ONEBODY);
+}
+
+// interaction predicate of list entry j of particle i: gap xi <= xi_cut (exact FP64 test)
+__device__ __forceinline__ bool interacting(const RepParams& P, double s_le, const double4& pi, const double4& pj) {
+    double dx, dy, dz;
+    min_image(P, s_le, pi, pj, dx, dy, dz);
+    const double d2 = (dx * dx + dy * dy) + dz * dz;
+    const double rc = (pi.w + pj.w) * P.c1;
+    return d2 <= rc * rc;
+}
+
+// One item of particle i: contribution f to its force and t to its torque.
+// Pair items also update the stored spring (entry e of i), the contact and
+// sliding bits, the largest overlap and the lower-id stress sums (addS).
+// Returns false for a pair that does not interact (nothing contributed).
+template <bool MIX, class AddS>
+__device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, const EvalCtx<MIX>& C, uint32_t i,
+                                          uint32_t e, const double4& pi, uint32_t idi,
+                                          const typename EvalCtx<MIX>::R* vi, const typename EvalCtx<MIX>::R* wi,
+                                          bool had_contact, typename EvalCtx<MIX>::R* f,
+                                          typename EvalCtx<MIX>::R* t, bool& contact, bool& slid, float& maxov,
+                                          AddS addS) {
+    using R = typename EvalCtx<MIX>::R;
+    const uint32_t npad = b.npad;
+    const R ai = (R)pi.w;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { f[d] = (R)0; t[d] = (R)0; }
+    contact = false;
+    slid = false;
+    const bool pair = e < kItemForce;
+    // ---- geometry of a pair item (FP64)
+    uint32_t j = 0, idj = 0;
+    double4 pj = make_double4(0.0, 0.0, 0.0, 0.0);
+    bool lo = true;
+    double dx = 0.0, dy = 0.0, dz = 0.0, h = 0.0;
+    int ky = 0;
+    R n[3] = {(R)0, (R)0, (R)0}, XA = (R)0, YA = (R)0;
+    if (pair) {
+        j = b.nbr[e * npad + i];
+        pj = b.pos[j];
+        idj = b.id[j];
+        lo = idi < idj;  // i holds the lower id
+        ky = lo ? min_image(P, C.s_le, pi, pj, dx, dy, dz) : min_image(P, C.s_le, pj, pi, dx, dy, dz);
+        const double d2 = (dx * dx + dy * dy) + dz * dz;
+        const double sa = pi.w + pj.w;
+        const double rc = sa * C.c1;
+        if (!(d2 <= rc * rc)) return false;
+        const double dist = sqrt(d2);
+        h = dist - sa;
+        const R inv = rrcp<R>((R)dist);
+        n[0] = (R)dx * inv; n[1] = (R)dy * inv; n[2] = (R)dz * inv;
+        const R aj = (R)pj.w;
+        const R aa = lo ? ai : aj, ab = lo ? aj : ai;
+        const R xi = (R)(2.0 * h) * rrcp<R>((R)sa);
+        const R xie = xi < C.xi_min ? C.xi_min : xi;
+        // resistance scalars X^A_11, Y^A_11 (Sec. II.B) in the symmetric form
+        const R pab = aa * ab, qab = aa * aa + ab * ab;
+        const R sR = aa + ab;
+        const R pre = C.eta6pi * rrcp<R>(sR * sR * sR);
+        const R lg = -rlog<R>(xie);
+        XA = pre * ((R)2 * pab * pab * rrcp<R>(xie) + pab * (qab + (R)7 * pab) * (R)0.2 * lg);
+        YA = pre * ((R)4 * pab * ((R)2 * qab + pab) * (R)(1.0 / 15.0) * lg);
+    }
+    // ---- one Philox block -> three normals (shared by both kinds of item)
+    R th[3] = {(R)0, (R)0, (R)0};
+    if (pair ? C.do_br : true) {
+        const uint32_t ida = pair ? (lo ? idi : idj) : idi;
+        const uint32_t idb = pair ? (lo ? idj : idi) : 0xFFFFFFFFu;
+        const uint32_t stream = pair ? 0u : (e == kItemForce ? 2u : 3u);
+        const uint4 w = philox10(C.ctr_lo, ida, idb, C.ctr_hi | stream, C.k0, C.k1);
+        normals3(w, th);
+    }
+    if (!pair) {
+        // eq. (force_drag) + (force_brownian_drag), or (torque_drag) + (torque_brownian_drag)
+        const double a = pi.w;
+        if (e == kItemForce) {
+            const R zeta = (R)(6.0 * kPi * P.eta * a);
+            const R sz = rsqrt_<R>(zeta);
+            const R uinf[3] = {(R)(P.gd * (pi.y - 0.5 * P.L[1])), (R)0, (R)0};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) f[d] = zeta * (uinf[d] - vi[d]) + C.bamp * sz * th[d];
+        } else {
+            const R zr = (R)(8.0 * kPi * P.eta * a * a * a);
+            const R szr = rsqrt_<R>(zr);
+            const R oinf[3] = {(R)0, (R)0, (R)(-0.5 * P.gd)};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) t[d] = zr * (oinf[d] - wi[d]) + C.bamp * szr * th[d];
+        }
+        return true;
+    }
+
+    // ---- pair item: velocities in canonical orientation; b's image moves with +k_y gammadot Ly
+    R va[3], vb[3], vj[3];
+    const R shiftv = (R)((double)ky * P.gdLy);
+    if (MIX) {
+        const float4 v4 = b.vsh[j];
+        vj[0] = v4.x; vj[1] = v4.y; vj[2] = v4.z;
+    } else {
+        const double4 v4 = b.vh[j];
+        vj[0] = (R)v4.x; vj[1] = (R)v4.y; vj[2] = (R)v4.z;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { va[d] = lo ? vi[d] : vj[d]; vb[d] = lo ? vj[d] : vi[d]; }
+    vb[0] = vb[0] + shiftv;
+
+    R fl[3] = {(R)0, (R)0, (R)0}, fb[3] = {(R)0, (R)0, (R)0}, fc[3] = {(R)0, (R)0, (R)0};
+    if (C.do_lub) {
+        // eq. (force_lub): (X^A N + Y^A T)(U_b - U_a)
+        R ur[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) ur[d] = vb[d] - va[d];
+        const R un = (n[0] * ur[0] + n[1] * ur[1]) + n[2] * ur[2];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) fl[d] = XA * (un * n[d]) + YA * (ur[d] - un * n[d]);
+    }
+    if (C.do_br) {
+        // eq. (force_brownian_lub): sqrt(2kT/dt) (sqrt(X^A) N + sqrt(Y^A) T) theta
+        const R tn = (n[0] * th[0] + n[1] * th[1]) + n[2] * th[2];
+        const R sx = rsqrt_<R>(XA), sy = rsqrt_<R>(YA);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) fb[d] = C.bamp * (sx * (tn * n[d]) + sy * (th[d] - tn * n[d]));
+    }
+    if (h < 0.0 && C.do_ct) {
+        // eq. (force_contact), (torque_contact); the spring s lives in canonical orientation
+        const R aj = (R)pj.w;
+        const R aa = lo ? ai : aj, ab = lo ? aj : ai;
+        const R delta = (R)(-h);
+        if ((float)(-h) > maxov) maxov = (float)(-h);
+        if (!MIX) {
+            // the spring is updated with the correctly rounded normal (bit-reproducible history)
+            const double dist = sqrt((dx * dx + dy * dy) + dz * dz);
+            n[0] = (R)(dx / dist); n[1] = (R)(dy / dist); n[2] = (R)(dz / dist);
+        }
+        R s[3] = {(R)0, (R)0, (R)0};
+        if (had_contact) {
+            if (MIX) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) s[d] = ((const float*)b.hs[d])[e * npad + i];
+            } else {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) s[d] = ((const double*)b.hs[d])[e * npad + i];
+            }
+        }
+        R wj[3];
+        if (MIX) {
+            const float4 w4 = b.wsh[j];
+            wj[0] = w4.x; wj[1] = w4.y; wj[2] = w4.z;
+        } else {
+            const double4 w4 = b.wh[j];
+            wj[0] = (R)w4.x; wj[1] = (R)w4.y; wj[2] = (R)w4.z;
+        }
+        R aw[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const R wa = lo ? wi[d] : wj[d], wb = lo ? wj[d] : wi[d];
+            aw[d] = aa * wa + ab * wb;
+        }
+        const R awn[3] = {aw[1] * n[2] - aw[2] * n[1], aw[2] * n[0] - aw[0] * n[2], aw[0] * n[1] - aw[1] * n[0]};
+        R vc[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) vc[d] = (va[d] - vb[d]) - awn[d];
+        const R vcn = (n[0] * vc[0] + n[1] * vc[1]) + n[2] * vc[2];
+        R vt[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) vt[d] = vc[d] - vcn * n[d];
+        const R sn = (n[0] * s[0] + n[1] * s[1]) + n[2] * s[2];
+        R pr[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) pr[d] = s[d] - sn * n[d];
+        const R ps = rsqrt_<R>((pr[0] * pr[0] + pr[1] * pr[1]) + pr[2] * pr[2]);
+        if (ps > (R)0) {
+            const R ss = rsqrt_<R>((s[0] * s[0] + s[1] * s[1]) + s[2] * s[2]);
+            const R fac = MIX ? ss * rrcp<R>(ps) : ss / ps;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) s[d] = pr[d] * fac;
+        } else {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) s[d] = pr[d];
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) s[d] = s[d] + C.dtR * vt[d];
+        const R ftmax = C.mukn * delta;
+        const R sl = rsqrt_<R>((s[0] * s[0] + s[1] * s[1]) + s[2] * s[2]);
+        if (C.kt * sl > ftmax) {
+            const R fac = MIX ? ftmax * rrcp<R>(C.kt * sl) : ftmax / (C.kt * sl);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) s[d] = s[d] * fac;
+            slid = true;
+        }
+        if (MIX) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ((float*)b.hs[d])[e * npad + i] = (float)s[d];
+        } else {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ((double*)b.hs[d])[e * npad + i] = (double)s[d];
+        }
+        contact = true;
+        const R ks[3] = {C.kt * s[0], C.kt * s[1], C.kt * s[2]};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) fc[d] = (C.kn * delta) * n[d] - ks[d];
+        const R nks[3] = {n[1] * ks[2] - n[2] * ks[1], n[2] * ks[0] - n[0] * ks[2], n[0] * ks[1] - n[1] * ks[0]};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) t[d] = ai * nks[d];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const R fs = fl[d] + fb[d] + fc[d];
+        f[d] = lo ? fs : -fs;
+    }
+    if (lo) {
+        // Sec. II.A, II.B, II.D: Sigma^X_ab -= F^X_a r_b / V, FP64
+        const double rr[3] = {dx * C.invV, dy * C.invV, dz * C.invV};
+#pragma unroll
+        for (int al = 0; al < 3; ++al)
+#pragma unroll
+            for (int be = 0; be < 3; ++be) {
+                addS(3 * al + be, -(double)fc[al] * rr[be]);
+                addS(9 + 3 * al + be, -(double)fl[al] * rr[be]);
+                addS(18 + 3 * al + be, -(double)fb[al] * rr[be]);
+            }
+    }
+    return true;
+}
+
+// i-side velocities as used by the pair arithmetic
+template <bool MIX>
+__device__ __forceinline__ void load_vw(const Bufs& b, uint32_t i, typename EvalCtx<MIX>::R* vi,
+                                        typename EvalCtx<MIX>::R* wi) {
+    using R = typename EvalCtx<MIX>::R;
+    if (MIX) {
+        const float4 v4 = b.vsh[i], w4 = b.wsh[i];
+        vi[0] = v4.x; vi[1] = v4.y; vi[2] = v4.z;
+        wi[0] = w4.x; wi[1] = w4.y; wi[2] = w4.z;
+    } else {
+        const double4 v4 = b.vh[i], w4 = b.wh[i];
+        vi[0] = (R)v4.x; vi[1] = (R)v4.y; vi[2] = (R)v4.z;
+        wi[0] = (R)w4.x; wi[1] = (R)w4.y; wi[2] = (R)w4.z;
+    }
+}
+
+// stores the force and torque of particle i, applies kick 2, flags non-finite values
+template <bool MIX>
+__device__ __forceinline__ void store_particle(const Bufs& b, const RepParams& P, int kick, uint32_t i,
+                                               const double* Ft, const double* Tt, uint64_t cm, uint64_t sm,
+                                               bool& bad) {
+    bad = !(isfinite(Ft[0]) && isfinite(Ft[1]) && isfinite(Ft[2]) && isfinite(Tt[0]) && isfinite(Tt[1]) &&
+            isfinite(Tt[2]));
+    b.cmask[i] = cm;
+    b.smask[i] = sm;
+    if (MIX) {
+        ((float4*)b.F)[i] = make_float4((float)Ft[0], (float)Ft[1], (float)Ft[2], 0.0f);
+        ((float4*)b.T)[i] = make_float4((float)Tt[0], (float)Tt[1], (float)Tt[2], 0.0f);
+    } else {
+        ((double4*)b.F)[i] = make_double4(Ft[0], Ft[1], Ft[2], 0.0);
+        ((double4*)b.T)[i] = make_double4(Tt[0], Tt[1], Tt[2], 0.0);
+    }
+    // kick 2 of velocity-Verlet
+    double4 vf = b.vh[i], wf = b.wh[i];
+    if (kick) {
+        const double a = b.pos[i].w;
+        const double m = (4.0 / 3.0) * kPi * P.rho * a * a * a;
+        const double I = 0.4 * m * a * a;
+        const double hm = P.half_dt / m, hI = P.half_dt / I;
+        vf.x += hm * Ft[0]; vf.y += hm * Ft[1]; vf.z += hm * Ft[2];
+        wf.x += hI * Tt[0]; wf.y += hI * Tt[1]; wf.z += hI * Tt[2];
+    }
+    b.vf[i] = vf;
+    b.wf[i] = wf;
+}
+
+// block partial of the 27 stress sums held in thread-private LDS slots sacc[c][thread]
+// (fixed order), stored for the reduction by a later launch; blockDim = NT
+template <int NT>
+__device__ __forceinline__ void write_block_partial(const Bufs& b, int q, double (*sacc)[NT]) {
+    __syncthreads();
+    __shared__ double quarter[108];
+    if (threadIdx.x < 108) {
+        const int c = threadIdx.x >> 2, k0 = (threadIdx.x & 3) * (NT / 4);
+        double t = 0.0;
+        for (int k = 0; k < NT / 4; ++k) t += sacc[c][k0 + k];
+        quarter[threadIdx.x] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 27) {
+        const int c = threadIdx.x;
+        const double t = ((quarter[4 * c] + quarter[4 * c + 1]) + quarter[4 * c + 2]) + quarter[4 * c + 3];
+        b.partial[((size_t)q * 27 + c) * b.nblk_max + blockIdx.x] = t;
+    }
+}
+
+// thread-private accumulation in LDS (each slot has one writer)
+struct LdsStress {
+    double* row0;  // &sacc[0][threadIdx.x]
+    int stride;
+    __device__ __forceinline__ void operator()(int c, double v) const { lds_add(row0 + c * stride, v); }
+};
+
+// ---------------------------------------------------------------------------
+// Variant 1: LN consecutive lanes share one particle and split its items
+// (e = sub, sub + LN, ...); lanes combine in a fixed butterfly.  With LN = 1
+// the items of a particle are summed by one lane in item order.
+// ---------------------------------------------------------------------------
+template <bool MIX, int LN>
+__global__ __launch_bounds__(kPairBlock) void k_pair(Bufs b, int q, int kick, int advance, uint32_t only_rep) {
+    using R = typename std::conditional<MIX, float, double>::type;
+    if (b.sys->halted) return;  // the host rebuilds the lists and repeats this launch
+    // the first blocks also reduce the stress of the previous evaluation (its partials
+    // have the other parity); with more blocks than compute units this costs little
+    finalize_all(b, 1 - q);
+    const uint32_t i = (blockIdx.x * kPairBlock + threadIdx.x) / LN;
+    const uint32_t sub = threadIdx.x % LN;
+    const uint32_t r = b.blk_rep[i / kTile];
+    if (only_rep != 0xFFFFFFFFu && r != only_rep) return;  // whole block belongs to one replica
+    const RepParams& P = b.reps[r];
+    RepDyn& D = b.dyn[r];
+    double s_le;
+    uint64_t step;
+    if (!eval_begin(b, q, advance, P, D, blockIdx.x == P.p_begin * LN / kPairBlock, s_le, step)) return;
+    EvalCtx<MIX> C;
+    make_ctx<MIX>(C, P, s_le, step);
+
     __shared__ double sacc[27][kPairBlock];
 #pragma unroll
     for (int t = 0; t < 27; ++t) sacc[t][threadIdx.x] = 0.0;
+    const LdsStress addS{&sacc[0][threadIdx.x], kPairBlock};
     float maxov = 0.0f;
     bool bad = false;
 
     if (i - P.p_begin < P.n) {
         const double4 pi = b.pos[i];
         const uint32_t idi = b.id[i];
-        const uint32_t k0 = (uint32_t)P.seed, k1 = (uint32_t)(P.seed >> 32);
-        const uint32_t ctr_lo = (uint32_t)step, ctr_hi = (uint32_t)(step >> 32) << 8;
         R vi[3], wi[3];
-        if (MIX) {
-            const float4 v4 = b.vsh[i], w4 = b.wsh[i];
-            vi[0] = v4.x; vi[1] = v4.y; vi[2] = v4.z;
-            wi[0] = w4.x; wi[1] = w4.y; wi[2] = w4.z;
-        } else {
-            const double4 v4 = b.vh[i], w4 = b.wh[i];
-            vi[0] = (R)v4.x; vi[1] = (R)v4.y; vi[2] = (R)v4.z;
-            wi[0] = (R)w4.x; wi[1] = (R)w4.y; wi[2] = (R)w4.z;
-        }
-        const R ai = (R)pi.w;
-        const double c1 = P.c1;
-        const R bamp = (R)P.bamp;
-        const R eta6pi = (R)(6.0 * kPi * P.eta);
-        const R xi_min = (R)P.xi_min;
-        const R kn = (R)P.kn, kt = (R)P.kt, mukn = (R)(P.mu * P.kn), dtR = (R)P.dt;
-        const bool do_lub = !(P.flags & F_NO_LUB), do_br = !(P.flags & F_NO_PAIR_BROWN);
-        const bool do_ct = !(P.flags & F_NO_CONTACT);
-
+        load_vw<MIX>(b, i, vi, wi);
         Acc<R> F, T;
         const uint32_t cnt = b.ncnt[i];
-        const uint32_t items = cnt + ((P.flags & F_NO_ONEBODY) ? 0u : 2u);
+        const uint32_t items = cnt + (C.do_one ? 2u : 0u);
         const uint64_t cm_old = b.cmask[i];
         uint64_t cm = 0ull, sm = 0ull;
-
-        for (uint32_t e = sub; e < items; e += LN) {
-            const bool pair = e < cnt;
-            // ---- geometry of a pair item (FP64), or nothing for a one-body item
-            uint32_t j = 0, idj = 0;
-            double4 pj = make_double4(0.0, 0.0, 0.0, 0.0);
-            bool lo = true;
-            double dx = 0.0, dy = 0.0, dz = 0.0, h = 0.0;
-            int ky = 0;
-            R n[3] = {(R)0, (R)0, (R)0}, XA = (R)0, YA = (R)0;
-            if (pair) {
-                j = b.nbr[e * npad + i];
-                pj = b.pos[j];
-                idj = b.id[j];
-                lo = idi < idj;  // this lane holds the lower id
-                ky = lo ? min_image(P, s_le, pi, pj, dx, dy, dz) : min_image(P, s_le, pj, pi, dx, dy, dz);
-                const double d2 = (dx * dx + dy * dy) + dz * dz;
-                const double sa = pi.w + pj.w;
-                const double rc = sa * c1;
-                if (!(d2 <= rc * rc)) continue;
-                const double dist = sqrt(d2);
-                h = dist - sa;
-                const R inv = rrcp<R>((R)dist);
-                n[0] = (R)dx * inv; n[1] = (R)dy * inv; n[2] = (R)dz * inv;
-                const R aj = (R)pj.w;
-                const R aa = lo ? ai : aj, ab = lo ? aj : ai;
-                const R xi = (R)(2.0 * h) * rrcp<R>((R)sa);
-                const R xie = xi < xi_min ? xi_min : xi;
-                // resistance scalars X^A_11, Y^A_11 (Sec. II.B) in the symmetric form
-                const R pab = aa * ab, qab = aa * aa + ab * ab;
-                const R sR = aa + ab;
-                const R pre = eta6pi * rrcp<R>(sR * sR * sR);
-                const R lg = -rlog<R>(xie);
-                XA = pre * ((R)2 * pab * pab * rrcp<R>(xie) + pab * (qab + (R)7 * pab) * (R)0.2 * lg);
-                YA = pre * ((R)4 * pab * ((R)2 * qab + pab) * (R)(1.0 / 15.0) * lg);
-            }
-            // ---- one Philox block -> three normals (shared by both kinds of item)
-            R th[3] = {(R)0, (R)0, (R)0};
-            const bool noise = pair ? do_br : true;
-            if (noise) {
-                const uint32_t ida = pair ? (lo ? idi : idj) : idi;
-                const uint32_t idb = pair ? (lo ? idj : idi) : 0xFFFFFFFFu;
-                const uint32_t stream = pair ? 0u : (e - cnt == 0 ? 2u : 3u);
-                const uint4 w = philox10(ctr_lo, ida, idb, ctr_hi | stream, k0, k1);
-                normals3(w, th);
-            }
-            if (!pair) {
-                // eq. (force_drag) + (force_brownian_drag), or (torque_drag) + (torque_brownian_drag)
-                const double a = pi.w;
-                if (e - cnt == 0) {
-                    const R zeta = (R)(6.0 * kPi * P.eta * a);
-                    const R sz = rsqrt_<R>(zeta);
-                    const R uinf[3] = {(R)(P.gd * (pi.y - 0.5 * P.L[1])), (R)0, (R)0};
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) F.add(d, zeta * (uinf[d] - vi[d]) + bamp * sz * th[d]);
-                } else {
-                    const R zr = (R)(8.0 * kPi * P.eta * a * a * a);
-                    const R szr = rsqrt_<R>(zr);
-                    const R oinf[3] = {(R)0, (R)0, (R)(-0.5 * P.gd)};
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) T.add(d, zr * (oinf[d] - wi[d]) + bamp * szr * th[d]);
-                }
+        for (uint32_t k = sub; k < items; k += LN) {
+            const uint32_t e = k < cnt ? k : kItemForce + (k - cnt);
+            R f[3], t[3];
+            bool contact, slid;
+            if (!eval_item<MIX>(b, P, C, i, e, pi, idi, vi, wi, k < cnt && ((cm_old >> k) & 1ull), f, t, contact,
+                                slid, maxov, addS))
                 continue;
+            if (contact) {
+                cm |= 1ull << k;
+                if (slid) sm |= 1ull << k;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) T.add(d, t[d]);
+            } else if (e == kItemTorque) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) T.add(d, t[d]);
             }
-
-            // ---- pair item: velocities in canonical orientation; b's image moves with +k_y gammadot Ly
-            R va[3], vb[3], vj[3];
-            const R shiftv = (R)((double)ky * P.gdLy);
-            if (MIX) {
-                const float4 v4 = b.vsh[j];
-                vj[0] = v4.x; vj[1] = v4.y; vj[2] = v4.z;
-            } else {
-                const double4 v4 = b.vh[j];
-                vj[0] = (R)v4.x; vj[1] = (R)v4.y; vj[2] = (R)v4.z;
-            }
+            if (e != kItemTorque) {
 #pragma unroll
-            for (int d = 0; d < 3; ++d) { va[d] = lo ? vi[d] : vj[d]; vb[d] = lo ? vj[d] : vi[d]; }
-            vb[0] = vb[0] + shiftv;
-
-            R fl[3] = {(R)0, (R)0, (R)0}, fb[3] = {(R)0, (R)0, (R)0}, fc[3] = {(R)0, (R)0, (R)0};
-            if (do_lub) {
-                // eq. (force_lub): (X^A N + Y^A T)(U_b - U_a)
-                R ur[3];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) ur[d] = vb[d] - va[d];
-                const R un = (n[0] * ur[0] + n[1] * ur[1]) + n[2] * ur[2];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) fl[d] = XA * (un * n[d]) + YA * (ur[d] - un * n[d]);
-            }
-            if (do_br) {
-                // eq. (force_brownian_lub): sqrt(2kT/dt) (sqrt(X^A) N + sqrt(Y^A) T) theta
-                const R tn = (n[0] * th[0] + n[1] * th[1]) + n[2] * th[2];
-                const R sx = rsqrt_<R>(XA), sy = rsqrt_<R>(YA);
-#pragma unroll
-                for (int d = 0; d < 3; ++d) fb[d] = bamp * (sx * (tn * n[d]) + sy * (th[d] - tn * n[d]));
-            }
-            if (h < 0.0 && do_ct) {
-                // eq. (force_contact), (torque_contact); the spring s lives in canonical orientation
-                const R aj = (R)pj.w;
-                const R aa = lo ? ai : aj, ab = lo ? aj : ai;
-                const R delta = (R)(-h);
-                if ((float)(-h) > maxov) maxov = (float)(-h);
-                if (!MIX) {
-                    // the spring is updated with the correctly rounded normal (bit-reproducible history)
-                    const double dist = sqrt((dx * dx + dy * dy) + dz * dz);
-                    n[0] = (R)(dx / dist); n[1] = (R)(dy / dist); n[2] = (R)(dz / dist);
-                }
-                R s[3] = {(R)0, (R)0, (R)0};
-                if ((cm_old >> e) & 1ull) {
-                    if (MIX) {
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) s[d] = ((const float*)b.hs[d])[e * npad + i];
-                    } else {
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) s[d] = ((const double*)b.hs[d])[e * npad + i];
-                    }
-                }
-                R wj[3];
-                if (MIX) {
-                    const float4 w4 = b.wsh[j];
-                    wj[0] = w4.x; wj[1] = w4.y; wj[2] = w4.z;
-                } else {
-                    const double4 w4 = b.wh[j];
-                    wj[0] = (R)w4.x; wj[1] = (R)w4.y; wj[2] = (R)w4.z;
-                }
-                R aw[3];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const R wa = lo ? wi[d] : wj[d], wb = lo ? wj[d] : wi[d];
-                    aw[d] = aa * wa + ab * wb;
-                }
-                const R awn[3] = {aw[1] * n[2] - aw[2] * n[1], aw[2] * n[0] - aw[0] * n[2],
-                                  aw[0] * n[1] - aw[1] * n[0]};
-                R vc[3];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) vc[d] = (va[d] - vb[d]) - awn[d];
-                const R vcn = (n[0] * vc[0] + n[1] * vc[1]) + n[2] * vc[2];
-                R vt[3];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) vt[d] = vc[d] - vcn * n[d];
-                const R sn = (n[0] * s[0] + n[1] * s[1]) + n[2] * s[2];
-                R pr[3];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) pr[d] = s[d] - sn * n[d];
-                const R ps = rsqrt_<R>((pr[0] * pr[0] + pr[1] * pr[1]) + pr[2] * pr[2]);
-                if (ps > (R)0) {
-                    const R ss = rsqrt_<R>((s[0] * s[0] + s[1] * s[1]) + s[2] * s[2]);
-                    const R fac = MIX ? ss * rrcp<R>(ps) : ss / ps;
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) s[d] = pr[d] * fac;
-                } else {
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) s[d] = pr[d];
-                }
-#pragma unroll
-                for (int d = 0; d < 3; ++d) s[d] = s[d] + dtR * vt[d];
-                const R ftmax = mukn * delta;
-                const R sl = rsqrt_<R>((s[0] * s[0] + s[1] * s[1]) + s[2] * s[2]);
-                if (kt * sl > ftmax) {
-                    const R fac = MIX ? ftmax * rrcp<R>(kt * sl) : ftmax / (kt * sl);
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) s[d] = s[d] * fac;
-                    sm |= 1ull << e;
-                }
-                if (MIX) {
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) ((float*)b.hs[d])[e * npad + i] = (float)s[d];
-                } else {
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) ((double*)b.hs[d])[e * npad + i] = (double)s[d];
-                }
-                cm |= 1ull << e;
-                const R ks[3] = {kt * s[0], kt * s[1], kt * s[2]};
-#pragma unroll
-                for (int d = 0; d < 3; ++d) fc[d] = (kn * delta) * n[d] - ks[d];
-                const R nks[3] = {n[1] * ks[2] - n[2] * ks[1], n[2] * ks[0] - n[0] * ks[2],
-                                  n[0] * ks[1] - n[1] * ks[0]};
-#pragma unroll
-                for (int d = 0; d < 3; ++d) T.add(d, ai * nks[d]);
-            }
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const R f = fl[d] + fb[d] + fc[d];
-                F.add(d, lo ? f : -f);
-            }
-            if (lo) {
-                // Sec. II.A, II.B, II.D: Sigma^X_ab -= F^X_a r_b / V, FP64
-                const double rr[3] = {dx * P.invV, dy * P.invV, dz * P.invV};
-#pragma unroll
-                for (int al = 0; al < 3; ++al)
-#pragma unroll
-                    for (int be = 0; be < 3; ++be) {
-                        lds_add(&sacc[3 * al + be][threadIdx.x], -(double)fc[al] * rr[be]);
-                        lds_add(&sacc[9 + 3 * al + be][threadIdx.x], -(double)fl[al] * rr[be]);
-                        lds_add(&sacc[18 + 3 * al + be][threadIdx.x], -(double)fb[al] * rr[be]);
-                    }
+                for (int d = 0; d < 3; ++d) F.add(d, f[d]);
             }
         }
-
         // combine the LN lanes of the particle (fixed butterfly order)
         double Ft[3], Tt[3];
 #pragma unroll
@@ -973,53 +1120,191 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(Bufs b, int q, int kick, in
             cm |= __shfl_xor(cm, 4);
             sm |= __shfl_xor(sm, 4);
         }
-
-        if (sub == 0) {
-            bad = !(isfinite(Ft[0]) && isfinite(Ft[1]) && isfinite(Ft[2]) && isfinite(Tt[0]) && isfinite(Tt[1]) &&
-                    isfinite(Tt[2]));
-            b.cmask[i] = cm;
-            b.smask[i] = sm;
-            if (MIX) {
-                ((float4*)b.F)[i] = make_float4((float)Ft[0], (float)Ft[1], (float)Ft[2], 0.0f);
-                ((float4*)b.T)[i] = make_float4((float)Tt[0], (float)Tt[1], (float)Tt[2], 0.0f);
-            } else {
-                ((double4*)b.F)[i] = make_double4(Ft[0], Ft[1], Ft[2], 0.0);
-                ((double4*)b.T)[i] = make_double4(Tt[0], Tt[1], Tt[2], 0.0);
-            }
-            // kick 2 of velocity-Verlet
-            double4 vf = b.vh[i], wf = b.wh[i];
-            if (kick) {
-                const double a = pi.w;
-                const double m = (4.0 / 3.0) * kPi * P.rho * a * a * a;
-                const double I = 0.4 * m * a * a;
-                const double hm = P.half_dt / m, hI = P.half_dt / I;
-                vf.x += hm * Ft[0]; vf.y += hm * Ft[1]; vf.z += hm * Ft[2];
-                wf.x += hI * Tt[0]; wf.y += hI * Tt[1]; wf.z += hI * Tt[2];
-            }
-            b.vf[i] = vf;
-            b.wf[i] = wf;
-        }
+        if (sub == 0) store_particle<MIX>(b, P, kick, i, Ft, Tt, cm, sm, bad);
     }
 
     // health: non-finite forces, largest overlap (relaxed atomics; read after the launch)
     if (bad) atomicOr(&D.health, H_NAN);
     block_atomic_max(maxov, D.maxov_bits[q]);
+    write_block_partial<kPairBlock>(b, q, sacc);
+}
 
-    // block partial of the 27 stress sums in a fixed order; reduced by a later launch.
-    // Thread t < 108 sums a quarter (32 slots) of component t / 4.
-    __syncthreads();
-    __shared__ double quarter[108];
-    if (threadIdx.x < 108) {
-        const int c = threadIdx.x >> 2, k0 = (threadIdx.x & 3) * (kPairBlock / 4);
-        double t = 0.0;
-        for (int k = 0; k < kPairBlock / 4; ++k) t += sacc[c][k0 + k];
-        quarter[threadIdx.x] = t;
+// ---------------------------------------------------------------------------
+// Variant 2 (wave-cooperative): a wave owns NP = 64 / LN particles.  Its lanes
+// first test the list entries (LN lanes per particle) and build, per
+// particle, the list of its items; the wave packs these lists into chunks of
+// 64 items without splitting a particle across chunks, then evaluates one
+// chunk at a time with every lane on one item, so lanes stay busy whatever
+// the spread of neighbour counts and interactions.  The last lane of each
+// particle's run sums the run's contributions from LDS in item order.
+// ---------------------------------------------------------------------------
+template <bool MIX, int LN>
+__global__ __launch_bounds__(256) void k_pairq(Bufs b, int q, int kick, int advance, uint32_t only_rep) {
+    using R = typename std::conditional<MIX, float, double>::type;
+    constexpr int NP = 64 / LN;  // particles per wave
+    if (b.sys->halted) return;
+    finalize_all(b, 1 - q);
+    const int w = threadIdx.x >> 6, p = threadIdx.x & 63;
+    const uint32_t base = (blockIdx.x * 4 + w) * NP;  // first particle of this wave
+    const uint32_t r = b.blk_rep[base / kTile];       // a block (4 NP <= 256 particles) is inside one tile
+    if (only_rep != 0xFFFFFFFFu && r != only_rep) return;
+    const RepParams& P = b.reps[r];
+    RepDyn& D = b.dyn[r];
+    double s_le;
+    uint64_t step;
+    if (!eval_begin(b, q, advance, P, D, blockIdx.x == P.p_begin / (4 * NP), s_le, step)) return;
+    EvalCtx<MIX> C;
+    make_ctx<MIX>(C, P, s_le, step);
+    const uint32_t npad = b.npad;
+
+    __shared__ uint16_t queue[4][NP * 64];   // items: particle slot << 8 | item code; 0xFFFF = empty
+    __shared__ uint32_t seg0[4][NP], nitems[4][NP];
+    __shared__ unsigned long long cmq[4][NP], smq[4][NP];
+    __shared__ R fbuf[4][6][64];
+    __shared__ uint8_t isct[4][64];
+    __shared__ uint32_t total_[4];
+
+    // ---- cull: which list entries interact (LN lanes per particle)
+    const uint32_t l = p / LN, sub = p % LN;
+    const uint32_t i = base + l;
+    const bool valid = i - P.p_begin < P.n;
+    uint64_t im = 0ull;
+    if (valid) {
+        const double4 pi = b.pos[i];
+        const uint32_t cnt = b.ncnt[i];
+        for (uint32_t e = sub; e < cnt; e += LN)
+            if (interacting(P, s_le, pi, b.pos[b.nbr[e * npad + i]])) im |= 1ull << e;
+    }
+    if (LN >= 2) im |= dpp_u64<0xB1>(im);
+    if (LN >= 4) im |= dpp_u64<0x4E>(im);
+    if (LN >= 8) im |= __shfl_xor(im, 4);
+    const uint32_t npair = (uint32_t)__popcll(im);
+    const uint32_t nk = valid ? npair + (C.do_one ? 2u : 0u) : 0u;
+    if (sub == 0) {
+        nitems[w][l] = nk;
+        cmq[w][l] = 0ull;
+        smq[w][l] = 0ull;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    // ---- pack: runs of items, never split across a 64-item chunk
+    if (p == 0) {
+        uint32_t off = 0;
+        for (int l2 = 0; l2 < NP; ++l2) {
+            const uint32_t len = nitems[w][l2];
+            if ((off & 63u) + len > 64u) off = (off + 63u) & ~63u;
+            seg0[w][l2] = off;
+            off += len;
+        }
+        total_[w] = off;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const uint32_t total = total_[w];
+    for (uint32_t s = p; s < total; s += 64) queue[w][s] = 0xFFFFu;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (valid) {
+        const uint32_t s0 = seg0[w][l];
+        uint64_t m = im;
+        uint32_t k = 0;
+        while (m) {
+            const uint32_t e = (uint32_t)__builtin_ctzll(m);
+            if (k % LN == sub) queue[w][s0 + k] = (uint16_t)((l << 8) | e);
+            m &= m - 1ull;
+            ++k;
+        }
+        if (C.do_one) {
+            if (k % LN == sub) queue[w][s0 + k] = (uint16_t)((l << 8) | kItemForce);
+            if ((k + 1) % LN == sub) queue[w][s0 + k + 1] = (uint16_t)((l << 8) | kItemTorque);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+
+    // ---- evaluate chunk by chunk
+    double acc[27];
+#pragma unroll
+    for (int c = 0; c < 27; ++c) acc[c] = 0.0;
+    auto addS = [&](int c, double v) { acc[c] += v; };
+    float maxov = 0.0f;
+    bool bad = false;
+    for (uint32_t c0 = 0; c0 < total; c0 += 64) {
+        const uint32_t code = c0 + p < total ? (uint32_t)queue[w][c0 + p] : 0xFFFFu;
+        R f[3] = {(R)0, (R)0, (R)0}, t[3] = {(R)0, (R)0, (R)0};
+        uint32_t li = 0;
+        uint8_t ct = 0;
+        if (code != 0xFFFFu) {
+            li = code >> 8;
+            const uint32_t e = code & 0xFFu;
+            const uint32_t ii = base + li;
+            const double4 pi = b.pos[ii];
+            const uint32_t idi = b.id[ii];
+            R vi[3], wi[3];
+            load_vw<MIX>(b, ii, vi, wi);
+            const bool had = e < kItemForce && ((b.cmask[ii] >> e) & 1ull);
+            bool contact, slid;
+            eval_item<MIX>(b, P, C, ii, e, pi, idi, vi, wi, had, f, t, contact, slid, maxov, addS);
+            if (contact) {
+                ct = 1;
+                atomicOr(&cmq[w][li], 1ull << e);
+                if (slid) atomicOr(&smq[w][li], 1ull << e);
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            fbuf[w][d][p] = f[d];
+            fbuf[w][3 + d][p] = t[d];
+        }
+        isct[w][p] = ct;
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (code != 0xFFFFu) {
+            const uint32_t first = seg0[w][li] - c0, len = nitems[w][li];
+            if (p == first + len - 1) {
+                // last item of the particle's run: sum the run in item order
+                Acc<R> F, T;
+                for (uint32_t k = first; k <= (uint32_t)p; ++k) {
+                    const uint32_t ck = queue[w][c0 + k] & 0xFFu;
+                    if (ck != kItemTorque) {
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) F.add(d, fbuf[w][d][k]);
+                    }
+                    if (ck == kItemTorque || isct[w][k]) {
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) T.add(d, fbuf[w][3 + d][k]);
+                    }
+                }
+                double Ft[3], Tt[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) { Ft[d] = F.get(d); Tt[d] = T.get(d); }
+                store_particle<MIX>(b, P, kick, base + li, Ft, Tt, cmq[w][li], smq[w][li], bad);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    // particles without any item (all terms switched off, no interacting pair)
+    if (valid && sub == 0 && nk == 0) {
+        const double z[3] = {0.0, 0.0, 0.0};
+        store_particle<MIX>(b, P, kick, i, z, z, 0ull, 0ull, bad);
+    }
+
+    if (bad) atomicOr(&D.health, H_NAN);
+    block_atomic_max(maxov, D.maxov_bits[q]);
+    // block partial of the stress: fixed-order sum over the block's lanes (DPP rows, then LDS)
+    __shared__ double rows[16][27];
+#pragma unroll
+    for (int c = 0; c < 27; ++c) {
+        const double v = row_sum_f64(acc[c]);
+        if ((p & 15) == 15) rows[threadIdx.x >> 4][c] = v;
     }
     __syncthreads();
     if (threadIdx.x < 27) {
         const int c = threadIdx.x;
-        const double t = ((quarter[4 * c] + quarter[4 * c + 1]) + quarter[4 * c + 2]) + quarter[4 * c + 3];
-        b.partial[((size_t)q * 27 + c) * b.nblk_max + blockIdx.x] = t;
+        double tsum = 0.0;
+        for (int k = 0; k < 16; ++k) tsum += rows[k][c];
+        b.partial[((size_t)q * 27 + c) * b.nblk_max + blockIdx.x] = tsum;
     }
 }
 
@@ -1097,6 +1382,16 @@ void launch_rebuild(const Bufs& b, hipStream_t st, int q, int in_step, uint32_t 
 
 template <bool MIX>
 static void launch_pair_t(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep) {
+    if (b.kern == 1) {  // wave-cooperative; 256-thread blocks of 4 * 64 / lanes particles
+        const dim3 blk(256);
+        const uint32_t g = b.npad / 256;
+        switch (b.lanes) {
+            case 1: hipLaunchKernelGGL((k_pairq<MIX, 1>), dim3(g), blk, 0, st, b, q, kick, advance, only_rep); break;
+            case 2: hipLaunchKernelGGL((k_pairq<MIX, 2>), dim3(2 * g), blk, 0, st, b, q, kick, advance, only_rep); break;
+            default: hipLaunchKernelGGL((k_pairq<MIX, 4>), dim3(4 * g), blk, 0, st, b, q, kick, advance, only_rep); break;
+        }
+        return;
+    }
     const dim3 blk(kPairBlock);
     const uint32_t g = b.npad / kPairBlock;
     switch (b.lanes) {

@@ -152,6 +152,12 @@ int validate(const sim_config* c, const double* radii, std::string& why) {
         why = "lanes must be 0, 1, 2, 4 or 8";
         return SIM_EINVAL;
     }
+    if (c->pair_kernel > SIM_KERNEL_WAVE) { why = "unknown pair_kernel"; return SIM_EINVAL; }
+    if (c->pair_kernel == SIM_KERNEL_WAVE && (c->lanes == 8 || c->nlist_cap > 62)) {
+        why = "the wave kernel needs lanes <= 4 and nlist_cap <= 62";
+        return SIM_EINVAL;
+    }
+    if (c->reserved != 0) { why = "reserved field must be 0"; return SIM_EINVAL; }
     if (c->n == 0 || c->n >= 0xFFFFFFFFu) { why = "n must be in [1, 2^32-2]"; return SIM_EINVAL; }
     if (!radii) { why = "null radii"; return SIM_EINVAL; }
     for (uint32_t i = 0; i < c->n; ++i)
@@ -317,17 +323,38 @@ void set_dyn(sim* s, int r, double s_le, uint64_t step) {
     s->ring_tail[r] = 0;
 }
 
-// Lanes per particle for the pair kernel: the fastest of 1, 2, 4, 8 over a few
-// evaluations of the actual system (few lanes suit large systems, more lanes
-// hide gather latency when particles are too few to fill the GPU).
-void tune_lanes(sim* s) {
+// Pair-kernel variant (lanes split items / wave-cooperative) and lanes per
+// particle: the fastest candidate over a few evaluations of the actual system
+// (few lanes suit large systems, more lanes hide gather latency when particles
+// are too few to fill the GPU).  want_kern / want_lanes: 0 = free.
+void set_variant(sim* s, int kern, int lanes) {
+    s->b.kern = kern;
+    s->b.lanes = lanes;
+    s->b.ppb = kern == 1 ? 256 / lanes : 128 / lanes;
+}
+
+void tune_pair(sim* s, int want_kern, int want_lanes) {
+    std::vector<std::pair<int, int>> cand;
+    for (int kern : {0, 1}) {
+        if (want_kern && want_kern - 1 != kern) continue;
+        if (kern == 1 && s->b.cap > 62) continue;
+        for (int L : {1, 2, 4, 8}) {
+            if (want_lanes && want_lanes != L) continue;
+            if (kern == 1 && L == 8) continue;
+            cand.push_back({kern, L});
+        }
+    }
+    if (cand.size() == 1) {
+        set_variant(s, cand[0].first, cand[0].second);
+        return;
+    }
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     float best = 1e30f;
-    int best_l = 1;
-    for (int L : {1, 2, 4, 8}) {
-        s->b.lanes = L;
+    std::pair<int, int> pick = cand[0];
+    for (auto c : cand) {
+        set_variant(s, c.first, c.second);
         launch_pair_force(s->b, s->st, s->par, 0, 0, 0xFFFFFFFFu);
         HIPCHK(hipEventRecord(e0, s->st));
         for (int k = 0; k < 4; ++k) launch_pair_force(s->b, s->st, s->par, 0, 0, 0xFFFFFFFFu);
@@ -337,12 +364,12 @@ void tune_lanes(sim* s) {
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
         if (ms < best) {
             best = ms;
-            best_l = L;
+            pick = c;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    s->b.lanes = best_l;
+    set_variant(s, pick.first, pick.second);
 }
 
 int check_rep(sim* s, int32_t r) {
@@ -380,8 +407,8 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         std::string why;
         if (validate(&cfgs[r], radii[r], why) != SIM_OK) return fail(nullptr, SIM_EINVAL, fmt("replica %d: %s", r, why.c_str()));
         if (cfgs[r].precision != cfgs[0].precision || cfgs[r].flags != cfgs[0].flags ||
-            cfgs[r].lanes != cfgs[0].lanes)
-            return fail(nullptr, SIM_EINVAL, "precision, flags and lanes must be equal for all replicas");
+            cfgs[r].lanes != cfgs[0].lanes || cfgs[r].pair_kernel != cfgs[0].pair_kernel)
+            return fail(nullptr, SIM_EINVAL, "precision, flags, lanes and pair_kernel must be equal for all replicas");
         if (!x0[r]) return fail(nullptr, SIM_EINVAL, fmt("replica %d: null positions", r));
         for (uint32_t i = 0; i < 3 * cfgs[r].n; ++i) {
             const double L = cfgs[r].box[i % 3];
@@ -508,15 +535,11 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         }
         s->step_now = cfgs[0].step0;
         launch_rebuild(b, s->st, 1 - s->par, 0, 0xFFFFFFFEu);
-        b.lanes = 1;
-        if (cfgs[0].lanes == 0) {
-            tune_lanes(s);
-            // the trial evaluations created springs: start again from an empty history
-            HIPCHK(hipMemsetAsync(b.cmask, 0, sizeof(uint64_t) * b.npad, s->st));
-            HIPCHK(hipMemsetAsync(b.smask, 0, sizeof(uint64_t) * b.npad, s->st));
-        } else {
-            b.lanes = (int)cfgs[0].lanes;
-        }
+        set_variant(s, 0, 1);
+        tune_pair(s, (int)cfgs[0].pair_kernel, (int)cfgs[0].lanes);
+        // trial evaluations created springs: start again from the empty history
+        HIPCHK(hipMemsetAsync(b.cmask, 0, sizeof(uint64_t) * b.npad, s->st));
+        HIPCHK(hipMemsetAsync(b.smask, 0, sizeof(uint64_t) * b.npad, s->st));
         launch_pair_force(b, s->st, s->par, 0, 0, 0xFFFFFFFFu);
         launch_finalize(b, s->st, s->par);
         HIPCHK(hipGetLastError());
@@ -941,7 +964,7 @@ int sim_stats(sim* s, int32_t r, sim_stats_t* out) {
         out->step = d[0].step_slot[s->par];
         out->le_offset = d[0].s_slot[s->par];
         out->lanes = s->b.lanes;
-        out->pad = 0;
+        out->pair_kernel = s->b.kern == 1 ? SIM_KERNEL_WAVE : SIM_KERNEL_LANES;
         return SIM_OK;
     } catch (const HipError& e) {
         return hip_fail(s, e);

@@ -21,6 +21,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ECAPACITY, ERANGE = 0, -1, -2, -3, -4, -
 FP64, MIXED = 0, 1
 FREEZE_X, NO_LUB, NO_PAIR_BROWN, NO_CONTACT, NO_ONEBODY = 0x1, 0x2, 0x4, 0x8, 0x10
 REBUILD_EACH_STEP, NO_GRAPH = 0x100, 0x200
+KERNEL_AUTO, KERNEL_LANES, KERNEL_WAVE = 0, 1, 2
 STRESS_CONTACT, STRESS_LUB, STRESS_BROWN, STRESS_DRAG, STRESS_TOTAL = range(5)
 STRESS_LAST, STRESS_MEAN = 0, 1
 
@@ -41,7 +42,7 @@ class _Config(C.Structure):
                 ("xi_min", C.c_double), ("skin", C.c_double), ("le_offset0", C.c_double),
                 ("max_overlap", C.c_double), ("seed", C.c_uint64), ("step0", C.c_uint64),
                 ("precision", C.c_int32), ("flags", C.c_uint32), ("nlist_cap", C.c_uint32),
-                ("lanes", C.c_uint32)]
+                ("lanes", C.c_uint32), ("pair_kernel", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class _Stats(C.Structure):
@@ -49,7 +50,7 @@ class _Stats(C.Structure):
                 ("max_overlap", C.c_double), ("neighbours_per_particle", C.c_double),
                 ("interacting_per_particle", C.c_double), ("contacts", C.c_int64), ("rebuilds", C.c_int64),
                 ("steps", C.c_int64), ("step", C.c_uint64), ("le_offset", C.c_double), ("lanes", C.c_int32),
-                ("pad", C.c_int32)]
+                ("pair_kernel", C.c_int32)]
 
 
 class SimError(RuntimeError):
@@ -149,6 +150,7 @@ class Config:
     flags: int = 0
     nlist_cap: int = 0
     lanes: int = 0
+    pair_kernel: int = 0
 
     def c(self, n) -> _Config:
         c = _Config()
@@ -162,6 +164,8 @@ class Config:
         c.seed, c.step0 = int(self.seed), int(self.step0)
         c.precision, c.flags, c.nlist_cap = int(self.precision), int(self.flags), int(self.nlist_cap)
         c.lanes = int(self.lanes)
+        c.pair_kernel = int(self.pair_kernel)
+        c.reserved = 0
         return c
 
 

@@ -145,16 +145,34 @@ def test_step_trajectory_fp64(P):
             assert np.array_equal(sim.contacts()[0], orc.contacts()[0])
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
-def test_lanes_per_particle(P, lanes):
-    """Every split of the neighbour list over lanes gives the oracle's forces and exact springs."""
+@pytest.mark.parametrize("kernel, lanes", [(1, 1), (1, 2), (1, 4), (1, 8), (2, 1), (2, 2), (2, 4)])
+def test_pair_kernel_variants(P, kernel, lanes):
+    """Every pair-kernel variant gives the oracle's forces and exact springs."""
     st = _state(n=1500, phi=0.55, seed=7)
     for prec, tol, exact in ((P.FP64, TOL_F64, True), (P.MIXED, TOL_MIX, False)):
-        _say(f"case: lanes={lanes} precision={prec} N=1500 phi=0.55, 3 steps")
-        sim = P.Sim(_cfg(P, st, precision=prec, lanes=lanes), st["radii"], st["x"], st["v"], st["w"])
-        assert sim.stats()["lanes"] == lanes
+        _say(f"case: kernel={kernel} lanes={lanes} precision={prec} N=1500 phi=0.55")
+        sim = P.Sim(_cfg(P, st, precision=prec, lanes=lanes, pair_kernel=kernel), st["radii"], st["x"], st["v"],
+                    st["w"])
+        assert sim.stats()["lanes"] == lanes and sim.stats()["pair_kernel"] == kernel
         orc = O.Oracle(O.Params(L=st["L"], **st["params"]), st["radii"], st["x"], st["v"], st["w"])
         _compare_eval(P, sim, orc, tol, exact=exact)
+
+
+def test_wave_kernel_bit_identical_to_one_lane(P):
+    """The wave-cooperative kernel sums each particle's items in the same order as the
+    one-lane kernel: whole trajectories agree bit for bit, in both precisions."""
+    st = _state(n=2000, phi=0.55, seed=8)
+    for prec in (P.FP64, P.MIXED):
+        runs = []
+        for kernel, lanes in ((1, 1), (2, 1), (2, 2), (2, 4)):
+            _say(f"case: 60 steps precision={prec} kernel={kernel} lanes={lanes}")
+            sim = P.Sim(_cfg(P, st, precision=prec, lanes=lanes, pair_kernel=kernel), st["radii"], st["x"],
+                        st["v"], st["w"])
+            sim.step(60)
+            runs.append(sim.get_state())
+        for other in runs[1:]:
+            for key in ("x", "v", "w", "F", "T"):
+                assert np.array_equal(runs[0][key], other[key]), key
 
 
 def test_planned_rebuilds_match_rebuild_every_step(P):
