@@ -147,7 +147,9 @@ def main():
         "data": "synthetic: seeded relaxed bidisperse packing",
         "config": {"workload": wl.name, "n": n, "phi": wl.phi, "pe": wl.pe,
                    "gammadot": st["params"]["gammadot"], "kT": st["params"]["kT"], "mu": wl.mu,
-                   "dt": wl.dt, "hip_graph": True},
+                   "dt": wl.dt, "hip_graph": True,
+                   "pair_kernel": {1: "lanes", 2: "wave"}[f64["stats"]["pair_kernel"]],
+                   "lanes_per_particle": f64["stats"]["lanes"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_pair<false>", "kernel_ms": f64["pair_ms"], "bytes_per_particle": bpp,
@@ -162,6 +164,8 @@ def main():
         am = bm * n / (mix["pair_ms"] * 1e-3) / 1e9
         se = np.hypot(block_se(f64["eta_series"]), block_se(mix["eta_series"]))
         out["mixed"] = {"value": vm, "ms_per_step": mix["seconds"] * 1e3 / args.steps, "dtype": "f32 pair / f64 state",
+                        "pair_kernel": {1: "lanes", 2: "wave"}[mix["stats"]["pair_kernel"]],
+                        "lanes_per_particle": mix["stats"]["lanes"],
                         "speedup_vs_fp64": vm / value, "pair_kernel_ms": mix["pair_ms"],
                         "roofline_frac": am / HBM_PEAK_GBS, "achieved_GBs": am,
                         "eta_r": mix["eta_mean"],
