@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3"])
+    ap.add_argument("--variants", action="store_true",
+                    help="only run 20 steps of each pair-kernel variant (a counter-collection driver)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the engine has no multi-GPU path",
@@ -120,6 +122,17 @@ def main():
     st = gen.make_state(wl)
     n = len(st["radii"])
     print(f"workload ready: {wl.name}", file=sys.stderr, flush=True)
+    if args.variants:
+        for prec in (P.FP64, P.MIXED):
+            for kern, lanes in ((P.KERNEL_LANES, 1), (P.KERNEL_LANES, 2), (P.KERNEL_LANES, 4),
+                                (P.KERNEL_WAVE, 1), (P.KERNEL_WAVE, 2)):
+                cfg = P.Config(box=st["L"], precision=prec, lanes=lanes, pair_kernel=kern, **st["params"])
+                sim = P.Sim(cfg, st["radii"], st["x"], st["v"], st["w"])
+                sim.step(20)
+                torch.cuda.synchronize()
+                sim.close()
+                print(f"variant precision={prec} kernel={kern} lanes={lanes} done", file=sys.stderr, flush=True)
+        return
     f64 = run_gpu(P, st, P.FP64, args.steps, args.warmup, args.prof_steps)
     print(f"fp64 done: {n * args.steps / f64['seconds']:.3e} particle-steps/s", file=sys.stderr, flush=True)
     mix = None
