@@ -12,6 +12,7 @@
  * independent of the thread count.
  */
 #include <math.h>
+#include <stdio.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -41,6 +42,8 @@ double pack_relax(int n, const double *a, double *x, const double L[3], double t
     int *sorted = (int *)malloc(sizeof(int) * (size_t)n);
     double *dx = (double *)malloc(sizeof(double) * 3 * (size_t)n);
     double *ov = (double *)malloc(sizeof(double) * (size_t)n);
+    double *xs = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *as = (double *)malloc(sizeof(double) * (size_t)n);
     double maxov = 0.0;
     int it;
     for (it = 0; it < maxiter; ++it) {
@@ -59,8 +62,17 @@ double pack_relax(int n, const double *a, double *x, const double L[3], double t
         memset(ccount, 0, sizeof(int) * (size_t)ncell);
         for (int i = 0; i < n; ++i) sorted[cstart[cell[i]] + ccount[cell[i]]++] = i;
 
+        /* cell-ordered copies, so that the candidate loop reads memory in order */
 #pragma omp parallel for schedule(static)
-        for (int i = 0; i < n; ++i) {
+        for (int q = 0; q < n; ++q) {
+            const int i = sorted[q];
+            for (int d = 0; d < 3; ++d) xs[3 * q + d] = x[3 * i + d];
+            as[q] = a[i];
+        }
+
+#pragma omp parallel for schedule(static)
+        for (int qi = 0; qi < n; ++qi) {
+            int i = sorted[qi];
             int ci = cell[i];
             int cx = ci % nc[0], cy = (ci / nc[0]) % nc[1], cz = ci / (nc[0] * nc[1]);
             double acc[3] = {0, 0, 0};
@@ -77,11 +89,11 @@ double pack_relax(int n, const double *a, double *x, const double L[3], double t
                             if (j == i) continue;
                             double r[3];
                             for (int d = 0; d < 3; ++d) {
-                                double t = x[3 * i + d] - x[3 * j + d];
+                                double t = xs[3 * qi + d] - xs[3 * q + d];
                                 r[d] = t - L[d] * rint(t / L[d]);
                             }
                             double d2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-                            double sa = a[i] + a[j];
+                            double sa = as[qi] + as[q];
                             if (d2 >= sa * sa) continue;
                             double dist = sqrt(d2);
                             double o = sa - dist;
@@ -98,11 +110,16 @@ double pack_relax(int n, const double *a, double *x, const double L[3], double t
         }
         maxov = 0.0;
         for (int i = 0; i < n; ++i) if (ov[i] > maxov) maxov = ov[i];
+        if (n >= 200000 && it % 100 == 0) {
+            fprintf(stderr, "pack: n=%d sweep %d max overlap %.3e (tol %.1e)\n", n, it, maxov, tol);
+            fflush(stderr);
+        }
         if (maxov <= tol) break;
+#pragma omp parallel for schedule(static)
         for (int i = 0; i < n; ++i)
             for (int d = 0; d < 3; ++d) x[3 * i + d] = wrap(x[3 * i + d] + dx[3 * i + d], L[d]);
     }
     if (iters) *iters = it;
-    free(cstart); free(ccount); free(cell); free(sorted); free(dx); free(ov);
+    free(cstart); free(ccount); free(cell); free(sorted); free(dx); free(ov); free(xs); free(as);
     return maxov;
 }
