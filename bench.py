@@ -96,6 +96,207 @@ def cpu_baseline(st, seconds_target=15.0):
                        f"FP64, cell list rebuilt every step ({el:.1f} s)")
 
 
+def eta_now(sim, P, r, gd, eta):
+    """Relative viscosity of the last evaluation of replica r (contact + lubrication + drag, Sec. IV.D)."""
+    return sim.stress(r, P.STRESS_TOTAL, P.STRESS_LAST)[0, 1] / (eta * gd)
+
+
+def pair_time(sim, steps=100):
+    """Average pair-kernel duration (ms) over `steps` steps, HIP events on the library stream."""
+    sim.profile(True)
+    sim.step(steps)
+    launches, ms = sim.kernel_time()
+    sim.profile(False)
+    return ms / max(launches, 1)
+
+
+def run_mixed_vs_fp64(P, st, steps, sample_every, say):
+    """One workload in FP64 and in mixed precision from the same state and seed.
+
+    Viscosity error, two protocols:
+      * shadow: every `sample_every` steps the FP64 trajectory's state (positions,
+        velocities, springs, offset, step counter) is injected into an FP64 and a
+        mixed handle, which evaluate it; the relative difference of eta_r at
+        identical states is recorded, and of its mean over the samples;
+      * free-running: both precisions integrate independently; the difference of
+        the mean eta_r over the run is compared with its block standard error.
+    """
+    import numpy as np
+    import torch
+    p = st["params"]
+    gd, eta = p["gammadot"], p["eta"]
+    n = len(st["radii"])
+    mk = lambda prec: P.Sim(P.Config(box=st["L"], precision=prec, **p), st["radii"], st["x"], st["v"], st["w"])
+    traj = mk(P.FP64)
+    probe64 = mk(P.FP64)
+    probe32 = mk(P.MIXED)
+    say(f"  handles ready (n={n})")
+    t64 = 0.0
+    sh64, sh32 = [], []
+    done = 0
+    while done < steps:
+        k = min(sample_every, steps - done)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        traj.step(k)
+        torch.cuda.synchronize()
+        t64 += time.perf_counter() - t0
+        done += k
+        s = traj.get_state()
+        cij, cs, _ = traj.contacts()
+        for pr, acc in ((probe64, sh64), (probe32, sh32)):
+            pr.set_state(0, s["x"], s["v"], s["w"], s_le=s["s_le"], step=s["step"], contacts=(cij, cs))
+            acc.append(eta_now(pr, P, 0, gd, eta))
+    say(f"  fp64 trajectory + {len(sh64)} shadow samples done")
+    drag = traj.stress(0, P.STRESS_DRAG)[0, 1]
+    ser64 = eta_r(traj.stress_series()[-steps:], gd, eta, drag)
+    st64 = traj.stats()
+    ms64 = pair_time(traj)
+    st64p = traj.stats()
+    for h in (traj, probe64, probe32):
+        h.close()
+    free = mk(P.MIXED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    free.step(steps)
+    torch.cuda.synchronize()
+    t32 = time.perf_counter() - t0
+    ser32 = eta_r(free.stress_series()[-steps:], gd, eta, drag)
+    st32 = free.stats()
+    ms32 = pair_time(free)
+    st32p = free.stats()
+    free.close()
+    say(f"  mixed free run done")
+    sh64, sh32 = np.array(sh64), np.array(sh32)
+    rel = (sh32 - sh64) / np.abs(sh64)
+    se = float(np.hypot(block_se(ser64), block_se(ser32)))
+    m64, m32 = float(ser64.mean()), float(ser32.mean())
+    k64, c64 = st64p["neighbours_per_particle"], st64p["contacts_per_particle"]
+    k32, c32 = st32p["neighbours_per_particle"], st32p["contacts_per_particle"]
+    ach64 = pair_bytes_per_particle(False, k64, c64) * n / (ms64 * 1e-3) / 1e9
+    ach32 = pair_bytes_per_particle(True, k32, c32) * n / (ms32 * 1e-3) / 1e9
+    return {
+        "fp64": {"value": n * steps / t64, "pair_kernel_ms": ms64, "hbm_frac": ach64 / HBM_PEAK_GBS,
+                 "pair_kernel": {1: "lanes", 2: "wave"}[st64["pair_kernel"]], "lanes": st64["lanes"],
+                 "rebuilds": st64["rebuilds"], "eta_r_mean": m64},
+        "mixed": {"value": n * steps / t32, "pair_kernel_ms": ms32, "hbm_frac": ach32 / HBM_PEAK_GBS,
+                  "pair_kernel": {1: "lanes", 2: "wave"}[st32["pair_kernel"]], "lanes": st32["lanes"],
+                  "rebuilds": st32["rebuilds"], "eta_r_mean": m32},
+        "mixed_speedup": (n * steps / t32) / (n * steps / t64),
+        "shadow": {"samples": int(len(rel)), "every_steps": sample_every,
+                   "eta_r_rel_err_max": float(np.abs(rel).max()),
+                   "eta_r_mean_rel_err": float((sh32.mean() - sh64.mean()) / abs(sh64.mean())),
+                   "eta_r_fp64_mean": float(sh64.mean())},
+        "free_running": {"eta_r_rel_diff": (m32 - m64) / abs(m64), "std_err_rel": se / abs(m64),
+                         "within_3_se": bool(abs(m32 - m64) <= 3 * se)},
+        "contacts_per_particle": c64, "sliding_fraction": st64p["sliding_fraction"],
+        "list_per_particle": k64,
+    }
+
+
+def bench_c3(P, gen, steps, sample_every, say):
+    out = {}
+    for pe in (0.1, 10.0, 1000.0):
+        wl = gen.Workload(f"bidisperse N=1000000 phi=0.56 Pe={pe:g}", 1_000_000, 0.56, pe, steps=steps)
+        st = gen.make_state(wl)
+        say(f"workload ready: {wl.name}")
+        out[f"Pe={pe:g}"] = run_mixed_vs_fp64(P, st, steps, sample_every, say)
+        say(f"Pe={pe:g}: fp64 {out[f'Pe={pe:g}']['fp64']['value']:.3e}  mixed {out[f'Pe={pe:g}']['mixed']['value']:.3e}")
+    return out
+
+
+def bench_sweep(P, gen, steps, warmup, say):
+    """64 replicas of uneven N, phi, Pe and seed in one handle (mixed and FP64),
+    against the same replicas stepped one handle at a time."""
+    import numpy as np
+    import torch
+    wls = gen.sweep_replicas(64)
+    sts = []
+    for r, wl in enumerate(wls):
+        sts.append(gen.make_state(wl))
+        if r % 8 == 7:
+            say(f"  packed {r + 1}/64 replicas")
+    ntot = sum(len(s["radii"]) for s in sts)
+    res = {"replicas": len(wls), "particles": ntot,
+           "n_range": [min(w.n for w in wls), max(w.n for w in wls)]}
+    for name, prec in (("mixed", P.MIXED), ("fp64", P.FP64)):
+        cfgs = [P.Config(box=s["L"], precision=prec, **s["params"]) for s in sts]
+        sim = P.Sim(cfgs, [s["radii"] for s in sts], [s["x"] for s in sts], [s["v"] for s in sts],
+                    [s["w"] for s in sts])
+        sim.step(warmup)
+        sim.reset_stress()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        eta = [float(sim.stress(r, P.STRESS_TOTAL, P.STRESS_MEAN)[0, 1] / (w.eta * w.rates()[0]))
+               for r, w in enumerate(wls)]
+        stt = sim.stats(0)
+        ms = pair_time(sim)
+        sim.close()
+        res[name] = {"value": ntot * steps / el, "ms_per_step": el * 1e3 / steps, "pair_kernel_ms": ms,
+                     "pair_kernel": {1: "lanes", 2: "wave"}[stt["pair_kernel"]], "lanes": stt["lanes"],
+                     "eta_r_mean_min": min(eta), "eta_r_mean_max": max(eta)}
+        if name == "mixed":
+            eta_mixed = np.array(eta)
+        else:
+            res["eta_r_rel_diff_max"] = float(np.max(np.abs(eta_mixed - np.array(eta)) / np.abs(np.array(eta))))
+        say(f"  batched {name}: {res[name]['value']:.3e} particle-steps/s")
+    # unbatched: one handle per replica, same steps, mixed
+    k = max(steps // 10, 50)
+    tot = 0.0
+    for s in sts:
+        h = P.Sim(P.Config(box=s["L"], precision=P.MIXED, **s["params"]), s["radii"], s["x"], s["v"], s["w"])
+        h.step(min(warmup, 50))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.step(k)
+        torch.cuda.synchronize()
+        tot += time.perf_counter() - t0
+        h.close()
+    res["unbatched_mixed"] = {"value": ntot * k / tot, "steps_each": k}
+    res["batched_speedup_vs_unbatched"] = res["mixed"]["value"] / res["unbatched_mixed"]["value"]
+    res["batched_mixed_vs_fp64"] = res["mixed"]["value"] / res["fp64"]["value"]
+    return res
+
+
+def bench_large(P, gen, steps, warmup, say):
+    """4,000,000 log-normal spheres, phi = 0.58, mu = 1, Pe = 1000, mixed precision."""
+    import torch
+    wl = gen.C5
+    st = gen.make_state(wl)
+    n = len(st["radii"])
+    say(f"workload ready: {wl.name}")
+    p = st["params"]
+    sim = P.Sim(P.Config(box=st["L"], precision=P.MIXED, **p), st["radii"], st["x"], st["v"], st["w"])
+    sim.step(warmup)
+    sim.reset_stress()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < steps:
+        k = min(2000, steps - done)
+        sim.step(k)
+        done += k
+        torch.cuda.synchronize()
+        say(f"  {done}/{steps} steps")
+    el = time.perf_counter() - t0
+    stt = sim.stats()
+    S = sim.stress(0, P.STRESS_TOTAL, P.STRESS_MEAN)
+    ms = pair_time(sim)
+    stp = sim.stats()
+    sim.close()
+    ach = pair_bytes_per_particle(True, stp["neighbours_per_particle"], stp["contacts_per_particle"]) * n / (
+        ms * 1e-3) / 1e9
+    return {"workload": wl.name, "n": n, "value": n * steps / el, "ms_per_step": el * 1e3 / steps,
+            "steps": steps, "pair_kernel_ms": ms, "hbm_frac": ach / HBM_PEAK_GBS,
+            "pair_kernel": {1: "lanes", 2: "wave"}[stt["pair_kernel"]], "lanes": stt["lanes"],
+            "contacts_per_particle": stt["contacts_per_particle"], "sliding_fraction": stt["sliding_fraction"],
+            "max_overlap": stt["max_overlap"], "rebuilds": stt["rebuilds"],
+            "stress_total_mean": S.tolist(), "eta_r_mean": S[0, 1] / (p["eta"] * p["gammadot"])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,7 +305,10 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=500)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "sweep", "large"],
+                    help="c2: 50,000 spheres (headline); c3: 1,000,000 spheres, mixed vs FP64 at three Pe; "
+                         "sweep: 64 batched replicas; large: 4,000,000 log-normal spheres")
+    ap.add_argument("--sample-every", type=int, default=250, help="c3: steps between shadow samples")
     ap.add_argument("--variants", action="store_true",
                     help="only run 20 steps of each pair-kernel variant (a counter-collection driver)")
     args = ap.parse_args()
@@ -118,7 +322,22 @@ def main():
     import paper_2307_13802_amd as P
     from inputs import gen
 
-    wl = gen.C2 if args.workload == "c2" else gen.C3
+    say = lambda m: print(m, file=sys.stderr, flush=True)
+    if args.workload in ("c3", "sweep", "large"):
+        steps = args.steps if args.steps != 10000 or args.workload == "large" else 5000
+        if args.workload == "c3":
+            res = {"workload": "bidisperse N=1000000 phi=0.56, Pe in {0.1, 10, 1000}, mixed vs FP64",
+                   "steps": steps, "results": bench_c3(P, gen, steps, args.sample_every, say)}
+        elif args.workload == "sweep":
+            res = {"workload": "64 replicas, N in [2000, 20000], phi in {0.45, 0.50, 0.54, 0.58}, "
+                               "Pe log-spaced 1e-2..1e3, seeds 0..63",
+                   "steps": steps, "results": bench_sweep(P, gen, steps, args.warmup, say)}
+        else:
+            res = bench_large(P, gen, args.steps, args.warmup, say)
+        res["unit"] = "particle-steps/s"
+        print(json.dumps(res), flush=True)
+        return
+    wl = gen.C2
     st = gen.make_state(wl)
     n = len(st["radii"])
     print(f"workload ready: {wl.name}", file=sys.stderr, flush=True)
