@@ -177,10 +177,10 @@ def run_mixed_vs_fp64(P, st, steps, sample_every, say):
     ach32 = pair_bytes_per_particle(True, k32, c32) * n / (ms32 * 1e-3) / 1e9
     return {
         "fp64": {"value": n * steps / t64, "pair_kernel_ms": ms64, "hbm_frac": ach64 / HBM_PEAK_GBS,
-                 "pair_kernel": {1: "lanes", 2: "wave"}[st64["pair_kernel"]], "lanes": st64["lanes"],
+                 "pair_kernel": {1: "lanes", 2: "wave", 3: "half"}[st64["pair_kernel"]], "lanes": st64["lanes"],
                  "rebuilds": st64["rebuilds"], "eta_r_mean": m64},
         "mixed": {"value": n * steps / t32, "pair_kernel_ms": ms32, "hbm_frac": ach32 / HBM_PEAK_GBS,
-                  "pair_kernel": {1: "lanes", 2: "wave"}[st32["pair_kernel"]], "lanes": st32["lanes"],
+                  "pair_kernel": {1: "lanes", 2: "wave", 3: "half"}[st32["pair_kernel"]], "lanes": st32["lanes"],
                   "rebuilds": st32["rebuilds"], "eta_r_mean": m32},
         "mixed_speedup": (n * steps / t32) / (n * steps / t64),
         "shadow": {"samples": int(len(rel)), "every_steps": sample_every,
@@ -236,7 +236,7 @@ def bench_sweep(P, gen, steps, warmup, say):
         ms = pair_time(sim)
         sim.close()
         res[name] = {"value": ntot * steps / el, "ms_per_step": el * 1e3 / steps, "pair_kernel_ms": ms,
-                     "pair_kernel": {1: "lanes", 2: "wave"}[stt["pair_kernel"]], "lanes": stt["lanes"],
+                     "pair_kernel": {1: "lanes", 2: "wave", 3: "half"}[stt["pair_kernel"]], "lanes": stt["lanes"],
                      "eta_r_mean_min": min(eta), "eta_r_mean_max": max(eta)}
         if name == "mixed":
             eta_mixed = np.array(eta)
@@ -291,7 +291,7 @@ def bench_large(P, gen, steps, warmup, say):
         ms * 1e-3) / 1e9
     return {"workload": wl.name, "n": n, "value": n * steps / el, "ms_per_step": el * 1e3 / steps,
             "steps": steps, "pair_kernel_ms": ms, "hbm_frac": ach / HBM_PEAK_GBS,
-            "pair_kernel": {1: "lanes", 2: "wave"}[stt["pair_kernel"]], "lanes": stt["lanes"],
+            "pair_kernel": {1: "lanes", 2: "wave", 3: "half"}[stt["pair_kernel"]], "lanes": stt["lanes"],
             "contacts_per_particle": stt["contacts_per_particle"], "sliding_fraction": stt["sliding_fraction"],
             "max_overlap": stt["max_overlap"], "rebuilds": stt["rebuilds"],
             "stress_total_mean": S.tolist(), "eta_r_mean": S[0, 1] / (p["eta"] * p["gammadot"])}
@@ -380,7 +380,7 @@ def main():
         "config": {"workload": wl.name, "n": n, "phi": wl.phi, "pe": wl.pe,
                    "gammadot": st["params"]["gammadot"], "kT": st["params"]["kT"], "mu": wl.mu,
                    "dt": wl.dt, "hip_graph": True,
-                   "pair_kernel": {1: "lanes", 2: "wave"}[f64["stats"]["pair_kernel"]],
+                   "pair_kernel": {1: "lanes", 2: "wave", 3: "half"}[f64["stats"]["pair_kernel"]],
                    "lanes_per_particle": f64["stats"]["lanes"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -396,7 +396,7 @@ def main():
         am = bm * n / (mix["pair_ms"] * 1e-3) / 1e9
         se = np.hypot(block_se(f64["eta_series"]), block_se(mix["eta_series"]))
         out["mixed"] = {"value": vm, "ms_per_step": mix["seconds"] * 1e3 / args.steps, "dtype": "f32 pair / f64 state",
-                        "pair_kernel": {1: "lanes", 2: "wave"}[mix["stats"]["pair_kernel"]],
+                        "pair_kernel": {1: "lanes", 2: "wave", 3: "half"}[mix["stats"]["pair_kernel"]],
                         "lanes_per_particle": mix["stats"]["lanes"],
                         "speedup_vs_fp64": vm / value, "pair_kernel_ms": mix["pair_ms"],
                         "roofline_frac": am / HBM_PEAK_GBS, "achieved_GBs": am,

@@ -115,18 +115,25 @@ typedef struct sim_config {
     uint32_t flags;         /* SIM_* flags, identical for all replicas               */
     uint32_t nlist_cap;     /* neighbour list capacity per particle; 0 selects 48    */
     uint32_t lanes;         /* lanes sharing one particle in the pair kernel: 1, 2, 4
-                               or 8 (at most 4 for SIM_KERNEL_WAVE); 0 = chosen by
-                               timing at creation                                     */
-    uint32_t pair_kernel;   /* SIM_KERNEL_AUTO, SIM_KERNEL_LANES or SIM_KERNEL_WAVE   */
+                               or 8 (at most 4 for SIM_KERNEL_WAVE, 1 for
+                               SIM_KERNEL_HALF); 0 = chosen by timing at creation    */
+    uint32_t pair_kernel;   /* SIM_KERNEL_AUTO, _LANES, _WAVE or _HALF                */
     uint32_t reserved;      /* must be 0                                             */
 } sim_config;
 
-/* sim_config.pair_kernel: both evaluate the same items in the same order and
- * give bit-identical forces; they differ only in how lanes share the work */
-#define SIM_KERNEL_AUTO  0  /* the faster of the two at creation (timed)              */
-#define SIM_KERNEL_LANES 1  /* each particle's items split over `lanes` lanes         */
+/* sim_config.pair_kernel: all evaluate the same pair terms (Sec. II.A-II.D,
+ * in canonical orientation, lower id first) and sum each particle's terms in
+ * the same item order, so forces, torques and springs are bit-identical
+ * between them (with one lane per particle); they differ in how lanes share
+ * the work */
+#define SIM_KERNEL_AUTO  0  /* the fastest at creation (timed)                        */
+#define SIM_KERNEL_LANES 1  /* each particle's items split over `lanes` lanes;
+                               every pair is evaluated by both of its particles       */
 #define SIM_KERNEL_WAVE  2  /* a wave tests its particles' list entries, then packs
                                their interacting pairs into full 64-lane batches      */
+#define SIM_KERNEL_HALF  3  /* every pair evaluated once, by its lower-id particle,
+                               packed 64 to a wave; a second launch sums each
+                               particle's pair terms and one-body terms              */
 
 typedef struct sim_stats_t {
     double  contacts_per_particle;  /* Z = 2 * contacts / n                          */
@@ -140,7 +147,7 @@ typedef struct sim_stats_t {
     uint64_t step;                  /* current step counter                            */
     double  le_offset;              /* current Lees-Edwards offset                     */
     int32_t lanes;                  /* lanes per particle used by the pair kernel       */
-    int32_t pair_kernel;            /* SIM_KERNEL_LANES or SIM_KERNEL_WAVE in use         */
+    int32_t pair_kernel;            /* SIM_KERNEL_LANES, _WAVE or _HALF in use             */
 } sim_stats_t;
 
 /* Checks a configuration and its radii on the host (no GPU needed).
@@ -149,8 +156,8 @@ typedef struct sim_stats_t {
  * xi_min >= xi_cut, a box side not larger than twice the largest
  * interaction range plus skin (the minimum image must be unique), a wrong
  * struct_size, nlist_cap > 64, lanes not in {0, 1, 2, 4, 8}, an unknown
- * pair_kernel, SIM_KERNEL_WAVE with lanes 8 or nlist_cap > 62, or a nonzero
- * reserved field. */
+ * pair_kernel, SIM_KERNEL_WAVE with lanes 8 or nlist_cap > 62,
+ * SIM_KERNEL_HALF with lanes > 1, or a nonzero reserved field. */
 int sim_validate(const sim_config* cfg, const double* radii);
 
 /* Creates a handle with n_replicas systems.  For replica r: radii[r] -> n
@@ -223,11 +230,16 @@ int sim_contacts(sim* s, int32_t replica, uint32_t* ij_2m, double* s_3m, int32_t
 int sim_stats(sim* s, int32_t replica, sim_stats_t* out);
 
 /* Kernel timing: when enabled, sim_step launches directly (no graph) and
- * brackets every pair-force launch with HIP events on the library stream.
- * sim_kernel_time returns the number of timed launches and their total
- * duration in milliseconds since the last enable. */
+ * brackets the launches of every step with HIP events on the library stream.
+ * sim_kernel_time returns the number of timed steps and the total duration,
+ * in milliseconds since the last enable, of their force evaluations (all
+ * pair-force launches).  sim_stage_time gives one stage: 0 = integrate
+ * (kick 1, drift), 1 = the pair kernel, 2 = the gather of SIM_KERNEL_HALF
+ * (0 for the other variants, whose pair kernel includes it); SIM_EINVAL for
+ * another stage. */
 int sim_profile(sim* s, int32_t enable);
 int sim_kernel_time(sim* s, int64_t* launches, double* total_ms);
+int sim_stage_time(sim* s, int32_t stage, int64_t* launches, double* total_ms);
 
 /* Destroys a handle and frees its device memory. */
 int sim_destroy(sim* s);

@@ -52,11 +52,9 @@ struct RepParams {
 struct RepDyn {
     double s_slot[2];         // Lees-Edwards offset of the evaluation with that parity
     uint64_t step_slot[2];    // step counter of that evaluation
-    double dmax_slot[2];      // bound on the non-affine displacement since the last build
     double t_slot[2];         // time since the last build
-    uint32_t stepmax_bits[2][kSpread];  // float bits: largest displacement of the step, spread
+    uint32_t maxov_bits[2][kSpread];    // float bits: largest overlap of that evaluation, spread
                                         // over slots to keep atomic contention low
-    uint32_t maxov_bits[2][kSpread];    // float bits: largest overlap of that evaluation
     uint32_t eval_id[2];      // serial number of the evaluation whose partials have that parity
     uint32_t rec[2];          // its series record number (1-based), 0 = not recorded
     uint32_t done_id[2][27];  // per stress component: evaluation already reduced
@@ -71,6 +69,8 @@ struct RepDyn {
 
 struct SysDyn {
     uint32_t halted;          // 1: some list may have expired; the remaining launches of the chunk do nothing
+    uint32_t expire[2];       // 1: the integrate of the step with that parity found a particle whose
+                              // displacement bound fails the list-validity test
     uint32_t pad;
     uint64_t rebuilds;
 };
@@ -99,6 +99,17 @@ struct Bufs {
     void* hs[3];      // double or float per component
     uint64_t* cmask;  // bit e: entry e holds a live contact
     uint64_t* smask;  // bit e: that contact slid at its last update
+    // half-pair evaluation: each interacting pair is evaluated once, by its
+    // lower-id particle, into its list entry; the higher-id particle reads it
+    // through the mirror index
+    uint8_t* lo0;     // first entry whose partner has the higher id (lists are sorted by id)
+    uint8_t* mir;     // [e * npad + i], entry with a lower-id partner j: the entry of i in j's list
+    uint64_t* imask;  // bit e: entry e (higher-id partner) interacts in the last evaluation
+    uint16_t* qoff;   // first of particle i's pairs within its wave's run (queue order)
+    void* pf;         // double4 / float4 per pair: force on the lower-id particle; the pairs of
+                      // the wave owning particles [64 w, 64 w + 64) sit in queue order
+                      // (particles in order, entries in order) from 64 w * cap
+    void* pt;         // same layout: n x (k_t s) of a contact
 
     // rebuild scratch
     uint32_t* key;        // cell key per particle
@@ -122,9 +133,12 @@ struct Bufs {
     double* ring;         // [rep][kRing][27]
     double* last;         // [rep][27]
     int lanes;            // pair kernel: lanes per particle (1, 2, 4, 8)
-    int kern;             // pair kernel: 0 = lanes split each particle's items, 1 = wave-cooperative
+    int kern;             // pair kernel: 0 = lanes split each particle's items, 1 = wave-cooperative,
+                          // 2 = half-pair evaluation + gather
     int ppb;              // particles per pair-kernel block (for the stress partials)
 
+    double* dacc;         // per particle: bound on its non-affine displacement since the last build
+    float* dpart;         // [parity][kTile-block]: largest dacc of the block after that step's drift
     uint32_t* blk_rep;    // replica of each kTile-block of particles
     RepParams* reps;
     RepDyn* dyn;
@@ -141,7 +155,11 @@ void launch_integrate(const Bufs& b, hipStream_t st, int q);
 // forces of a step (advance = 1: next step counter and offset, list-expiry test,
 // kick 2 if kick) or of the current state (advance = 0); only_rep: one replica
 // or 0xFFFFFFFF
-void launch_pair_force(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep);
+// mid: event recorded between the two launches of the half-pair variant (may be null);
+// fuse (half-pair variant only): the gather also takes kick 1 and the drift of the
+// next step, which then needs no integrate launch
+void launch_pair_force(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep,
+                       hipEvent_t mid = nullptr, int fuse = 0);
 // reduces pending stress partials of parity q
 void launch_finalize(const Bufs& b, hipStream_t st, int q);
 // Rebuild of cells and neighbour lists from the current positions; q is the

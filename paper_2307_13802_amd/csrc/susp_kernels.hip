@@ -160,9 +160,30 @@ __device__ __forceinline__ void block_atomic_max(float v, uint32_t* slots) {
     if (threadIdx.x == 0) {
         float m = rows[0];
         for (int k = 1; k < (int)(blockDim.x >> 4); ++k) m = fmaxf(m, rows[k]);
-        if (m > 0.0f) atomicMax(&slots[blockIdx.x % kSpread], __float_as_uint(m));
+        // the slot only grows during a launch: skip the atomic (which serialises with
+        // every other block's on the slot's cache line) unless this block raises it;
+        // the device-scope load reads the L2 copy, never a stale line of this CU
+        uint32_t* slot = &slots[blockIdx.x % kSpread];
+        const uint32_t mb = __float_as_uint(m);
+        if (m > 0.0f && mb > __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(slot, mb);
     }
     __syncthreads();
+}
+
+// block-wide max of a float, stored by thread 0 (no atomics)
+__device__ __forceinline__ void block_max_store(float v, float* out) {
+    __shared__ float rows[16];
+    v = fmaxf(v, dpp_f32<0x111>(v));
+    v = fmaxf(v, dpp_f32<0x112>(v));
+    v = fmaxf(v, dpp_f32<0x114>(v));
+    v = fmaxf(v, dpp_f32<0x118>(v));
+    if ((threadIdx.x & 15) == 15) rows[threadIdx.x >> 4] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = rows[0];
+        for (int k = 1; k < (int)(blockDim.x >> 4); ++k) m = fmaxf(m, rows[k]);
+        *out = m;
+    }
 }
 
 __device__ __forceinline__ float slots_max(const uint32_t* slots) {
@@ -216,79 +237,102 @@ __device__ void finalize_all(const Bufs& b, int x) {
 __global__ __launch_bounds__(256) void k_finalize(Bufs b, int x) { finalize_all(b, x); }
 
 // ---------------------------------------------------------------------------
-// Kick 1, drift and wrap of a step with parity q (velocity-Verlet, Sec. II;
-// sheared box, Sec. II.E).  Also bounds the step's non-affine displacement
-// |dx - U^inf dt| for the list-expiry test.
+// List validity.  A pair outside the list at the last build (|r| > r_c +
+// skin) can have come within r_c by time t only if 2 D + |gammadot| t (r_c +
+// 4 D) > skin, where D = max(d_i, d_j), d_i bounds particle i's non-affine
+// displacement since the build (drift minus the imposed flow integrated
+// along the path) and t is the time since the build: the affine part of the
+// relative motion is gammadot r_y t along x, with |r_y| <= r_c + 4 D over the
+// interval.  With 2 D <= skin this is implied by 2 D + |gammadot| t (r_c +
+// 2 skin) > skin, so each particle tests its own bound after its drift; one
+// failure flags the step (expire), its force launch does nothing and the
+// host rebuilds the lists from the moved positions before evaluating it.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ bool list_expired(const RepParams& P, double d, double t) {
+    return 2.0 * d + fabs(P.gd) * t * (P.rc_max + 2.0 * P.skin) > P.skin;
+}
+
+// ---------------------------------------------------------------------------
+// Kick 1, drift and wrap of a step with parity q (velocity-Verlet, Sec. II;
+// sheared box, Sec. II.E).  Also accumulates each particle's non-affine
+// displacement |dx - U^inf dt| and applies the list-validity test.
+// ---------------------------------------------------------------------------
+// Kick 1, drift and wrap of particle i for the step with parity q, from its
+// full-step velocities v, w, position x and the force and torque F, T of the
+// last evaluation (as stored); accumulates its displacement bound (dblk) and
+// applies the list-validity test (expire).
+template <bool MIX>
+__device__ __forceinline__ void integrate_particle(const Bufs& b, const RepParams& P, const RepDyn& D, int q,
+                                                   uint32_t i, double4 x, double4 v, double4 w, const double* F,
+                                                   const double* T, float& dblk, bool& expire) {
+    double disp = 0.0;
+    const double a = x.w;
+    const double m = (4.0 / 3.0) * kPi * P.rho * a * a * a;
+    const double I = 0.4 * m * a * a;
+    const double hm = P.half_dt / m, hI = P.half_dt / I;
+    v.x += hm * F[0]; v.y += hm * F[1]; v.z += hm * F[2];
+    w.x += hI * T[0]; w.y += hI * T[1]; w.z += hI * T[2];
+    if (!(P.flags & F_FREEZE_X)) {
+        const double yold = x.y;
+        const double vdx = v.x, vdy = v.y, vdz = v.z;  // drift velocity
+        x.x += P.dt * v.x;
+        x.y += P.dt * v.y;
+        x.z += P.dt * v.z;
+        const double s = next_offset(P, D.s_slot[1 - q]);
+        const double Lx = P.L[0], Ly = P.L[1], Lz = P.L[2];
+        if (x.y >= Ly) {
+            x.y -= Ly; x.x -= s; v.x -= P.gdLy;
+        } else if (x.y < 0.0) {
+            x.y += Ly; x.x += s; v.x += P.gdLy;
+            if (x.y >= Ly) x.y = 0.0;
+        }
+        x.x -= Lx * floor(x.x / Lx);
+        x.z -= Lz * floor(x.z / Lz);
+        if (x.x >= Lx) x.x -= Lx;
+        if (x.z >= Lz) x.z -= Lz;
+        // non-affine displacement of this step: drift minus the imposed flow
+        // integrated along the path, gammadot (y(t) - Ly/2) with y(t) = yold + vdy t
+        const double ux = P.gd * (yold - 0.5 * Ly) + 0.5 * P.gd * P.dt * vdy;
+        const double ex = P.dt * (vdx - ux), ey = P.dt * vdy, ez = P.dt * vdz;
+        disp = sqrt(ex * ex + ey * ey + ez * ez) * (1.0 + 1e-6) + 1e-30;
+        b.pos[i] = x;
+    }
+    b.vh[i] = v;
+    b.wh[i] = w;
+    if (MIX) {
+        b.vsh[i] = make_float4((float)v.x, (float)v.y, (float)v.z, 0.0f);
+        b.wsh[i] = make_float4((float)w.x, (float)w.y, (float)w.z, 0.0f);
+    }
+    const double d = b.dacc[i] + disp;
+    b.dacc[i] = d;
+    expire = list_expired(P, d, D.t_slot[1 - q] + P.dt);
+    dblk = (float)d * (1.0f + 1e-6f);
+}
+
 template <bool MIX>
 __global__ __launch_bounds__(256) void k_integrate(Bufs b, int q) {
     if (b.sys->halted) return;  // uniform: set by an earlier launch
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t r = b.blk_rep[i / kTile];
     const RepParams& P = b.reps[r];
-    RepDyn& D = b.dyn[r];
-    float disp = 0.0f;
+    const RepDyn& D = b.dyn[r];
+    float dblk = 0.0f;
+    bool expire = false;
     if (i - P.p_begin < P.n) {
-        double4 x = b.pos[i];
-        double4 v = b.vf[i];
-        double4 w = b.wf[i];
-        double Fx, Fy, Fz, Tx, Ty, Tz;
+        double F[3], T[3];
         if (MIX) {
             const float4 f = ((const float4*)b.F)[i], t = ((const float4*)b.T)[i];
-            Fx = f.x; Fy = f.y; Fz = f.z; Tx = t.x; Ty = t.y; Tz = t.z;
+            F[0] = f.x; F[1] = f.y; F[2] = f.z; T[0] = t.x; T[1] = t.y; T[2] = t.z;
         } else {
             const double4 f = ((const double4*)b.F)[i], t = ((const double4*)b.T)[i];
-            Fx = f.x; Fy = f.y; Fz = f.z; Tx = t.x; Ty = t.y; Tz = t.z;
+            F[0] = f.x; F[1] = f.y; F[2] = f.z; T[0] = t.x; T[1] = t.y; T[2] = t.z;
         }
-        const double a = x.w;
-        const double m = (4.0 / 3.0) * kPi * P.rho * a * a * a;
-        const double I = 0.4 * m * a * a;
-        const double hm = P.half_dt / m, hI = P.half_dt / I;
-        v.x += hm * Fx; v.y += hm * Fy; v.z += hm * Fz;
-        w.x += hI * Tx; w.y += hI * Ty; w.z += hI * Tz;
-        if (!(P.flags & F_FREEZE_X)) {
-            const double yold = x.y;
-            const double vdx = v.x, vdy = v.y, vdz = v.z;  // drift velocity
-            x.x += P.dt * v.x;
-            x.y += P.dt * v.y;
-            x.z += P.dt * v.z;
-            const double s = next_offset(P, D.s_slot[1 - q]);
-            const double Lx = P.L[0], Ly = P.L[1], Lz = P.L[2];
-            if (x.y >= Ly) {
-                x.y -= Ly; x.x -= s; v.x -= P.gdLy;
-            } else if (x.y < 0.0) {
-                x.y += Ly; x.x += s; v.x += P.gdLy;
-                if (x.y >= Ly) x.y = 0.0;
-            }
-            x.x -= Lx * floor(x.x / Lx);
-            x.z -= Lz * floor(x.z / Lz);
-            if (x.x >= Lx) x.x -= Lx;
-            if (x.z >= Lz) x.z -= Lz;
-            // non-affine displacement of this step: drift minus the imposed flow
-            // integrated along the path, gammadot (y(t) - Ly/2) with y(t) = yold + vdy t
-            const double ux = P.gd * (yold - 0.5 * Ly) + 0.5 * P.gd * P.dt * vdy;
-            const double ex = P.dt * (vdx - ux), ey = P.dt * vdy, ez = P.dt * vdz;
-            disp = (float)(sqrt(ex * ex + ey * ey + ez * ez) * (1.0 + 1e-6)) + 1e-30f;
-            b.pos[i] = x;
-        }
-        b.vh[i] = v;
-        b.wh[i] = w;
-        if (MIX) {
-            b.vsh[i] = make_float4((float)v.x, (float)v.y, (float)v.z, 0.0f);
-            b.wsh[i] = make_float4((float)w.x, (float)w.y, (float)w.z, 0.0f);
-        }
+        integrate_particle<MIX>(b, P, D, q, i, b.pos[i], b.vf[i], b.wf[i], F, T, dblk, expire);
     }
-    block_atomic_max(disp, D.stepmax_bits[q]);
+    if (expire) atomicOr(&b.sys->expire[q], 1u);  // rare: the lists are rebuilt before that
+    block_max_store(dblk, &b.dpart[(size_t)q * (b.npad / kTile) + blockIdx.x]);
 }
 
-// ---------------------------------------------------------------------------
-// List validity (the expiry test of the pair kernel).  A pair outside the list at the last build (|r| > r_c +
-// skin) can have come within r_c only if 2 D + |gammadot| t (r_c + 4 D) >
-// skin, where D bounds every particle's non-affine displacement since the
-// build and t is the time since the build (the affine part of the relative
-// motion is gammadot r_y t along x, with |r_y| <= r_c + 4 D).  With
-// 2 D <= skin this is implied by 2 D + |gammadot| t (r_c + 2 skin) > skin.
-// ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // Rebuild: Morton-ordered cells, deterministic order inside a cell (by id),
 // reorder of all particle data, neighbour list with history carry-over.
@@ -481,6 +525,7 @@ __global__ __launch_bounds__(256) void k_rb_gather(Bufs b, uint32_t ct_input_rep
 
 __global__ __launch_bounds__(256) void k_rb_copyback(Bufs b) {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    b.dacc[q] = 0.0;
     b.id[q] = b.alt_id[q];
     b.pos[q] = b.alt4[0][q];
     const double4 vh = b.alt4[1][q], wh = b.alt4[2][q];
@@ -594,16 +639,52 @@ __global__ __launch_bounds__(256) void k_rb_nlist(Bufs b, int q, int in_step) {
     b.smask[i] = sm;
 }
 
+// Mirror index of the half-pair variant: lo0[i] = first entry whose partner
+// has the higher id; for an entry with a lower-id partner j, the position of
+// i in j's list (lists are symmetric: the range test is symmetric in i, j).
+__global__ __launch_bounds__(256) void k_rb_mirror(Bufs b) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t r = b.blk_rep[i / kTile];
+    const RepParams& P = b.reps[r];
+    const uint32_t npad = b.npad;
+    if (i - P.p_begin >= P.n) {
+        b.lo0[i] = 0;
+        b.imask[i] = 0ull;
+        return;
+    }
+    const uint32_t idi = b.id[i], cnt = b.ncnt[i];
+    uint32_t e0 = cnt;
+    for (uint32_t e = 0; e < cnt; ++e) {
+        const uint32_t j = b.nbr[e * npad + i];
+        if (b.id[j] > idi) {
+            e0 = e;
+            break;
+        }
+        const uint32_t cj = b.ncnt[j];
+        uint32_t m = 0xFFu;
+        for (uint32_t k = 0; k < cj; ++k)
+            if (b.nbr[k * npad + j] == i) {
+                m = k;
+                break;
+            }
+        if (m == 0xFFu) {
+            atomicOr(&b.dyn[r].health, H_NLIST);
+            m = 0;
+        }
+        b.mir[e * npad + i] = (uint8_t)m;
+    }
+    b.lo0[i] = (uint8_t)e0;
+    b.imask[i] = 0ull;
+}
+
 // after a build every list holds all pairs within range plus the full skin;
 // q is the parity of the next force evaluation
 __global__ void k_rb_reset(Bufs b, int q) {
-    for (uint32_t r = threadIdx.x; r < b.nrep; r += blockDim.x) {
-        b.dyn[r].dmax_slot[1 - q] = 0.0;
-        b.dyn[r].t_slot[1 - q] = 0.0;
-        for (int k = 0; k < kSpread; ++k) b.dyn[r].stepmax_bits[q][k] = 0u;
-    }
+    for (uint32_t r = threadIdx.x; r < b.nrep; r += blockDim.x) b.dyn[r].t_slot[1 - q] = 0.0;
     if (threadIdx.x == 0) {
         b.sys->halted = 0u;
+        b.sys->expire[0] = 0u;
+        b.sys->expire[1] = 0u;
         b.sys->rebuilds += 1;
     }
 }
@@ -670,28 +751,19 @@ template <bool MIX> struct EvalCtx {
 __device__ __forceinline__ bool eval_begin(const Bufs& b, int q, int advance, const RepParams& P, RepDyn& D,
                                            bool first, double& s_le, uint64_t& step) {
     if (advance) {
-        // list-expiry test (the validity bound above) for every replica: one expired
-        // list halts the whole launch sequence until the host has rebuilt
-        bool expired = false;
-        for (uint32_t rr = 0; rr < b.nrep; ++rr) {
-            const RepParams& Q = b.reps[rr];
-            const RepDyn& E = b.dyn[rr];
-            const double dm = E.dmax_slot[1 - q] + (double)slots_max(E.stepmax_bits[q]);
-            const double tt = E.t_slot[1 - q] + Q.dt;
-            expired |= 2.0 * dm + fabs(Q.gd) * tt * (Q.rc_max + 2.0 * Q.skin) > Q.skin;
-        }
-        if (expired) {
+        // list-validity test of the step's integrate (any replica): one failure halts the
+        // whole launch sequence until the host has rebuilt
+        if (b.sys->expire[q]) {
             if (blockIdx.x == 0 && threadIdx.x == 0) b.sys->halted = 1u;
             return false;
         }
+        if (blockIdx.x == 0 && threadIdx.x == 0) b.sys->expire[1 - q] = 0u;  // for the next step
         s_le = next_offset(P, D.s_slot[1 - q]);
         step = D.step_slot[1 - q] + 1;
         if (first && threadIdx.x == 0) {
             D.s_slot[q] = s_le;
             D.step_slot[q] = step;
-            D.dmax_slot[q] = D.dmax_slot[1 - q] + (double)slots_max(D.stepmax_bits[q]);
             D.t_slot[q] = D.t_slot[1 - q] + P.dt;
-            for (int k = 0; k < kSpread; ++k) D.stepmax_bits[1 - q][k] = 0u;  // for the next step
             D.eval_seq += 1;
             D.eval_id[q] = D.eval_seq;
             D.nrec += 1;
@@ -741,17 +813,44 @@ __device__ __forceinline__ bool interacting(const RepParams& P, double s_le, con
     return d2 <= rc * rc;
 }
 
+// One-body item of particle i from its three normals th: eq. (force_drag) +
+// (force_brownian_drag) for e = kItemForce (into f), or eq. (torque_drag) +
+// (torque_brownian_drag) for e = kItemTorque (into t).
+template <bool MIX>
+__device__ __forceinline__ void onebody_terms(const RepParams& P, const EvalCtx<MIX>& C, const double4& pi,
+                                              uint32_t e, const typename EvalCtx<MIX>::R* vi,
+                                              const typename EvalCtx<MIX>::R* wi, const typename EvalCtx<MIX>::R* th,
+                                              typename EvalCtx<MIX>::R* f, typename EvalCtx<MIX>::R* t) {
+    using R = typename EvalCtx<MIX>::R;
+    const double a = pi.w;
+    if (e == kItemForce) {
+        const R zeta = (R)(6.0 * kPi * P.eta * a);
+        const R sz = rsqrt_<R>(zeta);
+        const R uinf[3] = {(R)(P.gd * (pi.y - 0.5 * P.L[1])), (R)0, (R)0};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) f[d] = zeta * (uinf[d] - vi[d]) + C.bamp * sz * th[d];
+    } else {
+        const R zr = (R)(8.0 * kPi * P.eta * a * a * a);
+        const R szr = rsqrt_<R>(zr);
+        const R oinf[3] = {(R)0, (R)0, (R)(-0.5 * P.gd)};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) t[d] = zr * (oinf[d] - wi[d]) + C.bamp * szr * th[d];
+    }
+}
+
 // One item of particle i: contribution f to its force and t to its torque.
 // Pair items also update the stored spring (entry e of i), the contact and
-// sliding bits, the largest overlap and the lower-id stress sums (addS).
-// Returns false for a pair that does not interact (nothing contributed).
-template <bool MIX, class AddS>
+// sliding bits, the largest overlap and the lower-id stress sums (addS); for
+// a contact, nks receives n x (k_t s), the torque per unit lever arm of both
+// spheres.  Returns false for a pair that does not interact (nothing
+// contributed).  LO_ONLY: the item is a pair whose partner has the higher id.
+template <bool MIX, bool LO_ONLY = false, class AddS>
 __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, const EvalCtx<MIX>& C, uint32_t i,
                                           uint32_t e, const double4& pi, uint32_t idi,
                                           const typename EvalCtx<MIX>::R* vi, const typename EvalCtx<MIX>::R* wi,
                                           bool had_contact, typename EvalCtx<MIX>::R* f,
                                           typename EvalCtx<MIX>::R* t, bool& contact, bool& slid, float& maxov,
-                                          AddS addS) {
+                                          AddS addS, typename EvalCtx<MIX>::R* nks_out = nullptr) {
     using R = typename EvalCtx<MIX>::R;
     const uint32_t npad = b.npad;
     const R ai = (R)pi.w;
@@ -759,7 +858,7 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
     for (int d = 0; d < 3; ++d) { f[d] = (R)0; t[d] = (R)0; }
     contact = false;
     slid = false;
-    const bool pair = e < kItemForce;
+    const bool pair = LO_ONLY || e < kItemForce;
     // ---- geometry of a pair item (FP64)
     uint32_t j = 0, idj = 0;
     double4 pj = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -771,7 +870,7 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
         j = b.nbr[e * npad + i];
         pj = b.pos[j];
         idj = b.id[j];
-        lo = idi < idj;  // i holds the lower id
+        lo = LO_ONLY || idi < idj;  // i holds the lower id
         ky = lo ? min_image(P, C.s_le, pi, pj, dx, dy, dz) : min_image(P, C.s_le, pj, pi, dx, dy, dz);
         const double d2 = (dx * dx + dy * dy) + dz * dz;
         const double sa = pi.w + pj.w;
@@ -803,21 +902,7 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
         normals3(w, th);
     }
     if (!pair) {
-        // eq. (force_drag) + (force_brownian_drag), or (torque_drag) + (torque_brownian_drag)
-        const double a = pi.w;
-        if (e == kItemForce) {
-            const R zeta = (R)(6.0 * kPi * P.eta * a);
-            const R sz = rsqrt_<R>(zeta);
-            const R uinf[3] = {(R)(P.gd * (pi.y - 0.5 * P.L[1])), (R)0, (R)0};
-#pragma unroll
-            for (int d = 0; d < 3; ++d) f[d] = zeta * (uinf[d] - vi[d]) + C.bamp * sz * th[d];
-        } else {
-            const R zr = (R)(8.0 * kPi * P.eta * a * a * a);
-            const R szr = rsqrt_<R>(zr);
-            const R oinf[3] = {(R)0, (R)0, (R)(-0.5 * P.gd)};
-#pragma unroll
-            for (int d = 0; d < 3; ++d) t[d] = zr * (oinf[d] - wi[d]) + C.bamp * szr * th[d];
-        }
+        onebody_terms<MIX>(P, C, pi, e, vi, wi, th, f, t);
         return true;
     }
 
@@ -933,6 +1018,10 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
         const R nks[3] = {n[1] * ks[2] - n[2] * ks[1], n[2] * ks[0] - n[0] * ks[2], n[0] * ks[1] - n[1] * ks[0]};
 #pragma unroll
         for (int d = 0; d < 3; ++d) t[d] = ai * nks[d];
+        if (nks_out) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) nks_out[d] = nks[d];
+        }
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -971,14 +1060,16 @@ __device__ __forceinline__ void load_vw(const Bufs& b, uint32_t i, typename Eval
 }
 
 // stores the force and torque of particle i, applies kick 2, flags non-finite values
-template <bool MIX>
+template <bool MIX, bool MASKS = true>
 __device__ __forceinline__ void store_particle(const Bufs& b, const RepParams& P, int kick, uint32_t i,
                                                const double* Ft, const double* Tt, uint64_t cm, uint64_t sm,
-                                               bool& bad) {
+                                               bool& bad, double4* vf_out = nullptr, double4* wf_out = nullptr) {
     bad = !(isfinite(Ft[0]) && isfinite(Ft[1]) && isfinite(Ft[2]) && isfinite(Tt[0]) && isfinite(Tt[1]) &&
             isfinite(Tt[2]));
-    b.cmask[i] = cm;
-    b.smask[i] = sm;
+    if (MASKS) {
+        b.cmask[i] = cm;
+        b.smask[i] = sm;
+    }
     if (MIX) {
         ((float4*)b.F)[i] = make_float4((float)Ft[0], (float)Ft[1], (float)Ft[2], 0.0f);
         ((float4*)b.T)[i] = make_float4((float)Tt[0], (float)Tt[1], (float)Tt[2], 0.0f);
@@ -998,6 +1089,10 @@ __device__ __forceinline__ void store_particle(const Bufs& b, const RepParams& P
     }
     b.vf[i] = vf;
     b.wf[i] = wf;
+    if (vf_out) {
+        *vf_out = vf;
+        *wf_out = wf;
+    }
 }
 
 // block partial of the 27 stress sums held in thread-private LDS slots sacc[c][thread]
@@ -1308,6 +1403,238 @@ __global__ __launch_bounds__(256) void k_pairq(Bufs b, int q, int kick, int adva
     }
 }
 
+// ---------------------------------------------------------------------------
+// Variant 3 (half-pair): every interacting pair is evaluated once, by its
+// lower-id particle.  k_half: a wave owns 64 particles; each lane tests the
+// entries of its particle whose partner has the higher id (a suffix of the
+// id-sorted list), the wave packs the interacting ones into a queue and
+// evaluates them 64 at a time, writing the pair force on the lower-id
+// particle and, for a contact, n x (k_t s) into the entry.  k_gather: each
+// lane sums its particle's pair terms in entry order (reading a lower-id
+// partner's result through the mirror index, negated), then the one-body
+// force and torque, then applies kick 2.  The sums run in the same item order
+// as the other variants, and the pair terms are the same bits, so forces,
+// torques and springs equal those of variant 1 with one lane per particle.
+// ---------------------------------------------------------------------------
+template <class R> struct Vec4;
+template <> struct Vec4<double> {
+    using T = double4;
+    static __device__ __forceinline__ T make(double x, double y, double z) { return make_double4(x, y, z, 0.0); }
+};
+template <> struct Vec4<float> {
+    using T = float4;
+    static __device__ __forceinline__ T make(float x, float y, float z) { return make_float4(x, y, z, 0.0f); }
+};
+
+template <bool MIX>
+__global__ __launch_bounds__(256) void k_half(Bufs b, int q, int advance, uint32_t only_rep) {
+    using R = typename std::conditional<MIX, float, double>::type;
+    using V4 = typename Vec4<R>::T;
+    if (b.sys->halted) return;
+    finalize_all(b, 1 - q);
+    const int w = threadIdx.x >> 6, p = threadIdx.x & 63;
+    const uint32_t base = blockIdx.x * 256 + w * 64;   // first particle of this wave
+    const uint32_t r = b.blk_rep[blockIdx.x];          // a block is one kTile of particles
+    if (only_rep != 0xFFFFFFFFu && r != only_rep) return;
+    const RepParams& P = b.reps[r];
+    RepDyn& D = b.dyn[r];
+    double s_le;
+    uint64_t step;
+    if (!eval_begin(b, q, advance, P, D, blockIdx.x == P.p_begin / 256, s_le, step)) return;
+    EvalCtx<MIX> C;
+    make_ctx<MIX>(C, P, s_le, step);
+    const uint32_t npad = b.npad;
+
+    __shared__ uint16_t queue[4][64 * 64];   // (particle slot << 6) | entry
+    __shared__ unsigned long long cmo[4][64], cmq[4][64], smq[4][64];
+
+    // ---- cull: interacting entries with a higher-id partner
+    const uint32_t i = base + p;
+    const bool valid = i - P.p_begin < P.n;
+    uint64_t im = 0ull;
+    if (valid) {
+        const double4 pi = b.pos[i];
+        const uint32_t cnt = b.ncnt[i];
+        for (uint32_t e = b.lo0[i]; e < cnt; ++e)
+            if (interacting(P, s_le, pi, b.pos[b.nbr[e * npad + i]])) im |= 1ull << e;
+        cmo[w][p] = b.cmask[i];
+    }
+    cmq[w][p] = 0ull;
+    smq[w][p] = 0ull;
+    // exclusive prefix of the per-particle counts across the wave
+    const uint32_t cnt_i = (uint32_t)__popcll(im);
+    uint32_t incl = cnt_i;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off);
+        if (p >= off) incl += y;
+    }
+    const uint32_t total = __shfl(incl, 63);
+    {
+        uint32_t k = incl - cnt_i;
+        if (valid) {
+            b.imask[i] = im;
+            b.qoff[i] = (uint16_t)k;
+        }
+        for (uint64_t m = im; m; m &= m - 1ull) queue[w][k++] = (uint16_t)((p << 6) | __builtin_ctzll(m));
+    }
+    // results of this wave's pairs: a contiguous run in queue order
+    V4* const pf = (V4*)b.pf + (size_t)base * b.cap;
+    V4* const pt = (V4*)b.pt + (size_t)base * b.cap;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+
+    // ---- evaluate the queue, one pair per lane
+    double acc[27];
+#pragma unroll
+    for (int c = 0; c < 27; ++c) acc[c] = 0.0;
+    auto addS = [&](int c, double v) { acc[c] += v; };
+    float maxov = 0.0f;
+    for (uint32_t k = p; k < total; k += 64) {
+        const uint32_t code = queue[w][k];
+        const uint32_t l = code >> 6, e = code & 63u;
+        const uint32_t ii = base + l;
+        const double4 pi = b.pos[ii];
+        const uint32_t idi = b.id[ii];
+        R vi[3], wi[3];
+        load_vw<MIX>(b, ii, vi, wi);
+        R f[3], t[3], nks[3];
+        bool contact, slid;
+        eval_item<MIX, true>(b, P, C, ii, e, pi, idi, vi, wi, (cmo[w][l] >> e) & 1ull, f, t, contact, slid, maxov,
+                             addS, nks);
+        pf[k] = Vec4<R>::make(f[0], f[1], f[2]);
+        if (contact) {
+            pt[k] = Vec4<R>::make(nks[0], nks[1], nks[2]);
+            atomicOr(&cmq[w][l], 1ull << e);
+            if (slid) atomicOr(&smq[w][l], 1ull << e);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (valid) {
+        b.cmask[i] = cmq[w][p];
+        b.smask[i] = smq[w][p];
+    }
+
+    block_atomic_max(maxov, D.maxov_bits[q]);
+    // block partial of the stress: fixed-order sum over the block's lanes (DPP rows, then LDS)
+    __shared__ double rows[16][27];
+#pragma unroll
+    for (int c = 0; c < 27; ++c) {
+        const double v = row_sum_f64(acc[c]);
+        if ((p & 15) == 15) rows[threadIdx.x >> 4][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 27) {
+        const int c = threadIdx.x;
+        double tsum = 0.0;
+        for (int k = 0; k < 16; ++k) tsum += rows[k][c];
+        b.partial[((size_t)q * 27 + c) * b.nblk_max + blockIdx.x] = tsum;
+    }
+}
+
+template <bool MIX>
+__device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& P, const RepDyn& D, int q, int kick,
+                                                int fuse, uint32_t i, float& dblk, bool& expire, bool& bad);
+
+// fuse: also take kick 1 and the drift of the next step (parity 1 - q) from the
+// new forces, as the integrate launch of that step would
+template <bool MIX>
+__global__ __launch_bounds__(256) void k_gather(Bufs b, int q, int kick, int fuse, uint32_t only_rep) {
+    if (b.sys->halted) return;
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t r = b.blk_rep[blockIdx.x];
+    if (only_rep != 0xFFFFFFFFu && r != only_rep) return;
+    const RepParams& P = b.reps[r];
+    RepDyn& D = b.dyn[r];
+    float dblk = 0.0f;
+    bool expire = false, bad = false;
+    if (i - P.p_begin < P.n) gather_particle<MIX>(b, P, D, q, kick, fuse, i, dblk, expire, bad);
+    if (bad) atomicOr(&D.health, H_NAN);
+    if (fuse) {
+        if (expire) atomicOr(&b.sys->expire[1 - q], 1u);
+        block_max_store(dblk, &b.dpart[(size_t)(1 - q) * (b.npad / kTile) + blockIdx.x]);
+    }
+}
+
+template <bool MIX>
+__device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& P, const RepDyn& D, int q, int kick,
+                                                int fuse, uint32_t i, float& dblk, bool& expire, bool& bad) {
+    using R = typename std::conditional<MIX, float, double>::type;
+    using V4 = typename Vec4<R>::T;
+    EvalCtx<MIX> C;
+    make_ctx<MIX>(C, P, D.s_slot[q], D.step_slot[q]);
+    const uint32_t npad = b.npad;
+    const double4 pi = b.pos[i];
+    const uint32_t idi = b.id[i];
+    const R ai = (R)pi.w;
+    R vi[3], wi[3];
+    load_vw<MIX>(b, i, vi, wi);
+    Acc<R> F, T;
+    const uint32_t cnt = b.ncnt[i], e0 = b.lo0[i];
+    const uint64_t im = b.imask[i], cm = b.cmask[i];
+    // pair k of the wave owning particle p sits at (p & ~63) * cap + k
+    size_t klo = (size_t)(i & ~63u) * b.cap + b.qoff[i];
+    for (uint32_t e = 0; e < cnt; ++e) {
+        size_t slot;
+        bool ct;
+        R sg;
+        if (e < e0) {  // lower-id partner j: its entry m holds the pair
+            const uint32_t j = b.nbr[e * npad + i];
+            const uint32_t m = b.mir[e * npad + i];
+            const uint64_t imj = b.imask[j];
+            if (!((imj >> m) & 1ull)) continue;
+            slot = (size_t)(j & ~63u) * b.cap + b.qoff[j] + (uint32_t)__popcll(imj & ((1ull << m) - 1ull));
+            ct = (b.cmask[j] >> m) & 1ull;
+            sg = (R)-1;
+        } else {
+            if (!((im >> e) & 1ull)) continue;
+            slot = klo++;
+            ct = (cm >> e) & 1ull;
+            sg = (R)1;
+        }
+        const V4 f = ((const V4*)b.pf)[slot];
+        F.add(0, sg * f.x);
+        F.add(1, sg * f.y);
+        F.add(2, sg * f.z);
+        if (ct) {
+            const V4 t = ((const V4*)b.pt)[slot];
+            T.add(0, ai * t.x);
+            T.add(1, ai * t.y);
+            T.add(2, ai * t.z);
+        }
+    }
+    if (C.do_one) {
+#pragma unroll
+        for (uint32_t e = kItemForce; e <= kItemTorque; ++e) {
+            R th[3], f[3], t[3];
+            const uint4 u = philox10(C.ctr_lo, idi, 0xFFFFFFFFu, C.ctr_hi | (e == kItemForce ? 2u : 3u), C.k0, C.k1);
+            normals3(u, th);
+            onebody_terms<MIX>(P, C, pi, e, vi, wi, th, f, t);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (e == kItemForce) F.add(d, f[d]);
+                else T.add(d, t[d]);
+            }
+        }
+    }
+    double Ft[3], Tt[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { Ft[d] = F.get(d); Tt[d] = T.get(d); }
+    double4 vf, wf;
+    store_particle<MIX, false>(b, P, kick, i, Ft, Tt, 0ull, 0ull, bad, &vf, &wf);
+    if (fuse) {
+        if (MIX) {  // the next kick uses the force as stored
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                Ft[d] = (double)(float)Ft[d];
+                Tt[d] = (double)(float)Tt[d];
+            }
+        }
+        integrate_particle<MIX>(b, P, D, 1 - q, i, pi, vf, wf, Ft, Tt, dblk, expire);
+    }
+}
+
 // diagnostics: mode 0 = interaction set, 1 = Verlet list, 2 = contacts (with springs)
 __global__ void k_diag(Bufs b, int p, uint32_t rep, uint32_t* out_ij, double* out_s, int32_t* out_sl,
                        uint32_t* count, uint32_t cap, int mode) {
@@ -1377,11 +1704,19 @@ void launch_rebuild(const Bufs& b, hipStream_t st, int q, int in_step, uint32_t 
     hipLaunchKernelGGL(k_rb_gather, dim3(np), dim3(256), 0, st, b, ct_input_rep);
     hipLaunchKernelGGL(k_rb_copyback, dim3(np), dim3(256), 0, st, b);
     hipLaunchKernelGGL(k_rb_nlist, dim3(np), dim3(256), 0, st, b, q, in_step);
+    hipLaunchKernelGGL(k_rb_mirror, dim3(np), dim3(256), 0, st, b);
     hipLaunchKernelGGL(k_rb_reset, dim3(1), dim3(256), 0, st, b, q);
 }
 
 template <bool MIX>
-static void launch_pair_t(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep) {
+static void launch_pair_t(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep,
+                          hipEvent_t mid, int fuse) {
+    if (b.kern == 2) {  // half-pair evaluation, then the per-particle gather
+        hipLaunchKernelGGL(k_half<MIX>, dim3(b.npad / 256), dim3(256), 0, st, b, q, advance, only_rep);
+        if (mid) (void)hipEventRecord(mid, st);
+        hipLaunchKernelGGL(k_gather<MIX>, dim3(b.npad / 256), dim3(256), 0, st, b, q, kick, fuse, only_rep);
+        return;
+    }
     if (b.kern == 1) {  // wave-cooperative; 256-thread blocks of 4 * 64 / lanes particles
         const dim3 blk(256);
         const uint32_t g = b.npad / 256;
@@ -1402,9 +1737,10 @@ static void launch_pair_t(const Bufs& b, hipStream_t st, int q, int kick, int ad
     }
 }
 
-void launch_pair_force(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep) {
-    if (b.mixed) launch_pair_t<true>(b, st, q, kick, advance, only_rep);
-    else launch_pair_t<false>(b, st, q, kick, advance, only_rep);
+void launch_pair_force(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep,
+                       hipEvent_t mid, int fuse) {
+    if (b.mixed) launch_pair_t<true>(b, st, q, kick, advance, only_rep, mid, fuse);
+    else launch_pair_t<false>(b, st, q, kick, advance, only_rep, mid, fuse);
 }
 
 void launch_diag(const Bufs& b, hipStream_t st, int p, uint32_t rep, uint32_t n, uint32_t* out_ij, double* out_s,

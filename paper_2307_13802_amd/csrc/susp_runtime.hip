@@ -77,6 +77,7 @@ struct sim {
     std::vector<hipEvent_t> ev;
     int64_t prof_launches = 0;
     double prof_ms = 0.0;
+    double prof_stage_ms[3] = {0.0, 0.0, 0.0};  // integrate, pair kernel, gather
     int64_t steps_total = 0;
     uint64_t step_now = 0;       // step counter of replica 0 (all replicas advance together)
     int par = 0;                 // parity of the current state (slot of the last evaluation)
@@ -152,7 +153,11 @@ int validate(const sim_config* c, const double* radii, std::string& why) {
         why = "lanes must be 0, 1, 2, 4 or 8";
         return SIM_EINVAL;
     }
-    if (c->pair_kernel > SIM_KERNEL_WAVE) { why = "unknown pair_kernel"; return SIM_EINVAL; }
+    if (c->pair_kernel > SIM_KERNEL_HALF) { why = "unknown pair_kernel"; return SIM_EINVAL; }
+    if (c->pair_kernel == SIM_KERNEL_HALF && c->lanes > 1) {
+        why = "the half-pair kernel uses one lane per pair (lanes 0 or 1)";
+        return SIM_EINVAL;
+    }
     if (c->pair_kernel == SIM_KERNEL_WAVE && (c->lanes == 8 || c->nlist_cap > 62)) {
         why = "the wave kernel needs lanes <= 4 and nlist_cap <= 62";
         return SIM_EINVAL;
@@ -198,18 +203,24 @@ template <class T> std::vector<T> d2h(sim* s, const T* dev, size_t off, size_t c
     return h;
 }
 
-// one time step with parity q, without a list rebuild; both kernels do nothing
-// once the expiry test of an earlier pair kernel has halted the chunk
-void enqueue_step(sim* s, hipStream_t st, int q) {
-    launch_integrate(s->b, st, q);
-    launch_pair_force(s->b, st, q, 1, 1, 0xFFFFFFFFu);
+// nsteps time steps, the first with parity q0, without a list rebuild; every
+// launch does nothing once the expiry test of an earlier one has halted the
+// chunk.  With the half-pair variant the gather of each step but the last
+// also takes kick 1 and the drift of the next step.
+void enqueue_steps(sim* s, hipStream_t st, int nsteps, int q0) {
+    const bool fuse = s->b.kern == 2;
+    for (int k = 0; k < nsteps; ++k) {
+        const int q = q0 ^ (k & 1);
+        if (k == 0 || !fuse) launch_integrate(s->b, st, q);
+        launch_pair_force(s->b, st, q, 1, 1, 0xFFFFFFFFu, nullptr, fuse && k + 1 < nsteps);
+    }
 }
 
 hipGraphExec_t capture(sim* s, int nsteps, int q0) {
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
     HIPCHK(hipStreamBeginCapture(s->cap_st, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < nsteps; ++k) enqueue_step(s, s->cap_st, q0 ^ (k & 1));
+    enqueue_steps(s, s->cap_st, nsteps, q0);
     HIPCHK(hipStreamEndCapture(s->cap_st, &g));
     HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
     HIPCHK(hipGraphDestroy(g));
@@ -330,17 +341,18 @@ void set_dyn(sim* s, int r, double s_le, uint64_t step) {
 void set_variant(sim* s, int kern, int lanes) {
     s->b.kern = kern;
     s->b.lanes = lanes;
-    s->b.ppb = kern == 1 ? 256 / lanes : 128 / lanes;
+    s->b.ppb = kern == 2 ? 256 : kern == 1 ? 256 / lanes : 128 / lanes;
 }
 
 void tune_pair(sim* s, int want_kern, int want_lanes) {
     std::vector<std::pair<int, int>> cand;
-    for (int kern : {0, 1}) {
+    for (int kern : {2, 0, 1}) {
         if (want_kern && want_kern - 1 != kern) continue;
         if (kern == 1 && s->b.cap > 62) continue;
         for (int L : {1, 2, 4, 8}) {
             if (want_lanes && want_lanes != L) continue;
             if (kern == 1 && L == 8) continue;
+            if (kern == 2 && L != 1) continue;
             cand.push_back({kern, L});
         }
     }
@@ -507,6 +519,12 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         for (int d = 0; d < 3; ++d) b.hs[d] = s->dalloc(np * cap * (s->mixed ? sizeof(float) : sizeof(double)));
         b.cmask = s->alloc<uint64_t>(np);
         b.smask = s->alloc<uint64_t>(np);
+        b.lo0 = s->alloc<uint8_t>(np);
+        b.mir = s->alloc<uint8_t>(np * cap);
+        b.imask = s->alloc<uint64_t>(np);
+        b.qoff = s->alloc<uint16_t>(np);
+        b.pf = s->dalloc(np * cap * (s->mixed ? sizeof(float4) : sizeof(double4)));
+        b.pt = s->dalloc(np * cap * (s->mixed ? sizeof(float4) : sizeof(double4)));
         b.key = s->alloc<uint32_t>(np);
         b.cell_cnt = s->alloc<uint32_t>(key);
         b.cell_fill = s->alloc<uint32_t>(key);
@@ -524,6 +542,8 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         b.ring = s->alloc<double>((size_t)n_replicas * kRing * 27);
         b.last = s->alloc<double>((size_t)n_replicas * 27);
         b.blk_rep = s->alloc<uint32_t>(blk_rep.size());
+        b.dacc = s->alloc<double>(np);
+        b.dpart = s->alloc<float>(2 * (np / kTile));
         b.reps = s->alloc<RepParams>(n_replicas);
         b.dyn = s->alloc<RepDyn>(n_replicas);
         b.sys = s->alloc<SysDyn>(1);
@@ -577,29 +597,36 @@ void launch_steps(sim* s, int64_t m) {
             HIPCHK(hipGraphLaunch(s->g1[q], s->st));
         }
     } else if (s->profile) {
-        if (s->ev.size() < 2) {
-            for (int k = 0; k < 2; ++k) {
+        if (s->ev.size() < 4) {
+            for (int k = 0; k < 4; ++k) {
                 hipEvent_t e;
                 HIPCHK(hipEventCreate(&e));
                 s->ev.push_back(e);
             }
         }
+        const bool half = s->b.kern == 2;
         for (; m > 0; --m, q ^= 1) {
-            launch_integrate(s->b, s->st, q);
             HIPCHK(hipEventRecord(s->ev[0], s->st));
-            launch_pair_force(s->b, s->st, q, 1, 1, 0xFFFFFFFFu);
+            launch_integrate(s->b, s->st, q);
             HIPCHK(hipEventRecord(s->ev[1], s->st));
-            HIPCHK(hipEventSynchronize(s->ev[1]));
+            launch_pair_force(s->b, s->st, q, 1, 1, 0xFFFFFFFFu, half ? s->ev[2] : nullptr);
+            HIPCHK(hipEventRecord(s->ev[3], s->st));
+            HIPCHK(hipEventSynchronize(s->ev[3]));
             SysDyn sy;
             HIPCHK(hipMemcpy(&sy, s->b.sys, sizeof sy, hipMemcpyDeviceToHost));
             if (sy.halted) break;  // that launch did nothing; the caller completes the step
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, s->ev[0], s->ev[1]));
+            float ms = 0.f, mi = 0.f, mp = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, s->ev[1], s->ev[3]));
+            HIPCHK(hipEventElapsedTime(&mi, s->ev[0], s->ev[1]));
+            if (half) HIPCHK(hipEventElapsedTime(&mp, s->ev[1], s->ev[2]));
             s->prof_ms += ms;
+            s->prof_stage_ms[0] += mi;
+            s->prof_stage_ms[1] += half ? mp : ms;
+            s->prof_stage_ms[2] += half ? ms - mp : 0.0;
             s->prof_launches += 1;
         }
     } else {
-        for (; m > 0; --m, q ^= 1) enqueue_step(s, s->st, q);
+        enqueue_steps(s, s->st, (int)m, q);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s->st));
@@ -609,11 +636,18 @@ void launch_steps(sim* s, int64_t m) {
 // growth since the last build (the bound grows at most linearly per step).
 int64_t plan_steps(sim* s, const std::vector<RepDyn>& dyn) {
     if (s->since_build <= 0) return s->plan_hint;
+    // largest displacement bound per replica after the last step's drift (block maxima)
+    const uint32_t nt = s->b.npad / kTile;
+    std::vector<float> dp(nt);
+    HIPCHK(hipMemcpyAsync(dp.data(), s->b.dpart + (size_t)s->par * nt, nt * sizeof(float), hipMemcpyDeviceToHost,
+                          s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
     double worst = 0.0;  // fraction of the skin used per step
     for (int r = 0; r < s->nrep; ++r) {
         const RepParams& P = s->P[r];
-        const double used = 2.0 * dyn[r].dmax_slot[s->par] +
-                            std::fabs(P.gd) * dyn[r].t_slot[s->par] * (P.rc_max + 2.0 * P.skin);
+        double dmax = 0.0;
+        for (uint32_t k = P.blk_begin; k < P.blk_begin + P.nblk; ++k) dmax = std::max(dmax, (double)dp[k]);
+        const double used = 2.0 * dmax + std::fabs(P.gd) * dyn[r].t_slot[s->par] * (P.rc_max + 2.0 * P.skin);
         worst = std::max(worst, used / P.skin / (double)s->since_build);
     }
     if (!(worst > 0.0)) return 1 << 20;
@@ -688,6 +722,15 @@ int sim_profile(sim* s, int32_t enable) {
     s->profile = enable ? 1 : 0;
     s->prof_launches = 0;
     s->prof_ms = 0.0;
+    for (double& t : s->prof_stage_ms) t = 0.0;
+    return SIM_OK;
+}
+
+int sim_stage_time(sim* s, int32_t stage, int64_t* launches, double* total_ms) {
+    if (!s) return fail(nullptr, SIM_EINVAL, "null handle");
+    if (stage < 0 || stage > 2) return fail(s, SIM_EINVAL, "stage must be 0, 1 or 2");
+    if (launches) *launches = s->prof_launches;
+    if (total_ms) *total_ms = s->prof_stage_ms[stage];
     return SIM_OK;
 }
 
@@ -964,7 +1007,7 @@ int sim_stats(sim* s, int32_t r, sim_stats_t* out) {
         out->step = d[0].step_slot[s->par];
         out->le_offset = d[0].s_slot[s->par];
         out->lanes = s->b.lanes;
-        out->pair_kernel = s->b.kern == 1 ? SIM_KERNEL_WAVE : SIM_KERNEL_LANES;
+        out->pair_kernel = s->b.kern + 1;  // SIM_KERNEL_LANES, _WAVE, _HALF
         return SIM_OK;
     } catch (const HipError& e) {
         return hip_fail(s, e);

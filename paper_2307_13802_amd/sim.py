@@ -21,7 +21,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ECAPACITY, ERANGE = 0, -1, -2, -3, -4, -
 FP64, MIXED = 0, 1
 FREEZE_X, NO_LUB, NO_PAIR_BROWN, NO_CONTACT, NO_ONEBODY = 0x1, 0x2, 0x4, 0x8, 0x10
 REBUILD_EACH_STEP, NO_GRAPH = 0x100, 0x200
-KERNEL_AUTO, KERNEL_LANES, KERNEL_WAVE = 0, 1, 2
+KERNEL_AUTO, KERNEL_LANES, KERNEL_WAVE, KERNEL_HALF = 0, 1, 2, 3
 STRESS_CONTACT, STRESS_LUB, STRESS_BROWN, STRESS_DRAG, STRESS_TOTAL = range(5)
 STRESS_LAST, STRESS_MEAN = 0, 1
 
@@ -94,6 +94,7 @@ def lib():
         "sim_stats": [vp, C.c_int32, C.POINTER(_Stats)],
         "sim_profile": [vp, C.c_int32],
         "sim_kernel_time": [vp, lp, dp],
+        "sim_stage_time": [vp, C.c_int32, lp, dp],
         "sim_destroy": [vp],
         "sim_last_error": [vp, C.c_char_p, C.c_size_t],
         "sim_set_allocator": [_ALLOC_CB, _FREE_CB, vp],
@@ -355,6 +356,12 @@ class Sim:
     def kernel_time(self):
         n, ms = C.c_int64(0), C.c_double(0)
         _check(lib().sim_kernel_time(self.h, C.byref(n), C.byref(ms)), self.h)
+        return n.value, ms.value
+
+    def stage_time(self, stage):
+        """(steps timed, total ms) of one stage: 0 integrate, 1 pair kernel, 2 gather."""
+        n, ms = C.c_int64(0), C.c_double(0)
+        _check(lib().sim_stage_time(self.h, int(stage), C.byref(n), C.byref(ms)), self.h)
         return n.value, ms.value
 
 

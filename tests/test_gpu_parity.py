@@ -145,7 +145,7 @@ def test_step_trajectory_fp64(P):
             assert np.array_equal(sim.contacts()[0], orc.contacts()[0])
 
 
-@pytest.mark.parametrize("kernel, lanes", [(1, 1), (1, 2), (1, 4), (1, 8), (2, 1), (2, 2), (2, 4)])
+@pytest.mark.parametrize("kernel, lanes", [(1, 1), (1, 2), (1, 4), (1, 8), (2, 1), (2, 2), (2, 4), (3, 1)])
 def test_pair_kernel_variants(P, kernel, lanes):
     """Every pair-kernel variant gives the oracle's forces and exact springs."""
     st = _state(n=1500, phi=0.55, seed=7)
@@ -158,13 +158,13 @@ def test_pair_kernel_variants(P, kernel, lanes):
         _compare_eval(P, sim, orc, tol, exact=exact)
 
 
-def test_wave_kernel_bit_identical_to_one_lane(P):
-    """The wave-cooperative kernel sums each particle's items in the same order as the
-    one-lane kernel: whole trajectories agree bit for bit, in both precisions."""
+def test_variants_bit_identical_to_one_lane(P):
+    """The wave-cooperative and the half-pair kernels sum each particle's items in the same
+    order as the one-lane kernel: whole trajectories agree bit for bit, in both precisions."""
     st = _state(n=2000, phi=0.55, seed=8)
     for prec in (P.FP64, P.MIXED):
         runs = []
-        for kernel, lanes in ((1, 1), (2, 1), (2, 2), (2, 4)):
+        for kernel, lanes in ((1, 1), (2, 1), (2, 2), (2, 4), (3, 1)):
             _say(f"case: 60 steps precision={prec} kernel={kernel} lanes={lanes}")
             sim = P.Sim(_cfg(P, st, precision=prec, lanes=lanes, pair_kernel=kernel), st["radii"], st["x"],
                         st["v"], st["w"])
@@ -237,14 +237,14 @@ def test_batched_replicas_match_single(P):
             assert np.array_equal(a[key], b[key]), key
 
 
-@pytest.mark.parametrize("lanes", [1, 2])
-def test_deterministic_and_restart(P, lanes):
+@pytest.mark.parametrize("kernel, lanes", [(0, 1), (0, 2), (3, 1)])
+def test_deterministic_and_restart(P, kernel, lanes):
     """Identical runs are bit-identical; a restart from get_state/contacts continues the
     run bit-identically with one lane per particle (list-independent summation order) and
     to rounding with several lanes (their split of the list depends on when it was built)."""
     st = _state(n=600, phi=0.55, seed=5)
-    cfg = _cfg(P, st, lanes=lanes)
-    _say(f"case: determinism and restart, 40 steps, lanes={lanes}")
+    cfg = _cfg(P, st, lanes=lanes, pair_kernel=kernel)
+    _say(f"case: determinism and restart, 40 steps, kernel={kernel} lanes={lanes}")
     s1 = P.Sim(cfg, st["radii"], st["x"], st["v"], st["w"])
     s2 = P.Sim(cfg, st["radii"], st["x"], st["v"], st["w"])
     s1.step(40)
