@@ -311,6 +311,9 @@ def main():
     ap.add_argument("--sample-every", type=int, default=250, help="c3: steps between shadow samples")
     ap.add_argument("--variants", action="store_true",
                     help="only run 20 steps of each pair-kernel variant (a counter-collection driver)")
+    ap.add_argument("--trace", action="store_true",
+                    help="profiler driver: a 256 MiB device copy (the calibration of the byte counters), then "
+                         "--steps steps of the workload (c2, or c3 at Pe = 10) in FP64 and in mixed precision")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the engine has no multi-GPU path",
@@ -323,6 +326,29 @@ def main():
     from inputs import gen
 
     say = lambda m: print(m, file=sys.stderr, flush=True)
+    if args.trace:
+        x = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        torch.cuda.synchronize()
+        torch.mul(x, 2.0, out=y)  # one elementwise kernel: 256 MiB read + 256 MiB written
+        torch.cuda.synchronize()
+        del x, y
+        wl = gen.C2 if args.workload == "c2" else gen.C3
+        st = gen.make_state(wl)
+        say(f"workload ready: {wl.name}")
+        for prec in (P.FP64, P.MIXED):
+            sim = P.Sim(P.Config(box=st["L"], precision=prec, **st["params"]), st["radii"], st["x"], st["v"], st["w"])
+            stt = sim.stats()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(args.steps)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            sim.close()
+            say(f"precision={prec} kernel={stt['pair_kernel']} lanes={stt['lanes']}: {args.steps} steps, "
+                f"{len(st['radii']) * args.steps / el:.3e} particle-steps/s")
+        return
     if args.workload in ("c3", "sweep", "large"):
         steps = args.steps if args.steps != 10000 or args.workload == "large" else 5000
         if args.workload == "c3":
@@ -344,7 +370,7 @@ def main():
     if args.variants:
         for prec in (P.FP64, P.MIXED):
             for kern, lanes in ((P.KERNEL_LANES, 1), (P.KERNEL_LANES, 2), (P.KERNEL_LANES, 4),
-                                (P.KERNEL_WAVE, 1), (P.KERNEL_WAVE, 2)):
+                                (P.KERNEL_WAVE, 1), (P.KERNEL_WAVE, 2), (P.KERNEL_HALF, 1)):
                 cfg = P.Config(box=st["L"], precision=prec, lanes=lanes, pair_kernel=kern, **st["params"])
                 sim = P.Sim(cfg, st["radii"], st["x"], st["v"], st["w"])
                 sim.step(20)

@@ -109,6 +109,15 @@ __device__ __forceinline__ int cell_coord(double x, double w, int n) {
 
 __device__ __forceinline__ float as_posf(uint32_t b) { return __uint_as_float(b); }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Particle kernels map block b to tile xcd_tile(b, g) so that every XCD
+// walks one contiguous range of Morton-ordered tiles: neighbours' data then
+// sits in the L2 of the XCD that reads it.  A bijection of [0, g).
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t g) {
+    const uint32_t x = b & 7u, k = b >> 3, per = g >> 3, rem = g & 7u;
+    return x * per + (x < rem ? x : rem) + k;
+}
+
 // Lees-Edwards offset one step after the stored one (same arithmetic everywhere)
 __device__ __forceinline__ double next_offset(const RepParams& P, double s_le) {
     double s = s_le + P.gdLy * P.dt;
@@ -312,7 +321,8 @@ __device__ __forceinline__ void integrate_particle(const Bufs& b, const RepParam
 template <bool MIX>
 __global__ __launch_bounds__(256) void k_integrate(Bufs b, int q) {
     if (b.sys->halted) return;  // uniform: set by an earlier launch
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t i = tile * blockDim.x + threadIdx.x;
     const uint32_t r = b.blk_rep[i / kTile];
     const RepParams& P = b.reps[r];
     const RepDyn& D = b.dyn[r];
@@ -330,7 +340,7 @@ __global__ __launch_bounds__(256) void k_integrate(Bufs b, int q) {
         integrate_particle<MIX>(b, P, D, q, i, b.pos[i], b.vf[i], b.wf[i], F, T, dblk, expire);
     }
     if (expire) atomicOr(&b.sys->expire[q], 1u);  // rare: the lists are rebuilt before that
-    block_max_store(dblk, &b.dpart[(size_t)q * (b.npad / kTile) + blockIdx.x]);
+    block_max_store(dblk, &b.dpart[(size_t)q * (b.npad / kTile) + tile]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1063,14 +1073,16 @@ __device__ __forceinline__ void load_vw(const Bufs& b, uint32_t i, typename Eval
 template <bool MIX, bool MASKS = true>
 __device__ __forceinline__ void store_particle(const Bufs& b, const RepParams& P, int kick, uint32_t i,
                                                const double* Ft, const double* Tt, uint64_t cm, uint64_t sm,
-                                               bool& bad, double4* vf_out = nullptr, double4* wf_out = nullptr) {
+                                               bool& bad, double4* vf_out = nullptr, double4* wf_out = nullptr,
+                                               bool store = true) {
     bad = !(isfinite(Ft[0]) && isfinite(Ft[1]) && isfinite(Ft[2]) && isfinite(Tt[0]) && isfinite(Tt[1]) &&
             isfinite(Tt[2]));
     if (MASKS) {
         b.cmask[i] = cm;
         b.smask[i] = sm;
     }
-    if (MIX) {
+    if (!store) {
+    } else if (MIX) {
         ((float4*)b.F)[i] = make_float4((float)Ft[0], (float)Ft[1], (float)Ft[2], 0.0f);
         ((float4*)b.T)[i] = make_float4((float)Tt[0], (float)Tt[1], (float)Tt[2], 0.0f);
     } else {
@@ -1087,8 +1099,10 @@ __device__ __forceinline__ void store_particle(const Bufs& b, const RepParams& P
         vf.x += hm * Ft[0]; vf.y += hm * Ft[1]; vf.z += hm * Ft[2];
         wf.x += hI * Tt[0]; wf.y += hI * Tt[1]; wf.z += hI * Tt[2];
     }
-    b.vf[i] = vf;
-    b.wf[i] = wf;
+    if (store) {
+        b.vf[i] = vf;
+        b.wf[i] = wf;
+    }
     if (vf_out) {
         *vf_out = vf;
         *wf_out = wf;
@@ -1098,7 +1112,7 @@ __device__ __forceinline__ void store_particle(const Bufs& b, const RepParams& P
 // block partial of the 27 stress sums held in thread-private LDS slots sacc[c][thread]
 // (fixed order), stored for the reduction by a later launch; blockDim = NT
 template <int NT>
-__device__ __forceinline__ void write_block_partial(const Bufs& b, int q, double (*sacc)[NT]) {
+__device__ __forceinline__ void write_block_partial(const Bufs& b, int q, double (*sacc)[NT], uint32_t tile) {
     __syncthreads();
     __shared__ double quarter[108];
     if (threadIdx.x < 108) {
@@ -1111,7 +1125,7 @@ __device__ __forceinline__ void write_block_partial(const Bufs& b, int q, double
     if (threadIdx.x < 27) {
         const int c = threadIdx.x;
         const double t = ((quarter[4 * c] + quarter[4 * c + 1]) + quarter[4 * c + 2]) + quarter[4 * c + 3];
-        b.partial[((size_t)q * 27 + c) * b.nblk_max + blockIdx.x] = t;
+        b.partial[((size_t)q * 27 + c) * b.nblk_max + tile] = t;
     }
 }
 
@@ -1134,7 +1148,8 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(Bufs b, int q, int kick, in
     // the first blocks also reduce the stress of the previous evaluation (its partials
     // have the other parity); with more blocks than compute units this costs little
     finalize_all(b, 1 - q);
-    const uint32_t i = (blockIdx.x * kPairBlock + threadIdx.x) / LN;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t i = (tile * kPairBlock + threadIdx.x) / LN;
     const uint32_t sub = threadIdx.x % LN;
     const uint32_t r = b.blk_rep[i / kTile];
     if (only_rep != 0xFFFFFFFFu && r != only_rep) return;  // whole block belongs to one replica
@@ -1142,7 +1157,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(Bufs b, int q, int kick, in
     RepDyn& D = b.dyn[r];
     double s_le;
     uint64_t step;
-    if (!eval_begin(b, q, advance, P, D, blockIdx.x == P.p_begin * LN / kPairBlock, s_le, step)) return;
+    if (!eval_begin(b, q, advance, P, D, tile == P.p_begin * LN / kPairBlock, s_le, step)) return;
     EvalCtx<MIX> C;
     make_ctx<MIX>(C, P, s_le, step);
 
@@ -1221,7 +1236,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(Bufs b, int q, int kick, in
     // health: non-finite forces, largest overlap (relaxed atomics; read after the launch)
     if (bad) atomicOr(&D.health, H_NAN);
     block_atomic_max(maxov, D.maxov_bits[q]);
-    write_block_partial<kPairBlock>(b, q, sacc);
+    write_block_partial<kPairBlock>(b, q, sacc, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -1240,14 +1255,15 @@ __global__ __launch_bounds__(256) void k_pairq(Bufs b, int q, int kick, int adva
     if (b.sys->halted) return;
     finalize_all(b, 1 - q);
     const int w = threadIdx.x >> 6, p = threadIdx.x & 63;
-    const uint32_t base = (blockIdx.x * 4 + w) * NP;  // first particle of this wave
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t base = (tile * 4 + w) * NP;  // first particle of this wave
     const uint32_t r = b.blk_rep[base / kTile];       // a block (4 NP <= 256 particles) is inside one tile
     if (only_rep != 0xFFFFFFFFu && r != only_rep) return;
     const RepParams& P = b.reps[r];
     RepDyn& D = b.dyn[r];
     double s_le;
     uint64_t step;
-    if (!eval_begin(b, q, advance, P, D, blockIdx.x == P.p_begin / (4 * NP), s_le, step)) return;
+    if (!eval_begin(b, q, advance, P, D, tile == P.p_begin / (4 * NP), s_le, step)) return;
     EvalCtx<MIX> C;
     make_ctx<MIX>(C, P, s_le, step);
     const uint32_t npad = b.npad;
@@ -1399,7 +1415,7 @@ __global__ __launch_bounds__(256) void k_pairq(Bufs b, int q, int kick, int adva
         const int c = threadIdx.x;
         double tsum = 0.0;
         for (int k = 0; k < 16; ++k) tsum += rows[k][c];
-        b.partial[((size_t)q * 27 + c) * b.nblk_max + blockIdx.x] = tsum;
+        b.partial[((size_t)q * 27 + c) * b.nblk_max + tile] = tsum;
     }
 }
 
@@ -1433,14 +1449,15 @@ __global__ __launch_bounds__(256) void k_half(Bufs b, int q, int advance, uint32
     if (b.sys->halted) return;
     finalize_all(b, 1 - q);
     const int w = threadIdx.x >> 6, p = threadIdx.x & 63;
-    const uint32_t base = blockIdx.x * 256 + w * 64;   // first particle of this wave
-    const uint32_t r = b.blk_rep[blockIdx.x];          // a block is one kTile of particles
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);  // a block is one kTile of particles
+    const uint32_t base = tile * 256 + w * 64;                // first particle of this wave
+    const uint32_t r = b.blk_rep[tile];
     if (only_rep != 0xFFFFFFFFu && r != only_rep) return;
     const RepParams& P = b.reps[r];
     RepDyn& D = b.dyn[r];
     double s_le;
     uint64_t step;
-    if (!eval_begin(b, q, advance, P, D, blockIdx.x == P.p_begin / 256, s_le, step)) return;
+    if (!eval_begin(b, q, advance, P, D, tile == P.p_begin / 256, s_le, step)) return;
     EvalCtx<MIX> C;
     make_ctx<MIX>(C, P, s_le, step);
     const uint32_t npad = b.npad;
@@ -1529,7 +1546,7 @@ __global__ __launch_bounds__(256) void k_half(Bufs b, int q, int advance, uint32
         const int c = threadIdx.x;
         double tsum = 0.0;
         for (int k = 0; k < 16; ++k) tsum += rows[k][c];
-        b.partial[((size_t)q * 27 + c) * b.nblk_max + blockIdx.x] = tsum;
+        b.partial[((size_t)q * 27 + c) * b.nblk_max + tile] = tsum;
     }
 }
 
@@ -1542,8 +1559,9 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
 template <bool MIX>
 __global__ __launch_bounds__(256) void k_gather(Bufs b, int q, int kick, int fuse, uint32_t only_rep) {
     if (b.sys->halted) return;
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    const uint32_t r = b.blk_rep[blockIdx.x];
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t i = tile * 256 + threadIdx.x;
+    const uint32_t r = b.blk_rep[tile];
     if (only_rep != 0xFFFFFFFFu && r != only_rep) return;
     const RepParams& P = b.reps[r];
     RepDyn& D = b.dyn[r];
@@ -1553,7 +1571,7 @@ __global__ __launch_bounds__(256) void k_gather(Bufs b, int q, int kick, int fus
     if (bad) atomicOr(&D.health, H_NAN);
     if (fuse) {
         if (expire) atomicOr(&b.sys->expire[1 - q], 1u);
-        block_max_store(dblk, &b.dpart[(size_t)(1 - q) * (b.npad / kTile) + blockIdx.x]);
+        block_max_store(dblk, &b.dpart[(size_t)(1 - q) * (b.npad / kTile) + tile]);
     }
 }
 
@@ -1621,8 +1639,10 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
     double Ft[3], Tt[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) { Ft[d] = F.get(d); Tt[d] = T.get(d); }
+    // a fused step keeps the full-step values in registers: only the last step of a
+    // launch sequence (never fused) leaves them in memory for the state readers
     double4 vf, wf;
-    store_particle<MIX, false>(b, P, kick, i, Ft, Tt, 0ull, 0ull, bad, &vf, &wf);
+    store_particle<MIX, false>(b, P, kick, i, Ft, Tt, 0ull, 0ull, bad, &vf, &wf, !fuse);
     if (fuse) {
         if (MIX) {  // the next kick uses the force as stored
 #pragma unroll
