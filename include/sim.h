@@ -115,7 +115,7 @@ typedef struct sim_config {
     uint32_t flags;         /* SIM_* flags, identical for all replicas               */
     uint32_t nlist_cap;     /* neighbour list capacity per particle; 0 selects 48    */
     uint32_t lanes;         /* lanes sharing one particle in the pair kernel: 1, 2, 4
-                               or 8 (at most 4 for SIM_KERNEL_WAVE, 1 for
+                               or 8 (at most 4 for SIM_KERNEL_WAVE and
                                SIM_KERNEL_HALF); 0 = chosen by timing at creation    */
     uint32_t pair_kernel;   /* SIM_KERNEL_AUTO, _LANES, _WAVE or _HALF                */
     uint32_t reserved;      /* must be 0                                             */
@@ -131,9 +131,11 @@ typedef struct sim_config {
                                every pair is evaluated by both of its particles       */
 #define SIM_KERNEL_WAVE  2  /* a wave tests its particles' list entries, then packs
                                their interacting pairs into full 64-lane batches      */
-#define SIM_KERNEL_HALF  3  /* every pair evaluated once, by its lower-id particle,
-                               packed 64 to a wave; a second launch sums each
-                               particle's pair terms and one-body terms              */
+#define SIM_KERNEL_HALF  3  /* every pair evaluated once, by its lower-id particle
+                               (`lanes` lanes per particle test its list), packed 64
+                               to a wave; a second launch sums each particle's pair
+                               terms and one-body terms in item order, so forces
+                               are bit-identical for every `lanes`                    */
 
 typedef struct sim_stats_t {
     double  contacts_per_particle;  /* Z = 2 * contacts / n                          */
@@ -157,7 +159,7 @@ typedef struct sim_stats_t {
  * interaction range plus skin (the minimum image must be unique), a wrong
  * struct_size, nlist_cap > 64, lanes not in {0, 1, 2, 4, 8}, an unknown
  * pair_kernel, SIM_KERNEL_WAVE with lanes 8 or nlist_cap > 62,
- * SIM_KERNEL_HALF with lanes > 1, or a nonzero reserved field. */
+ * SIM_KERNEL_HALF with lanes 8, or a nonzero reserved field. */
 int sim_validate(const sim_config* cfg, const double* radii);
 
 /* Creates a handle with n_replicas systems.  For replica r: radii[r] -> n

@@ -1421,11 +1421,12 @@ __global__ __launch_bounds__(256) void k_pairq(Bufs b, int q, int kick, int adva
 
 // ---------------------------------------------------------------------------
 // Variant 3 (half-pair): every interacting pair is evaluated once, by its
-// lower-id particle.  k_half: a wave owns 64 particles; each lane tests the
-// entries of its particle whose partner has the higher id (a suffix of the
-// id-sorted list), the wave packs the interacting ones into a queue and
+// lower-id particle.  k_half: a wave owns NP = 64 / LN particles; LN lanes
+// per particle test the entries whose partner has the higher id (a suffix of
+// the id-sorted list), the wave packs the interacting ones into a queue and
 // evaluates them 64 at a time, writing the pair force on the lower-id
-// particle and, for a contact, n x (k_t s) into the entry.  k_gather: each
+// particle and, for a contact, n x (k_t s), in queue order.  More lanes per
+// particle suit systems too small to fill the GPU with one.  k_gather: each
 // lane sums its particle's pair terms in entry order (reading a lower-id
 // partner's result through the mirror index, negated), then the one-body
 // force and torque, then applies kick 2.  The sums run in the same item order
@@ -1442,44 +1443,50 @@ template <> struct Vec4<float> {
     static __device__ __forceinline__ T make(float x, float y, float z) { return make_float4(x, y, z, 0.0f); }
 };
 
-template <bool MIX>
-__global__ __launch_bounds__(256) void k_half(Bufs b, int q, int advance, uint32_t only_rep) {
+template <bool MIX, int LN>
+__global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int advance, uint32_t only_rep) {
     using R = typename std::conditional<MIX, float, double>::type;
     using V4 = typename Vec4<R>::T;
+    constexpr int NP = 64 / LN;  // particles per wave
     if (b.sys->halted) return;
     finalize_all(b, 1 - q);
     const int w = threadIdx.x >> 6, p = threadIdx.x & 63;
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);  // a block is one kTile of particles
-    const uint32_t base = tile * 256 + w * 64;                // first particle of this wave
-    const uint32_t r = b.blk_rep[tile];
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);  // a block: 4 NP particles, inside one kTile
+    const uint32_t base = (tile * 4 + w) * NP;                // first particle of this wave
+    const uint32_t r = b.blk_rep[base / kTile];
     if (only_rep != 0xFFFFFFFFu && r != only_rep) return;
     const RepParams& P = b.reps[r];
     RepDyn& D = b.dyn[r];
     double s_le;
     uint64_t step;
-    if (!eval_begin(b, q, advance, P, D, tile == P.p_begin / 256, s_le, step)) return;
+    if (!eval_begin(b, q, advance, P, D, tile == P.p_begin / (4 * NP), s_le, step)) return;
     EvalCtx<MIX> C;
     make_ctx<MIX>(C, P, s_le, step);
     const uint32_t npad = b.npad;
 
-    __shared__ uint16_t queue[4][64 * 64];   // (particle slot << 6) | entry
-    __shared__ unsigned long long cmo[4][64], cmq[4][64], smq[4][64];
+    __shared__ uint16_t queue[4][NP * 64];   // (particle slot << 6) | entry
+    __shared__ unsigned long long cmo[4][NP], cmq[4][NP], smq[4][NP];
 
-    // ---- cull: interacting entries with a higher-id partner
-    const uint32_t i = base + p;
+    // ---- cull: interacting entries with a higher-id partner (LN lanes per particle)
+    const uint32_t l = p / LN, sub = p % LN;
+    const uint32_t i = base + l;
     const bool valid = i - P.p_begin < P.n;
     uint64_t im = 0ull;
     if (valid) {
         const double4 pi = b.pos[i];
         const uint32_t cnt = b.ncnt[i];
-        for (uint32_t e = b.lo0[i]; e < cnt; ++e)
+        for (uint32_t e = b.lo0[i] + sub; e < cnt; e += LN)
             if (interacting(P, s_le, pi, b.pos[b.nbr[e * npad + i]])) im |= 1ull << e;
-        cmo[w][p] = b.cmask[i];
+        if (sub == 0) cmo[w][l] = b.cmask[i];
     }
-    cmq[w][p] = 0ull;
-    smq[w][p] = 0ull;
+    if (LN >= 2) im |= dpp_u64<0xB1>(im);
+    if (LN >= 4) im |= dpp_u64<0x4E>(im);
+    if (sub == 0) {
+        cmq[w][l] = 0ull;
+        smq[w][l] = 0ull;
+    }
     // exclusive prefix of the per-particle counts across the wave
-    const uint32_t cnt_i = (uint32_t)__popcll(im);
+    const uint32_t cnt_i = sub == 0 ? (uint32_t)__popcll(im) : 0u;
     uint32_t incl = cnt_i;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -1487,13 +1494,13 @@ __global__ __launch_bounds__(256) void k_half(Bufs b, int q, int advance, uint32
         if (p >= off) incl += y;
     }
     const uint32_t total = __shfl(incl, 63);
-    {
+    if (sub == 0) {
         uint32_t k = incl - cnt_i;
         if (valid) {
             b.imask[i] = im;
             b.qoff[i] = (uint16_t)k;
         }
-        for (uint64_t m = im; m; m &= m - 1ull) queue[w][k++] = (uint16_t)((p << 6) | __builtin_ctzll(m));
+        for (uint64_t m = im; m; m &= m - 1ull) queue[w][k++] = (uint16_t)((l << 6) | __builtin_ctzll(m));
     }
     // results of this wave's pairs: a contiguous run in queue order
     V4* const pf = (V4*)b.pf + (size_t)base * b.cap;
@@ -1528,9 +1535,9 @@ __global__ __launch_bounds__(256) void k_half(Bufs b, int q, int advance, uint32
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    if (valid) {
-        b.cmask[i] = cmq[w][p];
-        b.smask[i] = smq[w][p];
+    if (valid && sub == 0) {
+        b.cmask[i] = cmq[w][l];
+        b.smask[i] = smq[w][l];
     }
 
     block_atomic_max(maxov, D.maxov_bits[q]);
@@ -1591,35 +1598,75 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
     Acc<R> F, T;
     const uint32_t cnt = b.ncnt[i], e0 = b.lo0[i];
     const uint64_t im = b.imask[i], cm = b.cmask[i];
-    // pair k of the wave owning particle p sits at (p & ~63) * cap + k
-    size_t klo = (size_t)(i & ~63u) * b.cap + b.qoff[i];
-    for (uint32_t e = 0; e < cnt; ++e) {
-        size_t slot;
-        bool ct;
-        R sg;
-        if (e < e0) {  // lower-id partner j: its entry m holds the pair
-            const uint32_t j = b.nbr[e * npad + i];
-            const uint32_t m = b.mir[e * npad + i];
-            const uint64_t imj = b.imask[j];
-            if (!((imj >> m) & 1ull)) continue;
-            slot = (size_t)(j & ~63u) * b.cap + b.qoff[j] + (uint32_t)__popcll(imj & ((1ull << m) - 1ull));
-            ct = (b.cmask[j] >> m) & 1ull;
-            sg = (R)-1;
-        } else {
-            if (!((im >> e) & 1ull)) continue;
-            slot = klo++;
-            ct = (cm >> e) & 1ull;
-            sg = (R)1;
+    // pair k of the wave owning particle p sits at (p & ~(NP - 1)) * cap + k, NP = 64 / lanes
+    const uint32_t wmask = ~(64u / (uint32_t)b.lanes - 1u);
+    size_t klo = (size_t)(i & wmask) * b.cap + b.qoff[i];
+    // entries in groups of GB: the loads of a group's stages (list, partner masks,
+    // pair records) are issued together; the sums still run in entry order
+    constexpr uint32_t GB = 4;
+    for (uint32_t c0 = 0; c0 < cnt; c0 += GB) {
+        uint32_t jj[GB], mm[GB], qj[GB];
+        uint64_t imj[GB], cmj[GB];
+#pragma unroll
+        for (uint32_t u = 0; u < GB; ++u) {
+            const uint32_t e = c0 + u;
+            jj[u] = 0u;
+            mm[u] = 0u;
+            if (e < cnt && e < e0) {  // lower-id partner j: its entry m holds the pair
+                jj[u] = b.nbr[e * npad + i];
+                mm[u] = b.mir[e * npad + i];
+            }
         }
-        const V4 f = ((const V4*)b.pf)[slot];
-        F.add(0, sg * f.x);
-        F.add(1, sg * f.y);
-        F.add(2, sg * f.z);
-        if (ct) {
-            const V4 t = ((const V4*)b.pt)[slot];
-            T.add(0, ai * t.x);
-            T.add(1, ai * t.y);
-            T.add(2, ai * t.z);
+#pragma unroll
+        for (uint32_t u = 0; u < GB; ++u) {
+            const uint32_t e = c0 + u;
+            imj[u] = 0ull;
+            cmj[u] = 0ull;
+            qj[u] = 0u;
+            if (e < cnt && e < e0) {
+                imj[u] = b.imask[jj[u]];
+                cmj[u] = b.cmask[jj[u]];
+                qj[u] = b.qoff[jj[u]];
+            }
+        }
+        size_t slot[GB];
+        bool use[GB], ct[GB];
+#pragma unroll
+        for (uint32_t u = 0; u < GB; ++u) {
+            const uint32_t e = c0 + u;
+            slot[u] = 0;
+            use[u] = false;
+            ct[u] = false;
+            if (e >= cnt) continue;
+            if (e < e0) {
+                use[u] = (imj[u] >> mm[u]) & 1ull;
+                slot[u] = (size_t)(jj[u] & wmask) * b.cap + qj[u] +
+                          (uint32_t)__popcll(imj[u] & ((1ull << mm[u]) - 1ull));
+                ct[u] = use[u] && ((cmj[u] >> mm[u]) & 1ull);
+            } else if ((im >> e) & 1ull) {
+                use[u] = true;
+                slot[u] = klo++;
+                ct[u] = (cm >> e) & 1ull;
+            }
+        }
+        V4 fv[GB], tv[GB];
+#pragma unroll
+        for (uint32_t u = 0; u < GB; ++u) {
+            if (use[u]) fv[u] = ((const V4*)b.pf)[slot[u]];
+            if (ct[u]) tv[u] = ((const V4*)b.pt)[slot[u]];
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < GB; ++u) {
+            if (!use[u]) continue;
+            const R sg = c0 + u < e0 ? (R)-1 : (R)1;
+            F.add(0, sg * fv[u].x);
+            F.add(1, sg * fv[u].y);
+            F.add(2, sg * fv[u].z);
+            if (ct[u]) {
+                T.add(0, ai * tv[u].x);
+                T.add(1, ai * tv[u].y);
+                T.add(2, ai * tv[u].z);
+            }
         }
     }
     if (C.do_one) {
@@ -1732,7 +1779,12 @@ template <bool MIX>
 static void launch_pair_t(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep,
                           hipEvent_t mid, int fuse) {
     if (b.kern == 2) {  // half-pair evaluation, then the per-particle gather
-        hipLaunchKernelGGL(k_half<MIX>, dim3(b.npad / 256), dim3(256), 0, st, b, q, advance, only_rep);
+        const uint32_t g = b.npad / 256;
+        switch (b.lanes) {
+            case 1: hipLaunchKernelGGL((k_half<MIX, 1>), dim3(g), dim3(256), 0, st, b, q, advance, only_rep); break;
+            case 2: hipLaunchKernelGGL((k_half<MIX, 2>), dim3(2 * g), dim3(256), 0, st, b, q, advance, only_rep); break;
+            default: hipLaunchKernelGGL((k_half<MIX, 4>), dim3(4 * g), dim3(256), 0, st, b, q, advance, only_rep); break;
+        }
         if (mid) (void)hipEventRecord(mid, st);
         hipLaunchKernelGGL(k_gather<MIX>, dim3(b.npad / 256), dim3(256), 0, st, b, q, kick, fuse, only_rep);
         return;

@@ -154,8 +154,8 @@ int validate(const sim_config* c, const double* radii, std::string& why) {
         return SIM_EINVAL;
     }
     if (c->pair_kernel > SIM_KERNEL_HALF) { why = "unknown pair_kernel"; return SIM_EINVAL; }
-    if (c->pair_kernel == SIM_KERNEL_HALF && c->lanes > 1) {
-        why = "the half-pair kernel uses one lane per pair (lanes 0 or 1)";
+    if (c->pair_kernel == SIM_KERNEL_HALF && c->lanes == 8) {
+        why = "the half-pair kernel needs lanes <= 4";
         return SIM_EINVAL;
     }
     if (c->pair_kernel == SIM_KERNEL_WAVE && (c->lanes == 8 || c->nlist_cap > 62)) {
@@ -343,7 +343,7 @@ void set_dyn(sim* s, int r, double s_le, uint64_t step) {
 void set_variant(sim* s, int kern, int lanes) {
     s->b.kern = kern;
     s->b.lanes = lanes;
-    s->b.ppb = kern == 2 ? 256 : kern == 1 ? 256 / lanes : 128 / lanes;
+    s->b.ppb = kern == 0 ? 128 / lanes : 256 / lanes;
 }
 
 void tune_pair(sim* s, int want_kern, int want_lanes) {
@@ -353,8 +353,7 @@ void tune_pair(sim* s, int want_kern, int want_lanes) {
         if (kern == 1 && s->b.cap > 62) continue;
         for (int L : {1, 2, 4, 8}) {
             if (want_lanes && want_lanes != L) continue;
-            if (kern == 1 && L == 8) continue;
-            if (kern == 2 && L != 1) continue;
+            if (kern != 0 && L == 8) continue;
             cand.push_back({kern, L});
         }
     }

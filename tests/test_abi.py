@@ -66,7 +66,7 @@ def test_validate_accepts_good_config():
     (dict(lanes=3), None, "lanes"),
     (dict(pair_kernel=4), None, "pair_kernel"),
     (dict(pair_kernel=2, lanes=8), None, "wave kernel"),
-    (dict(pair_kernel=3, lanes=2), None, "half-pair"),
+    (dict(pair_kernel=3, lanes=8), None, "half-pair"),
 ])
 def test_validate_rejects(kw, radii, needle):
     a = np.full(4, 1.0) if radii is None else radii
