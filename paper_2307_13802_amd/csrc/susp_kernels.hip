@@ -848,6 +848,14 @@ __device__ __forceinline__ void onebody_terms(const RepParams& P, const EvalCtx<
     }
 }
 
+// Partner data of a pair item loaded ahead of its evaluation (so that the
+// loads of many items are in flight together).
+template <class R> struct PairIn {
+    uint32_t j, idj;
+    double4 pj;
+    R vj[3], wj[3], s[3];  // half-step velocities of j, stored spring of the entry
+};
+
 // One item of particle i: contribution f to its force and t to its torque.
 // Pair items also update the stored spring (entry e of i), the contact and
 // sliding bits, the largest overlap and the lower-id stress sums (addS); for
@@ -860,7 +868,8 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
                                           const typename EvalCtx<MIX>::R* vi, const typename EvalCtx<MIX>::R* wi,
                                           bool had_contact, typename EvalCtx<MIX>::R* f,
                                           typename EvalCtx<MIX>::R* t, bool& contact, bool& slid, float& maxov,
-                                          AddS addS, typename EvalCtx<MIX>::R* nks_out = nullptr) {
+                                          AddS addS, typename EvalCtx<MIX>::R* nks_out = nullptr,
+                                          const PairIn<typename EvalCtx<MIX>::R>* pre = nullptr) {
     using R = typename EvalCtx<MIX>::R;
     const uint32_t npad = b.npad;
     const R ai = (R)pi.w;
@@ -877,9 +886,15 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
     int ky = 0;
     R n[3] = {(R)0, (R)0, (R)0}, XA = (R)0, YA = (R)0;
     if (pair) {
-        j = b.nbr[e * npad + i];
-        pj = b.pos[j];
-        idj = b.id[j];
+        if (pre) {
+            j = pre->j;
+            pj = pre->pj;
+            idj = pre->idj;
+        } else {
+            j = b.nbr[e * npad + i];
+            pj = b.pos[j];
+            idj = b.id[j];
+        }
         lo = LO_ONLY || idi < idj;  // i holds the lower id
         ky = lo ? min_image(P, C.s_le, pi, pj, dx, dy, dz) : min_image(P, C.s_le, pj, pi, dx, dy, dz);
         const double d2 = (dx * dx + dy * dy) + dz * dz;
@@ -919,7 +934,10 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
     // ---- pair item: velocities in canonical orientation; b's image moves with +k_y gammadot Ly
     R va[3], vb[3], vj[3];
     const R shiftv = (R)((double)ky * P.gdLy);
-    if (MIX) {
+    if (pre) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) vj[d] = pre->vj[d];
+    } else if (MIX) {
         const float4 v4 = b.vsh[j];
         vj[0] = v4.x; vj[1] = v4.y; vj[2] = v4.z;
     } else {
@@ -959,7 +977,10 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
             n[0] = (R)(dx / dist); n[1] = (R)(dy / dist); n[2] = (R)(dz / dist);
         }
         R s[3] = {(R)0, (R)0, (R)0};
-        if (had_contact) {
+        if (had_contact && pre) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) s[d] = pre->s[d];
+        } else if (had_contact) {
             if (MIX) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) s[d] = ((const float*)b.hs[d])[e * npad + i];
@@ -969,7 +990,10 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
             }
         }
         R wj[3];
-        if (MIX) {
+        if (pre) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) wj[d] = pre->wj[d];
+        } else if (MIX) {
             const float4 w4 = b.wsh[j];
             wj[0] = w4.x; wj[1] = w4.y; wj[2] = w4.z;
         } else {
@@ -1475,8 +1499,23 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
     if (valid) {
         const double4 pi = b.pos[i];
         const uint32_t cnt = b.ncnt[i];
-        for (uint32_t e = b.lo0[i] + sub; e < cnt; e += LN)
-            if (interacting(P, s_le, pi, b.pos[b.nbr[e * npad + i]])) im |= 1ull << e;
+        // entries in groups of 4: list loads together, then partner positions together
+        for (uint32_t c0 = b.lo0[i] + sub; c0 < cnt; c0 += 4 * LN) {
+            uint32_t jj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t e = c0 + u * LN;
+                jj[u] = e < cnt ? b.nbr[e * npad + i] : i;
+            }
+            double4 pj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pj[u] = b.pos[jj[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t e = c0 + u * LN;
+                if (e < cnt && interacting(P, s_le, pi, pj[u])) im |= 1ull << e;
+            }
+        }
         if (sub == 0) cmo[w][l] = b.cmask[i];
     }
     if (LN >= 2) im |= dpp_u64<0xB1>(im);
@@ -1518,14 +1557,23 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
         const uint32_t code = queue[w][k];
         const uint32_t l = code >> 6, e = code & 63u;
         const uint32_t ii = base + l;
+        const bool had = (cmo[w][l] >> e) & 1ull;
+        // own data and the list entry, then the partner's data and the spring, each
+        // group of loads in flight together
         const double4 pi = b.pos[ii];
         const uint32_t idi = b.id[ii];
         R vi[3], wi[3];
         load_vw<MIX>(b, ii, vi, wi);
+        PairIn<R> in;
+        in.j = b.nbr[e * npad + ii];
+        in.pj = b.pos[in.j];
+        in.idj = b.id[in.j];
+        load_vw<MIX>(b, in.j, in.vj, in.wj);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) in.s[d] = had ? ((const R*)b.hs[d])[e * npad + ii] : (R)0;
         R f[3], t[3], nks[3];
         bool contact, slid;
-        eval_item<MIX, true>(b, P, C, ii, e, pi, idi, vi, wi, (cmo[w][l] >> e) & 1ull, f, t, contact, slid, maxov,
-                             addS, nks);
+        eval_item<MIX, true>(b, P, C, ii, e, pi, idi, vi, wi, had, f, t, contact, slid, maxov, addS, nks, &in);
         pf[k] = Vec4<R>::make(f[0], f[1], f[2]);
         if (contact) {
             pt[k] = Vec4<R>::make(nks[0], nks[1], nks[2]);
