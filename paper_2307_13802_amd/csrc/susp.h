@@ -106,7 +106,7 @@ struct Bufs {
     uint8_t* mir;     // [e * npad + i], entry with a lower-id partner j: the entry of i in j's list
     uint64_t* imask;  // bit e: entry e (higher-id partner) interacts in the last evaluation
     uint16_t* qoff;   // first of particle i's pairs within its wave's run (queue order)
-    void* pf;         // double4 / float4 per pair: force on the lower-id particle; the pairs of
+    void* pf;         // 3 doubles / 4 floats per pair: force on the lower-id particle; the pairs of
                       // the wave owning particles [64 w, 64 w + 64) sit in queue order
                       // (particles in order, entries in order) from 64 w * cap
     void* pt;         // same layout: n x (k_t s) of a contact

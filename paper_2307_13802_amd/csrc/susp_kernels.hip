@@ -1457,25 +1457,37 @@ __global__ __launch_bounds__(256) void k_pairq(Bufs b, int q, int kick, int adva
 // as the other variants, and the pair terms are the same bits, so forces,
 // torques and springs equal those of variant 1 with one lane per particle.
 // ---------------------------------------------------------------------------
-template <class R> struct Vec4;
-template <> struct Vec4<double> {
-    using T = double4;
-    static __device__ __forceinline__ T make(double x, double y, double z) { return make_double4(x, y, z, 0.0); }
+// pair record: three components (24 B in FP64; a float4 in mixed precision,
+// so that one aligned access moves it)
+struct Rec3d {
+    double x, y, z;
 };
-template <> struct Vec4<float> {
+template <class R> struct PairRec;
+template <> struct PairRec<double> {
+    using T = Rec3d;
+    static __device__ __forceinline__ T make(double a, double b, double c) { return Rec3d{a, b, c}; }
+};
+template <> struct PairRec<float> {
     using T = float4;
-    static __device__ __forceinline__ T make(float x, float y, float z) { return make_float4(x, y, z, 0.0f); }
+    static __device__ __forceinline__ T make(float a, float b, float c) { return make_float4(a, b, c, 0.0f); }
 };
 
 template <bool MIX, int LN>
 __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int advance, uint32_t only_rep) {
     using R = typename std::conditional<MIX, float, double>::type;
-    using V4 = typename Vec4<R>::T;
+    using V3 = typename PairRec<R>::T;
     constexpr int NP = 64 / LN;  // particles per wave
     if (b.sys->halted) return;
-    finalize_all(b, 1 - q);
+    // the last 27 * nrep blocks reduce the stress of the previous evaluation (its
+    // partials have the other parity), beside the pair blocks rather than before them
+    const uint32_t npair_blk = gridDim.x - 27u * b.nrep;
+    if (blockIdx.x >= npair_blk) {
+        const uint32_t u = blockIdx.x - npair_blk;
+        finalize_unit(b, u / 27u, (int)(u % 27u), 1 - q);
+        return;
+    }
     const int w = threadIdx.x >> 6, p = threadIdx.x & 63;
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);  // a block: 4 NP particles, inside one kTile
+    const uint32_t tile = xcd_tile(blockIdx.x, npair_blk);  // a block: 4 NP particles, inside one kTile
     const uint32_t base = (tile * 4 + w) * NP;                // first particle of this wave
     const uint32_t r = b.blk_rep[base / kTile];
     if (only_rep != 0xFFFFFFFFu && r != only_rep) return;
@@ -1542,8 +1554,8 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
         for (uint64_t m = im; m; m &= m - 1ull) queue[w][k++] = (uint16_t)((l << 6) | __builtin_ctzll(m));
     }
     // results of this wave's pairs: a contiguous run in queue order
-    V4* const pf = (V4*)b.pf + (size_t)base * b.cap;
-    V4* const pt = (V4*)b.pt + (size_t)base * b.cap;
+    V3* const pf = (V3*)b.pf + (size_t)base * b.cap;
+    V3* const pt = (V3*)b.pt + (size_t)base * b.cap;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 
@@ -1574,9 +1586,9 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
         R f[3], t[3], nks[3];
         bool contact, slid;
         eval_item<MIX, true>(b, P, C, ii, e, pi, idi, vi, wi, had, f, t, contact, slid, maxov, addS, nks, &in);
-        pf[k] = Vec4<R>::make(f[0], f[1], f[2]);
+        pf[k] = PairRec<R>::make(f[0], f[1], f[2]);
         if (contact) {
-            pt[k] = Vec4<R>::make(nks[0], nks[1], nks[2]);
+            pt[k] = PairRec<R>::make(nks[0], nks[1], nks[2]);
             atomicOr(&cmq[w][l], 1ull << e);
             if (slid) atomicOr(&smq[w][l], 1ull << e);
         }
@@ -1634,7 +1646,7 @@ template <bool MIX>
 __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& P, const RepDyn& D, int q, int kick,
                                                 int fuse, uint32_t i, float& dblk, bool& expire, bool& bad) {
     using R = typename std::conditional<MIX, float, double>::type;
-    using V4 = typename Vec4<R>::T;
+    using V3 = typename PairRec<R>::T;
     EvalCtx<MIX> C;
     make_ctx<MIX>(C, P, D.s_slot[q], D.step_slot[q]);
     const uint32_t npad = b.npad;
@@ -1697,11 +1709,11 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
                 ct[u] = (cm >> e) & 1ull;
             }
         }
-        V4 fv[GB], tv[GB];
+        V3 fv[GB], tv[GB];
 #pragma unroll
         for (uint32_t u = 0; u < GB; ++u) {
-            if (use[u]) fv[u] = ((const V4*)b.pf)[slot[u]];
-            if (ct[u]) tv[u] = ((const V4*)b.pt)[slot[u]];
+            if (use[u]) fv[u] = ((const V3*)b.pf)[slot[u]];
+            if (ct[u]) tv[u] = ((const V3*)b.pt)[slot[u]];
         }
 #pragma unroll
         for (uint32_t u = 0; u < GB; ++u) {
@@ -1827,11 +1839,11 @@ template <bool MIX>
 static void launch_pair_t(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep,
                           hipEvent_t mid, int fuse) {
     if (b.kern == 2) {  // half-pair evaluation, then the per-particle gather
-        const uint32_t g = b.npad / 256;
+        const uint32_t g = b.npad / 256, fin = 27u * b.nrep;  // pair blocks, then finalize blocks
         switch (b.lanes) {
-            case 1: hipLaunchKernelGGL((k_half<MIX, 1>), dim3(g), dim3(256), 0, st, b, q, advance, only_rep); break;
-            case 2: hipLaunchKernelGGL((k_half<MIX, 2>), dim3(2 * g), dim3(256), 0, st, b, q, advance, only_rep); break;
-            default: hipLaunchKernelGGL((k_half<MIX, 4>), dim3(4 * g), dim3(256), 0, st, b, q, advance, only_rep); break;
+            case 1: hipLaunchKernelGGL((k_half<MIX, 1>), dim3(g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
+            case 2: hipLaunchKernelGGL((k_half<MIX, 2>), dim3(2 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
+            default: hipLaunchKernelGGL((k_half<MIX, 4>), dim3(4 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
         }
         if (mid) (void)hipEventRecord(mid, st);
         hipLaunchKernelGGL(k_gather<MIX>, dim3(b.npad / 256), dim3(256), 0, st, b, q, kick, fuse, only_rep);

@@ -531,8 +531,8 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         b.mir = s->alloc<uint8_t>(np * cap);
         b.imask = s->alloc<uint64_t>(np);
         b.qoff = s->alloc<uint16_t>(np);
-        b.pf = s->dalloc(np * cap * (s->mixed ? sizeof(float4) : sizeof(double4)));
-        b.pt = s->dalloc(np * cap * (s->mixed ? sizeof(float4) : sizeof(double4)));
+        b.pf = s->dalloc(np * cap * (s->mixed ? 4 * sizeof(float) : 3 * sizeof(double)));
+        b.pt = s->dalloc(np * cap * (s->mixed ? 4 * sizeof(float) : 3 * sizeof(double)));
         b.key = s->alloc<uint32_t>(np);
         b.cell_cnt = s->alloc<uint32_t>(key);
         b.cell_fill = s->alloc<uint32_t>(key);
