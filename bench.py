@@ -7,7 +7,8 @@ seeded relaxed packing, all inputs resident in HBM before timing.
 
 Prints one JSON line.  Besides the headline FP64 number it reports the mixed
 precision form on the same workload, the roofline of the pair-force kernel
-(algorithmic bytes / measured kernel time against 8 TB/s) and the FP64 CPU
+(algorithmic bytes / measured kernel time against 8 TB/s, with the measured
+traffic when the committed counter summary matches the kernel source) and the FP64 CPU
 oracle timed on a bounded sample of the same workload on the host.
 """
 import argparse
@@ -22,16 +23,45 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def pair_bytes_per_particle(mixed, k, c):
-    """Algorithmic HBM bytes of one pair-force launch per particle (j gathers excluded:
-    Morton order serves them from cache).  k = list entries, c = live springs per particle."""
-    if mixed:
-        # read: pos(x,y,z,a) 32, v/w FP32 copies 24, v/w FP64 for kick 2 48, id 4, count 4, masks 8
-        # write: F, T FP32 24, v, w FP64 48, masks 16; list 4k; springs FP32 read+write 24c
-        return 32 + 24 + 48 + 4 + 4 + 8 + 24 + 48 + 16 + 4 * k + 24 * c
-    # read: pos 32, v, w 48, id 4, count 4, masks 8; write: F, T 48, v, w 48, masks 16;
-    # list 4k; springs FP64 read+write 48c
-    return 32 + 48 + 4 + 4 + 8 + 48 + 48 + 16 + 4 * k + 48 * c
+KERNEL_SRC = os.path.join(ROOT, "paper_2307_13802_amd", "csrc", "susp_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_kernel_traffic.json")
+
+
+def half_bytes_per_particle(mixed, k, p, c):
+    """Algorithmic HBM bytes per particle of one half-pair kernel launch (partner gathers
+    excluded: Morton order serves them from cache).  k = list entries, p = interacting
+    pair sides, c = contact pair sides per particle; each pair is evaluated once, so a
+    particle owns p/2 pairs and c/2 contacts."""
+    own = 24 + 8 + 24 + 4 if mixed else 24 + 8 + 48 + 4   # x, a, v and w (FP32 copies in mixed), id
+    vec = 12 if mixed else 24                              # one 3-vector
+    return (own + 4 * k / 2                                # the half of the list with higher-id partners
+            + 2 * vec * c / 2                              # spring read and written per contact
+            + vec * p / 2 + vec * c / 2                    # pair force; n x k_t s of a contact
+            + 8 + 8 + 8 + 2)                               # interaction, contact, sliding masks; queue offset
+
+
+def gather_bytes_per_particle(mixed, k, p, c):
+    """Algorithmic HBM bytes per particle of one gather launch with the next step's kick
+    and drift fused: own state in and out, the list, every pair record once."""
+    vec = 12 if mixed else 24
+    own_in = 24 + 8 + 48 + 4 + 8                           # x, a, v, w, id, displacement bound
+    own_out = 24 + 48 + 8 + (24 if mixed else 0)           # x, v, w, bound (+ FP32 copies)
+    return own_in + own_out + 4 * k + k + vec * p / 2 + vec * c / 2
+
+
+def measured_traffic(mixed):
+    """HBM bytes per launch of the half-pair kernel on the 50,000-sphere workload from the
+    committed counter summary, if it was taken from the current kernel source."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha1") != sha:
+        return None
+    t = rec.get("mixed" if mixed else "fp64", {}).get("k_half")
+    return None if t is None else t["fetch_bytes"] + t["write_bytes"]
 
 
 def eta_r(series, gd, eta, drag_xy):
@@ -67,17 +97,44 @@ def run_gpu(P, st, precision, steps, warmup, prof_steps):
     stats = sim.stats()
     drag = sim.stress(0, P.STRESS_DRAG)[0, 1]
     mean = sim.stress(0, P.STRESS_TOTAL, P.STRESS_MEAN)[0, 1]
-    # pair-kernel timing with HIP events on the library stream
+    # per-stage kernel timing with HIP events on the library stream
     sim.profile(True)
     sim.step(prof_steps)
-    launches, ms = sim.kernel_time()
+    stage = [sim.stage_time(k) for k in range(3)]
     sim.profile(False)
     stats2 = sim.stats()
     p = st["params"]
     er = eta_r(ser, p["gammadot"], p["eta"], drag)
     sim.close()
+    n_l = max(stage[1][0], 1)
     return dict(seconds=t1 - t0, stats=stats, stats_prof=stats2, eta_mean=mean / (p["eta"] * p["gammadot"]),
-                eta_series=er, pair_ms=ms / max(launches, 1), launches=launches)
+                eta_series=er, pair_ms=stage[1][1] / n_l, gather_ms=stage[2][1] / n_l,
+                integrate_ms=stage[0][1] / n_l, launches=stage[1][0])
+
+
+def roofline(r, mixed, n):
+    """Roofline object of the dominant kernel (the pair kernel) from a run_gpu result."""
+    st = r["stats_prof"]
+    k, p, c = st["neighbours_per_particle"], st["interacting_per_particle"], st["contacts_per_particle"]
+    half = st["pair_kernel"] == 3
+    if half:
+        bpp = half_bytes_per_particle(mixed, k, p, c)
+        name = "k_half<%s>" % ("true" if mixed else "false")
+    else:  # a kernel evaluating every pair from both sides, with one-body terms and kick 2
+        bpp = 2 * half_bytes_per_particle(mixed, k, p, c) + 48
+        name = "k_pair<%s>" % ("true" if mixed else "false")
+    achieved = bpp * n / (r["pair_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(mixed) if half else None
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": name, "kernel_ms": r["pair_ms"],
+           "bytes_per_particle": bpp, "list_per_particle": k, "interacting_per_particle": p,
+           "contacts_per_particle": c}
+    if half:
+        gb = gather_bytes_per_particle(mixed, k, p, c)
+        out["gather"] = {"kernel": "k_gather<%s>" % ("true" if mixed else "false"), "kernel_ms": r["gather_ms"],
+                         "bytes_per_particle": gb,
+                         "frac": gb * n / (r["gather_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
 
 
 def cpu_baseline(st, seconds_target=15.0):
@@ -105,9 +162,18 @@ def pair_time(sim, steps=100):
     """Average pair-kernel duration (ms) over `steps` steps, HIP events on the library stream."""
     sim.profile(True)
     sim.step(steps)
-    launches, ms = sim.kernel_time()
+    launches, ms = sim.stage_time(1)
     sim.profile(False)
     return ms / max(launches, 1)
+
+
+def hbm_frac(stats, mixed, n, ms):
+    """Fraction of the HBM roofline of the pair kernel from its algorithmic bytes."""
+    k, p, c = stats["neighbours_per_particle"], stats["interacting_per_particle"], stats["contacts_per_particle"]
+    bpp = half_bytes_per_particle(mixed, k, p, c)
+    if stats["pair_kernel"] != 3:
+        bpp = 2 * bpp + 48
+    return bpp * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
 
 
 def run_mixed_vs_fp64(P, st, steps, sample_every, say):
@@ -172,14 +238,11 @@ def run_mixed_vs_fp64(P, st, steps, sample_every, say):
     se = float(np.hypot(block_se(ser64), block_se(ser32)))
     m64, m32 = float(ser64.mean()), float(ser32.mean())
     k64, c64 = st64p["neighbours_per_particle"], st64p["contacts_per_particle"]
-    k32, c32 = st32p["neighbours_per_particle"], st32p["contacts_per_particle"]
-    ach64 = pair_bytes_per_particle(False, k64, c64) * n / (ms64 * 1e-3) / 1e9
-    ach32 = pair_bytes_per_particle(True, k32, c32) * n / (ms32 * 1e-3) / 1e9
     return {
-        "fp64": {"value": n * steps / t64, "pair_kernel_ms": ms64, "hbm_frac": ach64 / HBM_PEAK_GBS,
+        "fp64": {"value": n * steps / t64, "pair_kernel_ms": ms64, "hbm_frac": hbm_frac(st64p, False, n, ms64),
                  "pair_kernel": {1: "lanes", 2: "wave", 3: "half"}[st64["pair_kernel"]], "lanes": st64["lanes"],
                  "rebuilds": st64["rebuilds"], "eta_r_mean": m64},
-        "mixed": {"value": n * steps / t32, "pair_kernel_ms": ms32, "hbm_frac": ach32 / HBM_PEAK_GBS,
+        "mixed": {"value": n * steps / t32, "pair_kernel_ms": ms32, "hbm_frac": hbm_frac(st32p, True, n, ms32),
                   "pair_kernel": {1: "lanes", 2: "wave", 3: "half"}[st32["pair_kernel"]], "lanes": st32["lanes"],
                   "rebuilds": st32["rebuilds"], "eta_r_mean": m32},
         "mixed_speedup": (n * steps / t32) / (n * steps / t64),
@@ -287,10 +350,8 @@ def bench_large(P, gen, steps, warmup, say):
     ms = pair_time(sim)
     stp = sim.stats()
     sim.close()
-    ach = pair_bytes_per_particle(True, stp["neighbours_per_particle"], stp["contacts_per_particle"]) * n / (
-        ms * 1e-3) / 1e9
     return {"workload": wl.name, "n": n, "value": n * steps / el, "ms_per_step": el * 1e3 / steps,
-            "steps": steps, "pair_kernel_ms": ms, "hbm_frac": ach / HBM_PEAK_GBS,
+            "steps": steps, "pair_kernel_ms": ms, "hbm_frac": hbm_frac(stp, True, n, ms),
             "pair_kernel": {1: "lanes", 2: "wave", 3: "half"}[stt["pair_kernel"]], "lanes": stt["lanes"],
             "contacts_per_particle": stt["contacts_per_particle"], "sliding_fraction": stt["sliding_fraction"],
             "max_overlap": stt["max_overlap"], "rebuilds": stt["rebuilds"],
@@ -386,10 +447,6 @@ def main():
         print(f"mixed done: {n * args.steps / mix['seconds']:.3e} particle-steps/s", file=sys.stderr, flush=True)
 
     value = n * args.steps / f64["seconds"]
-    k = f64["stats_prof"]["neighbours_per_particle"]
-    c = f64["stats_prof"]["contacts_per_particle"]
-    bpp = pair_bytes_per_particle(False, k, c)
-    achieved = bpp * n / (f64["pair_ms"] * 1e-3) / 1e9
     out = {
         "metric": "particle-steps/s + % HBM roofline; FP32-mixed vs FP64 at stated viscosity error",
         "value": value,
@@ -408,24 +465,17 @@ def main():
                    "dt": wl.dt, "hip_graph": True,
                    "pair_kernel": {1: "lanes", 2: "wave", 3: "half"}[f64["stats"]["pair_kernel"]],
                    "lanes_per_particle": f64["stats"]["lanes"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_pair<false>", "kernel_ms": f64["pair_ms"], "bytes_per_particle": bpp,
-                     "list_per_particle": k, "contacts_per_particle": c},
+        "roofline": roofline(f64, False, n),
         "eta_r_fp64": f64["eta_mean"],
     }
     if mix is not None:
         vm = n * args.steps / mix["seconds"]
-        km = mix["stats_prof"]["neighbours_per_particle"]
-        cm = mix["stats_prof"]["contacts_per_particle"]
-        bm = pair_bytes_per_particle(True, km, cm)
-        am = bm * n / (mix["pair_ms"] * 1e-3) / 1e9
+        rm = roofline(mix, True, n)
         se = np.hypot(block_se(f64["eta_series"]), block_se(mix["eta_series"]))
         out["mixed"] = {"value": vm, "ms_per_step": mix["seconds"] * 1e3 / args.steps, "dtype": "f32 pair / f64 state",
                         "pair_kernel": {1: "lanes", 2: "wave", 3: "half"}[mix["stats"]["pair_kernel"]],
                         "lanes_per_particle": mix["stats"]["lanes"],
-                        "speedup_vs_fp64": vm / value, "pair_kernel_ms": mix["pair_ms"],
-                        "roofline_frac": am / HBM_PEAK_GBS, "achieved_GBs": am,
+                        "speedup_vs_fp64": vm / value, "roofline": rm,
                         "eta_r": mix["eta_mean"],
                         "eta_r_rel_diff_free_running": (mix["eta_mean"] - f64["eta_mean"]) / f64["eta_mean"],
                         "eta_r_diff_std_err": float(se / abs(f64["eta_mean"]))}

@@ -96,7 +96,7 @@ struct Bufs {
     uint32_t* nbr;
     uint32_t* ncnt;
     // contact history per list entry, slot-major, canonical orientation (lower id first)
-    void* hs[3];      // double or float per component
+    void* hs;         // spring per entry: 3 doubles (3 floats in mixed precision), packed
     uint64_t* cmask;  // bit e: entry e holds a live contact
     uint64_t* smask;  // bit e: that contact slid at its last update
     // half-pair evaluation: each interacting pair is evaluated once, by its

@@ -142,6 +142,43 @@ template <int CTRL> __device__ __forceinline__ float dpp_f32(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
+// Pair records in memory: three doubles (24 B) in FP64; a float4 in mixed
+// precision, so that one aligned access moves it.
+struct Rec3d {
+    double x, y, z;
+};
+template <class R> struct PairRec;
+template <> struct PairRec<double> {
+    using T = Rec3d;
+    static __device__ __forceinline__ T make(double a, double b, double c) { return Rec3d{a, b, c}; }
+};
+template <> struct PairRec<float> {
+    using T = float4;
+    static __device__ __forceinline__ T make(float a, float b, float c) { return make_float4(a, b, c, 0.0f); }
+};
+
+// spring of list entry slot k (k = e * npad + i): three components, packed
+template <class R> struct Spring {
+    R x, y, z;
+};
+template <class R> __device__ __forceinline__ void load_spring(const Bufs& b, uint32_t k, R* s) {
+    const Spring<R> v = ((const Spring<R>*)b.hs)[k];
+    s[0] = v.x; s[1] = v.y; s[2] = v.z;
+}
+template <class R> __device__ __forceinline__ void store_spring(const Bufs& b, uint32_t k, const R* s) {
+    ((Spring<R>*)b.hs)[k] = Spring<R>{s[0], s[1], s[2]};
+}
+// in FP64 whatever the precision of the handle (rebuild carry, diagnostics)
+__device__ __forceinline__ void spring_f64(const Bufs& b, uint32_t k, double* s) {
+    if (b.mixed) {
+        float t[3];
+        load_spring<float>(b, k, t);
+        s[0] = t[0]; s[1] = t[1]; s[2] = t[2];
+    } else {
+        load_spring<double>(b, k, s);
+    }
+}
+
 // thread-private accumulation in LDS (each slot has one writer)
 __device__ __forceinline__ void lds_add(double* p, double v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -521,11 +558,9 @@ __global__ __launch_bounds__(256) void k_rb_gather(Bufs b, uint32_t ct_input_rep
                 break;
             }
             b.ct_id[c * npad + q] = b.id[b.nbr[e * npad + s]];
-            for (int d = 0; d < 3; ++d) {
-                const double hv = b.mixed ? (double)((const float*)b.hs[d])[e * npad + s]
-                                          : ((const double*)b.hs[d])[e * npad + s];
-                b.ct_s[(c * 3 + d) * npad + q] = hv;
-            }
+            double hv[3];
+            spring_f64(b, e * npad + s, hv);
+            for (int d = 0; d < 3; ++d) b.ct_s[(c * 3 + d) * npad + q] = hv[d];
             b.ct_sl[c * npad + q] = (uint8_t)((sm >> e) & 1ull);
             ++c;
         }
@@ -634,10 +669,13 @@ __global__ __launch_bounds__(256) void k_rb_nlist(Bufs b, int q, int in_step) {
         const uint32_t pid = b.ct_id[c * npad + i];
         for (uint32_t e = 0; e < cnt; ++e) {
             if (b.id[b.nbr[e * npad + i]] == pid) {
-                for (int d = 0; d < 3; ++d) {
-                    const double v = b.ct_s[(c * 3 + d) * npad + i];
-                    if (b.mixed) ((float*)b.hs[d])[e * npad + i] = (float)v;
-                    else ((double*)b.hs[d])[e * npad + i] = v;
+                double v[3];
+                for (int d = 0; d < 3; ++d) v[d] = b.ct_s[(c * 3 + d) * npad + i];
+                if (b.mixed) {
+                    const float f[3] = {(float)v[0], (float)v[1], (float)v[2]};
+                    store_spring<float>(b, e * npad + i, f);
+                } else {
+                    store_spring<double>(b, e * npad + i, v);
                 }
                 cm |= 1ull << e;
                 if (b.ct_sl[c * npad + i]) sm |= 1ull << e;
@@ -981,13 +1019,7 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
 #pragma unroll
             for (int d = 0; d < 3; ++d) s[d] = pre->s[d];
         } else if (had_contact) {
-            if (MIX) {
-#pragma unroll
-                for (int d = 0; d < 3; ++d) s[d] = ((const float*)b.hs[d])[e * npad + i];
-            } else {
-#pragma unroll
-                for (int d = 0; d < 3; ++d) s[d] = ((const double*)b.hs[d])[e * npad + i];
-            }
+            load_spring<R>(b, e * npad + i, s);
         }
         R wj[3];
         if (pre) {
@@ -1038,13 +1070,7 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
             for (int d = 0; d < 3; ++d) s[d] = s[d] * fac;
             slid = true;
         }
-        if (MIX) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) ((float*)b.hs[d])[e * npad + i] = (float)s[d];
-        } else {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) ((double*)b.hs[d])[e * npad + i] = (double)s[d];
-        }
+        store_spring<R>(b, e * npad + i, s);
         contact = true;
         const R ks[3] = {C.kt * s[0], C.kt * s[1], C.kt * s[2]};
 #pragma unroll
@@ -1457,20 +1483,6 @@ __global__ __launch_bounds__(256) void k_pairq(Bufs b, int q, int kick, int adva
 // as the other variants, and the pair terms are the same bits, so forces,
 // torques and springs equal those of variant 1 with one lane per particle.
 // ---------------------------------------------------------------------------
-// pair record: three components (24 B in FP64; a float4 in mixed precision,
-// so that one aligned access moves it)
-struct Rec3d {
-    double x, y, z;
-};
-template <class R> struct PairRec;
-template <> struct PairRec<double> {
-    using T = Rec3d;
-    static __device__ __forceinline__ T make(double a, double b, double c) { return Rec3d{a, b, c}; }
-};
-template <> struct PairRec<float> {
-    using T = float4;
-    static __device__ __forceinline__ T make(float a, float b, float c) { return make_float4(a, b, c, 0.0f); }
-};
 
 template <bool MIX, int LN>
 __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int advance, uint32_t only_rep) {
@@ -1581,8 +1593,8 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
         in.pj = b.pos[in.j];
         in.idj = b.id[in.j];
         load_vw<MIX>(b, in.j, in.vj, in.wj);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) in.s[d] = had ? ((const R*)b.hs[d])[e * npad + ii] : (R)0;
+        if (had) load_spring<R>(b, e * npad + ii, in.s);
+        else in.s[0] = in.s[1] = in.s[2] = (R)0;
         R f[3], t[3], nks[3];
         bool contact, slid;
         eval_item<MIX, true>(b, P, C, ii, e, pi, idi, vi, wi, had, f, t, contact, slid, maxov, addS, nks, &in);
@@ -1795,9 +1807,7 @@ __global__ void k_diag(Bufs b, int p, uint32_t rep, uint32_t* out_ij, double* ou
             out_ij[2 * k] = idi;
             out_ij[2 * k + 1] = idj;
             if (mode == 2) {
-                for (int d = 0; d < 3; ++d)
-                    out_s[3 * k + d] = b.mixed ? (double)((const float*)b.hs[d])[e * b.npad + i]
-                                               : ((const double*)b.hs[d])[e * b.npad + i];
+                spring_f64(b, e * b.npad + i, out_s + 3 * k);
                 out_sl[k] = (int32_t)((sm >> e) & 1ull);
             }
         }

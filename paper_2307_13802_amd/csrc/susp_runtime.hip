@@ -524,7 +524,7 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         b.id = s->alloc<uint32_t>(np);
         b.nbr = s->alloc<uint32_t>(np * cap);
         b.ncnt = s->alloc<uint32_t>(np);
-        for (int d = 0; d < 3; ++d) b.hs[d] = s->dalloc(np * cap * (s->mixed ? sizeof(float) : sizeof(double)));
+        b.hs = s->dalloc(np * cap * 3 * (s->mixed ? sizeof(float) : sizeof(double)));
         b.cmask = s->alloc<uint64_t>(np);
         b.smask = s->alloc<uint64_t>(np);
         b.lo0 = s->alloc<uint8_t>(np);
