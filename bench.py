@@ -374,7 +374,10 @@ def main():
                     help="only run 20 steps of each pair-kernel variant (a counter-collection driver)")
     ap.add_argument("--trace", action="store_true",
                     help="profiler driver: a 256 MiB device copy (the calibration of the byte counters), then "
-                         "--steps steps of the workload (c2, or c3 at Pe = 10) in FP64 and in mixed precision")
+                         "--steps steps of the workload (c2, or c3 at Pe = 10) in FP64 and in mixed precision "
+                         "with the pair kernel --pair-kernel / --lanes (a profiler distorts the timed choice)")
+    ap.add_argument("--pair-kernel", type=int, default=3, help="--trace: 0 auto, 1 lanes, 2 wave, 3 half")
+    ap.add_argument("--lanes", type=int, default=1, help="--trace: lanes per particle (0 = auto)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the engine has no multi-GPU path",
@@ -399,7 +402,8 @@ def main():
         st = gen.make_state(wl)
         say(f"workload ready: {wl.name}")
         for prec in (P.FP64, P.MIXED):
-            sim = P.Sim(P.Config(box=st["L"], precision=prec, **st["params"]), st["radii"], st["x"], st["v"], st["w"])
+            sim = P.Sim(P.Config(box=st["L"], precision=prec, pair_kernel=args.pair_kernel, lanes=args.lanes,
+                                 **st["params"]), st["radii"], st["x"], st["v"], st["w"])
             stt = sim.stats()
             torch.cuda.synchronize()
             t0 = time.perf_counter()

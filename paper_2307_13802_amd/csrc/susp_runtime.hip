@@ -512,6 +512,8 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         b.cap = cap;
         b.mixed = s->mixed;
         const size_t np = p;
+        // list entry slots e * npad + i are 32-bit indices on the device
+        if ((uint64_t)np * cap >= (1ull << 32)) throw std::string(fmt("%zu particle slots x %u list entries exceed 2^32", np, cap));
         b.pos = s->alloc<double4>(np);
         b.vh = s->alloc<double4>(np);
         b.wh = s->alloc<double4>(np);
