@@ -78,11 +78,17 @@ extern "C" {
 #define SIM_NO_PAIR_BROWN     0x004u /* drop the pairwise Brownian force             */
 #define SIM_NO_CONTACT        0x008u /* drop contact force and torque                */
 #define SIM_NO_ONEBODY        0x010u /* drop one-body drag and Brownian terms        */
+#define SIM_LUB_ROT           0x020u /* model switch: add the rotational lubrication
+                                        couplings Y^B, Y^C to the pair force and torques
+                                        (eq. force_lub, torque_lub1, torque_lub2) and the
+                                        pairwise Brownian torques (eq. torque_brownian_lub1,
+                                        torque_brownian_lub2); half-pair kernel only       */
 #define SIM_REBUILD_EACH_STEP 0x100u /* rebuild the neighbour list every step        */
 #define SIM_NO_GRAPH          0x200u /* launch kernels directly, no HIP graph        */
 
 /* sim_stress components and modes */
-#define SIM_STRESS_CONTACT 0      /* -F^C (x) r / V                     (Sec. II.A) */
+#define SIM_STRESS_CONTACT 0      /* -(F^C + F^R) (x) r / V: contact and
+                                     short-ranged repulsion       (Sec. II.A, IV.B) */
 #define SIM_STRESS_LUB     1      /* -F^{H,L} (x) r / V                 (Sec. II.B) */
 #define SIM_STRESS_BROWN   2      /* -F^{B,L} (x) r / V, instantaneous  (Sec. II.D) */
 #define SIM_STRESS_DRAG    3      /* (1/V) sum 20/3 pi eta a^3 E        (Sec. II.B) */
@@ -109,6 +115,10 @@ typedef struct sim_config {
     double   skin;          /* Verlet skin, length; <= 0 selects 0.2 * min radius    */
     double   le_offset0;    /* initial Lees-Edwards offset (x shift of the y image)  */
     double   max_overlap;   /* health limit on the overlap; <= 0 selects 0.1 * min a */
+    double   repulsion;     /* A >= 0 of the short-ranged repulsion (A / kappa)
+                               exp(-h / kappa) n, kappa = 0.01 (a_i + a_j), on the
+                               pairs within the lubrication cut-off (Sec. IV.B);
+                               0 = none; > 0 needs the half-pair kernel              */
     uint64_t seed;          /* key of the counter-based noise generator             */
     uint64_t step0;         /* step counter of the initial state                     */
     int32_t  precision;     /* SIM_FP64 or SIM_MIXED, identical for all replicas     */
@@ -154,12 +164,13 @@ typedef struct sim_stats_t {
 
 /* Checks a configuration and its radii on the host (no GPU needed).
  * radii: n doubles, host memory.  Returns SIM_EINVAL for n = 0, a <= 0,
- * dt <= 0, rho/eta <= 0, kn/kt < 0, mu < 0, kT < 0, xi_min <= 0,
+ * dt <= 0, rho/eta <= 0, kn/kt < 0, mu < 0, kT < 0, repulsion < 0, xi_min <= 0,
  * xi_min >= xi_cut, a box side not larger than twice the largest
  * interaction range plus skin (the minimum image must be unique), a wrong
  * struct_size, nlist_cap > 64, lanes not in {0, 1, 2, 4, 8}, an unknown
  * pair_kernel, SIM_KERNEL_WAVE with lanes 8 or nlist_cap > 62,
- * SIM_KERNEL_HALF with lanes 8, or a nonzero reserved field. */
+ * SIM_KERNEL_HALF with lanes 8, SIM_LUB_ROT or repulsion > 0 with
+ * SIM_KERNEL_LANES or SIM_KERNEL_WAVE, or a nonzero reserved field. */
 int sim_validate(const sim_config* cfg, const double* radii);
 
 /* Creates a handle with n_replicas systems.  For replica r: radii[r] -> n
@@ -192,6 +203,16 @@ int sim_reset_stress(sim* s);
  * number of steps available; if it exceeds cap, SIM_ERANGE is returned and
  * nothing is consumed. */
 int sim_stress_series(sim* s, int32_t replica, double* out, int64_t cap, int64_t* count);
+
+/* Structural Brownian stress of the current configuration of one replica
+ * (Sec. II.D): -(kT / V) sum_i (a_i / Delta_i) sum_{j in shell of i}
+ * n_ij (x) n_ij, with the shell of i the partners whose gap
+ * h = |r| - (a_i + a_j) is at most Delta_i = 0.05 a_i (contacts included).
+ * It is not part of the total stress.  Rebuilds the neighbour lists first
+ * (which changes no trajectory).  3x3 row-major, FP64, host memory.
+ * SIM_EINVAL if the list range cannot cover the shell (skin + (a_i + a_j)
+ * xi_cut / 2 < 0.05 a_max for some pair). */
+int sim_structural_stress(sim* s, int32_t replica, double out[9]);
 
 /* Positions of one replica in id order, wrapped into [0, L), FP64, 3n doubles. */
 int sim_positions(sim* s, int32_t replica, double* out_3n);

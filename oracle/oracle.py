@@ -28,6 +28,7 @@ NO_PAIR_BROWN = 0x4
 NO_CONTACT = 0x8
 NO_ONEBODY = 0x10
 CELLS = 0x20
+LUB_ROT = 0x40
 
 
 def build(force: bool = False) -> str:
@@ -43,7 +44,7 @@ def build(force: bool = False) -> str:
 class _Params(C.Structure):
     _fields_ = [("L", C.c_double * 3), ("rho", C.c_double), ("eta", C.c_double), ("kn", C.c_double),
                 ("kt", C.c_double), ("mu", C.c_double), ("kT", C.c_double), ("gammadot", C.c_double),
-                ("dt", C.c_double), ("xi_cut", C.c_double), ("xi_min", C.c_double),
+                ("dt", C.c_double), ("xi_cut", C.c_double), ("xi_min", C.c_double), ("rep_A", C.c_double),
                 ("seed", C.c_uint64), ("flags", C.c_uint32), ("pad", C.c_uint32)]
 
 
@@ -65,6 +66,8 @@ def lib():
         _lib.orc_get_state.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, dp, C.POINTER(C.c_uint64)]
         _lib.orc_get_norms.argtypes = [C.c_void_p, dp, dp]
         _lib.orc_get_stress.argtypes = [C.c_void_p, dp]
+        _lib.orc_structural_stress.argtypes = [C.c_void_p, dp]
+        _lib.orc_lub_rot_scalars.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, dp]
         _lib.orc_get_contacts.restype = C.c_int
         _lib.orc_get_contacts.argtypes = [C.c_void_p, C.c_int, up, dp, C.POINTER(C.c_int32)]
         _lib.orc_get_pairs.restype = C.c_int
@@ -100,6 +103,7 @@ class Params:
     dt: float = 1e-4
     xi_cut: float = 0.05
     xi_min: float = 1e-3
+    rep_A: float = 0.0
     seed: int = 0
     flags: int = 0
 
@@ -107,7 +111,7 @@ class Params:
         p = _Params()
         for d in range(3):
             p.L[d] = float(self.L[d])
-        for f in ("rho", "eta", "kn", "kt", "mu", "kT", "gammadot", "dt", "xi_cut", "xi_min"):
+        for f in ("rho", "eta", "kn", "kt", "mu", "kT", "gammadot", "dt", "xi_cut", "xi_min", "rep_A"):
             setattr(p, f, float(getattr(self, f)))
         p.seed = int(self.seed)
         p.flags = int(self.flags)
@@ -133,6 +137,13 @@ def lub_scalars(eta, ai, aj, xi):
     ya = np.zeros(1)
     lib().orc_lub_scalars(eta, ai, aj, xi, _d(xa), _d(ya))
     return float(xa[0]), float(ya[0])
+
+
+def lub_rot_scalars(eta, ai, aj, xi):
+    """(Y^B_11, Y^B_21, Y^C_11, Y^C_12, Y^C_21, Y^C_22) of Sec. II.B."""
+    out = np.zeros(6)
+    lib().orc_lub_rot_scalars(eta, ai, aj, xi, _d(out))
+    return tuple(float(t) for t in out)
 
 
 class Oracle:
@@ -198,6 +209,12 @@ class Oracle:
         out = np.zeros(27)
         lib().orc_get_stress(self._h, _d(out))
         return out.reshape(3, 3, 3)
+
+    def structural_stress(self):
+        """(3, 3) structural Brownian stress of the current configuration, Sec. II.D."""
+        out = np.zeros(9)
+        lib().orc_structural_stress(self._h, _d(out))
+        return out.reshape(3, 3)
 
     def contacts(self):
         n = lib().orc_get_contacts(self._h, 0, _u(np.zeros(2, np.uint32)), _d(np.zeros(3)), None)

@@ -61,12 +61,15 @@
 #define ORC_NO_CONTACT   0x8u  /* drop the contact force                  */
 #define ORC_NO_ONEBODY   0x10u /* drop one-body drag and Brownian terms   */
 #define ORC_CELLS        0x20u /* find pairs with a cell list, not O(N^2) */
+#define ORC_LUB_ROT      0x40u /* model switch: rotational lubrication couplings (Y^B, Y^C)
+                                  and the pairwise Brownian torques of Sec. II.B-II.C */
 
 typedef struct {
     double L[3];          /* box lengths Lx, Ly, Lz                         */
     double rho, eta, kn, kt, mu, kT, gammadot, dt;
     double xi_cut;        /* lubrication cut-off on the dimensionless gap   */
     double xi_min;        /* regularisation xi_eff                          */
+    double rep_A;         /* short-ranged repulsion scale A (0 = none)      */
     uint64_t seed;        /* Philox key                                     */
     uint32_t flags;
     uint32_t pad;
@@ -138,12 +141,18 @@ void orc_gauss3(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c
 
 /* Noise streams in the last counter word. */
 #define ORC_STREAM_PAIR_FORCE 0u
+#define ORC_STREAM_PAIR_TORQUE 1u
 #define ORC_STREAM_ONE_FORCE  2u
 #define ORC_STREAM_ONE_TORQUE 3u
 
 static void gauss_pair(const orc_params *p, uint64_t k, uint32_t i, uint32_t j, double g[3])
 {
     orc_gauss3(p->seed, (uint32_t)k, i, j, ((uint32_t)(k >> 32) << 8) | ORC_STREAM_PAIR_FORCE, g);
+}
+
+static void gauss_pair_torque(const orc_params *p, uint64_t k, uint32_t i, uint32_t j, double g[3])
+{
+    orc_gauss3(p->seed, (uint32_t)k, i, j, ((uint32_t)(k >> 32) << 8) | ORC_STREAM_PAIR_TORQUE, g);
 }
 
 static void gauss_one(const orc_params *p, uint64_t k, uint32_t i, uint32_t stream, double g[3])
@@ -166,6 +175,21 @@ void orc_lub_scalars(double eta, double ai, double aj, double xi, double *XA, do
     *XA = pre * ((2.0 * beta * beta) / opb3 * (1.0 / xi)
                  + (beta * (1.0 + 7.0 * beta + beta * beta)) / (5.0 * opb3) * lg);
     *YA = pre * ((4.0 * beta * (2.0 + beta + 2.0 * beta * beta)) / (15.0 * opb3) * lg);
+}
+
+/* Rotational lubrication scalars, Sec. II.B, exactly as printed: Y^B_11,
+ * Y^B_21 (prefactors -4 pi eta a_i^2, -4 pi eta a_j^2) and Y^C_11, Y^C_12,
+ * Y^C_21, Y^C_22 (prefactors 8 pi eta a_i^3, 8 pi eta a_j^3), beta = a_j/a_i. */
+void orc_lub_rot_scalars(double eta, double ai, double aj, double xi, double out[6])
+{
+    double beta = aj / ai, ib = ai / aj;
+    double lg = log(1.0 / xi);
+    out[0] = -4.0 * ORC_PI * eta * ai * ai * (beta * (4.0 + beta) / (5.0 * (1.0 + beta) * (1.0 + beta))) * lg;
+    out[1] = -4.0 * ORC_PI * eta * aj * aj * (ib * (4.0 + ib) / (5.0 * (1.0 + ib) * (1.0 + ib))) * lg;
+    out[2] = 8.0 * ORC_PI * eta * ai * ai * ai * (2.0 * beta / (5.0 * (1.0 + beta))) * lg;
+    out[3] = 8.0 * ORC_PI * eta * ai * ai * ai * (beta * beta / (10.0 * (1.0 + beta))) * lg;
+    out[4] = 8.0 * ORC_PI * eta * aj * aj * aj * (ib * ib / (10.0 * (1.0 + ib))) * lg;
+    out[5] = 8.0 * ORC_PI * eta * aj * aj * aj * (2.0 * ib / (5.0 * (1.0 + ib))) * lg;
 }
 
 /* ------------------------------------------------------------------ */
@@ -274,14 +298,71 @@ static void pair_force(orc_state *S, int i, int j, contact_io *io)
         double un = dot3(n, ur);
         for (int d = 0; d < 3; ++d) FL[d] = XA * (un * n[d]) + YA * (ur[d] - un * n[d]);
     }
+    double th[3] = {0, 0, 0};
     if (!(p->flags & ORC_NO_PAIR_BROWN)) {
         /* eq. (force_brownian_lub): sqrt(2kT/dt) (sqrt(X^A) N + sqrt(Y^A) T) theta */
-        double th[3];
         gauss_pair(p, S->k, (uint32_t)i, (uint32_t)j, th);
         double b = sqrt(2.0 * p->kT / p->dt);
         double tn = dot3(n, th);
         double sx = sqrt(XA), sy = sqrt(YA);
         for (int d = 0; d < 3; ++d) FB[d] = b * (sx * (tn * n[d]) + sy * (th[d] - tn * n[d]));
+    }
+    if (p->flags & ORC_LUB_ROT) {
+        /* The rotational couplings are printed for n_ij pointing from i to j (the text's
+           convention); with n from j to i (the reading under which the printed contact force
+           repels) that vector is -n.  Both the lubrication and the Brownian parts act on the
+           lubrication pairs. */
+        double Y[6];
+        orc_lub_rot_scalars(p->eta, S->a[i], S->a[j], xie, Y);
+        const double YB11 = Y[0], YB21 = Y[1], YC11 = Y[2], YC12 = Y[3], YC21 = Y[4], YC22 = Y[5];
+        double nij[3] = {-n[0], -n[1], -n[2]};
+        const double *wi = &S->w[3 * i], *wj = &S->w[3 * j];
+        double Ti[3] = {0, 0, 0}, Tj[3] = {0, 0, 0};
+        if (!(p->flags & ORC_NO_LUB)) {
+            /* eq. (force_lub), rotational part: Y^B_11 (Omega_i x n_ij) + Y^B_21 (Omega_j x n_ij) */
+            double ci[3], cj[3];
+            cross3(wi, nij, ci);
+            cross3(wj, nij, cj);
+            for (int d = 0; d < 3; ++d) FL[d] += YB11 * ci[d] + YB21 * cj[d];
+            /* eq. (torque_lub1), (torque_lub2) */
+            double ur[3] = {Uj[0] - vi[0], Uj[1] - vi[1], Uj[2] - vi[2]};
+            double urn[3];
+            cross3(ur, nij, urn);
+            double oi[3], oj[3];
+            for (int d = 0; d < 3; ++d) {
+                oi[d] = YC11 * wi[d] + YC12 * wj[d];
+                oj[d] = YC21 * wi[d] + YC22 * wj[d];
+            }
+            double oin = dot3(n, oi), ojn = dot3(n, oj);
+            for (int d = 0; d < 3; ++d) {
+                Ti[d] += YB11 * urn[d] - (oi[d] - oin * n[d]);
+                Tj[d] += YB21 * urn[d] - (oj[d] - ojn * n[d]);
+            }
+        }
+        if (!(p->flags & ORC_NO_PAIR_BROWN)) {
+            /* eq. (torque_brownian_lub1), (torque_brownian_lub2): the force's theta and a
+               second vector chi (stream 1); a negative radicand is read as zero */
+            double chi[3];
+            gauss_pair_torque(p, S->k, (uint32_t)i, (uint32_t)j, chi);
+            double b = sqrt(2.0 * p->kT / p->dt);
+            double thn[3];
+            cross3(th, nij, thn);
+            double cn = dot3(n, chi);
+            double ri = YC11 - YB11 * YB11 / YA, rj = YC22 - YB21 * YB21 / YA;
+            double si = ri > 0.0 ? sqrt(ri) : 0.0, sj = rj > 0.0 ? sqrt(rj) : 0.0;
+            double sya = sqrt(YA);
+            for (int d = 0; d < 3; ++d) {
+                double tchi = chi[d] - cn * n[d];
+                Ti[d] += b * (YB11 / sya * thn[d] + si * tchi);
+                Tj[d] += b * (YB21 / sya * thn[d] + sj * tchi);
+            }
+        }
+        for (int d = 0; d < 3; ++d) {
+            S->T[3 * i + d] += Ti[d];
+            S->T[3 * j + d] += Tj[d];
+        }
+        S->Tabs[i] += norm3(Ti);
+        S->Tabs[j] += norm3(Tj);
     }
     if (h < 0.0 && !(p->flags & ORC_NO_CONTACT)) {
         /* eq. (force_contact), (torque_contact) with the Coulomb limit */
@@ -343,6 +424,14 @@ static void pair_force(orc_state *S, int i, int j, contact_io *io)
         S->Tabs[j] += S->a[j] * tnorm;
     }
 
+    if (p->rep_A > 0.0) {
+        /* short-ranged repulsion of Sec. IV.B, A/kappa exp((a_i + a_j - |r|)/kappa) n,
+           kappa = 0.01 (a_i + a_j), on the pairs within the lubrication cut-off; an
+           interparticle force, kept with the contact force (and the contact stress) */
+        double kappa = 0.01 * sa;
+        double fr = p->rep_A / kappa * exp((sa - dist) / kappa);
+        for (int d = 0; d < 3; ++d) FC[d] += fr * n[d];
+    }
     double V = p->L[0] * p->L[1] * p->L[2];
     for (int d = 0; d < 3; ++d) {
         double f = FL[d] + FB[d] + FC[d];
@@ -594,6 +683,30 @@ void orc_get_norms(const orc_state *S, double *Fabs, double *Tabs)
 }
 
 void orc_get_stress(const orc_state *S, double out[27]) { memcpy(out, S->stress, sizeof(S->stress)); }
+
+/* Structural Brownian stress of the current configuration, Sec. II.D:
+   -(kT/V) sum_i (a_i/Delta_i) sum_{j: h_ij <= Delta_i} n_ij (x) n_ij with
+   Delta_i = 0.05 a_i and h_ij = |r_ij| - (a_i + a_j); all pairs, brute force. */
+void orc_structural_stress(const orc_state *S, double out[9])
+{
+    const orc_params *p = &S->p;
+    double acc[9] = {0};
+    for (int i = 0; i < S->n; ++i)
+        for (int j = 0; j < S->n; ++j) {
+            if (j == i) continue;
+            double r[3];
+            min_image(p, S->s_le, &S->x[3 * i], &S->x[3 * j], r);
+            double dist = sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+            double h = dist - (S->a[i] + S->a[j]);
+            double delta = 0.05 * S->a[i];
+            if (!(h <= delta)) continue;
+            double wgt = S->a[i] / delta;
+            for (int al = 0; al < 3; ++al)
+                for (int be = 0; be < 3; ++be) acc[3 * al + be] += wgt * (r[al] / dist) * (r[be] / dist);
+        }
+    double V = p->L[0] * p->L[1] * p->L[2];
+    for (int k = 0; k < 9; ++k) out[k] = -p->kT / V * acc[k];
+}
 
 /* Contacts (sorted by (i, j)); returns the count, fills at most cap. */
 int orc_get_contacts(const orc_state *S, int cap, uint32_t *ij, double *s, int32_t *sliding)

@@ -14,7 +14,7 @@ constexpr double kPi = 3.14159265358979323846;
 
 enum : uint32_t {
     F_FREEZE_X = 0x001u, F_NO_LUB = 0x002u, F_NO_PAIR_BROWN = 0x004u, F_NO_CONTACT = 0x008u,
-    F_NO_ONEBODY = 0x010u, F_REBUILD_EACH_STEP = 0x100u, F_NO_GRAPH = 0x200u,
+    F_NO_ONEBODY = 0x010u, F_LUB_ROT = 0x020u, F_REBUILD_EACH_STEP = 0x100u, F_NO_GRAPH = 0x200u,
 };
 
 enum : uint32_t { H_NAN = 1u, H_OVERLAP = 2u, H_NLIST = 4u };
@@ -26,6 +26,8 @@ struct RepParams {
     double gd, gdLy;          // shear rate, shear rate * Ly
     double dt, half_dt;
     double rho, eta, kn, kt, mu;
+    double rep_A;             // short-ranged repulsion scale A (0 = none)
+    double kT;
     double bamp;              // sqrt(2 kT / dt)
     double c1;                // 1 + xi_cut / 2
     double xi_min;
@@ -109,7 +111,11 @@ struct Bufs {
     void* pf;         // 3 doubles / 4 floats per pair: force on the lower-id particle; the pairs of
                       // the wave owning particles [64 w, 64 w + 64) sit in queue order
                       // (particles in order, entries in order) from 64 w * cap
-    void* pt;         // same layout: n x (k_t s) of a contact
+    void* pt;         // same layout: torque on the lower-id particle (contact, or every pair
+                      // with the rotational couplings)
+    void* pt2;        // same layout: torque on the higher-id particle
+    int rot;          // rotational lubrication couplings and pairwise Brownian torques on
+    int ext;          // some model extension on (repulsion or the rotational couplings)
 
     // rebuild scratch
     uint32_t* key;        // cell key per particle
@@ -168,6 +174,9 @@ void launch_finalize(const Bufs& b, hipStream_t st, int q);
 // history from the current lists; 0xFFFFFFFE = every replica takes the
 // host-written compact table; else that replica does.
 void launch_rebuild(const Bufs& b, hipStream_t st, int q, int in_step, uint32_t ct_input_rep);
+// structural Brownian stress sums of one replica at parity p: nblk = n_pad / 256
+// blocks, 9 doubles each into part
+void launch_struct(const Bufs& b, hipStream_t st, int p, uint32_t rep, uint32_t nblk, double* part);
 void launch_diag(const Bufs& b, hipStream_t st, int p, uint32_t rep, uint32_t n, uint32_t* out_ij, double* out_s,
                  int32_t* out_sl, uint32_t* count, uint32_t cap, int mode);
 

@@ -762,6 +762,16 @@ template <> __device__ __forceinline__ double rlog<double>(double x) { return lo
 template <> __device__ __forceinline__ float rlog<float>(float x) {
     return 0.69314718055994531f * __builtin_amdgcn_logf(x);
 }
+template <class R> __device__ __forceinline__ void cross3r(const R* a, const R* b, R* c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+template <class R> __device__ __forceinline__ R rexp(R x);
+template <> __device__ __forceinline__ double rexp<double>(double x) { return exp(x); }
+template <> __device__ __forceinline__ float rexp<float>(float x) {
+    return __builtin_amdgcn_exp2f(1.4426950408889634f * x);
+}
 template <class R> __device__ __forceinline__ R rsqrt_(R x);
 template <> __device__ __forceinline__ double rsqrt_<double>(double x) { return sqrt(x); }
 template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -789,8 +799,8 @@ template <bool MIX> struct EvalCtx {
     using R = typename std::conditional<MIX, float, double>::type;
     double s_le, c1, invV;
     uint32_t k0, k1, ctr_lo, ctr_hi;
-    R bamp, eta6pi, xi_min, kn, kt, mukn, dtR;
-    bool do_lub, do_br, do_ct, do_one;
+    R bamp, eta6pi, xi_min, kn, kt, mukn, dtR, repA;
+    bool do_lub, do_br, do_ct, do_one, do_rep, do_rot;
 };
 
 // Step bookkeeping shared by the pair kernels.  Returns false when the launch
@@ -850,6 +860,9 @@ __device__ __forceinline__ void make_ctx(EvalCtx<MIX>& C, const RepParams& P, do
     C.do_br = !(P.flags & F_NO_PAIR_BROWN);
     C.do_ct = !(P.flags & F_NO_CONTACT);
     C.do_one = !(P.flags & F_NO_ONEBODY);
+    C.repA = (R)P.rep_A;
+    C.do_rep = P.rep_A > 0.0;
+    C.do_rot = (P.flags & F_LUB_ROT) != 0;
 }
 
 // interaction predicate of list entry j of particle i: gap xi <= xi_cut (exact FP64 test)
@@ -896,17 +909,22 @@ template <class R> struct PairIn {
 
 // One item of particle i: contribution f to its force and t to its torque.
 // Pair items also update the stored spring (entry e of i), the contact and
-// sliding bits, the largest overlap and the lower-id stress sums (addS); for
-// a contact, nks receives n x (k_t s), the torque per unit lever arm of both
-// spheres.  Returns false for a pair that does not interact (nothing
-// contributed).  LO_ONLY: the item is a pair whose partner has the higher id.
-template <bool MIX, bool LO_ONLY = false, class AddS>
+// sliding bits, the largest overlap and the lower-id stress sums (addS).
+// tb_out (LO_ONLY): without ROT, n x (k_t s) of a contact (the torque per unit
+// lever arm of both spheres); with ROT, the pair's torque on the higher-id
+// partner.
+// Returns false for a pair that does not interact (nothing contributed).
+// LO_ONLY: the item is a pair whose partner has the higher id.  EXT: the
+// model extensions are compiled in (the short-ranged repulsion, and the
+// rotational lubrication couplings with the pairwise Brownian torques, which
+// need LO_ONLY and preloaded partner data), each on when its parameter says.
+template <bool MIX, bool LO_ONLY = false, bool EXT = false, class AddS>
 __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, const EvalCtx<MIX>& C, uint32_t i,
                                           uint32_t e, const double4& pi, uint32_t idi,
                                           const typename EvalCtx<MIX>::R* vi, const typename EvalCtx<MIX>::R* wi,
                                           bool had_contact, typename EvalCtx<MIX>::R* f,
                                           typename EvalCtx<MIX>::R* t, bool& contact, bool& slid, float& maxov,
-                                          AddS addS, typename EvalCtx<MIX>::R* nks_out = nullptr,
+                                          AddS addS, typename EvalCtx<MIX>::R* tb_out = nullptr,
                                           const PairIn<typename EvalCtx<MIX>::R>* pre = nullptr) {
     using R = typename EvalCtx<MIX>::R;
     const uint32_t npad = b.npad;
@@ -922,7 +940,7 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
     bool lo = true;
     double dx = 0.0, dy = 0.0, dz = 0.0, h = 0.0;
     int ky = 0;
-    R n[3] = {(R)0, (R)0, (R)0}, XA = (R)0, YA = (R)0;
+    R n[3] = {(R)0, (R)0, (R)0}, XA = (R)0, YA = (R)0, lgv = (R)0;
     if (pair) {
         if (pre) {
             j = pre->j;
@@ -952,6 +970,7 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
         const R sR = aa + ab;
         const R pre = C.eta6pi * rrcp<R>(sR * sR * sR);
         const R lg = -rlog<R>(xie);
+        lgv = lg;
         XA = pre * ((R)2 * pab * pab * rrcp<R>(xie) + pab * (qab + (R)7 * pab) * (R)0.2 * lg);
         YA = pre * ((R)4 * pab * ((R)2 * qab + pab) * (R)(1.0 / 15.0) * lg);
     }
@@ -1002,6 +1021,71 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
         const R sx = rsqrt_<R>(XA), sy = rsqrt_<R>(YA);
 #pragma unroll
         for (int d = 0; d < 3; ++d) fb[d] = C.bamp * (sx * (tn * n[d]) + sy * (th[d] - tn * n[d]));
+    }
+    const bool ROT = EXT && C.do_rot;
+    R trot_a[3] = {(R)0, (R)0, (R)0}, trot_b[3] = {(R)0, (R)0, (R)0};
+    if (ROT) {
+        // Rotational couplings, eq. (force_lub), (torque_lub1), (torque_lub2), and pairwise
+        // Brownian torques, eq. (torque_brownian_lub1), (torque_brownian_lub2).  The printed
+        // signs hold for the unit vector from a to b, which is -n here; the scalars Y^B, Y^C
+        // in the form symmetric in the radii (a = lower id, b = higher id).
+        const R aa = (R)pi.w, ab = (R)pj.w;  // LO_ONLY: i is a
+        const R sR = aa + ab, i5s2 = (R)0.2 * rrcp<R>(sR * sR), isR = rrcp<R>(sR);
+        const R pie = (R)kPi * (R)P.eta;
+        const R YB11 = -(R)4 * pie * aa * aa * ab * ((R)4 * aa + ab) * i5s2 * lgv;
+        const R YB21 = -(R)4 * pie * ab * ab * aa * ((R)4 * ab + aa) * i5s2 * lgv;
+        const R YC11 = (R)3.2 * pie * aa * aa * aa * ab * isR * lgv;
+        const R YC12 = (R)0.8 * pie * aa * aa * ab * ab * isR * lgv;  // = Y^C_21
+        const R YC22 = (R)3.2 * pie * ab * ab * ab * aa * isR * lgv;
+        const R nab[3] = {-n[0], -n[1], -n[2]};
+        const R* wa = wi;
+        const R* wb = pre->wj;
+        if (C.do_lub) {
+            R ca[3], cb[3], urn[3], oa[3], ob[3];
+            cross3r(wa, nab, ca);
+            cross3r(wb, nab, cb);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) fl[d] = fl[d] + (YB11 * ca[d] + YB21 * cb[d]);
+            R ur[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) ur[d] = vb[d] - va[d];
+            cross3r(ur, nab, urn);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                oa[d] = YC11 * wa[d] + YC12 * wb[d];
+                ob[d] = YC12 * wa[d] + YC22 * wb[d];
+            }
+            const R oan = (n[0] * oa[0] + n[1] * oa[1]) + n[2] * oa[2];
+            const R obn = (n[0] * ob[0] + n[1] * ob[1]) + n[2] * ob[2];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                trot_a[d] = YB11 * urn[d] - (oa[d] - oan * n[d]);
+                trot_b[d] = YB21 * urn[d] - (ob[d] - obn * n[d]);
+            }
+        }
+        if (C.do_br) {
+            // the force's theta and a second vector chi (stream 1); a negative radicand is read as 0
+            R chi[3], thn[3];
+            normals3(philox10(C.ctr_lo, idi, idj, C.ctr_hi | 1u, C.k0, C.k1), chi);
+            cross3r(th, nab, thn);
+            const R cn = (n[0] * chi[0] + n[1] * chi[1]) + n[2] * chi[2];
+            const R iya = rrcp<R>(YA);
+            const R ra = YC11 - YB11 * YB11 * iya, rb = YC22 - YB21 * YB21 * iya;
+            const R sa_ = ra > (R)0 ? rsqrt_<R>(ra) : (R)0, sb_ = rb > (R)0 ? rsqrt_<R>(rb) : (R)0;
+            const R isya = rrcp<R>(rsqrt_<R>(YA));
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const R tchi = chi[d] - cn * n[d];
+                trot_a[d] = trot_a[d] + C.bamp * (YB11 * isya * thn[d] + sa_ * tchi);
+                trot_b[d] = trot_b[d] + C.bamp * (YB21 * isya * thn[d] + sb_ * tchi);
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) t[d] = trot_a[d];
+        if (tb_out) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) tb_out[d] = trot_b[d];
+        }
     }
     if (h < 0.0 && C.do_ct) {
         // eq. (force_contact), (torque_contact); the spring s lives in canonical orientation
@@ -1076,12 +1160,30 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
 #pragma unroll
         for (int d = 0; d < 3; ++d) fc[d] = (C.kn * delta) * n[d] - ks[d];
         const R nks[3] = {n[1] * ks[2] - n[2] * ks[1], n[2] * ks[0] - n[0] * ks[2], n[0] * ks[1] - n[1] * ks[0]};
+        if (ROT) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) t[d] = ai * nks[d];
-        if (nks_out) {
+            for (int d = 0; d < 3; ++d) t[d] = t[d] + ai * nks[d];
+        } else {
 #pragma unroll
-            for (int d = 0; d < 3; ++d) nks_out[d] = nks[d];
+            for (int d = 0; d < 3; ++d) t[d] = ai * nks[d];
         }
+        if (tb_out) {
+            if (ROT) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) tb_out[d] = tb_out[d] + aj * nks[d];
+            } else {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) tb_out[d] = nks[d];
+            }
+        }
+    }
+    if (EXT && C.do_rep) {
+        // short-ranged repulsion (A / kappa) exp(-h / kappa) n, kappa = 0.01 (a_a + a_b) (Sec. IV.B),
+        // an interparticle force like contact: it joins fc (and the contact stress)
+        const R kappa = (R)(0.01 * (pi.w + pj.w));
+        const R fr = C.repA * rrcp<R>(kappa) * rexp<R>(-(R)h * rrcp<R>(kappa));
+#pragma unroll
+        for (int d = 0; d < 3; ++d) fc[d] = fc[d] + fr * n[d];
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -1484,7 +1586,7 @@ __global__ __launch_bounds__(256) void k_pairq(Bufs b, int q, int kick, int adva
 // torques and springs equal those of variant 1 with one lane per particle.
 // ---------------------------------------------------------------------------
 
-template <bool MIX, int LN>
+template <bool MIX, int LN, bool EXT>
 __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int advance, uint32_t only_rep) {
     using R = typename std::conditional<MIX, float, double>::type;
     using V3 = typename PairRec<R>::T;
@@ -1568,6 +1670,7 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
     // results of this wave's pairs: a contiguous run in queue order
     V3* const pf = (V3*)b.pf + (size_t)base * b.cap;
     V3* const pt = (V3*)b.pt + (size_t)base * b.cap;
+    V3* const pt2 = (V3*)b.pt2 + (size_t)base * b.cap;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 
@@ -1595,12 +1698,17 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
         load_vw<MIX>(b, in.j, in.vj, in.wj);
         if (had) load_spring<R>(b, e * npad + ii, in.s);
         else in.s[0] = in.s[1] = in.s[2] = (R)0;
-        R f[3], t[3], nks[3];
+        R f[3], t[3], tb[3];  // tb: written by eval_item where it is used (contact, or the couplings)
         bool contact, slid;
-        eval_item<MIX, true>(b, P, C, ii, e, pi, idi, vi, wi, had, f, t, contact, slid, maxov, addS, nks, &in);
+        eval_item<MIX, true, EXT>(b, P, C, ii, e, pi, idi, vi, wi, had, f, t, contact, slid, maxov, addS, tb, &in);
         pf[k] = PairRec<R>::make(f[0], f[1], f[2]);
+        if (EXT && C.do_rot) {  // torques on the lower- and the higher-id particle
+            pt[k] = PairRec<R>::make(t[0], t[1], t[2]);
+            pt2[k] = PairRec<R>::make(tb[0], tb[1], tb[2]);
+        } else if (contact) {  // n x (k_t s): each side scales it by its radius
+            pt[k] = PairRec<R>::make(tb[0], tb[1], tb[2]);
+        }
         if (contact) {
-            pt[k] = PairRec<R>::make(nks[0], nks[1], nks[2]);
             atomicOr(&cmq[w][l], 1ull << e);
             if (slid) atomicOr(&smq[w][l], 1ull << e);
         }
@@ -1629,13 +1737,13 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
     }
 }
 
-template <bool MIX>
+template <bool MIX, bool ROT>
 __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& P, const RepDyn& D, int q, int kick,
                                                 int fuse, uint32_t i, float& dblk, bool& expire, bool& bad);
 
 // fuse: also take kick 1 and the drift of the next step (parity 1 - q) from the
 // new forces, as the integrate launch of that step would
-template <bool MIX>
+template <bool MIX, bool ROT>
 __global__ __launch_bounds__(256) void k_gather(Bufs b, int q, int kick, int fuse, uint32_t only_rep) {
     if (b.sys->halted) return;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -1646,7 +1754,7 @@ __global__ __launch_bounds__(256) void k_gather(Bufs b, int q, int kick, int fus
     RepDyn& D = b.dyn[r];
     float dblk = 0.0f;
     bool expire = false, bad = false;
-    if (i - P.p_begin < P.n) gather_particle<MIX>(b, P, D, q, kick, fuse, i, dblk, expire, bad);
+    if (i - P.p_begin < P.n) gather_particle<MIX, ROT>(b, P, D, q, kick, fuse, i, dblk, expire, bad);
     if (bad) atomicOr(&D.health, H_NAN);
     if (fuse) {
         if (expire) atomicOr(&b.sys->expire[1 - q], 1u);
@@ -1654,7 +1762,7 @@ __global__ __launch_bounds__(256) void k_gather(Bufs b, int q, int kick, int fus
     }
 }
 
-template <bool MIX>
+template <bool MIX, bool ROT>
 __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& P, const RepDyn& D, int q, int kick,
                                                 int fuse, uint32_t i, float& dblk, bool& expire, bool& bad) {
     using R = typename std::conditional<MIX, float, double>::type;
@@ -1714,18 +1822,19 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
                 use[u] = (imj[u] >> mm[u]) & 1ull;
                 slot[u] = (size_t)(jj[u] & wmask) * b.cap + qj[u] +
                           (uint32_t)__popcll(imj[u] & ((1ull << mm[u]) - 1ull));
-                ct[u] = use[u] && ((cmj[u] >> mm[u]) & 1ull);
+                ct[u] = use[u] && (ROT || ((cmj[u] >> mm[u]) & 1ull));
             } else if ((im >> e) & 1ull) {
                 use[u] = true;
                 slot[u] = klo++;
-                ct[u] = (cm >> e) & 1ull;
+                ct[u] = ROT || ((cm >> e) & 1ull);
             }
         }
         V3 fv[GB], tv[GB];
 #pragma unroll
         for (uint32_t u = 0; u < GB; ++u) {
             if (use[u]) fv[u] = ((const V3*)b.pf)[slot[u]];
-            if (ct[u]) tv[u] = ((const V3*)b.pt)[slot[u]];
+            // with ROT the torque record of the particle's own side of the pair
+            if (ct[u]) tv[u] = ((const V3*)(ROT && c0 + u < e0 ? b.pt2 : b.pt))[slot[u]];
         }
 #pragma unroll
         for (uint32_t u = 0; u < GB; ++u) {
@@ -1735,9 +1844,10 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
             F.add(1, sg * fv[u].y);
             F.add(2, sg * fv[u].z);
             if (ct[u]) {
-                T.add(0, ai * tv[u].x);
-                T.add(1, ai * tv[u].y);
-                T.add(2, ai * tv[u].z);
+                const R sc = ROT ? (R)1 : ai;  // without ROT the record is n x (k_t s)
+                T.add(0, ROT ? tv[u].x : sc * tv[u].x);
+                T.add(1, ROT ? tv[u].y : sc * tv[u].y);
+                T.add(2, ROT ? tv[u].z : sc * tv[u].z);
             }
         }
     }
@@ -1772,6 +1882,51 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
         }
         integrate_particle<MIX>(b, P, D, 1 - q, i, pi, vf, wf, Ft, Tt, dblk, expire);
     }
+}
+
+// Structural Brownian stress sum of one replica (Sec. II.D) at parity p:
+// per particle i, (a_i / Delta_i) n n over its list partners with gap
+// h <= Delta_i = 0.05 a_i, in list (id) order; part[block * 9 + c] receives
+// the block's fixed-order sum.  The caller scales by -kT / V.
+__global__ __launch_bounds__(256) void k_struct(Bufs b, uint32_t rep, int p, double* part) {
+    const RepParams& P = b.reps[rep];
+    const uint32_t i = P.p_begin + blockIdx.x * 256 + threadIdx.x;
+    double acc[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) acc[c] = 0.0;
+    if (i - P.p_begin < P.n) {
+        const double4 pi = b.pos[i];
+        const double s_le = b.dyn[rep].s_slot[p];
+        const double delta = 0.05 * pi.w, wgt = pi.w / delta;
+        const uint32_t cnt = b.ncnt[i];
+        for (uint32_t e = 0; e < cnt; ++e) {
+            const double4 pj = b.pos[b.nbr[e * b.npad + i]];
+            double r[3];
+            min_image(P, s_le, pi, pj, r[0], r[1], r[2]);
+            const double dist = sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+            if (!(dist - (pi.w + pj.w) <= delta)) continue;
+#pragma unroll
+            for (int al = 0; al < 3; ++al)
+#pragma unroll
+                for (int be = 0; be < 3; ++be) acc[3 * al + be] += wgt * (r[al] / dist) * (r[be] / dist);
+        }
+    }
+    __shared__ double rows[16][9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        const double v = row_sum_f64(acc[c]);
+        if ((threadIdx.x & 15) == 15) rows[threadIdx.x >> 4][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        double t = 0.0;
+        for (int k = 0; k < 16; ++k) t += rows[k][threadIdx.x];
+        part[blockIdx.x * 9 + threadIdx.x] = t;
+    }
+}
+
+void launch_struct(const Bufs& b, hipStream_t st, int p, uint32_t rep, uint32_t nblk, double* part) {
+    hipLaunchKernelGGL(k_struct, dim3(nblk), dim3(256), 0, st, b, rep, p, part);
 }
 
 // diagnostics: mode 0 = interaction set, 1 = Verlet list, 2 = contacts (with springs)
@@ -1850,13 +2005,22 @@ static void launch_pair_t(const Bufs& b, hipStream_t st, int q, int kick, int ad
                           hipEvent_t mid, int fuse) {
     if (b.kern == 2) {  // half-pair evaluation, then the per-particle gather
         const uint32_t g = b.npad / 256, fin = 27u * b.nrep;  // pair blocks, then finalize blocks
-        switch (b.lanes) {
-            case 1: hipLaunchKernelGGL((k_half<MIX, 1>), dim3(g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
-            case 2: hipLaunchKernelGGL((k_half<MIX, 2>), dim3(2 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
-            default: hipLaunchKernelGGL((k_half<MIX, 4>), dim3(4 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
+        if (b.ext) {
+            switch (b.lanes) {
+                case 1: hipLaunchKernelGGL((k_half<MIX, 1, true>), dim3(g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
+                case 2: hipLaunchKernelGGL((k_half<MIX, 2, true>), dim3(2 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
+                default: hipLaunchKernelGGL((k_half<MIX, 4, true>), dim3(4 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
+            }
+        } else {
+            switch (b.lanes) {
+                case 1: hipLaunchKernelGGL((k_half<MIX, 1, false>), dim3(g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
+                case 2: hipLaunchKernelGGL((k_half<MIX, 2, false>), dim3(2 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
+                default: hipLaunchKernelGGL((k_half<MIX, 4, false>), dim3(4 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
+            }
         }
         if (mid) (void)hipEventRecord(mid, st);
-        hipLaunchKernelGGL(k_gather<MIX>, dim3(b.npad / 256), dim3(256), 0, st, b, q, kick, fuse, only_rep);
+        if (b.rot) hipLaunchKernelGGL((k_gather<MIX, true>), dim3(b.npad / 256), dim3(256), 0, st, b, q, kick, fuse, only_rep);
+        else hipLaunchKernelGGL((k_gather<MIX, false>), dim3(b.npad / 256), dim3(256), 0, st, b, q, kick, fuse, only_rep);
         return;
     }
     if (b.kern == 1) {  // wave-cooperative; 256-thread blocks of 4 * 64 / lanes particles

@@ -84,6 +84,8 @@ struct sim {
     int64_t since_build = 0;     // steps since the last list build
     int64_t plan = 16;           // rebuild when since_build reaches this
     int64_t plan_hint = 16;      // first chunk after a build
+    double* struct_part = nullptr;  // block sums of the structural Brownian stress
+    uint32_t struct_cap = 0;
 
     void* dalloc(size_t bytes) {
         if (bytes == 0) bytes = 256;
@@ -154,6 +156,11 @@ int validate(const sim_config* c, const double* radii, std::string& why) {
         return SIM_EINVAL;
     }
     if (c->pair_kernel > SIM_KERNEL_HALF) { why = "unknown pair_kernel"; return SIM_EINVAL; }
+    if (((c->flags & SIM_LUB_ROT) || c->repulsion > 0.0) &&
+        (c->pair_kernel == SIM_KERNEL_LANES || c->pair_kernel == SIM_KERNEL_WAVE)) {
+        why = "SIM_LUB_ROT and the repulsion need the half-pair kernel (pair_kernel 0 or SIM_KERNEL_HALF)";
+        return SIM_EINVAL;
+    }
     if (c->pair_kernel == SIM_KERNEL_HALF && c->lanes == 8) {
         why = "the half-pair kernel needs lanes <= 4";
         return SIM_EINVAL;
@@ -171,8 +178,8 @@ int validate(const sim_config* c, const double* radii, std::string& why) {
         if (!(c->box[d] > 0.0) || !std::isfinite(c->box[d])) { why = "box sides must be positive"; return SIM_EINVAL; }
     if (!(c->dt > 0.0)) { why = "dt must be positive"; return SIM_EINVAL; }
     if (!(c->rho > 0.0) || !(c->eta > 0.0)) { why = "rho and eta must be positive"; return SIM_EINVAL; }
-    if (c->kn < 0.0 || c->kt < 0.0 || c->mu < 0.0 || c->kT < 0.0) {
-        why = "kn, kt, mu and kT must be non-negative";
+    if (c->kn < 0.0 || c->kt < 0.0 || c->mu < 0.0 || c->kT < 0.0 || !(c->repulsion >= 0.0)) {
+        why = "kn, kt, mu, kT and repulsion must be non-negative";
         return SIM_EINVAL;
     }
     if (!std::isfinite(c->gammadot)) { why = "gammadot must be finite"; return SIM_EINVAL; }
@@ -350,6 +357,7 @@ void tune_pair(sim* s, int want_kern, int want_lanes) {
     std::vector<std::pair<int, int>> cand;
     for (int kern : {2, 0, 1}) {
         if (want_kern && want_kern - 1 != kern) continue;
+        if (s->b.ext && kern != 2) continue;  // the model extensions live in the half-pair kernel
         if (kern == 1 && s->b.cap > 62) continue;
         for (int L : {1, 2, 4, 8}) {
             if (want_lanes && want_lanes != L) continue;
@@ -468,6 +476,8 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
             P.dt = c.dt;
             P.half_dt = 0.5 * c.dt;
             P.rho = c.rho; P.eta = c.eta; P.kn = c.kn; P.kt = c.kt; P.mu = c.mu;
+            P.rep_A = c.repulsion;
+            P.kT = c.kT;
             P.bamp = std::sqrt(2.0 * c.kT / c.dt);
             P.c1 = 1.0 + 0.5 * c.xi_cut;
             P.xi_min = c.xi_min;
@@ -535,6 +545,11 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         b.qoff = s->alloc<uint16_t>(np);
         b.pf = s->dalloc(np * cap * (s->mixed ? 4 * sizeof(float) : 3 * sizeof(double)));
         b.pt = s->dalloc(np * cap * (s->mixed ? 4 * sizeof(float) : 3 * sizeof(double)));
+        b.pt2 = s->dalloc(np * cap * (s->mixed ? 4 * sizeof(float) : 3 * sizeof(double)));
+        b.rot = (s->flags & SIM_LUB_ROT) ? 1 : 0;
+        b.ext = b.rot;
+        for (int r = 0; r < n_replicas; ++r)
+            if (cfgs[r].repulsion > 0.0) b.ext = 1;
         b.key = s->alloc<uint32_t>(np);
         b.cell_cnt = s->alloc<uint32_t>(key);
         b.cell_fill = s->alloc<uint32_t>(key);
@@ -869,6 +884,37 @@ int sim_get_state(sim* s, int32_t r, double* x, double* v, double* w, double* F,
             if (step) *step = d[0].step_slot[s->par];
         }
         return SIM_OK;
+    } catch (const HipError& e) {
+        return hip_fail(s, e);
+    }
+}
+
+int sim_structural_stress(sim* s, int32_t r, double out[9]) {
+    if (int rc = check_rep(s, r)) return rc;
+    if (!out) return fail(s, SIM_EINVAL, "null output");
+    const RepParams& P = s->P[r];
+    // the list (range (a_i + a_j)(1 + xi_cut/2) + skin) must hold every shell partner
+    const double amin = min_radius(s->radii[r].data(), P.n), amax = max_radius(s->radii[r].data(), P.n);
+    if (P.skin + amin * (2.0 * (P.c1 - 1.0)) < 0.05 * amax)
+        return fail(s, SIM_EINVAL, "the neighbour list range does not cover the 0.05 a shell");
+    try {
+        launch_rebuild(s->b, s->st, 1 - s->par, 0, 0xFFFFFFFFu);
+        s->since_build = 0;
+        s->plan = s->plan_hint;
+        const uint32_t nblk = P.n_pad / 256;
+        if (s->struct_cap < nblk) {
+            s->struct_part = s->alloc<double>((size_t)nblk * 9);
+            s->struct_cap = nblk;
+        }
+        launch_struct(s->b, s->st, s->par, (uint32_t)r, nblk, s->struct_part);
+        HIPCHK(hipGetLastError());
+        auto h = d2h(s, s->struct_part, 0, (size_t)nblk * 9);
+        double acc[9] = {0};
+        for (uint32_t k = 0; k < nblk; ++k)
+            for (int c = 0; c < 9; ++c) acc[c] += h[(size_t)k * 9 + c];
+        const double V = P.L[0] * P.L[1] * P.L[2];
+        for (int c = 0; c < 9; ++c) out[c] = -P.kT / V * acc[c];
+        return check_health(s);
     } catch (const HipError& e) {
         return hip_fail(s, e);
     }

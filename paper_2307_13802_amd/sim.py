@@ -19,7 +19,7 @@ HEADER = os.path.join(ROOT, "include", "sim.h")
 
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ECAPACITY, ERANGE = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED = 0, 1
-FREEZE_X, NO_LUB, NO_PAIR_BROWN, NO_CONTACT, NO_ONEBODY = 0x1, 0x2, 0x4, 0x8, 0x10
+FREEZE_X, NO_LUB, NO_PAIR_BROWN, NO_CONTACT, NO_ONEBODY, LUB_ROT = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 REBUILD_EACH_STEP, NO_GRAPH = 0x100, 0x200
 KERNEL_AUTO, KERNEL_LANES, KERNEL_WAVE, KERNEL_HALF = 0, 1, 2, 3
 STRESS_CONTACT, STRESS_LUB, STRESS_BROWN, STRESS_DRAG, STRESS_TOTAL = range(5)
@@ -40,7 +40,7 @@ class _Config(C.Structure):
                 ("eta", C.c_double), ("kn", C.c_double), ("kt", C.c_double), ("mu", C.c_double),
                 ("kT", C.c_double), ("gammadot", C.c_double), ("dt", C.c_double), ("xi_cut", C.c_double),
                 ("xi_min", C.c_double), ("skin", C.c_double), ("le_offset0", C.c_double),
-                ("max_overlap", C.c_double), ("seed", C.c_uint64), ("step0", C.c_uint64),
+                ("max_overlap", C.c_double), ("repulsion", C.c_double), ("seed", C.c_uint64), ("step0", C.c_uint64),
                 ("precision", C.c_int32), ("flags", C.c_uint32), ("nlist_cap", C.c_uint32),
                 ("lanes", C.c_uint32), ("pair_kernel", C.c_uint32), ("reserved", C.c_uint32)]
 
@@ -85,6 +85,7 @@ def lib():
         "sim_reset_stress": [vp],
         "sim_stress_series": [vp, C.c_int32, dp, C.c_int64, lp],
         "sim_positions": [vp, C.c_int32, dp],
+        "sim_structural_stress": [vp, C.c_int32, dp],
         "sim_get_state": [vp, C.c_int32, dp, dp, dp, dp, dp, dp, C.POINTER(C.c_uint64)],
         "sim_set_state": [vp, C.c_int32, dp, dp, dp, dp, dp, C.c_double, C.c_uint64, up, dp, C.c_int64],
         "sim_forces": [vp, C.c_int32, dp, dp],
@@ -145,6 +146,7 @@ class Config:
     skin: float = 0.0
     le_offset0: float = 0.0
     max_overlap: float = 0.0
+    repulsion: float = 0.0
     seed: int = 0
     step0: int = 0
     precision: int = FP64
@@ -160,7 +162,7 @@ class Config:
         for d in range(3):
             c.box[d] = float(self.box[d])
         for f in ("rho", "eta", "kn", "kt", "mu", "kT", "gammadot", "dt", "xi_cut", "xi_min", "skin",
-                  "le_offset0", "max_overlap"):
+                  "le_offset0", "max_overlap", "repulsion"):
             setattr(c, f, float(getattr(self, f)))
         c.seed, c.step0 = int(self.seed), int(self.step0)
         c.precision, c.flags, c.nlist_cap = int(self.precision), int(self.flags), int(self.nlist_cap)
@@ -278,6 +280,12 @@ class Sim:
         out = np.zeros((max(cnt.value, 1), 27))
         _check(lib().sim_stress_series(self.h, replica, _dp(out), cnt.value, C.byref(cnt)), self.h)
         return out[: cnt.value].reshape(-1, 3, 3, 3)
+
+    def structural_stress(self, replica=0):
+        """Structural Brownian stress of the current configuration (3x3)."""
+        out = np.zeros(9)
+        _check(lib().sim_structural_stress(self.h, replica, _dp(out)), self.h)
+        return out.reshape(3, 3)
 
     def positions(self, replica=0):
         out = np.zeros((self.n[replica], 3))

@@ -67,6 +67,9 @@ def test_validate_accepts_good_config():
     (dict(pair_kernel=4), None, "pair_kernel"),
     (dict(pair_kernel=2, lanes=8), None, "wave kernel"),
     (dict(pair_kernel=3, lanes=8), None, "half-pair"),
+    (dict(flags=0x20, pair_kernel=1), None, "SIM_LUB_ROT"),
+    (dict(repulsion=1.0, pair_kernel=2), None, "half-pair kernel"),
+    (dict(repulsion=-1.0), None, "non-negative"),
 ])
 def test_validate_rejects(kw, radii, needle):
     a = np.full(4, 1.0) if radii is None else radii

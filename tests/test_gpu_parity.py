@@ -299,3 +299,72 @@ def test_large_sampled_fp64(P):
         worst = max(worst, np.linalg.norm(Fg[i] - F) / fa, np.linalg.norm(Tg[i] - T) / max(ta, 1e-300))
     _say(f"  worst sampled error {worst:.2e}")
     assert worst <= TOL_F64
+
+
+def test_repulsion_matches_oracle(P):
+    """Short-ranged repulsion (Sec. IV.B), A = 100 kT: forces, exact springs and the contact
+    stress (which holds the repulsion) against the oracle, both precisions, and one step."""
+    st = _state(n=500, phi=0.5, seed=12)
+    A = 100.0 * st["params"]["kT"]
+    for prec, tol, exact in ((P.FP64, TOL_F64, True), (P.MIXED, TOL_MIX, False)):
+        for lanes in (1, 2):
+            _say(f"case: repulsion A=100 kT precision={prec} lanes={lanes}")
+            sim = P.Sim(_cfg(P, st, precision=prec, repulsion=A, pair_kernel=3, lanes=lanes), st["radii"],
+                        st["x"], st["v"], st["w"])
+            orc = O.Oracle(O.Params(L=st["L"], rep_A=A, **st["params"]), st["radii"], st["x"], st["v"], st["w"])
+            _compare_eval(P, sim, orc, tol, exact=exact)
+    sim = P.Sim(_cfg(P, st, repulsion=A), st["radii"], st["x"], st["v"], st["w"])
+    orc = O.Oracle(O.Params(L=st["L"], rep_A=A, **st["params"]), st["radii"], st["x"], st["v"], st["w"])
+    sim.step(3)
+    orc.step(3)
+    gs, os_ = sim.get_state(), orc.state()
+    assert np.abs(gs["x"] - os_["x"]).max() < 1e-11
+
+
+def test_structural_stress_matches_oracle(P):
+    """Structural Brownian stress (Sec. II.D) of the GPU state against the oracle's brute force,
+    at creation and after 40 sheared steps (Lees-Edwards offset non-zero)."""
+    st = _state(n=800, phi=0.55, seed=13)
+    sim = P.Sim(_cfg(P, st, lanes=1), st["radii"], st["x"], st["v"], st["w"])
+    for k in range(2):
+        gs = sim.get_state()
+        _say(f"case: structural stress N=800 after {40 * k} steps, s_le={gs['s_le']:.3e}")
+        orc = O.Oracle(O.Params(L=st["L"], **st["params"]), st["radii"], gs["x"], gs["v"], gs["w"], s_le=gs["s_le"])
+        Sg, So = sim.structural_stress(), orc.structural_stress()
+        _say(f"  max rel err {np.abs(Sg - So).max() / np.abs(So).max():.2e}")
+        assert np.abs(Sg - So).max() <= 1e-12 * np.abs(So).max()
+        sim.step(40)
+    # the rebuild it performs changes no trajectory: compare with a run that never asked
+    ref = P.Sim(_cfg(P, st, lanes=1), st["radii"], st["x"], st["v"], st["w"])
+    ref.step(80)
+    a, b = sim.get_state(), ref.get_state()
+    for key in ("x", "v", "w", "F", "T"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_rotational_couplings_match_oracle(P):
+    """Rotational lubrication couplings and pairwise Brownian torques (SIM_LUB_ROT): forces,
+    torques, exact springs and stresses against the oracle in both precisions and for 1 and 2
+    cull lanes; with the repulsion as well; then a short FP64 trajectory."""
+    st = _state(n=500, phi=0.5, seed=14)
+    A = 10.0 * st["params"]["kT"]
+    for prec, tol, exact in ((P.FP64, TOL_F64, True), (P.MIXED, TOL_MIX, False)):
+        for lanes, rep in ((1, 0.0), (2, 0.0), (1, A)):
+            _say(f"case: LUB_ROT precision={prec} lanes={lanes} repulsion={rep}")
+            sim = P.Sim(_cfg(P, st, precision=prec, flags=P.LUB_ROT, pair_kernel=3, lanes=lanes, repulsion=rep),
+                        st["radii"], st["x"], st["v"], st["w"])
+            orc = O.Oracle(O.Params(L=st["L"], flags=O.LUB_ROT, rep_A=rep, **st["params"]), st["radii"], st["x"],
+                           st["v"], st["w"])
+            _compare_eval(P, sim, orc, tol, exact=exact)
+    sim = P.Sim(_cfg(P, st, flags=P.LUB_ROT, repulsion=A), st["radii"], st["x"], st["v"], st["w"])
+    orc = O.Oracle(O.Params(L=st["L"], flags=O.LUB_ROT, rep_A=A, **st["params"]), st["radii"], st["x"], st["v"],
+                   st["w"])
+    for k in range(3):
+        sim.step(2)
+        orc.step(2)
+        gs, os_ = sim.get_state(), orc.state()
+        dx = np.abs(gs["x"] - os_["x"]).max()
+        dw = np.abs(gs["w"] - os_["w"]).max() / np.abs(os_["w"]).max()
+        _say(f"  after {2 * (k + 1)} steps: |dx| {dx:.2e} |dw|/|w| {dw:.2e}")
+        assert dx < 1e-11 and dw < 1e-9
+        assert np.array_equal(sim.contacts()[0], orc.contacts()[0])

@@ -568,3 +568,178 @@ def test_table1_peclet_numbers():
         assert 6 * PI * eta * a ** 3 * gd / kT == pytest.approx(pe, rel=0.05)
         g2, k2 = gen.pe_to_rates(pe, eta)
         assert 6 * PI * eta * g2 / k2 == pytest.approx(pe, rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Short-ranged repulsion (Sec. IV.B) and the structural Brownian stress (Sec. II.D)
+# --------------------------------------------------------------------------
+ONLY_REP = O.NO_LUB | O.NO_PAIR_BROWN | O.NO_CONTACT | O.NO_ONEBODY
+
+
+def test_repulsion_two_spheres_closed_form():
+    A = 0.7
+    for a in ((1.0, 1.0), (1.0, 1.4)):
+        for xi in (-4e-3, 0.0, 0.01, 0.049):
+            o, n, dist = _two(xi, a=a, flags=ONLY_REP | O.FREEZE_X, rep_A=A, direction=(0.3, -0.5, 0.8))
+            F = o.state()["F"]
+            sa = sum(a)
+            kappa = 0.01 * sa
+            expect = A / kappa * math.exp(-(dist - sa) / kappa) * n   # pushes particle 0 away from 1
+            assert np.allclose(F[0], expect, rtol=1e-12, atol=0), (a, xi)
+            assert np.array_equal(F[1], -F[0])
+            assert np.abs(o.state()["T"]).max() == 0.0
+            # kept with the contact stress: -F (x) r / V, r = x_0 - x_1
+            S = o.stress()
+            V = 20.0 ** 3
+            assert np.allclose(S[0], -np.outer(F[0], dist * n) / V, rtol=1e-12, atol=1e-30)
+            assert np.abs(S[1]).max() == 0.0 and np.abs(S[2]).max() == 0.0
+
+
+def test_repulsion_off_beyond_cutoff_and_adds_to_contact():
+    o, n, dist = _two(0.0501, flags=ONLY_REP, rep_A=1.0)
+    assert np.abs(o.state()["F"]).max() == 0.0
+    # with contact on: Hookean part plus the repulsion, both along n
+    kn = 1e4
+    o, n, dist = _two(-2e-3, flags=O.NO_LUB | O.NO_PAIR_BROWN | O.NO_ONEBODY, rep_A=0.5, kn=kn, mu=0.0)
+    F = o.state()["F"][0]
+    delta = 2.0 - dist
+    expect = (kn * delta + 0.5 / 0.02 * math.exp(delta / 0.02)) * n
+    assert np.allclose(F, expect, rtol=1e-12, atol=0)
+
+
+def test_structural_stress_shells():
+    """Bidisperse pair: the shell of each particle is 0.05 a_i, so a gap between 0.05 and 0.07
+    counts only on the larger sphere's side; the tensor is -(kT/V) sum (a_i/Delta_i) n n."""
+    L, kT = 20.0, 0.3
+    u = np.array([1.0, 2.0, -2.0]) / 3.0
+    for h, weight in ((0.03, 40.0), (0.06, 20.0), (0.08, 0.0), (-0.01, 40.0)):
+        c = np.array([10.0, 10.0, 10.0])
+        x = np.array([c, c - (2.4 + h) * u])
+        o = O.Oracle(_params((L, L, L), kT=kT), np.array([1.0, 1.4]), x, np.zeros((2, 3)), np.zeros((2, 3)))
+        S = o.structural_stress()
+        assert np.allclose(S, -kT / L ** 3 * weight * np.outer(u, u), rtol=1e-12, atol=1e-30), h
+
+
+def test_structural_stress_trace_counts_shell_neighbours():
+    """Trace = -(kT/V) * 20 * (ordered pairs within the shell), counted here directly."""
+    n, L = 300, (16.0, 16.0, 16.0)
+    a = gen.radii_bidisperse(n, 3)
+    x, v, w = gen.random_state(n, L, a, seed=5)
+    kT = 0.8
+    o = O.Oracle(_params(L, kT=kT), a, x, v, w)
+    S = o.structural_stress()
+    d = x[:, None, :] - x[None, :, :]
+    d -= np.asarray(L) * np.rint(d / np.asarray(L))
+    dist = np.linalg.norm(d, axis=2)
+    h = dist - (a[:, None] + a[None, :])
+    inshell = (h <= 0.05 * a[:, None]) & ~np.eye(n, dtype=bool)
+    assert inshell.sum() > 20
+    V = np.prod(L)
+    assert math.isclose(np.trace(S), -kT / V * 20.0 * inshell.sum(), rel_tol=1e-12)
+    assert np.allclose(S, S.T, rtol=0, atol=1e-15 * np.abs(S).max())
+
+
+# --------------------------------------------------------------------------
+# Rotational lubrication couplings and pairwise Brownian torques (Sec. II.B-II.C)
+# --------------------------------------------------------------------------
+ROT_ONLY_LUB = O.FREEZE_X | O.NO_PAIR_BROWN | O.NO_CONTACT | O.NO_ONEBODY | O.LUB_ROT
+
+
+def test_rot_scalars_equal_spheres_and_label_swap():
+    eta, xi = 0.1, 0.02
+    L = math.log(1 / xi)
+    a = 1.3
+    YB11, YB21, YC11, YC12, YC21, YC22 = O.lub_rot_scalars(eta, a, a, xi)
+    # equal spheres: Y^B = -pi eta a^2 ln(1/xi), Y^C_11 = 1.6 pi eta a^3 ln, Y^C_12 = 0.4 pi eta a^3 ln
+    assert math.isclose(YB11, -PI * eta * a * a * L, rel_tol=1e-14) and math.isclose(YB21, YB11, rel_tol=1e-14)
+    assert math.isclose(YC11, 1.6 * PI * eta * a ** 3 * L, rel_tol=1e-14) and math.isclose(YC22, YC11, rel_tol=1e-14)
+    assert math.isclose(YC12, 0.4 * PI * eta * a ** 3 * L, rel_tol=1e-14) and math.isclose(YC21, YC12, rel_tol=1e-14)
+    for ai, aj in ((1.0, 1.4), (0.6, 1.6)):
+        y = O.lub_rot_scalars(eta, ai, aj, xi)
+        z = O.lub_rot_scalars(eta, aj, ai, xi)
+        assert np.allclose([y[1], y[0], y[5], y[4], y[3], y[2]], z, rtol=1e-13, atol=0)
+        assert math.isclose(y[3], y[4], rel_tol=1e-13)   # Y^C_12 = Y^C_21
+
+
+def _pair_state(a, xi, direction, v, w, L=20.0):
+    a = np.array(a, float)
+    n = np.array(direction, float)
+    n /= np.linalg.norm(n)
+    sa = a.sum()
+    dist = sa * (1 + xi / 2)
+    c = np.array([L / 2] * 3)
+    return a, np.array([c + 0.5 * dist * n, c - 0.5 * dist * n]), n, dist, c
+
+
+def test_rigid_rotation_of_a_pair_is_force_free_to_order_h():
+    """A pair turning rigidly with the fluid (U_i = Omega x (x_i - c), Omega_i = Omega) is nearly
+    free of lubrication force and torque: with the printed scalars F_i = -Y^A h (Omega x n),
+    T_i = -Y^B_11 h T Omega, T_j = -Y^B_21 h T Omega, h the gap (n from j to i)."""
+    eta = 0.1
+    Om = np.array([0.4, -0.7, 0.25])
+    for a in ((1.0, 1.0), (1.0, 1.4), (0.6, 1.6)):
+        for xi in (2e-3, 0.02):
+            a_, x, n, dist, c = _pair_state(a, xi, (0.3, -0.5, 0.8), None, None)
+            v = np.cross(Om, x - c)
+            w = np.array([Om, Om])
+            o = O.Oracle(_params((20.0,) * 3, eta=eta, flags=ROT_ONLY_LUB), a_, x, v, w)
+            st = o.state()
+            h = dist - a_.sum()
+            XA, YA = O.lub_scalars(eta, a_[0], a_[1], xi)
+            YB11, YB21 = O.lub_rot_scalars(eta, a_[0], a_[1], xi)[:2]
+            TOm = Om - (Om @ n) * n
+            scale = YA * dist * np.linalg.norm(Om)
+            assert np.abs(st["F"][0] - (-YA * h * np.cross(Om, n))).max() < 1e-12 * scale, (a, xi)
+            assert np.abs(st["T"][0] - (-YB11 * h * TOm)).max() < 1e-12 * scale * dist
+            assert np.abs(st["T"][1] - (-YB21 * h * TOm)).max() < 1e-12 * scale * dist
+
+
+def _resistance(a, xi, direction, eta=0.1):
+    cols = []
+    for k in range(12):
+        V = np.zeros(12)
+        V[k] = 1.0
+        a_, x, n, dist, c = _pair_state(a, xi, direction, None, None)
+        o = O.Oracle(_params((20.0,) * 3, eta=eta, flags=ROT_ONLY_LUB), a_, x, V[:6].reshape(2, 3),
+                     V[6:].reshape(2, 3))
+        st = o.state()
+        cols.append(-np.concatenate([st["F"].ravel(), st["T"].ravel()]))
+    return np.array(cols).T, n
+
+
+def test_pair_resistance_symmetric_and_dissipative():
+    """The 12x12 matrix taking (U_i, U_j, Omega_i, Omega_j) to -(F_i, F_j, T_i, T_j) is symmetric
+    (reciprocal theorem; it fixes the signs of the Y^B couplings in force and torque) and
+    positive semi-definite (lubrication only dissipates)."""
+    for a in ((1.0, 1.0), (1.0, 1.4), (0.6, 1.6)):
+        R, _ = _resistance(a, 0.01, (0.3, -0.5, 0.8))
+        assert np.abs(R - R.T).max() <= 1e-13 * np.abs(R).max()
+        ev = np.linalg.eigvalsh(0.5 * (R + R.T))
+        assert ev.min() >= -1e-12 * ev.max()
+        assert np.abs(R[:6, 6:]).max() > 0.01 * np.abs(R).max()   # the couplings are really there
+
+
+def test_pair_brownian_torques_fluctuation_dissipation():
+    """Covariances of the pair's Brownian force and torques over many steps against 2kT/dt times
+    the corresponding blocks of the lubrication resistance: <F_i T_i^T> = b^2 R_{F_i Omega_i},
+    <T_i T_i^T> = b^2 R_{T_i Omega_i}, <T_j T_j^T> = b^2 R_{T_j Omega_j}."""
+    a, xi, kT, dt = (1.0, 1.4), 0.01, 0.5, 1e-4
+    R, n = _resistance(a, xi, (0.3, -0.5, 0.8))
+    a_, x, n, dist, c = _pair_state(a, xi, (0.3, -0.5, 0.8), None, None)
+    o = O.Oracle(_params((20.0,) * 3, kT=kT, dt=dt, seed=21,
+                         flags=O.FREEZE_X | O.NO_LUB | O.NO_CONTACT | O.NO_ONEBODY | O.LUB_ROT),
+                 a_, x, np.zeros((2, 3)), np.zeros((2, 3)))
+    K = 20000
+    Fs, Ti, Tj = np.zeros((K, 3)), np.zeros((K, 3)), np.zeros((K, 3))
+    for k in range(K):
+        o.step(1)
+        st = o.state()
+        Fs[k], Ti[k], Tj[k] = st["F"][0], st["T"][0], st["T"][1]
+    b2 = 2 * kT / dt
+    for A, B, target in ((Fs, Ti, R[0:3, 6:9]), (Ti, Ti, R[6:9, 6:9]), (Tj, Tj, R[9:12, 9:12])):
+        est = A.T @ B / K
+        # standard error of each entry of a mean of products: sqrt((<a^2><b^2> + <ab>^2) / K)
+        va, vb = (A * A).mean(axis=0), (B * B).mean(axis=0)
+        se = np.sqrt((np.outer(va, vb) + est * est) / K)
+        assert (np.abs(est - b2 * target) < 6 * se + 1e-12 * b2 * np.abs(target).max()).all(), (est / b2, target)
+    assert (np.abs(Ti.mean(axis=0)) < 6 * np.sqrt((Ti * Ti).mean(axis=0) / K)).all()
