@@ -214,6 +214,36 @@ int sim_stress_series(sim* s, int32_t replica, double* out, int64_t cap, int64_t
  * xi_cut / 2 < 0.05 a_max for some pair). */
 int sim_structural_stress(sim* s, int32_t replica, double out[9]);
 
+/* Analysis of the trajectories (Sec. III), computed on the device.
+ *
+ * sim_displacement: each particle's accumulated non-affine displacement
+ * (the drift of every step minus the imposed flow integrated along it; the
+ * plain unwrapped displacement when gammadot = 0) since sim_create,
+ * sim_set_state of its replica or sim_reset_displacement; id order, 3n
+ * doubles.  sim_msd: its mean square per axis, out[3] = <dx^2>, <dy^2>,
+ * <dz^2> over the replica's particles (the MSD of Sec. III.B).
+ * sim_reset_displacement: zero for every replica. */
+int sim_displacement(sim* s, int32_t replica, double* out_3n);
+int sim_msd(sim* s, int32_t replica, double out[3]);
+int sim_reset_displacement(sim* s);
+
+/* Histogram of the pair distances r = |r_ij| < r_max of the current
+ * configuration of one replica (each pair once; minimum image in the sheared
+ * box), nbins bins of width r_max / nbins, added to nothing: counts receives
+ * nbins integers.  Dividing by the ideal-gas count of each shell gives g(r)
+ * (Sec. III.A).  Rebuilds the neighbour lists first (which changes no
+ * trajectory).  SIM_EINVAL for nbins outside [1, 2^24] or r_max outside
+ * (0, 2 a_min (1 + xi_cut/2) + skin], the range every list covers. */
+int sim_rdf(sim* s, int32_t replica, double r_max, int32_t nbins, uint64_t* counts);
+
+/* Time autocorrelation of one recorded stress component (component
+ * SIM_STRESS_CONTACT, _LUB or _BROWN, entry alpha, beta in 0..2) over the
+ * per-step records since sim_reset_stress (at most the last 8192):
+ * out[k] = mean over t of S(t) S(t + k), k < nlag, for Green-Kubo integrals
+ * (Sec. III.C).  SIM_ERANGE if fewer than nlag records are available. */
+int sim_stress_acf(sim* s, int32_t replica, int32_t component, int32_t alpha, int32_t beta, int64_t nlag,
+                   double* out);
+
 /* Positions of one replica in id order, wrapped into [0, L), FP64, 3n doubles. */
 int sim_positions(sim* s, int32_t replica, double* out_3n);
 

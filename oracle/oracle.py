@@ -67,6 +67,8 @@ def lib():
         _lib.orc_get_norms.argtypes = [C.c_void_p, dp, dp]
         _lib.orc_get_stress.argtypes = [C.c_void_p, dp]
         _lib.orc_structural_stress.argtypes = [C.c_void_p, dp]
+        _lib.orc_get_disp.argtypes = [C.c_void_p, dp]
+        _lib.orc_rdf.argtypes = [C.c_void_p, C.c_double, C.c_int, C.POINTER(C.c_uint64)]
         _lib.orc_lub_rot_scalars.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, dp]
         _lib.orc_get_contacts.restype = C.c_int
         _lib.orc_get_contacts.argtypes = [C.c_void_p, C.c_int, up, dp, C.POINTER(C.c_int32)]
@@ -209,6 +211,18 @@ class Oracle:
         out = np.zeros(27)
         lib().orc_get_stress(self._h, _d(out))
         return out.reshape(3, 3, 3)
+
+    def displacement(self):
+        """(n, 3) accumulated non-affine displacement (drift minus the imposed flow)."""
+        out = np.zeros((self.n, 3))
+        lib().orc_get_disp(self._h, _d(out))
+        return out
+
+    def rdf(self, r_max, nbins):
+        """Pair-distance histogram (each pair once, r < r_max)."""
+        out = np.zeros(nbins, np.uint64)
+        lib().orc_rdf(self._h, float(r_max), int(nbins), out.ctypes.data_as(C.POINTER(C.c_uint64)))
+        return out
 
     def structural_stress(self):
         """(3, 3) structural Brownian stress of the current configuration, Sec. II.D."""

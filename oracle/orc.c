@@ -93,6 +93,7 @@ typedef struct {
     orc_contact *c; int nc, capc; /* contact history, sorted by (i, j)       */
     uint32_t *pairs; int npairs, cappairs; /* interaction set of last eval   */
     double stress[27];            /* contact, lubrication, Brownian 3x3     */
+    double *disp;                 /* 3n: accumulated non-affine displacement */
 } orc_state;
 
 /* ------------------------------------------------------------------ */
@@ -574,6 +575,15 @@ static void step(orc_state *S)
     const double Lx = p->L[0], Ly = p->L[1], Lz = p->L[2];
     kick(S);
     if (!(p->flags & ORC_FREEZE_X)) {
+        /* non-affine displacement of the drift: dt v minus the imposed flow integrated along
+           the straight path, gammadot (y(t) - Ly/2) e_x with y(t) = y + v_y t */
+        for (int i = 0; i < S->n; ++i) {
+            const double *x = &S->x[3 * i], *v = &S->v[3 * i];
+            double ux = p->gammadot * (x[1] - 0.5 * Ly) + 0.5 * p->gammadot * p->dt * v[1];
+            S->disp[3 * i] += p->dt * (v[0] - ux);
+            S->disp[3 * i + 1] += p->dt * v[1];
+            S->disp[3 * i + 2] += p->dt * v[2];
+        }
         for (int q = 0; q < 3 * S->n; ++q) S->x[q] += p->dt * S->v[q];
     }
     S->s_le = S->s_le + p->gammadot * Ly * p->dt;
@@ -617,6 +627,7 @@ orc_state *orc_new(const orc_params *p, int n, const double *a, const double *x,
     S->T = (double *)calloc(3 * (size_t)n, sizeof(double));
     S->Fabs = (double *)calloc((size_t)n, sizeof(double));
     S->Tabs = (double *)calloc((size_t)n, sizeof(double));
+    S->disp = (double *)calloc(3 * (size_t)n, sizeof(double));
     for (int i = 0; i < n; ++i) {
         S->a[i] = a[i];
         S->m[i] = (4.0 / 3.0) * ORC_PI * p->rho * a[i] * a[i] * a[i];   /* Sec. II */
@@ -647,7 +658,7 @@ void orc_free(orc_state *S)
 {
     if (!S) return;
     free(S->a); free(S->m); free(S->I); free(S->x); free(S->v); free(S->w);
-    free(S->F); free(S->T); free(S->Fabs); free(S->Tabs); free(S->c); free(S->pairs);
+    free(S->F); free(S->T); free(S->Fabs); free(S->Tabs); free(S->c); free(S->pairs); free(S->disp);
     free(S);
 }
 
@@ -683,6 +694,25 @@ void orc_get_norms(const orc_state *S, double *Fabs, double *Tabs)
 }
 
 void orc_get_stress(const orc_state *S, double out[27]) { memcpy(out, S->stress, sizeof(S->stress)); }
+
+void orc_get_disp(const orc_state *S, double *out_3n) { memcpy(out_3n, S->disp, sizeof(double) * 3 * (size_t)S->n); }
+
+/* Histogram of pair distances r < r_max (each pair once, minimum image in the sheared
+   box), bins of width r_max / nbins; brute force over all pairs. */
+void orc_rdf(const orc_state *S, double r_max, int nbins, uint64_t *counts)
+{
+    for (int k = 0; k < nbins; ++k) counts[k] = 0;
+    for (int i = 0; i < S->n; ++i)
+        for (int j = i + 1; j < S->n; ++j) {
+            double r[3];
+            min_image(&S->p, S->s_le, &S->x[3 * i], &S->x[3 * j], r);
+            double d = sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+            if (!(d < r_max)) continue;
+            int k = (int)(d / r_max * (double)nbins);
+            if (k >= nbins) k = nbins - 1;
+            counts[k] += 1;
+        }
+}
 
 /* Structural Brownian stress of the current configuration, Sec. II.D:
    -(kT/V) sum_i (a_i/Delta_i) sum_{j: h_ij <= Delta_i} n_ij (x) n_ij with

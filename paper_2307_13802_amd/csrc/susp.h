@@ -130,7 +130,7 @@ struct Bufs {
     uint8_t* ct_sl;       // sliding flag
     uint32_t* ct_n;
     // staging copies for the reorder
-    double4* alt4[7];
+    double4* alt4[8];
     uint32_t* alt_id;
 
     // stress: per pair-kernel block partial sums (two parities), ring of per-step values
@@ -144,6 +144,8 @@ struct Bufs {
     int ppb;              // particles per pair-kernel block (for the stress partials)
 
     double* dacc;         // per particle: bound on its non-affine displacement since the last build
+    double4* disp;        // per particle: accumulated non-affine displacement (x, y, z) since the
+                          // creation, the last state upload or sim_reset_displacement
     float* dpart;         // [parity][kTile-block]: largest dacc of the block after that step's drift
     uint32_t* blk_rep;    // replica of each kTile-block of particles
     RepParams* reps;
@@ -174,6 +176,15 @@ void launch_finalize(const Bufs& b, hipStream_t st, int q);
 // history from the current lists; 0xFFFFFFFE = every replica takes the
 // host-written compact table; else that replica does.
 void launch_rebuild(const Bufs& b, hipStream_t st, int q, int in_step, uint32_t ct_input_rep);
+// mean-square displacement sums of one replica: nblk = n_pad / 256 blocks, 3 doubles each
+void launch_msd(const Bufs& b, hipStream_t st, uint32_t rep, uint32_t nblk, double* part);
+// pair-distance histogram of one replica at parity p (each pair once, r < r_max)
+void launch_rdf(const Bufs& b, hipStream_t st, int p, uint32_t rep, uint32_t nblk, double r_max, uint32_t nbins,
+                unsigned long long* counts);
+// autocorrelation of one recorded stress component of one replica over the records
+// [first, first + count) of the ring: out[lag] = mean_t s(t) s(t + lag), lag < nlag
+void launch_acf(const Bufs& b, hipStream_t st, uint32_t rep, int comp, uint32_t first, uint32_t count,
+                uint32_t nlag, double* out);
 // structural Brownian stress sums of one replica at parity p: nblk = n_pad / 256
 // blocks, 9 doubles each into part
 void launch_struct(const Bufs& b, hipStream_t st, int p, uint32_t rep, uint32_t nblk, double* part);

@@ -342,6 +342,9 @@ __device__ __forceinline__ void integrate_particle(const Bufs& b, const RepParam
         const double ex = P.dt * (vdx - ux), ey = P.dt * vdy, ez = P.dt * vdz;
         disp = sqrt(ex * ex + ey * ey + ez * ez) * (1.0 + 1e-6) + 1e-30;
         b.pos[i] = x;
+        double4 da = b.disp[i];
+        da.x += ex; da.y += ey; da.z += ez;
+        b.disp[i] = da;
     }
     b.vh[i] = v;
     b.wh[i] = w;
@@ -520,7 +523,7 @@ __global__ __launch_bounds__(256) void k_rb_gather(Bufs b, uint32_t ct_input_rep
     const uint32_t npad = b.npad;
     if (q - P.p_begin >= P.n) {
         b.alt_id[q] = kNoId;
-        for (int a = 0; a < 7; ++a) b.alt4[a][q] = make_double4(0.0, 0.0, 0.0, 0.0);
+        for (int a = 0; a < 8; ++a) b.alt4[a][q] = make_double4(0.0, 0.0, 0.0, 0.0);
         b.ct_n[q] = 0u;
         return;
     }
@@ -531,6 +534,7 @@ __global__ __launch_bounds__(256) void k_rb_gather(Bufs b, uint32_t ct_input_rep
     b.alt4[2][q] = b.wh[s];
     b.alt4[3][q] = b.vf[s];
     b.alt4[4][q] = b.wf[s];
+    b.alt4[7][q] = b.disp[s];
     if (b.mixed) {
         const float4 f = ((const float4*)b.F)[s], t = ((const float4*)b.T)[s];
         b.alt4[5][q] = make_double4(f.x, f.y, f.z, 0.0);
@@ -578,6 +582,7 @@ __global__ __launch_bounds__(256) void k_rb_copyback(Bufs b) {
     b.wh[q] = wh;
     b.vf[q] = b.alt4[3][q];
     b.wf[q] = b.alt4[4][q];
+    b.disp[q] = b.alt4[7][q];
     if (b.mixed) {
         const double4 f = b.alt4[5][q], t = b.alt4[6][q];
         ((float4*)b.F)[q] = make_float4((float)f.x, (float)f.y, (float)f.z, 0.0f);
@@ -1882,6 +1887,92 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
         }
         integrate_particle<MIX>(b, P, D, 1 - q, i, pi, vf, wf, Ft, Tt, dblk, expire);
     }
+}
+
+// Mean-square non-affine displacement sums of one replica (the MSD of
+// Sec. III.B): part[block * 3 + d] = fixed-order block sum of disp_d^2.
+__global__ __launch_bounds__(256) void k_msd(Bufs b, uint32_t rep, double* part) {
+    const RepParams& P = b.reps[rep];
+    const uint32_t i = P.p_begin + blockIdx.x * 256 + threadIdx.x;
+    double acc[3] = {0.0, 0.0, 0.0};
+    if (i - P.p_begin < P.n) {
+        const double4 d = b.disp[i];
+        acc[0] = d.x * d.x; acc[1] = d.y * d.y; acc[2] = d.z * d.z;
+    }
+    __shared__ double rows[16][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double v = row_sum_f64(acc[c]);
+        if ((threadIdx.x & 15) == 15) rows[threadIdx.x >> 4][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double t = 0.0;
+        for (int k = 0; k < 16; ++k) t += rows[k][threadIdx.x];
+        part[blockIdx.x * 3 + threadIdx.x] = t;
+    }
+}
+
+void launch_msd(const Bufs& b, hipStream_t st, uint32_t rep, uint32_t nblk, double* part) {
+    hipLaunchKernelGGL(k_msd, dim3(nblk), dim3(256), 0, st, b, rep, part);
+}
+
+// Histogram of pair distances r < r_max of one replica at parity p (each pair
+// once, from its lower-id side; the list holds every pair within its range),
+// nbins bins of width r_max / nbins; integer counts, so the order of the
+// atomic increments does not matter.
+__global__ __launch_bounds__(256) void k_rdf(Bufs b, uint32_t rep, int p, double r_max, uint32_t nbins,
+                                             unsigned long long* counts) {
+    const RepParams& P = b.reps[rep];
+    const uint32_t i = P.p_begin + blockIdx.x * 256 + threadIdx.x;
+    if (i - P.p_begin >= P.n) return;
+    const double4 pi = b.pos[i];
+    const uint32_t idi = b.id[i];
+    const double s_le = b.dyn[rep].s_slot[p];
+    const uint32_t cnt = b.ncnt[i];
+    for (uint32_t e = 0; e < cnt; ++e) {
+        const uint32_t j = b.nbr[e * b.npad + i];
+        if (!(idi < b.id[j])) continue;
+        double dx, dy, dz;
+        min_image(P, s_le, pi, b.pos[j], dx, dy, dz);
+        const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+        if (!(r < r_max)) continue;
+        uint32_t k = (uint32_t)(r / r_max * (double)nbins);
+        if (k >= nbins) k = nbins - 1;
+        atomicAdd(&counts[k], 1ull);
+    }
+}
+
+void launch_rdf(const Bufs& b, hipStream_t st, int p, uint32_t rep, uint32_t nblk, double r_max, uint32_t nbins,
+                unsigned long long* counts) {
+    hipLaunchKernelGGL(k_rdf, dim3(nblk), dim3(256), 0, st, b, rep, p, r_max, nbins, counts);
+}
+
+// Time autocorrelation of recorded stress component comp (0..26) of one
+// replica: one block per lag, a fixed-order sum over the record pairs.
+__global__ __launch_bounds__(256) void k_acf(Bufs b, uint32_t rep, int comp, uint32_t first, uint32_t count,
+                                             double* out) {
+    const uint32_t lag = blockIdx.x;
+    const double* ring = b.ring + (size_t)rep * kRing * 27;
+    double acc = 0.0;
+    for (uint32_t t = threadIdx.x; t + lag < count; t += blockDim.x) {
+        const uint32_t s0 = (first + t) % kRing, s1 = (first + t + lag) % kRing;
+        acc += ring[(size_t)s0 * 27 + comp] * ring[(size_t)s1 * 27 + comp];
+    }
+    __shared__ double rows[16];
+    acc = row_sum_f64(acc);
+    if ((threadIdx.x & 15) == 15) rows[threadIdx.x >> 4] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 4); ++k) t += rows[k];
+        out[lag] = lag < count ? t / (double)(count - lag) : 0.0;
+    }
+}
+
+void launch_acf(const Bufs& b, hipStream_t st, uint32_t rep, int comp, uint32_t first, uint32_t count,
+                uint32_t nlag, double* out) {
+    hipLaunchKernelGGL(k_acf, dim3(nlag), dim3(256), 0, st, b, rep, comp, first, count, out);
 }
 
 // Structural Brownian stress sum of one replica (Sec. II.D) at parity p:

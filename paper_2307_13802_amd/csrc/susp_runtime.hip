@@ -101,6 +101,17 @@ struct sim {
         return p;
     }
     template <class T> T* alloc(size_t count) { return (T*)dalloc(count * sizeof(T)); }
+    // frees one allocation made by dalloc (after the stream's work on it)
+    void release(void* p) {
+        for (size_t k = 0; k < allocs.size(); ++k)
+            if (allocs[k].first == p) {
+                (void)hipStreamSynchronize(st);
+                if (ffn) ffn(p, actx);
+                else (void)hipFree(p);
+                allocs.erase(allocs.begin() + (long)k);
+                return;
+            }
+    }
 
     ~sim() {
         for (int k = 0; k < 2; ++k) {
@@ -327,6 +338,8 @@ void upload_state(sim* s, int r, const double* x, const double* v, const double*
             up(s->b.ct_s + ((size_t)(kCtCap + c) * 3 + d) * npad + p0, cvs.data() + ((size_t)c * 3 + d) * np,
                np * sizeof(double));
     }
+    // its displacement record starts again
+    HIPCHK(hipMemsetAsync(s->b.disp + p0, 0, np * sizeof(double4), st));
     // list of this replica becomes invalid; its history now comes from the table
     HIPCHK(hipMemsetAsync(s->b.ncnt + p0, 0, np * sizeof(uint32_t), st));
     HIPCHK(hipMemsetAsync(s->b.cmask + p0, 0, np * sizeof(uint64_t), st));
@@ -560,7 +573,8 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         b.ct_s = s->alloc<double>(np * 2 * kCtCap * 3);
         b.ct_sl = s->alloc<uint8_t>(np * kCtCap);
         b.ct_n = s->alloc<uint32_t>(np * 2);
-        for (int a = 0; a < 7; ++a) b.alt4[a] = s->alloc<double4>(np);
+        for (int a = 0; a < 8; ++a) b.alt4[a] = s->alloc<double4>(np);
+        b.disp = s->alloc<double4>(np);
         b.alt_id = s->alloc<uint32_t>(np);
         b.nblk_max = (uint32_t)(np / 128 * 8);               // 128-thread pair blocks, up to 8 lanes
         b.partial = s->alloc<double>((size_t)2 * b.nblk_max * 27);
@@ -883,6 +897,108 @@ int sim_get_state(sim* s, int32_t r, double* x, double* v, double* w, double* F,
             if (le_offset) *le_offset = d[0].s_slot[s->par];
             if (step) *step = d[0].step_slot[s->par];
         }
+        return SIM_OK;
+    } catch (const HipError& e) {
+        return hip_fail(s, e);
+    }
+}
+
+int sim_reset_displacement(sim* s) {
+    if (!s) return fail(nullptr, SIM_EINVAL, "null handle");
+    try {
+        HIPCHK(hipMemsetAsync(s->b.disp, 0, sizeof(double4) * s->b.npad, s->st));
+        HIPCHK(hipStreamSynchronize(s->st));
+        return SIM_OK;
+    } catch (const HipError& e) {
+        return hip_fail(s, e);
+    }
+}
+
+int sim_displacement(sim* s, int32_t r, double* out_3n) {
+    if (int rc = check_rep(s, r)) return rc;
+    if (!out_3n) return fail(s, SIM_EINVAL, "null output");
+    try {
+        const RepParams& P = s->P[r];
+        auto id = d2h(s, s->b.id, P.p_begin, P.n_pad);
+        auto d = d2h(s, s->b.disp, P.p_begin, P.n_pad);
+        for (size_t q = 0; q < P.n_pad; ++q) {
+            if (id[q] == kNoId) continue;
+            out_3n[3 * id[q]] = d[q].x;
+            out_3n[3 * id[q] + 1] = d[q].y;
+            out_3n[3 * id[q] + 2] = d[q].z;
+        }
+        return SIM_OK;
+    } catch (const HipError& e) {
+        return hip_fail(s, e);
+    }
+}
+
+int sim_msd(sim* s, int32_t r, double out[3]) {
+    if (int rc = check_rep(s, r)) return rc;
+    if (!out) return fail(s, SIM_EINVAL, "null output");
+    try {
+        const RepParams& P = s->P[r];
+        const uint32_t nblk = P.n_pad / 256;
+        if (s->struct_cap < nblk) {
+            s->struct_part = s->alloc<double>((size_t)nblk * 9);
+            s->struct_cap = nblk;
+        }
+        launch_msd(s->b, s->st, (uint32_t)r, nblk, s->struct_part);
+        HIPCHK(hipGetLastError());
+        auto h = d2h(s, s->struct_part, 0, (size_t)nblk * 3);
+        double acc[3] = {0, 0, 0};
+        for (uint32_t k = 0; k < nblk; ++k)
+            for (int c = 0; c < 3; ++c) acc[c] += h[(size_t)k * 3 + c];
+        for (int c = 0; c < 3; ++c) out[c] = acc[c] / (double)P.n;
+        return SIM_OK;
+    } catch (const HipError& e) {
+        return hip_fail(s, e);
+    }
+}
+
+int sim_rdf(sim* s, int32_t r, double r_max, int32_t nbins, uint64_t* counts) {
+    if (int rc = check_rep(s, r)) return rc;
+    if (!counts || nbins <= 0 || nbins > (1 << 24)) return fail(s, SIM_EINVAL, "need counts and 0 < nbins <= 2^24");
+    const RepParams& P = s->P[r];
+    const double amin = min_radius(s->radii[r].data(), P.n);
+    const double rl_min = 2.0 * amin * P.c1 + P.skin;  // every list holds all pairs within this range
+    if (!(r_max > 0.0) || r_max > rl_min)
+        return fail(s, SIM_EINVAL, fmt("r_max must be in (0, %g], the smallest list range", rl_min));
+    try {
+        launch_rebuild(s->b, s->st, 1 - s->par, 0, 0xFFFFFFFFu);
+        s->since_build = 0;
+        s->plan = s->plan_hint;
+        unsigned long long* dc = s->alloc<unsigned long long>((size_t)nbins);  // zeroed
+        launch_rdf(s->b, s->st, s->par, (uint32_t)r, P.n_pad / 256, r_max, (uint32_t)nbins, dc);
+        HIPCHK(hipGetLastError());
+        auto h = d2h(s, dc, 0, (size_t)nbins);
+        for (int k = 0; k < nbins; ++k) counts[k] = h[k];
+        s->release(dc);
+        return check_health(s);
+    } catch (const HipError& e) {
+        return hip_fail(s, e);
+    }
+}
+
+int sim_stress_acf(sim* s, int32_t r, int32_t component, int32_t alpha, int32_t beta, int64_t nlag, double* out) {
+    if (int rc = check_rep(s, r)) return rc;
+    if (!out || component < 0 || component > SIM_STRESS_BROWN || alpha < 0 || alpha > 2 || beta < 0 || beta > 2 ||
+        nlag <= 0)
+        return fail(s, SIM_EINVAL, "bad component, index, lag count or output");
+    try {
+        auto d = d2h(s, s->b.dyn, (size_t)r, 1);
+        const uint32_t head = d[0].nrec;  // records 1..head; record k sits in slot (k - 1) % kRing
+        uint32_t first = d[0].rec_base;
+        if (head - first > (uint32_t)kRing) first = head - kRing;
+        const uint32_t count = head - first;
+        if ((int64_t)count < nlag) return fail(s, SIM_ERANGE, fmt("%u records since the reset, %lld lags asked", count, (long long)nlag));
+        double* dout = s->alloc<double>((size_t)nlag);
+        launch_acf(s->b, s->st, (uint32_t)r, component * 9 + alpha * 3 + beta, first % kRing, count,
+                   (uint32_t)nlag, dout);
+        HIPCHK(hipGetLastError());
+        auto h = d2h(s, dout, 0, (size_t)nlag);
+        std::copy(h.begin(), h.end(), out);
+        s->release(dout);
         return SIM_OK;
     } catch (const HipError& e) {
         return hip_fail(s, e);

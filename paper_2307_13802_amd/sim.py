@@ -86,6 +86,11 @@ def lib():
         "sim_stress_series": [vp, C.c_int32, dp, C.c_int64, lp],
         "sim_positions": [vp, C.c_int32, dp],
         "sim_structural_stress": [vp, C.c_int32, dp],
+        "sim_displacement": [vp, C.c_int32, dp],
+        "sim_msd": [vp, C.c_int32, dp],
+        "sim_reset_displacement": [vp],
+        "sim_rdf": [vp, C.c_int32, C.c_double, C.c_int32, C.POINTER(C.c_uint64)],
+        "sim_stress_acf": [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int64, dp],
         "sim_get_state": [vp, C.c_int32, dp, dp, dp, dp, dp, dp, C.POINTER(C.c_uint64)],
         "sim_set_state": [vp, C.c_int32, dp, dp, dp, dp, dp, C.c_double, C.c_uint64, up, dp, C.c_int64],
         "sim_forces": [vp, C.c_int32, dp, dp],
@@ -286,6 +291,34 @@ class Sim:
         out = np.zeros(9)
         _check(lib().sim_structural_stress(self.h, replica, _dp(out)), self.h)
         return out.reshape(3, 3)
+
+    def displacement(self, replica=0):
+        """Accumulated non-affine displacement per particle, (n, 3), id order."""
+        out = np.zeros((self.n[replica], 3))
+        _check(lib().sim_displacement(self.h, replica, _dp(out)), self.h)
+        return out
+
+    def msd(self, replica=0):
+        """Mean square of the accumulated displacement per axis, (3,)."""
+        out = np.zeros(3)
+        _check(lib().sim_msd(self.h, replica, _dp(out)), self.h)
+        return out
+
+    def reset_displacement(self):
+        _check(lib().sim_reset_displacement(self.h), self.h)
+
+    def rdf(self, r_max, nbins, replica=0):
+        """Pair-distance histogram of the current configuration (counts per bin)."""
+        out = np.zeros(nbins, np.uint64)
+        _check(lib().sim_rdf(self.h, replica, float(r_max), int(nbins), out.ctypes.data_as(C.POINTER(C.c_uint64))),
+               self.h)
+        return out
+
+    def stress_acf(self, component, alpha, beta, nlag, replica=0):
+        """Time autocorrelation of a recorded stress entry over the records since the reset."""
+        out = np.zeros(nlag)
+        _check(lib().sim_stress_acf(self.h, replica, component, alpha, beta, int(nlag), _dp(out)), self.h)
+        return out
 
     def positions(self, replica=0):
         out = np.zeros((self.n[replica], 3))

@@ -368,3 +368,73 @@ def test_rotational_couplings_match_oracle(P):
         _say(f"  after {2 * (k + 1)} steps: |dx| {dx:.2e} |dw|/|w| {dw:.2e}")
         assert dx < 1e-11 and dw < 1e-9
         assert np.array_equal(sim.contacts()[0], orc.contacts()[0])
+
+
+def test_displacement_msd_rdf_match_oracle(P):
+    """Accumulated non-affine displacement and its mean square, and the pair-distance histogram of
+    the sheared state, against the oracle (histogram bit-exact on the GPU's own state)."""
+    st = _state(n=600, phi=0.5, seed=15)
+    sim = P.Sim(_cfg(P, st), st["radii"], st["x"], st["v"], st["w"])
+    orc = O.Oracle(O.Params(L=st["L"], **st["params"]), st["radii"], st["x"], st["v"], st["w"])
+    _say("case: displacement, MSD and g(r) after 40 sheared steps, N=600")
+    sim.step(40)
+    orc.step(40)
+    dg, do = sim.displacement(), orc.displacement()
+    err = np.abs(dg - do).max() / np.abs(do).max()
+    _say(f"  displacement rel err {err:.2e}")
+    assert err < 1e-10
+    assert np.allclose(sim.msd(), (do ** 2).mean(axis=0), rtol=1e-9, atol=0)
+    gs = sim.get_state()
+    ref = O.Oracle(O.Params(L=st["L"], **st["params"]), st["radii"], gs["x"], gs["v"], gs["w"], s_le=gs["s_le"])
+    r_max = 2.0 * 1.0 * 1.025 + 0.2
+    hg, ho = sim.rdf(r_max, 50), ref.rdf(r_max, 50)
+    _say(f"  g(r) pairs {hg.sum()} / {ho.sum()}")
+    assert np.array_equal(hg, ho)
+    sim.reset_displacement()
+    assert np.abs(sim.displacement()).max() == 0.0
+    with pytest.raises(P.SimError):
+        sim.rdf(10.0, 50)   # beyond the range every list covers
+
+
+def test_stress_acf_matches_series(P):
+    st = _state(n=500, phi=0.5, seed=16)
+    sim = P.Sim(_cfg(P, st), st["radii"], st["x"], st["v"], st["w"])
+    sim.step(10)
+    sim.reset_stress()
+    sim.stress_series()
+    sim.step(300)
+    _say("case: stress autocorrelation over 300 records")
+    series = sim.stress_series()   # reading the series does not consume the records the ACF uses
+    assert len(series) == 300
+    for comp in (P.STRESS_BROWN, P.STRESS_LUB):
+        acf = sim.stress_acf(comp, 0, 1, 40)
+        s = series[:, comp, 0, 1]
+        ref = np.array([np.mean(s[: len(s) - k] * s[k:]) for k in range(40)])
+        assert np.allclose(acf, ref, rtol=1e-12, atol=1e-30 * abs(ref[0]))
+
+
+def test_dilute_msd_closed_form_gpu(P):
+    """phi = 0.001: the one-body drag and noise alone give the Ornstein-Uhlenbeck MSD
+    2 kT m / gamma^2 (gamma t / m - 1 + exp(-gamma t / m)) per axis (Sec. III.B)."""
+    n, a, rho, eta, kT = 3000, 1.0, 0.1, 0.1, 1.0
+    radii = np.full(n, a)
+    Lb = (n * 4.0 / 3.0 * math.pi / 0.001) ** (1.0 / 3.0)
+    rng = np.random.default_rng(17)
+    x = gen.relaxed_positions(radii, Lb, 17)   # no overlaps
+    m = 4.0 / 3.0 * math.pi * rho * a ** 3
+    v = rng.standard_normal((n, 3)) * math.sqrt(kT / m)
+    w = rng.standard_normal((n, 3)) * math.sqrt(kT / (0.4 * m * a * a))
+    cfg = P.Config(box=(Lb, Lb, Lb), rho=rho, eta=eta, kT=kT, gammadot=0.0, dt=1e-4, seed=5)
+    sim = P.Sim(cfg, radii, x, v, w)
+    gamma = 6 * math.pi * eta * a
+    _say("case: dilute MSD, N=3000 phi=0.001")
+    done = 0
+    for steps in (500, 1500, 4000):
+        sim.step(steps - done)
+        done = steps
+        t = steps * 1e-4
+        expect = 2 * kT * m / gamma ** 2 * (gamma * t / m - 1 + math.exp(-gamma * t / m))
+        msd = sim.msd()
+        _say(f"  t={t:.2f}: MSD per axis {msd} expected {expect:.4e}")
+        # each axis is a mean over 3000 independent particles: relative s.e. ~ sqrt(2/3000)
+        assert np.all(np.abs(msd / expect - 1) < 6 * math.sqrt(2.0 / n))

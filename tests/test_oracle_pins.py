@@ -743,3 +743,55 @@ def test_pair_brownian_torques_fluctuation_dissipation():
         se = np.sqrt((np.outer(va, vb) + est * est) / K)
         assert (np.abs(est - b2 * target) < 6 * se + 1e-12 * b2 * np.abs(target).max()).all(), (est / b2, target)
     assert (np.abs(Ti.mean(axis=0)) < 6 * np.sqrt((Ti * Ti).mean(axis=0) / K)).all()
+
+
+# --------------------------------------------------------------------------
+# Trajectory analysis: non-affine displacement, pair-distance histogram
+# --------------------------------------------------------------------------
+def test_displacement_of_a_free_particle_in_shear():
+    """A force-free particle starting with the local flow velocity and moving across y drifts
+    away from the flow by exactly -gammadot v_y t^2 / 2 along x (wrapping through the sheared
+    boundary changes nothing), and by v_y t along y."""
+    L, gd, vy, dt = 12.0, 0.8, 3.0, 1e-3
+    y0 = 10.5
+    x = np.array([[5.0, y0, 6.0], [1.0, 1.0, 1.0]])
+    a = np.array([1.0, 1.0])
+    v = np.array([[gd * (y0 - L / 2), vy, 0.0], [gd * (1.0 - L / 2), 0.0, 0.0]])
+    o = O.Oracle(_params((L, L, L), gammadot=gd, dt=dt, flags=O.NO_ONEBODY | O.NO_PAIR_BROWN), a, x, v, np.zeros((2, 3)))
+    nsteps = 1000                     # crosses y = L after ~500 steps
+    o.step(nsteps)
+    t = nsteps * dt
+    d = o.displacement()
+    assert o.state()["x"][0, 1] < y0   # it went through the boundary
+    assert math.isclose(d[0, 0], -0.5 * gd * vy * t * t, rel_tol=1e-10)
+    assert math.isclose(d[0, 1], vy * t, rel_tol=1e-12) and d[0, 2] == 0.0
+    assert np.abs(d[1]).max() < 1e-15   # the second sphere rides with the flow
+
+
+def test_displacement_matches_positions_modulo_box():
+    """Without shear the accumulated displacement is the unwrapped motion: positions change by
+    it modulo the box."""
+    n, L = 200, (14.0, 14.0, 14.0)
+    a = gen.radii_bidisperse(n, 8)
+    x, v, w = gen.random_state(n, L, a, seed=9, kT=4.0)
+    o = O.Oracle(_params(L, kT=4.0, dt=2e-4, seed=3, flags=O.NO_CONTACT), a, x, v, w)
+    o.step(300)
+    d = o.displacement()
+    jump = (o.state()["x"] - x - d) / np.asarray(L)
+    assert np.abs(jump - np.rint(jump)).max() < 1e-10
+    assert np.abs(d).max() > 1e-3
+
+
+def test_rdf_histogram_brute_force():
+    n, L = 300, (13.0, 13.0, 13.0)
+    a = gen.radii_bidisperse(n, 5)
+    x, v, w = gen.random_state(n, L, a, seed=6)
+    o = O.Oracle(_params(L), a, x, v, w)
+    r_max, nb = 3.0, 30
+    h = o.rdf(r_max, nb)
+    d = x[:, None, :] - x[None, :, :]
+    d -= np.asarray(L) * np.rint(d / np.asarray(L))
+    r = np.linalg.norm(d, axis=2)[np.triu_indices(n, 1)]
+    ref, _ = np.histogram(r[r < r_max], bins=nb, range=(0.0, r_max))
+    assert h.sum() == ref.sum() > 100
+    assert np.abs(h.astype(np.int64) - ref).sum() <= 2   # a distance on a bin edge may round either way
