@@ -438,3 +438,39 @@ def test_dilute_msd_closed_form_gpu(P):
         _say(f"  t={t:.2f}: MSD per axis {msd} expected {expect:.4e}")
         # each axis is a mean over 3000 independent particles: relative s.e. ~ sqrt(2/3000)
         assert np.all(np.abs(msd / expect - 1) < 6 * math.sqrt(2.0 / n))
+
+
+@pytest.mark.parametrize("name, n, phi, radii_kind, mu, prec", [
+    ("bidisperse N=1000000 phi=0.56", 1_000_000, 0.56, "bidisperse", 0.5, "mixed"),
+    ("bidisperse N=1000000 phi=0.56 FP64", 1_000_000, 0.56, "bidisperse", 0.5, "fp64"),
+    ("log-normal N=4000000 phi=0.58 mu=1", 4_000_000, 0.58, "lognormal", 1.0, "mixed"),
+])
+def test_full_size_sampled(P, name, n, phi, radii_kind, mu, prec):
+    """The benchmark's launch configuration (half-pair kernel, one cull lane) at the full sizes
+    of the 1M- and 4M-sphere workloads: forces and torques of sampled particles against the
+    oracle's one-particle evaluation.  Positions are uniform random (overlaps allowed, the
+    overlap limit raised), so no packing is needed; only the force law is compared."""
+    rng = np.random.default_rng(n + 1)
+    a = gen.radii_bidisperse(n, 3) if radii_kind == "bidisperse" else gen.radii_lognormal(n, 3)
+    L = gen.box_length(a, phi)
+    x = rng.random((n, 3)) * L
+    gd, kT = gen.pe_to_rates(10.0)
+    m = 4.0 / 3.0 * math.pi * 0.1 * a ** 3
+    v = rng.standard_normal((n, 3)) * np.sqrt(kT / m)[:, None]
+    v[:, 0] += gd * (x[:, 1] - 0.5 * L)
+    w = rng.standard_normal((n, 3)) * np.sqrt(kT / (0.4 * m * a * a))[:, None]
+    prm = dict(rho=0.1, eta=0.1, kn=1e4, kt=2e4 / 7, mu=mu, kT=kT, gammadot=gd, dt=1e-4, xi_cut=0.05,
+               xi_min=1e-3, seed=7)
+    _say(f"case: {name}, sampled forces at creation")
+    cfg = P.Config(box=(L, L, L), precision=P.MIXED if prec == "mixed" else P.FP64, pair_kernel=3, lanes=1,
+                   max_overlap=10.0, nlist_cap=64, **prm)
+    sim = P.Sim(cfg, a, x, v, w)
+    Fg, Tg = sim.forces()
+    zero = np.zeros((n, 3))
+    one = O.Oracle(O.Params(L=(L, L, L), **prm), a, x, v, w, F=zero, T=zero)
+    worst = 0.0
+    for i in rng.choice(n, 24, replace=False):
+        F, T, fa, ta = one.particle_force(int(i))
+        worst = max(worst, np.linalg.norm(Fg[i] - F) / fa, np.linalg.norm(Tg[i] - T) / max(ta, 1e-300))
+    _say(f"  worst sampled error {worst:.2e}")
+    assert worst <= (TOL_MIX if prec == "mixed" else TOL_F64)
