@@ -8,7 +8,6 @@
 namespace susp {
 
 constexpr int kTile = 256;               // replicas are padded to multiples of this many particles
-constexpr int kSpread = 16;              // slots per replica for block-level atomic maxima
 constexpr uint32_t kNoId = 0xFFFFFFFFu;  // id of a padding slot
 constexpr double kPi = 3.14159265358979323846;
 
@@ -55,8 +54,6 @@ struct RepDyn {
     double s_slot[2];         // Lees-Edwards offset of the evaluation with that parity
     uint64_t step_slot[2];    // step counter of that evaluation
     double t_slot[2];         // time since the last build
-    uint32_t maxov_bits[2][kSpread];    // float bits: largest overlap of that evaluation, spread
-                                        // over slots to keep atomic contention low
     uint32_t eval_id[2];      // serial number of the evaluation whose partials have that parity
     uint32_t rec[2];          // its series record number (1-based), 0 = not recorded
     uint32_t done_id[2][27];  // per stress component: evaluation already reduced
@@ -135,6 +132,7 @@ struct Bufs {
 
     // stress: per pair-kernel block partial sums (two parities), ring of per-step values
     double* partial;      // [parity][27][blk]
+    float* ovpart;        // [parity][blk]: largest overlap seen by each pair-kernel block
     uint32_t nblk_max;    // pair-kernel blocks at 8 lanes per particle (partials per parity)
     double* ring;         // [rep][kRing][27]
     double* last;         // [rep][27]

@@ -193,30 +193,7 @@ __device__ __forceinline__ double row_sum_f64(double x) {
     return x;
 }
 
-// block-wide max of a non-negative float, then one atomic per block into one
-// of kSpread slots (readers take the max over the slots)
-__device__ __forceinline__ void block_atomic_max(float v, uint32_t* slots) {
-    __shared__ float rows[16];
-    v = fmaxf(v, dpp_f32<0x111>(v));
-    v = fmaxf(v, dpp_f32<0x112>(v));
-    v = fmaxf(v, dpp_f32<0x114>(v));
-    v = fmaxf(v, dpp_f32<0x118>(v));
-    if ((threadIdx.x & 15) == 15) rows[threadIdx.x >> 4] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float m = rows[0];
-        for (int k = 1; k < (int)(blockDim.x >> 4); ++k) m = fmaxf(m, rows[k]);
-        // the slot only grows during a launch: skip the atomic (which serialises with
-        // every other block's on the slot's cache line) unless this block raises it;
-        // the device-scope load reads the L2 copy, never a stale line of this CU
-        uint32_t* slot = &slots[blockIdx.x % kSpread];
-        const uint32_t mb = __float_as_uint(m);
-        if (m > 0.0f && mb > __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(slot, mb);
-    }
-    __syncthreads();
-}
-
-// block-wide max of a float, stored by thread 0 (no atomics)
+// block-wide max of a non-negative float, stored by thread 0
 __device__ __forceinline__ void block_max_store(float v, float* out) {
     __shared__ float rows[16];
     v = fmaxf(v, dpp_f32<0x111>(v));
@@ -232,13 +209,6 @@ __device__ __forceinline__ void block_max_store(float v, float* out) {
     }
 }
 
-__device__ __forceinline__ float slots_max(const uint32_t* slots) {
-    float m = 0.0f;
-#pragma unroll
-    for (int k = 0; k < kSpread; ++k) m = fmaxf(m, __uint_as_float(slots[k]));
-    return m;
-}
-
 // Reduction of one stress component c of replica r from the partials of
 // parity x, in a fixed order (one block), unless already done; component 0
 // also checks the overlap limit.
@@ -252,8 +222,19 @@ __device__ void finalize_unit(const Bufs& b, uint32_t r, int c, int x) {
     double v = 0.0;
     for (uint32_t k = threadIdx.x; k < nblk; k += blockDim.x) v += part[k];
     __shared__ double rows[16];
+    __shared__ float mrows[16];
     v = row_sum_f64(v);
     if ((threadIdx.x & 15) == 15) rows[threadIdx.x >> 4] = v;
+    if (c == 0) {  // largest overlap of the evaluation, from the block maxima
+        const float* op = b.ovpart + (size_t)x * b.nblk_max + blk0;
+        float m = 0.0f;
+        for (uint32_t k = threadIdx.x; k < nblk; k += blockDim.x) m = fmaxf(m, op[k]);
+        m = fmaxf(m, dpp_f32<0x111>(m));
+        m = fmaxf(m, dpp_f32<0x112>(m));
+        m = fmaxf(m, dpp_f32<0x114>(m));
+        m = fmaxf(m, dpp_f32<0x118>(m));
+        if ((threadIdx.x & 15) == 15) mrows[threadIdx.x >> 4] = m;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
@@ -265,10 +246,10 @@ __device__ void finalize_unit(const Bufs& b, uint32_t r, int c, int x) {
             D.stress_sum[c] += t;
         }
         if (c == 0) {
-            const float mo = slots_max(D.maxov_bits[x]);
+            float mo = 0.0f;
+            for (int k = 0; k < (int)(blockDim.x >> 4); ++k) mo = fmaxf(mo, mrows[k]);
             if ((double)mo > P.max_overlap) D.health |= H_OVERLAP;
             D.maxov_last_bits = __float_as_uint(mo);
-            for (int k = 0; k < kSpread; ++k) D.maxov_bits[x][k] = 0u;
         }
         D.done_id[x][c] = id;
     }
@@ -363,7 +344,9 @@ __global__ __launch_bounds__(256) void k_integrate(Bufs b, int q) {
     if (b.sys->halted) return;  // uniform: set by an earlier launch
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t i = tile * blockDim.x + threadIdx.x;
-    const uint32_t r = b.blk_rep[i / kTile];
+    // replicas are padded to whole tiles, so r is uniform over a block (here and in
+    // every kernel): readfirstlane keeps it, and what derives from it, scalar
+    const uint32_t r = __builtin_amdgcn_readfirstlane(b.blk_rep[i / kTile]);
     const RepParams& P = b.reps[r];
     const RepDyn& D = b.dyn[r];
     float dblk = 0.0f;
@@ -397,7 +380,7 @@ __global__ void k_rb_zero(Bufs b) {
 
 __global__ __launch_bounds__(256) void k_rb_keys(Bufs b) {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t r = b.blk_rep[q / kTile];
+    const uint32_t r = __builtin_amdgcn_readfirstlane(b.blk_rep[q / kTile]);
     const RepParams& P = b.reps[r];
     const uint32_t lq = q - P.p_begin;
     if (lq < P.n) {
@@ -485,7 +468,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(Bufs b) {
 
 __global__ __launch_bounds__(256) void k_rb_scatter(Bufs b) {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t r = b.blk_rep[q / kTile];
+    const uint32_t r = __builtin_amdgcn_readfirstlane(b.blk_rep[q / kTile]);
     const RepParams& P = b.reps[r];
     if (q - P.p_begin < P.n) {
         const uint32_t key = b.key[q];
@@ -518,7 +501,7 @@ __global__ void k_rb_cellsort(Bufs b) {
 // table keyed by partner id
 __global__ __launch_bounds__(256) void k_rb_gather(Bufs b, uint32_t ct_input_rep) {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t r = b.blk_rep[q / kTile];
+    const uint32_t r = __builtin_amdgcn_readfirstlane(b.blk_rep[q / kTile]);
     const RepParams& P = b.reps[r];
     const uint32_t npad = b.npad;
     if (q - P.p_begin >= P.n) {
@@ -600,7 +583,7 @@ __global__ __launch_bounds__(256) void k_rb_copyback(Bufs b) {
 // carried contact history is attached to its list entry.
 __global__ __launch_bounds__(256) void k_rb_nlist(Bufs b, int q, int in_step) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t r = b.blk_rep[i / kTile];
+    const uint32_t r = __builtin_amdgcn_readfirstlane(b.blk_rep[i / kTile]);
     const RepParams& P = b.reps[r];
     const uint32_t npad = b.npad, cap = b.cap;
     if (i - P.p_begin >= P.n) {
@@ -697,7 +680,7 @@ __global__ __launch_bounds__(256) void k_rb_nlist(Bufs b, int q, int in_step) {
 // i in j's list (lists are symmetric: the range test is symmetric in i, j).
 __global__ __launch_bounds__(256) void k_rb_mirror(Bufs b) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t r = b.blk_rep[i / kTile];
+    const uint32_t r = __builtin_amdgcn_readfirstlane(b.blk_rep[i / kTile]);
     const RepParams& P = b.reps[r];
     const uint32_t npad = b.npad;
     if (i - P.p_begin >= P.n) {
@@ -808,21 +791,13 @@ template <bool MIX> struct EvalCtx {
     bool do_lub, do_br, do_ct, do_one, do_rep, do_rot;
 };
 
-// Step bookkeeping shared by the pair kernels.  Returns false when the launch
-// must do nothing (a list may have expired).  first: this block is the first
-// of its replica (it records the step's offset, counter and bound).
-__device__ __forceinline__ bool eval_begin(const Bufs& b, int q, int advance, const RepParams& P, RepDyn& D,
-                                           bool first, double& s_le, uint64_t& step) {
+// Step bookkeeping shared by the pair kernels.  eval_record: the writes of an
+// evaluation that goes ahead, with its offset and step counter (first: this
+// block is the first of its replica and records them, with the bound's time).
+__device__ __forceinline__ void eval_record(const Bufs& b, int q, int advance, const RepParams& P, RepDyn& D,
+                                            bool first, double s_le, uint64_t step) {
     if (advance) {
-        // list-validity test of the step's integrate (any replica): one failure halts the
-        // whole launch sequence until the host has rebuilt
-        if (b.sys->expire[q]) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) b.sys->halted = 1u;
-            return false;
-        }
         if (blockIdx.x == 0 && threadIdx.x == 0) b.sys->expire[1 - q] = 0u;  // for the next step
-        s_le = next_offset(P, D.s_slot[1 - q]);
-        step = D.step_slot[1 - q] + 1;
         if (first && threadIdx.x == 0) {
             D.s_slot[q] = s_le;
             D.step_slot[q] = step;
@@ -832,15 +807,25 @@ __device__ __forceinline__ bool eval_begin(const Bufs& b, int q, int advance, co
             D.nrec += 1;
             D.rec[q] = D.nrec;
         }
-    } else {
-        s_le = D.s_slot[q];
-        step = D.step_slot[q];
-        if (first && threadIdx.x == 0) {
-            D.eval_seq += 1;
-            D.eval_id[q] = D.eval_seq;
-            D.rec[q] = 0u;
-        }
+    } else if (first && threadIdx.x == 0) {
+        D.eval_seq += 1;
+        D.eval_id[q] = D.eval_seq;
+        D.rec[q] = 0u;
     }
+}
+
+// Returns false when the launch must do nothing (a list may have expired: the
+// list-validity test of the step's integrate failed for some replica, and one
+// failure halts the whole launch sequence until the host has rebuilt).
+__device__ __forceinline__ bool eval_begin(const Bufs& b, int q, int advance, const RepParams& P, RepDyn& D,
+                                           bool first, double& s_le, uint64_t& step) {
+    if (advance && b.sys->expire[q]) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) b.sys->halted = 1u;
+        return false;
+    }
+    s_le = advance ? next_offset(P, D.s_slot[1 - q]) : D.s_slot[q];
+    step = advance ? D.step_slot[1 - q] + 1 : D.step_slot[q];
+    eval_record(b, q, advance, P, D, first, s_le, step);
     return true;
 }
 
@@ -1308,7 +1293,7 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(Bufs b, int q, int kick, in
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t i = (tile * kPairBlock + threadIdx.x) / LN;
     const uint32_t sub = threadIdx.x % LN;
-    const uint32_t r = b.blk_rep[i / kTile];
+    const uint32_t r = __builtin_amdgcn_readfirstlane(b.blk_rep[i / kTile]);
     if (only_rep != 0xFFFFFFFFu && r != only_rep) return;  // whole block belongs to one replica
     const RepParams& P = b.reps[r];
     RepDyn& D = b.dyn[r];
@@ -1390,9 +1375,9 @@ __global__ __launch_bounds__(kPairBlock) void k_pair(Bufs b, int q, int kick, in
         if (sub == 0) store_particle<MIX>(b, P, kick, i, Ft, Tt, cm, sm, bad);
     }
 
-    // health: non-finite forces, largest overlap (relaxed atomics; read after the launch)
+    // health: non-finite forces (relaxed atomic; read after the launch), largest overlap
     if (bad) atomicOr(&D.health, H_NAN);
-    block_atomic_max(maxov, D.maxov_bits[q]);
+    block_max_store(maxov, &b.ovpart[(size_t)q * b.nblk_max + tile]);
     write_block_partial<kPairBlock>(b, q, sacc, tile);
 }
 
@@ -1414,7 +1399,7 @@ __global__ __launch_bounds__(256) void k_pairq(Bufs b, int q, int kick, int adva
     const int w = threadIdx.x >> 6, p = threadIdx.x & 63;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t base = (tile * 4 + w) * NP;  // first particle of this wave
-    const uint32_t r = b.blk_rep[base / kTile];       // a block (4 NP <= 256 particles) is inside one tile
+    const uint32_t r = __builtin_amdgcn_readfirstlane(b.blk_rep[base / kTile]);       // a block (4 NP <= 256 particles) is inside one tile
     if (only_rep != 0xFFFFFFFFu && r != only_rep) return;
     const RepParams& P = b.reps[r];
     RepDyn& D = b.dyn[r];
@@ -1559,7 +1544,7 @@ __global__ __launch_bounds__(256) void k_pairq(Bufs b, int q, int kick, int adva
     }
 
     if (bad) atomicOr(&D.health, H_NAN);
-    block_atomic_max(maxov, D.maxov_bits[q]);
+    block_max_store(maxov, &b.ovpart[(size_t)q * b.nblk_max + tile]);
     // block partial of the stress: fixed-order sum over the block's lanes (DPP rows, then LDS)
     __shared__ double rows[16][27];
 #pragma unroll
@@ -1596,11 +1581,11 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
     using R = typename std::conditional<MIX, float, double>::type;
     using V3 = typename PairRec<R>::T;
     constexpr int NP = 64 / LN;  // particles per wave
-    if (b.sys->halted) return;
     // the last 27 * nrep blocks reduce the stress of the previous evaluation (its
     // partials have the other parity), beside the pair blocks rather than before them
     const uint32_t npair_blk = gridDim.x - 27u * b.nrep;
     if (blockIdx.x >= npair_blk) {
+        if (b.sys->halted) return;
         const uint32_t u = blockIdx.x - npair_blk;
         finalize_unit(b, u / 27u, (int)(u % 27u), 1 - q);
         return;
@@ -1608,47 +1593,96 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
     const int w = threadIdx.x >> 6, p = threadIdx.x & 63;
     const uint32_t tile = xcd_tile(blockIdx.x, npair_blk);  // a block: 4 NP particles, inside one kTile
     const uint32_t base = (tile * 4 + w) * NP;                // first particle of this wave
-    const uint32_t r = b.blk_rep[base / kTile];
-    if (only_rep != 0xFFFFFFFFu && r != only_rep) return;
+    const uint32_t l = p / LN, sub = p % LN;
+    const uint32_t i = base + l;
+    const uint32_t npad = b.npad;
+    // The cull reads only list and position data, which stay in bounds whatever the
+    // step's state, and padding slots have empty lists: it runs before any exit test,
+    // so that its loads are issued at once, beside those of the replica's parameters
+    // and the step's bookkeeping, rather than after a chain of dependent checks.
+    // (Loads complete in issue order: the ones needed first are issued first.)
+    // (r is the same for the whole wave: readfirstlane keeps it, and what derives from
+    // the replica's parameters, such as the noise keys, in scalar registers)
+    const uint32_t r = __builtin_amdgcn_readfirstlane(b.blk_rep[base / kTile]);
+    const uint32_t halted = b.sys->halted, expired = b.sys->expire[q] & (advance ? ~0u : 0u);
+    const uint32_t cnt = min(b.ncnt[i], b.cap), e_lo = b.lo0[i];
+    const double4 pi = b.pos[i];
+    const uint64_t cm_i = b.cmask[i];
+    // the first group of partners as well in FP64 (in mixed precision the registers
+    // they hold through the prologue cost more than the early loads gain)
+    constexpr uint32_t G0 = MIX ? 0u : 4u;
+    uint32_t jj0[4];
+    double4 pj0[4];
+    if constexpr (G0 > 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {  // slots past the count hold stale indices: loaded, not used
+            const uint32_t e = e_lo + sub + u * LN;
+            const uint32_t j = b.nbr[min(e, b.cap - 1u) * npad + i];
+            jj0[u] = e < cnt ? j : i;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pj0[u] = b.pos[jj0[u]];
+    }
     const RepParams& P = b.reps[r];
     RepDyn& D = b.dyn[r];
-    double s_le;
-    uint64_t step;
-    if (!eval_begin(b, q, advance, P, D, tile == P.p_begin / (4 * NP), s_le, step)) return;
+    // offset and step counter of this evaluation (the bookkeeping of eval_begin
+    // without its writes, which follow the exit tests)
+    const double s_le = advance ? next_offset(P, D.s_slot[1 - q]) : D.s_slot[q];
+    const uint64_t step = advance ? D.step_slot[1 - q] + 1 : D.step_slot[q];
+
+    // exit tests and the step's bookkeeping (the writes of eval_begin): after the
+    // cull in FP64; before it in mixed precision, where the registers the cull's
+    // values hold through the tests cost more than the shorter chain gains
+    auto go = [&]() -> bool {
+        if (halted) return false;
+        if (only_rep != 0xFFFFFFFFu && r != only_rep) return false;
+        if (expired) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) b.sys->halted = 1u;
+            return false;
+        }
+        eval_record(b, q, advance, P, D, tile == P.p_begin / (4 * NP), s_le, step);
+        return true;
+    };
+    if constexpr (MIX) {
+        if (!go()) return;
+    }
+
+    // ---- cull: interacting entries with a higher-id partner (LN lanes per particle)
+    uint64_t im = 0ull;
+    if constexpr (G0 > 0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t e = e_lo + sub + u * LN;
+            if (e < cnt && interacting(P, s_le, pi, pj0[u])) im |= 1ull << e;
+        }
+    }
+    for (uint32_t c0 = e_lo + sub + G0 * LN; c0 < cnt; c0 += 4 * LN) {
+        uint32_t jj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t e = c0 + u * LN;
+            jj[u] = e < cnt ? b.nbr[e * npad + i] : i;
+        }
+        double4 pj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pj[u] = b.pos[jj[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t e = c0 + u * LN;
+            if (e < cnt && interacting(P, s_le, pi, pj[u])) im |= 1ull << e;
+        }
+    }
+
+    if constexpr (!MIX) {
+        if (!go()) return;
+    }
     EvalCtx<MIX> C;
     make_ctx<MIX>(C, P, s_le, step);
-    const uint32_t npad = b.npad;
 
     __shared__ uint16_t queue[4][NP * 64];   // (particle slot << 6) | entry
     __shared__ unsigned long long cmo[4][NP], cmq[4][NP], smq[4][NP];
-
-    // ---- cull: interacting entries with a higher-id partner (LN lanes per particle)
-    const uint32_t l = p / LN, sub = p % LN;
-    const uint32_t i = base + l;
     const bool valid = i - P.p_begin < P.n;
-    uint64_t im = 0ull;
-    if (valid) {
-        const double4 pi = b.pos[i];
-        const uint32_t cnt = b.ncnt[i];
-        // entries in groups of 4: list loads together, then partner positions together
-        for (uint32_t c0 = b.lo0[i] + sub; c0 < cnt; c0 += 4 * LN) {
-            uint32_t jj[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t e = c0 + u * LN;
-                jj[u] = e < cnt ? b.nbr[e * npad + i] : i;
-            }
-            double4 pj[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) pj[u] = b.pos[jj[u]];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint32_t e = c0 + u * LN;
-                if (e < cnt && interacting(P, s_le, pi, pj[u])) im |= 1ull << e;
-            }
-        }
-        if (sub == 0) cmo[w][l] = b.cmask[i];
-    }
+    if (valid && sub == 0) cmo[w][l] = cm_i;
     if (LN >= 2) im |= dpp_u64<0xB1>(im);
     if (LN >= 4) im |= dpp_u64<0x4E>(im);
     if (sub == 0) {
@@ -1725,9 +1759,15 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
         b.smask[i] = smq[w][l];
     }
 
-    block_atomic_max(maxov, D.maxov_bits[q]);
-    // block partial of the stress: fixed-order sum over the block's lanes (DPP rows, then LDS)
+    // block partial of the stress (fixed-order sum over the block's lanes: DPP rows,
+    // then LDS) and the block's largest overlap, behind one barrier
     __shared__ double rows[16][27];
+    __shared__ float mrows[16];
+    maxov = fmaxf(maxov, dpp_f32<0x111>(maxov));
+    maxov = fmaxf(maxov, dpp_f32<0x112>(maxov));
+    maxov = fmaxf(maxov, dpp_f32<0x114>(maxov));
+    maxov = fmaxf(maxov, dpp_f32<0x118>(maxov));
+    if ((p & 15) == 15) mrows[threadIdx.x >> 4] = maxov;
 #pragma unroll
     for (int c = 0; c < 27; ++c) {
         const double v = row_sum_f64(acc[c]);
@@ -1739,6 +1779,10 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
         double tsum = 0.0;
         for (int k = 0; k < 16; ++k) tsum += rows[k][c];
         b.partial[((size_t)q * 27 + c) * b.nblk_max + tile] = tsum;
+    } else if (threadIdx.x == 32) {
+        float m = mrows[0];
+        for (int k = 1; k < 16; ++k) m = fmaxf(m, mrows[k]);
+        b.ovpart[(size_t)q * b.nblk_max + tile] = m;
     }
 }
 
@@ -1753,7 +1797,7 @@ __global__ __launch_bounds__(256) void k_gather(Bufs b, int q, int kick, int fus
     if (b.sys->halted) return;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t i = tile * 256 + threadIdx.x;
-    const uint32_t r = b.blk_rep[tile];
+    const uint32_t r = __builtin_amdgcn_readfirstlane(b.blk_rep[tile]);
     if (only_rep != 0xFFFFFFFFu && r != only_rep) return;
     const RepParams& P = b.reps[r];
     RepDyn& D = b.dyn[r];

@@ -578,6 +578,7 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         b.alt_id = s->alloc<uint32_t>(np);
         b.nblk_max = (uint32_t)(np / 128 * 8);               // 128-thread pair blocks, up to 8 lanes
         b.partial = s->alloc<double>((size_t)2 * b.nblk_max * 27);
+        b.ovpart = s->alloc<float>((size_t)2 * b.nblk_max);
         b.ring = s->alloc<double>((size_t)n_replicas * kRing * 27);
         b.last = s->alloc<double>((size_t)n_replicas * 27);
         b.blk_rep = s->alloc<uint32_t>(blk_rep.size());
