@@ -829,28 +829,41 @@ __device__ __forceinline__ bool eval_begin(const Bufs& b, int q, int advance, co
     return true;
 }
 
-template <bool MIX>
+// values uniform over the wave (the evaluation's constants): readfirstlane keeps
+// them in scalar registers whatever path they were loaded through
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ __forceinline__ double uni(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint64_t lo = uni((uint32_t)u), hi = uni((uint32_t)(u >> 32));
+    return __longlong_as_double((long long)(lo | (hi << 32)));
+}
+
+// UNI: move the constants to scalar registers (pays where vector registers bind the
+// occupancy; the kernels evaluating several items per lane run short of scalar ones)
+template <bool MIX, bool UNI = false>
 __device__ __forceinline__ void make_ctx(EvalCtx<MIX>& C, const RepParams& P, double s_le, uint64_t step) {
     using R = typename EvalCtx<MIX>::R;
-    C.s_le = s_le;
-    C.c1 = P.c1;
-    C.invV = P.invV;
-    C.k0 = (uint32_t)P.seed;
-    C.k1 = (uint32_t)(P.seed >> 32);
-    C.ctr_lo = (uint32_t)step;
-    C.ctr_hi = (uint32_t)(step >> 32) << 8;
-    C.bamp = (R)P.bamp;
-    C.eta6pi = (R)(6.0 * kPi * P.eta);
-    C.xi_min = (R)P.xi_min;
-    C.kn = (R)P.kn;
-    C.kt = (R)P.kt;
-    C.mukn = (R)(P.mu * P.kn);
-    C.dtR = (R)P.dt;
+    auto uni = [](auto v) { return UNI ? susp::uni(v) : v; };
+    C.s_le = uni(s_le);
+    C.c1 = uni(P.c1);
+    C.invV = uni(P.invV);
+    C.k0 = uni((uint32_t)P.seed);
+    C.k1 = uni((uint32_t)(P.seed >> 32));
+    C.ctr_lo = uni((uint32_t)step);
+    C.ctr_hi = uni((uint32_t)(step >> 32) << 8);
+    C.bamp = uni((R)P.bamp);
+    C.eta6pi = uni((R)(6.0 * kPi * P.eta));
+    C.xi_min = uni((R)P.xi_min);
+    C.kn = uni((R)P.kn);
+    C.kt = uni((R)P.kt);
+    C.mukn = uni((R)(P.mu * P.kn));
+    C.dtR = uni((R)P.dt);
     C.do_lub = !(P.flags & F_NO_LUB);
     C.do_br = !(P.flags & F_NO_PAIR_BROWN);
     C.do_ct = !(P.flags & F_NO_CONTACT);
     C.do_one = !(P.flags & F_NO_ONEBODY);
-    C.repA = (R)P.rep_A;
+    C.repA = uni((R)P.rep_A);
     C.do_rep = P.rep_A > 0.0;
     C.do_rot = (P.flags & F_LUB_ROT) != 0;
 }
@@ -1608,8 +1621,8 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
     const uint32_t cnt = min(b.ncnt[i], b.cap), e_lo = b.lo0[i];
     const double4 pi = b.pos[i];
     const uint64_t cm_i = b.cmask[i];
-    // the first group of partners as well in FP64 (in mixed precision the registers
-    // they hold through the prologue cost more than the early loads gain)
+    // the first group of partners as well in FP64 (in mixed precision, where the
+    // evaluation is shorter, the early group measured slower)
     constexpr uint32_t G0 = MIX ? 0u : 4u;
     uint32_t jj0[4];
     double4 pj0[4];
@@ -1630,9 +1643,7 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
     const double s_le = advance ? next_offset(P, D.s_slot[1 - q]) : D.s_slot[q];
     const uint64_t step = advance ? D.step_slot[1 - q] + 1 : D.step_slot[q];
 
-    // exit tests and the step's bookkeeping (the writes of eval_begin): after the
-    // cull in FP64; before it in mixed precision, where the registers the cull's
-    // values hold through the tests cost more than the shorter chain gains
+    // exit tests and the step's bookkeeping (the writes of eval_begin), after the cull
     auto go = [&]() -> bool {
         if (halted) return false;
         if (only_rep != 0xFFFFFFFFu && r != only_rep) return false;
@@ -1643,9 +1654,6 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
         eval_record(b, q, advance, P, D, tile == P.p_begin / (4 * NP), s_le, step);
         return true;
     };
-    if constexpr (MIX) {
-        if (!go()) return;
-    }
 
     // ---- cull: interacting entries with a higher-id partner (LN lanes per particle)
     uint64_t im = 0ull;
@@ -1673,11 +1681,9 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
         }
     }
 
-    if constexpr (!MIX) {
-        if (!go()) return;
-    }
+    if (!go()) return;
     EvalCtx<MIX> C;
-    make_ctx<MIX>(C, P, s_le, step);
+    make_ctx<MIX, true>(C, P, s_le, step);
 
     __shared__ uint16_t queue[4][NP * 64];   // (particle slot << 6) | entry
     __shared__ unsigned long long cmo[4][NP], cmq[4][NP], smq[4][NP];
@@ -1817,7 +1823,7 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
     using R = typename std::conditional<MIX, float, double>::type;
     using V3 = typename PairRec<R>::T;
     EvalCtx<MIX> C;
-    make_ctx<MIX>(C, P, D.s_slot[q], D.step_slot[q]);
+    make_ctx<MIX, true>(C, P, D.s_slot[q], D.step_slot[q]);
     const uint32_t npad = b.npad;
     const double4 pi = b.pos[i];
     const uint32_t idi = b.id[i];
