@@ -49,16 +49,17 @@ def gather_bytes_per_particle(mixed, k, p, c):
     return own_in + own_out + 4 * k + k + vec * p / 2 + vec * c / 2
 
 
-def measured_traffic(mixed):
+def measured_traffic(mixed, lanes, n):
     """HBM bytes per launch of the half-pair kernel on the 50,000-sphere workload from the
-    committed counter summary, if it was taken from the current kernel source."""
+    committed counter summary, if it was taken from the current kernel source in the same
+    launch configuration (lanes per particle) and size as the timed run."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
         sha = hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha1") != sha:
+    if rec.get("kernel_source_sha1") != sha or rec.get("lanes") != lanes or rec.get("n") != n:
         return None
     t = rec.get("mixed" if mixed else "fp64", {}).get("k_half")
     return None if t is None else t["fetch_bytes"] + t["write_bytes"]
@@ -124,7 +125,7 @@ def roofline(r, mixed, n):
         bpp = 2 * half_bytes_per_particle(mixed, k, p, c) + 48
         name = "k_pair<%s>" % ("true" if mixed else "false")
     achieved = bpp * n / (r["pair_ms"] * 1e-3) / 1e9
-    traffic = measured_traffic(mixed) if half else None
+    traffic = measured_traffic(mixed, st["lanes"], n) if half else None
     out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": name, "kernel_ms": r["pair_ms"],
            "bytes_per_particle": bpp, "list_per_particle": k, "interacting_per_particle": p,
