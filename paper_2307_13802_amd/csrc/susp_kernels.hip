@@ -795,9 +795,9 @@ template <bool MIX> struct EvalCtx {
 // evaluation that goes ahead, with its offset and step counter (first: this
 // block is the first of its replica and records them, with the bound's time).
 __device__ __forceinline__ void eval_record(const Bufs& b, int q, int advance, const RepParams& P, RepDyn& D,
-                                            bool first, double s_le, uint64_t step) {
+                                            bool first, double s_le, uint64_t step, bool leader) {
     if (advance) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) b.sys->expire[1 - q] = 0u;  // for the next step
+        if (leader && threadIdx.x == 0) b.sys->expire[1 - q] = 0u;  // for the next step (one block of the launch)
         if (first && threadIdx.x == 0) {
             D.s_slot[q] = s_le;
             D.step_slot[q] = step;
@@ -825,7 +825,7 @@ __device__ __forceinline__ bool eval_begin(const Bufs& b, int q, int advance, co
     }
     s_le = advance ? next_offset(P, D.s_slot[1 - q]) : D.s_slot[q];
     step = advance ? D.step_slot[1 - q] + 1 : D.step_slot[q];
-    eval_record(b, q, advance, P, D, first, s_le, step);
+    eval_record(b, q, advance, P, D, first, s_le, step, blockIdx.x == 0);
     return true;
 }
 
@@ -1594,17 +1594,17 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
     using R = typename std::conditional<MIX, float, double>::type;
     using V3 = typename PairRec<R>::T;
     constexpr int NP = 64 / LN;  // particles per wave
-    // the last 27 * nrep blocks reduce the stress of the previous evaluation (its
-    // partials have the other parity), beside the pair blocks rather than before them
-    const uint32_t npair_blk = gridDim.x - 27u * b.nrep;
-    if (blockIdx.x >= npair_blk) {
-        if (b.sys->halted) return;
-        const uint32_t u = blockIdx.x - npair_blk;
-        finalize_unit(b, u / 27u, (int)(u % 27u), 1 - q);
+    // the first blocks (27 * nrep, padded to a multiple of 8 so that the XCD order of
+    // the pair blocks is kept) reduce the stress of the previous evaluation (its
+    // partials have the other parity): dispatched first, they run beside the pair blocks
+    const uint32_t nfin = (27u * b.nrep + 7u) & ~7u, npair_blk = gridDim.x - nfin;
+    if (blockIdx.x < nfin) {
+        if (blockIdx.x >= 27u * b.nrep || b.sys->halted) return;
+        finalize_unit(b, blockIdx.x / 27u, (int)(blockIdx.x % 27u), 1 - q);
         return;
     }
     const int w = threadIdx.x >> 6, p = threadIdx.x & 63;
-    const uint32_t tile = xcd_tile(blockIdx.x, npair_blk);  // a block: 4 NP particles, inside one kTile
+    const uint32_t tile = xcd_tile(blockIdx.x - nfin, npair_blk);  // a block: 4 NP particles, inside one kTile
     const uint32_t base = (tile * 4 + w) * NP;                // first particle of this wave
     const uint32_t l = p / LN, sub = p % LN;
     const uint32_t i = base + l;
@@ -1648,10 +1648,10 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
         if (halted) return false;
         if (only_rep != 0xFFFFFFFFu && r != only_rep) return false;
         if (expired) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) b.sys->halted = 1u;
+            if (blockIdx.x == nfin && threadIdx.x == 0) b.sys->halted = 1u;
             return false;
         }
-        eval_record(b, q, advance, P, D, tile == P.p_begin / (4 * NP), s_le, step);
+        eval_record(b, q, advance, P, D, tile == P.p_begin / (4 * NP), s_le, step, blockIdx.x == nfin);
         return true;
     };
 
@@ -2145,7 +2145,7 @@ template <bool MIX>
 static void launch_pair_t(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep,
                           hipEvent_t mid, int fuse) {
     if (b.kern == 2) {  // half-pair evaluation, then the per-particle gather
-        const uint32_t g = b.npad / 256, fin = 27u * b.nrep;  // pair blocks, then finalize blocks
+        const uint32_t g = b.npad / 256, fin = (27u * b.nrep + 7u) & ~7u;  // finalize blocks, then pair blocks
         if (b.ext) {
             switch (b.lanes) {
                 case 1: hipLaunchKernelGGL((k_half<MIX, 1, true>), dim3(g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
