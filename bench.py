@@ -49,17 +49,18 @@ def gather_bytes_per_particle(mixed, k, p, c):
     return own_in + own_out + 4 * k + k + vec * p / 2 + vec * c / 2
 
 
-def measured_traffic(mixed, lanes, n):
+def measured_traffic(mixed, lanes, n, occ):
     """HBM bytes per launch of the half-pair kernel on the 50,000-sphere workload from the
     committed counter summary, if it was taken from the current kernel source in the same
-    launch configuration (lanes per particle) and size as the timed run."""
+    launch configuration (lanes per particle, form) and size as the timed run."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
         sha = hashlib.sha1(open(KERNEL_SRC, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha1") != sha or rec.get("lanes") != lanes or rec.get("n") != n:
+    if (rec.get("kernel_source_sha1") != sha or rec.get("lanes") != lanes or rec.get("n") != n
+            or rec.get("occupancy_form", 0) != occ):
         return None
     t = rec.get("mixed" if mixed else "fp64", {}).get("k_half")
     return None if t is None else t["fetch_bytes"] + t["write_bytes"]
@@ -125,7 +126,7 @@ def roofline(r, mixed, n):
         bpp = 2 * half_bytes_per_particle(mixed, k, p, c) + 48
         name = "k_pair<%s>" % ("true" if mixed else "false")
     achieved = bpp * n / (r["pair_ms"] * 1e-3) / 1e9
-    traffic = measured_traffic(mixed, st["lanes"], n) if half else None
+    traffic = measured_traffic(mixed, st["lanes"], n, st["occupancy_form"]) if half else None
     out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": name, "kernel_ms": r["pair_ms"],
            "bytes_per_particle": bpp, "list_per_particle": k, "interacting_per_particle": p,
@@ -242,6 +243,7 @@ def run_mixed_vs_fp64(P, st, steps, sample_every, say):
     return {
         "fp64": {"value": n * steps / t64, "pair_kernel_ms": ms64, "hbm_frac": hbm_frac(st64p, False, n, ms64),
                  "pair_kernel": {1: "lanes", 2: "wave", 3: "half"}[st64["pair_kernel"]], "lanes": st64["lanes"],
+                 "occupancy_form": st64["occupancy_form"],
                  "rebuilds": st64["rebuilds"], "eta_r_mean": m64},
         "mixed": {"value": n * steps / t32, "pair_kernel_ms": ms32, "hbm_frac": hbm_frac(st32p, True, n, ms32),
                   "pair_kernel": {1: "lanes", 2: "wave", 3: "half"}[st32["pair_kernel"]], "lanes": st32["lanes"],
@@ -301,6 +303,7 @@ def bench_sweep(P, gen, steps, warmup, say):
         sim.close()
         res[name] = {"value": ntot * steps / el, "ms_per_step": el * 1e3 / steps, "pair_kernel_ms": ms,
                      "pair_kernel": {1: "lanes", 2: "wave", 3: "half"}[stt["pair_kernel"]], "lanes": stt["lanes"],
+                     "occupancy_form": stt["occupancy_form"],
                      "eta_r_mean_min": min(eta), "eta_r_mean_max": max(eta)}
         if name == "mixed":
             eta_mixed = np.array(eta)
@@ -379,6 +382,8 @@ def main():
                          "with the pair kernel --pair-kernel / --lanes (a profiler distorts the timed choice)")
     ap.add_argument("--pair-kernel", type=int, default=3, help="--trace: 0 auto, 1 lanes, 2 wave, 3 half")
     ap.add_argument("--lanes", type=int, default=1, help="--trace: lanes per particle (0 = auto)")
+    ap.add_argument("--form", default="auto", choices=["auto", "latency", "occupancy"],
+                    help="--trace, FP64 half-pair kernel: its form (auto = chosen by timing at creation)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the engine has no multi-GPU path",
@@ -402,9 +407,11 @@ def main():
         wl = gen.C2 if args.workload == "c2" else gen.C3
         st = gen.make_state(wl)
         say(f"workload ready: {wl.name}")
+        form = {"auto": 0, "latency": P.HALF_OCC_OFF, "occupancy": P.HALF_OCC_ON}[args.form]
         for prec in (P.FP64, P.MIXED):
             sim = P.Sim(P.Config(box=st["L"], precision=prec, pair_kernel=args.pair_kernel, lanes=args.lanes,
-                                 **st["params"]), st["radii"], st["x"], st["v"], st["w"])
+                                 flags=form if prec == P.FP64 else 0, **st["params"]),
+                        st["radii"], st["x"], st["v"], st["w"])
             stt = sim.stats()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -412,7 +419,8 @@ def main():
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
             sim.close()
-            say(f"precision={prec} kernel={stt['pair_kernel']} lanes={stt['lanes']}: {args.steps} steps, "
+            say(f"precision={prec} kernel={stt['pair_kernel']} lanes={stt['lanes']} "
+                f"occupancy_form={stt['occupancy_form']}: {args.steps} steps, "
                 f"{len(st['radii']) * args.steps / el:.3e} particle-steps/s")
         return
     if args.workload in ("c3", "sweep", "large"):
@@ -469,7 +477,8 @@ def main():
                    "gammadot": st["params"]["gammadot"], "kT": st["params"]["kT"], "mu": wl.mu,
                    "dt": wl.dt, "hip_graph": True,
                    "pair_kernel": {1: "lanes", 2: "wave", 3: "half"}[f64["stats"]["pair_kernel"]],
-                   "lanes_per_particle": f64["stats"]["lanes"]},
+                   "lanes_per_particle": f64["stats"]["lanes"],
+                   "occupancy_form": f64["stats"]["occupancy_form"]},
         "roofline": roofline(f64, False, n),
         "eta_r_fp64": f64["eta_mean"],
     }
@@ -480,6 +489,7 @@ def main():
         out["mixed"] = {"value": vm, "ms_per_step": mix["seconds"] * 1e3 / args.steps, "dtype": "f32 pair / f64 state",
                         "pair_kernel": {1: "lanes", 2: "wave", 3: "half"}[mix["stats"]["pair_kernel"]],
                         "lanes_per_particle": mix["stats"]["lanes"],
+                        "occupancy_form": mix["stats"]["occupancy_form"],
                         "speedup_vs_fp64": vm / value, "roofline": rm,
                         "eta_r": mix["eta_mean"],
                         "eta_r_rel_diff_free_running": (mix["eta_mean"] - f64["eta_mean"]) / f64["eta_mean"],

@@ -85,6 +85,15 @@ extern "C" {
                                         torque_brownian_lub2); half-pair kernel only       */
 #define SIM_REBUILD_EACH_STEP 0x100u /* rebuild the neighbour list every step        */
 #define SIM_NO_GRAPH          0x200u /* launch kernels directly, no HIP graph        */
+#define SIM_HALF_OCC_ON       0x400u /* half-pair kernel, FP64, no model switch: use its
+                                        form for occupancy (the pair queue in rounds, part
+                                        of the stress sums in LDS, 3 waves per SIMD) rather
+                                        than choosing by timing at creation; the same
+                                        results bit for bit                             */
+#define SIM_HALF_OCC_OFF      0x800u /* ... never use that form                       */
+#define SIM_SMALL_QUEUE      0x1000u /* test switch: that form processes its pair queue
+                                        64 items per round (instead of 2048), so that
+                                        every wave takes several rounds                 */
 
 /* sim_stress components and modes */
 #define SIM_STRESS_CONTACT 0      /* -(F^C + F^R) (x) r / V: contact and
@@ -160,10 +169,15 @@ typedef struct sim_stats_t {
     double  le_offset;              /* current Lees-Edwards offset                     */
     int32_t lanes;                  /* lanes per particle used by the pair kernel       */
     int32_t pair_kernel;            /* SIM_KERNEL_LANES, _WAVE or _HALF in use             */
+    int32_t occupancy_form;         /* 1: the half-pair kernel's form for occupancy is in
+                                       use (see SIM_HALF_OCC_ON), 0 otherwise            */
+    int32_t reserved;               /* 0                                                 */
 } sim_stats_t;
 
 /* Checks a configuration and its radii on the host (no GPU needed).
- * radii: n doubles, host memory.  Returns SIM_EINVAL for n = 0, a <= 0,
+ * radii: n doubles, host memory.  Returns SIM_EINVAL for both SIM_HALF_OCC_ON
+ * and SIM_HALF_OCC_OFF, SIM_HALF_OCC_ON with SIM_MIXED, SIM_LUB_ROT,
+ * repulsion > 0 or a pair_kernel other than 0 and SIM_KERNEL_HALF, n = 0, a <= 0,
  * dt <= 0, rho/eta <= 0, kn/kt < 0, mu < 0, kT < 0, repulsion < 0, xi_min <= 0,
  * xi_min >= xi_cut, a box side not larger than twice the largest
  * interaction range plus skin (the minimum image must be unique), a wrong

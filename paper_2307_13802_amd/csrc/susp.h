@@ -140,6 +140,8 @@ struct Bufs {
     int kern;             // pair kernel: 0 = lanes split each particle's items, 1 = wave-cooperative,
                           // 2 = half-pair evaluation + gather
     int ppb;              // particles per pair-kernel block (for the stress partials)
+    int occ;              // half-pair kernel in FP64 without extensions: 1 = its form for occupancy
+    uint32_t qcap;        // queue items per round of that form (2048; 64 under SIM_SMALL_QUEUE)
 
     double* dacc;         // per particle: bound on its non-affine displacement since the last build
     double4* disp;        // per particle: accumulated non-affine displacement (x, y, z) since the

@@ -1589,8 +1589,12 @@ __global__ __launch_bounds__(256) void k_pairq(Bufs b, int q, int kick, int adva
 // torques and springs equal those of variant 1 with one lane per particle.
 // ---------------------------------------------------------------------------
 
-template <bool MIX, int LN, bool EXT>
-__global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int advance, uint32_t only_rep) {
+// OCC (FP64 without the model extensions): the form for occupancy -- the queue is
+// processed in rounds of kQCap items and 13 of the 27 stress sums live in LDS, so
+// that the kernel fits 3 waves per SIMD; it pays on systems that fill the GPU many
+// times over, while small ones (one round of waves) want the shortest wave.
+template <bool MIX, int LN, bool EXT, bool OCC = false>
+__global__ __launch_bounds__(256, (MIX || OCC) ? 3 : 2) void k_half(Bufs b, int q, int advance, uint32_t only_rep) {
     using R = typename std::conditional<MIX, float, double>::type;
     using V3 = typename PairRec<R>::T;
     constexpr int NP = 64 / LN;  // particles per wave
@@ -1685,7 +1689,12 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
     EvalCtx<MIX> C;
     make_ctx<MIX, true>(C, P, s_le, step);
 
-    __shared__ uint16_t queue[4][NP * 64];   // (particle slot << 6) | entry
+    // The queue holds up to qc items of a wave at a time: all of them (NP * 64), or with
+    // OCC b.qcap <= 2048 (a wave's interacting pairs seldom exceed a few hundred; more
+    // are evaluated in further rounds).
+    constexpr uint32_t kQCap = OCC ? 2048u : (uint32_t)NP * 64u;
+    const uint32_t qc = OCC ? min(b.qcap, kQCap) : kQCap;
+    __shared__ uint16_t queue[4][kQCap];   // (particle slot << 6) | entry
     __shared__ unsigned long long cmo[4][NP], cmq[4][NP], smq[4][NP];
     const bool valid = i - P.p_begin < P.n;
     if (valid && sub == 0) cmo[w][l] = cm_i;
@@ -1704,29 +1713,33 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
         if (p >= off) incl += y;
     }
     const uint32_t total = __shfl(incl, 63);
-    if (sub == 0) {
-        uint32_t k = incl - cnt_i;
-        if (valid) {
-            b.imask[i] = im;
-            b.qoff[i] = (uint16_t)k;
-        }
-        for (uint64_t m = im; m; m &= m - 1ull) queue[w][k++] = (uint16_t)((l << 6) | __builtin_ctzll(m));
+    const uint32_t qk0 = incl - cnt_i;  // the particle's first position in the wave's queue order
+    if (sub == 0 && valid) {
+        b.imask[i] = im;
+        b.qoff[i] = (uint16_t)qk0;
     }
     // results of this wave's pairs: a contiguous run in queue order
     V3* const pf = (V3*)b.pf + (size_t)base * b.cap;
     V3* const pt = (V3*)b.pt + (size_t)base * b.cap;
     V3* const pt2 = (V3*)b.pt2 + (size_t)base * b.cap;
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 
     // ---- evaluate the queue, one pair per lane
-    double acc[27];
+    // stress sums: the first NR components in registers, the others in per-lane LDS
+    // slots (one writer each); the same additions in the same order either way
+    constexpr int NR = OCC && !MIX ? 14 : 27, NL = 27 - NR;
+    __shared__ double sacc[NL > 0 ? NL : 1][NL > 0 ? 256 : 1];
+    double acc[NR];
 #pragma unroll
-    for (int c = 0; c < 27; ++c) acc[c] = 0.0;
-    auto addS = [&](int c, double v) { acc[c] += v; };
+    for (int c = 0; c < NR; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int c = 0; c < NL; ++c) sacc[c][threadIdx.x] = 0.0;
+    auto addS = [&](int c, double v) {
+        if (c < NR) acc[c < NR ? c : 0] += v;
+        else sacc[c < NR ? 0 : c - NR][threadIdx.x] += v;
+    };
     float maxov = 0.0f;
-    for (uint32_t k = p; k < total; k += 64) {
-        const uint32_t code = queue[w][k];
+    // one pair: item k of the wave's queue order, code (particle slot << 6) | entry
+    auto eval_pair = [&](uint32_t k, uint32_t code) {
         const uint32_t l = code >> 6, e = code & 63u;
         const uint32_t ii = base + l;
         const bool had = (cmo[w][l] >> e) & 1ull;
@@ -1757,6 +1770,32 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
             atomicOr(&cmq[w][l], 1ull << e);
             if (slid) atomicOr(&smq[w][l], 1ull << e);
         }
+    };
+    auto fill = [&](uint32_t r0) {  // the items of positions [r0, r0 + qc) of the queue order
+        if (sub == 0) {
+            uint32_t k = qk0;
+            for (uint64_t m = im; m; m &= m - 1ull, ++k)
+                if (k - r0 < qc) queue[w][k - r0] = (uint16_t)((l << 6) | __builtin_ctzll(m));
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    };
+    if constexpr (OCC) {
+        for (uint32_t r0 = 0; r0 < total; r0 += qc) {
+            fill(r0);
+            const uint32_t nq = min(total - r0, qc);
+            for (uint32_t kq = p; kq < nq; kq += 64) eval_pair(r0 + kq, queue[w][kq]);
+            __builtin_amdgcn_wave_barrier();  // the queue is refilled by the next round
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        }
+    } else {  // one round holds every item
+        if (sub == 0) {
+            uint32_t k = qk0;
+            for (uint64_t m = im; m; m &= m - 1ull) queue[w][k++] = (uint16_t)((l << 6) | __builtin_ctzll(m));
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        for (uint32_t k = p; k < total; k += 64) eval_pair(k, queue[w][k]);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1776,7 +1815,7 @@ __global__ __launch_bounds__(256, MIX ? 3 : 2) void k_half(Bufs b, int q, int ad
     if ((p & 15) == 15) mrows[threadIdx.x >> 4] = maxov;
 #pragma unroll
     for (int c = 0; c < 27; ++c) {
-        const double v = row_sum_f64(acc[c]);
+        const double v = row_sum_f64(c < NR ? acc[c < NR ? c : 0] : sacc[c < NR ? 0 : c - NR][threadIdx.x]);
         if ((p & 15) == 15) rows[threadIdx.x >> 4][c] = v;
     }
     __syncthreads();
@@ -2151,6 +2190,12 @@ static void launch_pair_t(const Bufs& b, hipStream_t st, int q, int kick, int ad
                 case 1: hipLaunchKernelGGL((k_half<MIX, 1, true>), dim3(g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
                 case 2: hipLaunchKernelGGL((k_half<MIX, 2, true>), dim3(2 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
                 default: hipLaunchKernelGGL((k_half<MIX, 4, true>), dim3(4 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
+            }
+        } else if (!MIX && b.occ) {
+            switch (b.lanes) {
+                case 1: hipLaunchKernelGGL((k_half<false, 1, false, true>), dim3(g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
+                case 2: hipLaunchKernelGGL((k_half<false, 2, false, true>), dim3(2 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
+                default: hipLaunchKernelGGL((k_half<false, 4, false, true>), dim3(4 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
             }
         } else {
             switch (b.lanes) {

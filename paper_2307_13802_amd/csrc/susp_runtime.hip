@@ -172,6 +172,16 @@ int validate(const sim_config* c, const double* radii, std::string& why) {
         why = "SIM_LUB_ROT and the repulsion need the half-pair kernel (pair_kernel 0 or SIM_KERNEL_HALF)";
         return SIM_EINVAL;
     }
+    if ((c->flags & SIM_HALF_OCC_ON) && (c->flags & SIM_HALF_OCC_OFF)) {
+        why = "SIM_HALF_OCC_ON and SIM_HALF_OCC_OFF exclude each other";
+        return SIM_EINVAL;
+    }
+    if ((c->flags & SIM_HALF_OCC_ON) &&
+        (c->precision != SIM_FP64 || (c->flags & SIM_LUB_ROT) || c->repulsion > 0.0 ||
+         (c->pair_kernel != SIM_KERNEL_AUTO && c->pair_kernel != SIM_KERNEL_HALF))) {
+        why = "SIM_HALF_OCC_ON needs FP64, no model switch and the half-pair kernel";
+        return SIM_EINVAL;
+    }
     if (c->pair_kernel == SIM_KERNEL_HALF && c->lanes == 8) {
         why = "the half-pair kernel needs lanes <= 4";
         return SIM_EINVAL;
@@ -360,14 +370,18 @@ void set_dyn(sim* s, int r, double s_le, uint64_t step) {
 // the half-pair variant also saves the integrate launch of fused steps).
 // The trial steps change the state: the caller restores it afterwards.
 // want_kern / want_lanes: 0 = free.
-void set_variant(sim* s, int kern, int lanes) {
+void set_variant(sim* s, int kern, int lanes, int occ = 0) {
     s->b.kern = kern;
     s->b.lanes = lanes;
+    s->b.occ = occ;
     s->b.ppb = kern == 0 ? 128 / lanes : 256 / lanes;
 }
 
 void tune_pair(sim* s, int want_kern, int want_lanes) {
-    std::vector<std::pair<int, int>> cand;
+    struct Cand {
+        int kern, lanes, occ;
+    };
+    std::vector<Cand> cand;
     for (int kern : {2, 0, 1}) {
         if (want_kern && want_kern - 1 != kern) continue;
         if (s->b.ext && kern != 2) continue;  // the model extensions live in the half-pair kernel
@@ -375,31 +389,40 @@ void tune_pair(sim* s, int want_kern, int want_lanes) {
         for (int L : {1, 2, 4, 8}) {
             if (want_lanes && want_lanes != L) continue;
             if (kern != 0 && L == 8) continue;
-            cand.push_back({kern, L});
+            // the half-pair kernel's form for occupancy (FP64, no extensions), unless forced
+            const bool occ_ok = kern == 2 && !s->mixed && !s->b.ext && !(s->flags & SIM_HALF_OCC_OFF);
+            if (!(occ_ok && (s->flags & SIM_HALF_OCC_ON))) cand.push_back({kern, L, 0});
+            if (occ_ok) cand.push_back({kern, L, 1});
         }
     }
     if (cand.size() == 1) {
-        set_variant(s, cand[0].first, cand[0].second);
+        set_variant(s, cand[0].kern, cand[0].lanes, cand[0].occ);
         return;
     }
     constexpr int kTrial = 4;
-    hipEvent_t e0, e1;
+    hipEvent_t e0, e1, e2;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventCreate(&e2));
     float best = 1e30f;
-    std::pair<int, int> pick = cand[0];
+    Cand pick = cand[0];
     for (auto c : cand) {
-        set_variant(s, c.first, c.second);
+        set_variant(s, c.kern, c.lanes, c.occ);
         int q = 1 - s->par;
         launch_rebuild(s->b, s->st, q, 0, 0xFFFFFFFFu);
         enqueue_steps(s, s->st, 2, q);  // warm-up
         launch_rebuild(s->b, s->st, q, 0, 0xFFFFFFFFu);
+        // two timed runs of kTrial steps (the faster counts: one run can catch a stall)
         HIPCHK(hipEventRecord(e0, s->st));
         enqueue_steps(s, s->st, kTrial, q);
         HIPCHK(hipEventRecord(e1, s->st));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        enqueue_steps(s, s->st, kTrial, q ^ (kTrial & 1));
+        HIPCHK(hipEventRecord(e2, s->st));
+        HIPCHK(hipEventSynchronize(e2));
+        float ms1 = 0.f, ms2 = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms1, e0, e1));
+        HIPCHK(hipEventElapsedTime(&ms2, e1, e2));
+        float ms = std::min(ms1, ms2);
         SysDyn sy;
         HIPCHK(hipMemcpy(&sy, s->b.sys, sizeof sy, hipMemcpyDeviceToHost));
         if (sy.halted) ms = 1e30f;  // a list expired during the trial: no valid timing
@@ -410,7 +433,8 @@ void tune_pair(sim* s, int want_kern, int want_lanes) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    set_variant(s, pick.first, pick.second);
+    (void)hipEventDestroy(e2);
+    set_variant(s, pick.kern, pick.lanes, pick.occ);
 }
 
 int check_rep(sim* s, int32_t r) {
@@ -559,6 +583,7 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         b.pf = s->dalloc(np * cap * (s->mixed ? 4 * sizeof(float) : 3 * sizeof(double)));
         b.pt = s->dalloc(np * cap * (s->mixed ? 4 * sizeof(float) : 3 * sizeof(double)));
         b.pt2 = s->dalloc(np * cap * (s->mixed ? 4 * sizeof(float) : 3 * sizeof(double)));
+        b.qcap = (s->flags & SIM_SMALL_QUEUE) ? 64u : 2048u;
         b.rot = (s->flags & SIM_LUB_ROT) ? 1 : 0;
         b.ext = b.rot;
         for (int r = 0; r < n_replicas; ++r)
@@ -1187,6 +1212,8 @@ int sim_stats(sim* s, int32_t r, sim_stats_t* out) {
         out->le_offset = d[0].s_slot[s->par];
         out->lanes = s->b.lanes;
         out->pair_kernel = s->b.kern + 1;  // SIM_KERNEL_LANES, _WAVE, _HALF
+        out->occupancy_form = s->b.kern == 2 && s->b.occ && !s->mixed && !s->b.ext ? 1 : 0;
+        out->reserved = 0;
         return SIM_OK;
     } catch (const HipError& e) {
         return hip_fail(s, e);

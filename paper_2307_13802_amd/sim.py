@@ -21,6 +21,8 @@ OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, ECAPACITY, ERANGE = 0, -1, -2, -3, -4, -
 FP64, MIXED = 0, 1
 FREEZE_X, NO_LUB, NO_PAIR_BROWN, NO_CONTACT, NO_ONEBODY, LUB_ROT = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 REBUILD_EACH_STEP, NO_GRAPH = 0x100, 0x200
+HALF_OCC_ON, HALF_OCC_OFF = 0x400, 0x800  # half-pair kernel, FP64: force or forbid its form for occupancy
+SMALL_QUEUE = 0x1000  # test switch: that form's pair queue in rounds of 64 items
 KERNEL_AUTO, KERNEL_LANES, KERNEL_WAVE, KERNEL_HALF = 0, 1, 2, 3
 STRESS_CONTACT, STRESS_LUB, STRESS_BROWN, STRESS_DRAG, STRESS_TOTAL = range(5)
 STRESS_LAST, STRESS_MEAN = 0, 1
@@ -50,7 +52,7 @@ class _Stats(C.Structure):
                 ("max_overlap", C.c_double), ("neighbours_per_particle", C.c_double),
                 ("interacting_per_particle", C.c_double), ("contacts", C.c_int64), ("rebuilds", C.c_int64),
                 ("steps", C.c_int64), ("step", C.c_uint64), ("le_offset", C.c_double), ("lanes", C.c_int32),
-                ("pair_kernel", C.c_int32)]
+                ("pair_kernel", C.c_int32), ("occupancy_form", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SimError(RuntimeError):

@@ -70,6 +70,11 @@ def test_validate_accepts_good_config():
     (dict(flags=0x20, pair_kernel=1), None, "SIM_LUB_ROT"),
     (dict(repulsion=1.0, pair_kernel=2), None, "half-pair kernel"),
     (dict(repulsion=-1.0), None, "non-negative"),
+    (dict(flags=0x400 | 0x800), None, "exclude each other"),
+    (dict(flags=0x400, precision=1), None, "SIM_HALF_OCC_ON"),
+    (dict(flags=0x400 | 0x20), None, "SIM_HALF_OCC_ON"),
+    (dict(flags=0x400, repulsion=1.0), None, "SIM_HALF_OCC_ON"),
+    (dict(flags=0x400, pair_kernel=1), None, "SIM_HALF_OCC_ON"),
 ])
 def test_validate_rejects(kw, radii, needle):
     a = np.full(4, 1.0) if radii is None else radii

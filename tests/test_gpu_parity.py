@@ -159,15 +159,22 @@ def test_pair_kernel_variants(P, kernel, lanes):
 
 
 def test_variants_bit_identical_to_one_lane(P):
-    """The wave-cooperative and the half-pair kernels sum each particle's items in the same
-    order as the one-lane kernel: whole trajectories agree bit for bit, in both precisions."""
+    """The wave-cooperative and the half-pair kernels (in FP64 also the half-pair kernel's form
+    for occupancy, with its queue in rounds of 2048 or of 64 items) sum each particle's items in
+    the same order as the one-lane kernel: whole trajectories agree bit for bit, in both
+    precisions."""
     st = _state(n=2000, phi=0.55, seed=8)
     for prec in (P.FP64, P.MIXED):
         runs = []
-        for kernel, lanes in ((1, 1), (2, 1), (2, 2), (2, 4), (3, 1), (3, 2), (3, 4)):
-            _say(f"case: 60 steps precision={prec} kernel={kernel} lanes={lanes}")
-            sim = P.Sim(_cfg(P, st, precision=prec, lanes=lanes, pair_kernel=kernel), st["radii"], st["x"],
-                        st["v"], st["w"])
+        cases = [(1, 1, 0), (2, 1, 0), (2, 2, 0), (2, 4, 0), (3, 1, P.HALF_OCC_OFF), (3, 2, P.HALF_OCC_OFF),
+                 (3, 4, P.HALF_OCC_OFF)]
+        if prec == P.FP64:
+            cases += [(3, 1, P.HALF_OCC_ON), (3, 2, P.HALF_OCC_ON), (3, 4, P.HALF_OCC_ON),
+                      (3, 1, P.HALF_OCC_ON | P.SMALL_QUEUE), (3, 2, P.HALF_OCC_ON | P.SMALL_QUEUE)]
+        for kernel, lanes, flags in cases:
+            _say(f"case: 60 steps precision={prec} kernel={kernel} lanes={lanes} flags={flags:#x}")
+            sim = P.Sim(_cfg(P, st, precision=prec, lanes=lanes, pair_kernel=kernel, flags=flags), st["radii"],
+                        st["x"], st["v"], st["w"])
             sim.step(60)
             runs.append(sim.get_state())
         for other in runs[1:]:
