@@ -67,7 +67,8 @@ struct sim {
     Bufs b{};
     hipStream_t st = nullptr;
     hipStream_t cap_st = nullptr;            // stream used only to capture graphs
-    hipGraphExec_t g1[2] = {nullptr, nullptr}, gk[2] = {nullptr, nullptr};  // by parity of the first step
+    // step graphs [1 step | kGraphSteps][parity of the first step][integrates first][hands over fused]
+    hipGraphExec_t gc[2][2][2][2] = {};
     std::vector<std::pair<void*, size_t>> allocs;
     void* (*afn)(size_t, void*) = nullptr;
     void (*ffn)(void*, void*) = nullptr;
@@ -114,10 +115,11 @@ struct sim {
     }
 
     ~sim() {
-        for (int k = 0; k < 2; ++k) {
-            if (g1[k]) (void)hipGraphExecDestroy(g1[k]);
-            if (gk[k]) (void)hipGraphExecDestroy(gk[k]);
-        }
+        for (auto& a : gc)
+            for (auto& b2 : a)
+                for (auto& c : b2)
+                    for (auto& g : c)
+                        if (g) (void)hipGraphExecDestroy(g);
         for (auto& e : ev) (void)hipEventDestroy(e);
         (void)hipStreamSynchronize(st);
         for (auto& a : allocs) {
@@ -235,20 +237,25 @@ template <class T> std::vector<T> d2h(sim* s, const T* dev, size_t off, size_t c
 // launch does nothing once the expiry test of an earlier one has halted the
 // chunk.  With the half-pair variant the gather of each step but the last
 // also takes kick 1 and the drift of the next step.
-void enqueue_steps(sim* s, hipStream_t st, int nsteps, int q0) {
+// With the half-pair kernel a step's gather also takes kick 1 and the drift of
+// the next step (fused), so only the first step of a launch sequence integrates
+// and only its last leaves the full-step values in memory.  integrate_first:
+// this run of steps starts a sequence; fuse_last: it does not end one (the next
+// run continues it without an integrate).
+void enqueue_steps(sim* s, hipStream_t st, int nsteps, int q0, bool integrate_first = true, bool fuse_last = false) {
     const bool fuse = s->b.kern == 2;
     for (int k = 0; k < nsteps; ++k) {
         const int q = q0 ^ (k & 1);
-        if (k == 0 || !fuse) launch_integrate(s->b, st, q);
-        launch_pair_force(s->b, st, q, 1, 1, 0xFFFFFFFFu, nullptr, fuse && k + 1 < nsteps);
+        if ((k == 0 && integrate_first) || !fuse) launch_integrate(s->b, st, q);
+        launch_pair_force(s->b, st, q, 1, 1, 0xFFFFFFFFu, nullptr, fuse && (k + 1 < nsteps || fuse_last));
     }
 }
 
-hipGraphExec_t capture(sim* s, int nsteps, int q0) {
+hipGraphExec_t capture(sim* s, int nsteps, int q0, bool integrate_first, bool fuse_last) {
     hipGraph_t g = nullptr;
     hipGraphExec_t ge = nullptr;
     HIPCHK(hipStreamBeginCapture(s->cap_st, hipStreamCaptureModeThreadLocal));
-    enqueue_steps(s, s->cap_st, nsteps, q0);
+    enqueue_steps(s, s->cap_st, nsteps, q0, integrate_first, fuse_last);
     HIPCHK(hipStreamEndCapture(s->cap_st, &g));
     HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
     HIPCHK(hipGraphDestroy(g));
@@ -661,11 +668,17 @@ void launch_steps(sim* s, int64_t m) {
     int q = 1 - s->par;
     const bool graph = !(s->flags & SIM_NO_GRAPH) && !s->profile;
     if (graph) {
-        if (m >= kGraphSteps && !s->gk[q]) s->gk[q] = capture(s, kGraphSteps, q);
-        for (; m >= kGraphSteps; m -= kGraphSteps) HIPCHK(hipGraphLaunch(s->gk[q], s->st));
-        for (; m > 0; --m, q ^= 1) {
-            if (!s->g1[q]) s->g1[q] = capture(s, 1, q);
-            HIPCHK(hipGraphLaunch(s->g1[q], s->st));
+        // the m steps form one launch sequence: graphs of kGraphSteps steps, then of 1,
+        // chained through the fused gather; only the first integrates, only the last
+        // leaves full-step values
+        for (bool first = true; m > 0; first = false) {
+            const int n = m >= kGraphSteps ? kGraphSteps : 1;
+            const bool more = m > n;
+            hipGraphExec_t& g = s->gc[n == 1 ? 0 : 1][q][first ? 1 : 0][more ? 1 : 0];
+            if (!g) g = capture(s, n, q, first, more);
+            HIPCHK(hipGraphLaunch(g, s->st));
+            m -= n;
+            q ^= n & 1;
         }
     } else if (s->profile) {
         if (s->ev.size() < 4) {
