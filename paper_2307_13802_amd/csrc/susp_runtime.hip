@@ -26,7 +26,8 @@ void (*g_free)(void*, void*) = nullptr;
 void* g_alloc_ctx = nullptr;
 
 constexpr uint32_t kDefaultCap = 48;
-constexpr int kGraphSteps = 8;
+constexpr int kGraphSteps = 8;     // step graphs of kGraphLong, kGraphSteps and 1 steps
+constexpr int kGraphLong = 64;
 
 struct HipError {
     hipError_t e;
@@ -67,8 +68,9 @@ struct sim {
     Bufs b{};
     hipStream_t st = nullptr;
     hipStream_t cap_st = nullptr;            // stream used only to capture graphs
-    // step graphs [1 step | kGraphSteps][parity of the first step][integrates first][hands over fused]
-    hipGraphExec_t gc[2][2][2][2] = {};
+    // step graphs [1 | kGraphSteps | kGraphLong steps][parity of the first step][integrates first]
+    // [hands over fused]
+    hipGraphExec_t gc[3][2][2][2] = {};
     std::vector<std::pair<void*, size_t>> allocs;
     void* (*afn)(size_t, void*) = nullptr;
     void (*ffn)(void*, void*) = nullptr;
@@ -662,19 +664,19 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
 
 namespace {
 
-// Launches m steps on the library stream (graphs of kGraphSteps and of 1 step,
+// Launches m steps on the library stream (chained step graphs, see below,
 // or direct launches), then waits.  Step k of the chunk has parity par^1^(k&1).
 void launch_steps(sim* s, int64_t m) {
     int q = 1 - s->par;
     const bool graph = !(s->flags & SIM_NO_GRAPH) && !s->profile;
     if (graph) {
-        // the m steps form one launch sequence: graphs of kGraphSteps steps, then of 1,
-        // chained through the fused gather; only the first integrates, only the last
-        // leaves full-step values
+        // the m steps form one launch sequence: graphs of kGraphLong steps, then of
+        // kGraphSteps, then of 1, chained through the fused gather; only the first
+        // integrates, only the last leaves full-step values
         for (bool first = true; m > 0; first = false) {
-            const int n = m >= kGraphSteps ? kGraphSteps : 1;
+            const int n = m >= kGraphLong ? kGraphLong : m >= kGraphSteps ? kGraphSteps : 1;
             const bool more = m > n;
-            hipGraphExec_t& g = s->gc[n == 1 ? 0 : 1][q][first ? 1 : 0][more ? 1 : 0];
+            hipGraphExec_t& g = s->gc[n == 1 ? 0 : n == kGraphSteps ? 1 : 2][q][first ? 1 : 0][more ? 1 : 0];
             if (!g) g = capture(s, n, q, first, more);
             HIPCHK(hipGraphLaunch(g, s->st));
             m -= n;
