@@ -25,6 +25,7 @@ HBM_PEAK_GBS = 8000.0
 
 KERNEL_SRC = os.path.join(ROOT, "paper_2307_13802_amd", "csrc", "susp_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_kernel_traffic.json")
+VALU_PEAK = 256 * 4 * 2.4e9  # VALU issue slots per second: 256 CUs x 4 SIMDs x 2.4 GHz
 
 
 def half_bytes_per_particle(mixed, k, p, c):
@@ -49,10 +50,10 @@ def gather_bytes_per_particle(mixed, k, p, c):
     return own_in + own_out + 4 * k + k + vec * p / 2 + vec * c / 2
 
 
-def measured_traffic(mixed, lanes, n, occ):
-    """HBM bytes per launch of the half-pair kernel on the 50,000-sphere workload from the
-    committed counter summary, if it was taken from the current kernel source in the same
-    launch configuration (lanes per particle, form) and size as the timed run."""
+def counter_record(lanes, n, occ):
+    """The committed counter record of the half-pair kernel on the 50,000-sphere workload, if it
+    was taken from the current kernel source in the same launch configuration (lanes per
+    particle, form) and size as the timed run."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
@@ -62,8 +63,21 @@ def measured_traffic(mixed, lanes, n, occ):
     if (rec.get("kernel_source_sha1") != sha or rec.get("lanes") != lanes or rec.get("n") != n
             or rec.get("occupancy_form", 0) != occ):
         return None
-    t = rec.get("mixed" if mixed else "fp64", {}).get("k_half")
+    return rec
+
+
+def measured_traffic(mixed, lanes, n, occ):
+    """HBM bytes per launch of the half-pair kernel (calibrated FETCH_SIZE + WRITE_SIZE)."""
+    rec = counter_record(lanes, n, occ)
+    t = None if rec is None else rec.get("mixed" if mixed else "fp64", {}).get("k_half")
     return None if t is None else t["fetch_bytes"] + t["write_bytes"]
+
+
+def measured_valu(mixed, lanes, n, occ):
+    """VALU-busy SIMD-cycles per launch of the half-pair kernel (4 x SQ_ACTIVE_INST_VALU)."""
+    rec = counter_record(lanes, n, occ)
+    v = None if rec is None else rec.get("valu_busy_simd_cycles", {})
+    return None if not v else v.get("mixed" if mixed else "fp64")
 
 
 def eta_r(series, gd, eta, drag_xy):
@@ -127,10 +141,17 @@ def roofline(r, mixed, n):
         name = "k_pair<%s>" % ("true" if mixed else "false")
     achieved = bpp * n / (r["pair_ms"] * 1e-3) / 1e9
     traffic = measured_traffic(mixed, st["lanes"], n, st["occupancy_form"]) if half else None
+    valu = measured_valu(mixed, st["lanes"], n, st["occupancy_form"]) if half else None
     out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": name, "kernel_ms": r["pair_ms"],
            "bytes_per_particle": bpp, "list_per_particle": k, "interacting_per_particle": p,
            "contacts_per_particle": c}
+    if valu is not None:
+        # the kernel is bound by load latency and VALU issue rather than by HBM: the VALU-busy
+        # cycles (counters) per second of its time, against 256 CUs x 4 SIMDs x 2.4 GHz
+        va = valu / (r["pair_ms"] * 1e-3)
+        out["alu"] = {"bound": "alu", "achieved": va, "peak": VALU_PEAK, "unit": "VALU-busy SIMD-cycles/s",
+                      "frac": va / VALU_PEAK}
     if half:
         gb = gather_bytes_per_particle(mixed, k, p, c)
         out["gather"] = {"kernel": "k_gather<%s>" % ("true" if mixed else "false"), "kernel_ms": r["gather_ms"],
