@@ -163,11 +163,12 @@ void launch_integrate(const Bufs& b, hipStream_t st, int q);
 // forces of a step (advance = 1: next step counter and offset, list-expiry test,
 // kick 2 if kick) or of the current state (advance = 0); only_rep: one replica
 // or 0xFFFFFFFF
-// mid: event recorded between the two launches of the half-pair variant (may be null);
-// fuse (half-pair variant only): the gather also takes kick 1 and the drift of the
-// next step, which then needs no integrate launch
+// kev: null, or events {pair start, pair end, gather start, gather end} that the
+// hardware records when those kernels start and end (the gather pair only with the
+// half-pair variant); fuse (half-pair variant only): the gather also takes kick 1
+// and the drift of the next step, which then needs no integrate launch
 void launch_pair_force(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep,
-                       hipEvent_t mid = nullptr, int fuse = 0);
+                       const hipEvent_t* kev = nullptr, int fuse = 0);
 // reduces pending stress partials of parity q
 void launch_finalize(const Bufs& b, hipStream_t st, int q);
 // Rebuild of cells and neighbour lists from the current positions; q is the

@@ -13,6 +13,8 @@
 // the contact-history update are evaluated operation by operation in the
 // same order as the plain FP64 definition, so neighbour sets and springs are
 // bit-reproducible; FP64 division and square root are IEEE correctly rounded.
+#include <hip/hip_ext.h>
+
 #include "susp.h"
 
 namespace susp {
@@ -2180,59 +2182,68 @@ void launch_rebuild(const Bufs& b, hipStream_t st, int q, int in_step, uint32_t 
     hipLaunchKernelGGL(k_rb_reset, dim3(1), dim3(256), 0, st, b, q);
 }
 
+// One launch, or with ev (start, stop) a launch whose events are recorded by the
+// hardware when the kernel starts and ends (the profiled pass times kernels so).
+template <typename F, typename... Args>
+static void launch_k(F kern, dim3 grid, dim3 blk, hipStream_t st, const hipEvent_t* ev, Args... args) {
+    if (ev) hipExtLaunchKernelGGL(kern, grid, blk, 0, st, ev[0], ev[1], 0u, args...);
+    else hipLaunchKernelGGL(kern, grid, blk, 0, st, args...);
+}
+
 template <bool MIX>
 static void launch_pair_t(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep,
-                          hipEvent_t mid, int fuse) {
+                          const hipEvent_t* kev, int fuse) {
+    const hipEvent_t* ev0 = kev;                        // pair kernel
+    const hipEvent_t* ev1 = kev ? kev + 2 : nullptr;    // gather
     if (b.kern == 2) {  // half-pair evaluation, then the per-particle gather
         const uint32_t g = b.npad / 256, fin = (27u * b.nrep + 7u) & ~7u;  // finalize blocks, then pair blocks
         if (b.ext) {
             switch (b.lanes) {
-                case 1: hipLaunchKernelGGL((k_half<MIX, 1, true>), dim3(g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
-                case 2: hipLaunchKernelGGL((k_half<MIX, 2, true>), dim3(2 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
-                default: hipLaunchKernelGGL((k_half<MIX, 4, true>), dim3(4 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
+                case 1: launch_k(k_half<MIX, 1, true>, dim3(g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
+                case 2: launch_k(k_half<MIX, 2, true>, dim3(2 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
+                default: launch_k(k_half<MIX, 4, true>, dim3(4 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
             }
         } else if (!MIX && b.occ) {
             switch (b.lanes) {
-                case 1: hipLaunchKernelGGL((k_half<false, 1, false, true>), dim3(g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
-                case 2: hipLaunchKernelGGL((k_half<false, 2, false, true>), dim3(2 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
-                default: hipLaunchKernelGGL((k_half<false, 4, false, true>), dim3(4 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
+                case 1: launch_k(k_half<false, 1, false, true>, dim3(g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
+                case 2: launch_k(k_half<false, 2, false, true>, dim3(2 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
+                default: launch_k(k_half<false, 4, false, true>, dim3(4 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
             }
         } else {
             switch (b.lanes) {
-                case 1: hipLaunchKernelGGL((k_half<MIX, 1, false>), dim3(g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
-                case 2: hipLaunchKernelGGL((k_half<MIX, 2, false>), dim3(2 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
-                default: hipLaunchKernelGGL((k_half<MIX, 4, false>), dim3(4 * g + fin), dim3(256), 0, st, b, q, advance, only_rep); break;
+                case 1: launch_k(k_half<MIX, 1, false>, dim3(g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
+                case 2: launch_k(k_half<MIX, 2, false>, dim3(2 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
+                default: launch_k(k_half<MIX, 4, false>, dim3(4 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
             }
         }
-        if (mid) (void)hipEventRecord(mid, st);
-        if (b.rot) hipLaunchKernelGGL((k_gather<MIX, true>), dim3(b.npad / 256), dim3(256), 0, st, b, q, kick, fuse, only_rep);
-        else hipLaunchKernelGGL((k_gather<MIX, false>), dim3(b.npad / 256), dim3(256), 0, st, b, q, kick, fuse, only_rep);
+        if (b.rot) launch_k(k_gather<MIX, true>, dim3(b.npad / 256), dim3(256), st, ev1, b, q, kick, fuse, only_rep);
+        else launch_k(k_gather<MIX, false>, dim3(b.npad / 256), dim3(256), st, ev1, b, q, kick, fuse, only_rep);
         return;
     }
     if (b.kern == 1) {  // wave-cooperative; 256-thread blocks of 4 * 64 / lanes particles
         const dim3 blk(256);
         const uint32_t g = b.npad / 256;
         switch (b.lanes) {
-            case 1: hipLaunchKernelGGL((k_pairq<MIX, 1>), dim3(g), blk, 0, st, b, q, kick, advance, only_rep); break;
-            case 2: hipLaunchKernelGGL((k_pairq<MIX, 2>), dim3(2 * g), blk, 0, st, b, q, kick, advance, only_rep); break;
-            default: hipLaunchKernelGGL((k_pairq<MIX, 4>), dim3(4 * g), blk, 0, st, b, q, kick, advance, only_rep); break;
+            case 1: launch_k(k_pairq<MIX, 1>, dim3(g), blk, st, ev0, b, q, kick, advance, only_rep); break;
+            case 2: launch_k(k_pairq<MIX, 2>, dim3(2 * g), blk, st, ev0, b, q, kick, advance, only_rep); break;
+            default: launch_k(k_pairq<MIX, 4>, dim3(4 * g), blk, st, ev0, b, q, kick, advance, only_rep); break;
         }
         return;
     }
     const dim3 blk(kPairBlock);
     const uint32_t g = b.npad / kPairBlock;
     switch (b.lanes) {
-        case 1: hipLaunchKernelGGL((k_pair<MIX, 1>), dim3(g), blk, 0, st, b, q, kick, advance, only_rep); break;
-        case 2: hipLaunchKernelGGL((k_pair<MIX, 2>), dim3(2 * g), blk, 0, st, b, q, kick, advance, only_rep); break;
-        case 4: hipLaunchKernelGGL((k_pair<MIX, 4>), dim3(4 * g), blk, 0, st, b, q, kick, advance, only_rep); break;
-        default: hipLaunchKernelGGL((k_pair<MIX, 8>), dim3(8 * g), blk, 0, st, b, q, kick, advance, only_rep); break;
+        case 1: launch_k(k_pair<MIX, 1>, dim3(g), blk, st, ev0, b, q, kick, advance, only_rep); break;
+        case 2: launch_k(k_pair<MIX, 2>, dim3(2 * g), blk, st, ev0, b, q, kick, advance, only_rep); break;
+        case 4: launch_k(k_pair<MIX, 4>, dim3(4 * g), blk, st, ev0, b, q, kick, advance, only_rep); break;
+        default: launch_k(k_pair<MIX, 8>, dim3(8 * g), blk, st, ev0, b, q, kick, advance, only_rep); break;
     }
 }
 
 void launch_pair_force(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep,
-                       hipEvent_t mid, int fuse) {
-    if (b.mixed) launch_pair_t<true>(b, st, q, kick, advance, only_rep, mid, fuse);
-    else launch_pair_t<false>(b, st, q, kick, advance, only_rep, mid, fuse);
+                       const hipEvent_t* kev, int fuse) {
+    if (b.mixed) launch_pair_t<true>(b, st, q, kick, advance, only_rep, kev, fuse);
+    else launch_pair_t<false>(b, st, q, kick, advance, only_rep, kev, fuse);
 }
 
 void launch_diag(const Bufs& b, hipStream_t st, int p, uint32_t rep, uint32_t n, uint32_t* out_ij, double* out_s,

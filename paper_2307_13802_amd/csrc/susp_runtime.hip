@@ -683,8 +683,9 @@ void launch_steps(sim* s, int64_t m) {
             q ^= n & 1;
         }
     } else if (s->profile) {
-        if (s->ev.size() < 4) {
-            for (int k = 0; k < 4; ++k) {
+        // kernel times from events the hardware records at each kernel's start and end
+        if (s->ev.size() < 6) {
+            for (size_t k = s->ev.size(); k < 6; ++k) {
                 hipEvent_t e;
                 HIPCHK(hipEventCreate(&e));
                 s->ev.push_back(e);
@@ -695,20 +696,19 @@ void launch_steps(sim* s, int64_t m) {
             HIPCHK(hipEventRecord(s->ev[0], s->st));
             launch_integrate(s->b, s->st, q);
             HIPCHK(hipEventRecord(s->ev[1], s->st));
-            launch_pair_force(s->b, s->st, q, 1, 1, 0xFFFFFFFFu, half ? s->ev[2] : nullptr);
-            HIPCHK(hipEventRecord(s->ev[3], s->st));
-            HIPCHK(hipEventSynchronize(s->ev[3]));
+            launch_pair_force(s->b, s->st, q, 1, 1, 0xFFFFFFFFu, &s->ev[2]);
+            HIPCHK(hipEventSynchronize(half ? s->ev[5] : s->ev[3]));
             SysDyn sy;
             HIPCHK(hipMemcpy(&sy, s->b.sys, sizeof sy, hipMemcpyDeviceToHost));
             if (sy.halted) break;  // that launch did nothing; the caller completes the step
-            float ms = 0.f, mi = 0.f, mp = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, s->ev[1], s->ev[3]));
+            float mi = 0.f, mp = 0.f, mg = 0.f;
             HIPCHK(hipEventElapsedTime(&mi, s->ev[0], s->ev[1]));
-            if (half) HIPCHK(hipEventElapsedTime(&mp, s->ev[1], s->ev[2]));
-            s->prof_ms += ms;
+            HIPCHK(hipEventElapsedTime(&mp, s->ev[2], s->ev[3]));
+            if (half) HIPCHK(hipEventElapsedTime(&mg, s->ev[4], s->ev[5]));
+            s->prof_ms += mp + mg;
             s->prof_stage_ms[0] += mi;
-            s->prof_stage_ms[1] += half ? mp : ms;
-            s->prof_stage_ms[2] += half ? ms - mp : 0.0;
+            s->prof_stage_ms[1] += mp;
+            s->prof_stage_ms[2] += mg;
             s->prof_launches += 1;
         }
     } else {
