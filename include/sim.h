@@ -296,14 +296,17 @@ int sim_contacts(sim* s, int32_t replica, uint32_t* ij_2m, double* s_3m, int32_t
 /* Statistics of one replica at the last evaluation. */
 int sim_stats(sim* s, int32_t replica, sim_stats_t* out);
 
-/* Kernel timing: when enabled, sim_step launches directly (no graph) and
- * brackets the launches of every step with HIP events on the library stream.
- * sim_kernel_time returns the number of timed steps and the total duration,
- * in milliseconds since the last enable, of their force evaluations (all
- * pair-force launches).  sim_stage_time gives one stage: 0 = integrate
- * (kick 1, drift), 1 = the pair kernel, 2 = the gather of SIM_KERNEL_HALF
- * (0 for the other variants, whose pair kernel includes it); SIM_EINVAL for
- * another stage. */
+/* Kernel timing: when enabled, sim_step launches directly (no graph), in the
+ * same sequence as the graphs, in batches of up to 32 steps without a host
+ * wait, and each force kernel with HIP events that the hardware records when
+ * the kernel starts and ends (on the library stream).  sim_kernel_time returns
+ * the number of timed steps and the total duration, in milliseconds since the
+ * last enable, of their force evaluations (all pair-force launches); a batch
+ * in which a list expiry halted a step is not counted.  sim_stage_time gives
+ * one stage: 0 = the integrate launches (with SIM_KERNEL_HALF one per batch:
+ * the gathers integrate the other steps), 1 = the pair kernel, 2 = the gather
+ * of SIM_KERNEL_HALF (0 for the other variants, whose pair kernel includes
+ * it); SIM_EINVAL for another stage. */
 int sim_profile(sim* s, int32_t enable);
 int sim_kernel_time(sim* s, int64_t* launches, double* total_ms);
 int sim_stage_time(sim* s, int32_t stage, int64_t* launches, double* total_ms);

@@ -683,33 +683,46 @@ void launch_steps(sim* s, int64_t m) {
             q ^= n & 1;
         }
     } else if (s->profile) {
-        // kernel times from events the hardware records at each kernel's start and end
-        if (s->ev.size() < 6) {
-            for (size_t k = s->ev.size(); k < 6; ++k) {
-                hipEvent_t e;
-                HIPCHK(hipEventCreate(&e));
-                s->ev.push_back(e);
-            }
+        // Kernel times from events the hardware records at each kernel's start and end,
+        // on the same launch sequence as the graphs (fused steps, no host wait inside a
+        // batch); a batch in which a list expiry halted a step is not counted.
+        constexpr int kBatch = 32;
+        while (s->ev.size() < 6 * (size_t)kBatch) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            s->ev.push_back(e);
         }
         const bool half = s->b.kern == 2;
-        for (; m > 0; --m, q ^= 1) {
-            HIPCHK(hipEventRecord(s->ev[0], s->st));
-            launch_integrate(s->b, s->st, q);
-            HIPCHK(hipEventRecord(s->ev[1], s->st));
-            launch_pair_force(s->b, s->st, q, 1, 1, 0xFFFFFFFFu, &s->ev[2]);
-            HIPCHK(hipEventSynchronize(half ? s->ev[5] : s->ev[3]));
+        while (m > 0) {
+            const int nb = (int)std::min<int64_t>(m, kBatch);
+            for (int k = 0; k < nb; ++k) {
+                const int qk = q ^ (k & 1);
+                hipEvent_t* e = &s->ev[6 * (size_t)k];
+                if (k == 0 || !half) {
+                    HIPCHK(hipEventRecord(e[0], s->st));
+                    launch_integrate(s->b, s->st, qk);
+                    HIPCHK(hipEventRecord(e[1], s->st));
+                }
+                launch_pair_force(s->b, s->st, qk, 1, 1, 0xFFFFFFFFu, &e[2], half && k + 1 < nb);
+            }
+            HIPCHK(hipStreamSynchronize(s->st));
             SysDyn sy;
             HIPCHK(hipMemcpy(&sy, s->b.sys, sizeof sy, hipMemcpyDeviceToHost));
-            if (sy.halted) break;  // that launch did nothing; the caller completes the step
-            float mi = 0.f, mp = 0.f, mg = 0.f;
-            HIPCHK(hipEventElapsedTime(&mi, s->ev[0], s->ev[1]));
-            HIPCHK(hipEventElapsedTime(&mp, s->ev[2], s->ev[3]));
-            if (half) HIPCHK(hipEventElapsedTime(&mg, s->ev[4], s->ev[5]));
-            s->prof_ms += mp + mg;
-            s->prof_stage_ms[0] += mi;
-            s->prof_stage_ms[1] += mp;
-            s->prof_stage_ms[2] += mg;
-            s->prof_launches += 1;
+            if (sy.halted) break;  // the caller completes the halted step
+            for (int k = 0; k < nb; ++k) {
+                hipEvent_t* e = &s->ev[6 * (size_t)k];
+                float mi = 0.f, mp = 0.f, mg = 0.f;
+                if (k == 0 || !half) HIPCHK(hipEventElapsedTime(&mi, e[0], e[1]));
+                HIPCHK(hipEventElapsedTime(&mp, e[2], e[3]));
+                if (half) HIPCHK(hipEventElapsedTime(&mg, e[4], e[5]));
+                s->prof_ms += mp + mg;
+                s->prof_stage_ms[0] += mi;
+                s->prof_stage_ms[1] += mp;
+                s->prof_stage_ms[2] += mg;
+                s->prof_launches += 1;
+            }
+            m -= nb;
+            q ^= nb & 1;
         }
     } else {
         enqueue_steps(s, s->st, (int)m, q);
