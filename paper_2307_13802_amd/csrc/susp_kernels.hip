@@ -79,16 +79,20 @@ __device__ __forceinline__ void normals3(uint4 w, float g[3]) {
 // ---------------------------------------------------------------------------
 // (t * (1/L) rounds to the same integer as t / L except within an ulp of a
 // half-integer, i.e. for separations of half a box, far outside any list range.)
+__device__ __forceinline__ int min_image(const double* L, const double* invL, double s_le, const double4& pa,
+                                         const double4& pb, double& dx, double& dy, double& dz) {
+    dy = pa.y - pb.y;
+    const double ky = rint(dy * invL[1]);
+    dy = dy - ky * L[1];
+    dx = (pa.x - pb.x) - ky * s_le;
+    dx = dx - L[0] * rint(dx * invL[0]);
+    dz = pa.z - pb.z;
+    dz = dz - L[2] * rint(dz * invL[2]);
+    return (int)ky;
+}
 __device__ __forceinline__ int min_image(const RepParams& P, double s_le, const double4& pa, const double4& pb,
                                          double& dx, double& dy, double& dz) {
-    dy = pa.y - pb.y;
-    const double ky = rint(dy * P.invL[1]);
-    dy = dy - ky * P.L[1];
-    dx = (pa.x - pb.x) - ky * s_le;
-    dx = dx - P.L[0] * rint(dx * P.invL[0]);
-    dz = pa.z - pb.z;
-    dz = dz - P.L[2] * rint(dz * P.invL[2]);
-    return (int)ky;
+    return min_image(P.L, P.invL, s_le, pa, pb, dx, dy, dz);
 }
 
 __device__ __forceinline__ uint32_t part1by2(uint32_t v) {
@@ -277,8 +281,9 @@ __global__ __launch_bounds__(256) void k_finalize(Bufs b, int x) { finalize_all(
 // failure flags the step (expire), its force launch does nothing and the
 // host rebuilds the lists from the moved positions before evaluating it.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool list_expired(const RepParams& P, double d, double t) {
-    return 2.0 * d + fabs(P.gd) * t * (P.rc_max + 2.0 * P.skin) > P.skin;
+// (rcs = r_c + 2 skin, with r_c the largest interaction range)
+__device__ __forceinline__ bool list_expired(double gd, double rcs, double skin, double d, double t) {
+    return 2.0 * d + fabs(gd) * t * rcs > skin;
 }
 
 // ---------------------------------------------------------------------------
@@ -286,33 +291,64 @@ __device__ __forceinline__ bool list_expired(const RepParams& P, double d, doubl
 // sheared box, Sec. II.E).  Also accumulates each particle's non-affine
 // displacement |dx - U^inf dt| and applies the list-validity test.
 // ---------------------------------------------------------------------------
-// Kick 1, drift and wrap of particle i for the step with parity q, from its
-// full-step velocities v, w, position x and the force and torque F, T of the
-// last evaluation (as stored); accumulates its displacement bound (dblk) and
-// applies the list-validity test (expire).
-template <bool MIX>
-__device__ __forceinline__ void integrate_particle(const Bufs& b, const RepParams& P, const RepDyn& D, int q,
-                                                   uint32_t i, double4 x, double4 v, double4 w, const double* F,
-                                                   const double* T, float& dblk, bool& expire) {
-    double disp = 0.0;
-    const double a = x.w;
-    const double m = (4.0 / 3.0) * kPi * P.rho * a * a * a;
+// What kick 1, the drift, the wrap and the validity test of the step with parity q
+// read of the replica's parameters and bookkeeping.  Kernels read it before their
+// first store: the compiler cannot tell that those stores leave it unchanged, and
+// would otherwise read each value again after them (a memory round trip at the end
+// of every lane's work).
+struct DriftPar {
+    double L[3], gd, gdLy, dt, half_dt, rho, skin, rcs, s_next, t_next;
+    uint32_t flags;
+};
+__device__ __forceinline__ DriftPar drift_par(const RepParams& P, const RepDyn& D, int q) {
+    DriftPar d;
+    for (int k = 0; k < 3; ++k) d.L[k] = P.L[k];
+    d.gd = P.gd;
+    d.gdLy = P.gdLy;
+    d.dt = P.dt;
+    d.half_dt = P.half_dt;
+    d.rho = P.rho;
+    d.skin = P.skin;
+    d.rcs = P.rc_max + 2.0 * P.skin;
+    d.s_next = next_offset(P, D.s_slot[1 - q]);
+    d.t_next = D.t_slot[1 - q] + P.dt;
+    d.flags = P.flags;
+    return d;
+}
+
+// one half kick of velocity-Verlet: v += dt/2 F / m, w += dt/2 T / I
+__device__ __forceinline__ void half_kick(double a, double rho, double half_dt, const double* F, const double* T,
+                                          double4& v, double4& w) {
+    const double m = (4.0 / 3.0) * kPi * rho * a * a * a;
     const double I = 0.4 * m * a * a;
-    const double hm = P.half_dt / m, hI = P.half_dt / I;
+    const double hm = half_dt / m, hI = half_dt / I;
     v.x += hm * F[0]; v.y += hm * F[1]; v.z += hm * F[2];
     w.x += hI * T[0]; w.y += hI * T[1]; w.z += hI * T[2];
-    if (!(P.flags & F_FREEZE_X)) {
+}
+
+// Kick 1, drift and wrap of particle i (parameters dp of the step), from its
+// full-step velocities v, w, position x and the force and torque F, T of the
+// last evaluation (as stored); da, dacc: its displacement records as read;
+// accumulates its displacement bound (dblk) and applies the list-validity test
+// (expire).
+template <bool MIX>
+__device__ __forceinline__ void integrate_particle(const Bufs& b, const DriftPar& dp, uint32_t i, double4 x,
+                                                   double4 v, double4 w, const double* F, const double* T,
+                                                   double4 da, double dacc, float& dblk, bool& expire) {
+    double disp = 0.0;
+    half_kick(x.w, dp.rho, dp.half_dt, F, T, v, w);
+    if (!(dp.flags & F_FREEZE_X)) {
         const double yold = x.y;
         const double vdx = v.x, vdy = v.y, vdz = v.z;  // drift velocity
-        x.x += P.dt * v.x;
-        x.y += P.dt * v.y;
-        x.z += P.dt * v.z;
-        const double s = next_offset(P, D.s_slot[1 - q]);
-        const double Lx = P.L[0], Ly = P.L[1], Lz = P.L[2];
+        x.x += dp.dt * v.x;
+        x.y += dp.dt * v.y;
+        x.z += dp.dt * v.z;
+        const double s = dp.s_next;
+        const double Lx = dp.L[0], Ly = dp.L[1], Lz = dp.L[2];
         if (x.y >= Ly) {
-            x.y -= Ly; x.x -= s; v.x -= P.gdLy;
+            x.y -= Ly; x.x -= s; v.x -= dp.gdLy;
         } else if (x.y < 0.0) {
-            x.y += Ly; x.x += s; v.x += P.gdLy;
+            x.y += Ly; x.x += s; v.x += dp.gdLy;
             if (x.y >= Ly) x.y = 0.0;
         }
         x.x -= Lx * floor(x.x / Lx);
@@ -321,11 +357,10 @@ __device__ __forceinline__ void integrate_particle(const Bufs& b, const RepParam
         if (x.z >= Lz) x.z -= Lz;
         // non-affine displacement of this step: drift minus the imposed flow
         // integrated along the path, gammadot (y(t) - Ly/2) with y(t) = yold + vdy t
-        const double ux = P.gd * (yold - 0.5 * Ly) + 0.5 * P.gd * P.dt * vdy;
-        const double ex = P.dt * (vdx - ux), ey = P.dt * vdy, ez = P.dt * vdz;
+        const double ux = dp.gd * (yold - 0.5 * Ly) + 0.5 * dp.gd * dp.dt * vdy;
+        const double ex = dp.dt * (vdx - ux), ey = dp.dt * vdy, ez = dp.dt * vdz;
         disp = sqrt(ex * ex + ey * ey + ez * ez) * (1.0 + 1e-6) + 1e-30;
         b.pos[i] = x;
-        double4 da = b.disp[i];
         da.x += ex; da.y += ey; da.z += ez;
         b.disp[i] = da;
     }
@@ -335,9 +370,9 @@ __device__ __forceinline__ void integrate_particle(const Bufs& b, const RepParam
         b.vsh[i] = make_float4((float)v.x, (float)v.y, (float)v.z, 0.0f);
         b.wsh[i] = make_float4((float)w.x, (float)w.y, (float)w.z, 0.0f);
     }
-    const double d = b.dacc[i] + disp;
+    const double d = dacc + disp;
     b.dacc[i] = d;
-    expire = list_expired(P, d, D.t_slot[1 - q] + P.dt);
+    expire = list_expired(dp.gd, dp.rcs, dp.skin, d, dp.t_next);
     dblk = (float)d * (1.0f + 1e-6f);
 }
 
@@ -351,6 +386,7 @@ __global__ __launch_bounds__(256) void k_integrate(Bufs b, int q) {
     const uint32_t r = __builtin_amdgcn_readfirstlane(b.blk_rep[i / kTile]);
     const RepParams& P = b.reps[r];
     const RepDyn& D = b.dyn[r];
+    const DriftPar dp = drift_par(P, D, q);
     float dblk = 0.0f;
     bool expire = false;
     if (i - P.p_begin < P.n) {
@@ -362,7 +398,7 @@ __global__ __launch_bounds__(256) void k_integrate(Bufs b, int q) {
             const double4 f = ((const double4*)b.F)[i], t = ((const double4*)b.T)[i];
             F[0] = f.x; F[1] = f.y; F[2] = f.z; T[0] = t.x; T[1] = t.y; T[2] = t.z;
         }
-        integrate_particle<MIX>(b, P, D, q, i, b.pos[i], b.vf[i], b.wf[i], F, T, dblk, expire);
+        integrate_particle<MIX>(b, dp, i, b.pos[i], b.vf[i], b.wf[i], F, T, b.disp[i], b.dacc[i], dblk, expire);
     }
     if (expire) atomicOr(&b.sys->expire[q], 1u);  // rare: the lists are rebuilt before that
     block_max_store(dblk, &b.dpart[(size_t)q * (b.npad / kTile) + tile]);
@@ -788,8 +824,12 @@ constexpr uint32_t kItemTorque = 65u;  // item code of the one-body torque
 template <bool MIX> struct EvalCtx {
     using R = typename std::conditional<MIX, float, double>::type;
     double s_le, c1, invV;
+    // the box: a pair loop that stores its results would otherwise read these from the
+    // parameters again in every pass (eval_item's BOXC; the FP64 occupancy form of the
+    // half-pair kernel has no scalar registers to spare and reads them)
+    double L[3], invL[3], gdLy;
     uint32_t k0, k1, ctr_lo, ctr_hi;
-    R bamp, eta6pi, xi_min, kn, kt, mukn, dtR, repA;
+    R bamp, eta6pi, xi_min, kn, kt, mukn, dtR, repA, pieta;
     bool do_lub, do_br, do_ct, do_one, do_rep, do_rot;
 };
 
@@ -848,6 +888,11 @@ __device__ __forceinline__ void make_ctx(EvalCtx<MIX>& C, const RepParams& P, do
     using R = typename EvalCtx<MIX>::R;
     auto uni = [](auto v) { return UNI ? susp::uni(v) : v; };
     C.s_le = uni(s_le);
+    for (int k = 0; k < 3; ++k) {
+        C.L[k] = uni(P.L[k]);
+        C.invL[k] = uni(P.invL[k]);
+    }
+    C.gdLy = uni(P.gdLy);
     C.c1 = uni(P.c1);
     C.invV = uni(P.invV);
     C.k0 = uni((uint32_t)P.seed);
@@ -866,6 +911,7 @@ __device__ __forceinline__ void make_ctx(EvalCtx<MIX>& C, const RepParams& P, do
     C.do_ct = !(P.flags & F_NO_CONTACT);
     C.do_one = !(P.flags & F_NO_ONEBODY);
     C.repA = uni((R)P.rep_A);
+    C.pieta = uni((R)kPi * (R)P.eta);
     C.do_rep = P.rep_A > 0.0;
     C.do_rot = (P.flags & F_LUB_ROT) != 0;
 }
@@ -923,7 +969,7 @@ template <class R> struct PairIn {
 // model extensions are compiled in (the short-ranged repulsion, and the
 // rotational lubrication couplings with the pairwise Brownian torques, which
 // need LO_ONLY and preloaded partner data), each on when its parameter says.
-template <bool MIX, bool LO_ONLY = false, bool EXT = false, class AddS>
+template <bool MIX, bool LO_ONLY = false, bool EXT = false, bool BOXC = true, class AddS>
 __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, const EvalCtx<MIX>& C, uint32_t i,
                                           uint32_t e, const double4& pi, uint32_t idi,
                                           const typename EvalCtx<MIX>::R* vi, const typename EvalCtx<MIX>::R* wi,
@@ -957,11 +1003,15 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
             idj = b.id[j];
         }
         lo = LO_ONLY || idi < idj;  // i holds the lower id
-        ky = lo ? min_image(P, C.s_le, pi, pj, dx, dy, dz) : min_image(P, C.s_le, pj, pi, dx, dy, dz);
+        const double* L = BOXC ? C.L : P.L;
+        const double* invL = BOXC ? C.invL : P.invL;
+        ky = lo ? min_image(L, invL, C.s_le, pi, pj, dx, dy, dz) : min_image(L, invL, C.s_le, pj, pi, dx, dy, dz);
         const double d2 = (dx * dx + dy * dy) + dz * dz;
         const double sa = pi.w + pj.w;
         const double rc = sa * C.c1;
-        if (!(d2 <= rc * rc)) return false;
+        // (the half-pair kernel evaluates only pairs its cull found in range, with the
+        // same arithmetic)
+        if (!(LO_ONLY && BOXC) && !(d2 <= rc * rc)) return false;
         const double dist = sqrt(d2);
         h = dist - sa;
         const R inv = rrcp<R>((R)dist);
@@ -995,7 +1045,7 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
 
     // ---- pair item: velocities in canonical orientation; b's image moves with +k_y gammadot Ly
     R va[3], vb[3], vj[3];
-    const R shiftv = (R)((double)ky * P.gdLy);
+    const R shiftv = (R)((double)ky * (BOXC ? C.gdLy : P.gdLy));
     if (pre) {
 #pragma unroll
         for (int d = 0; d < 3; ++d) vj[d] = pre->vj[d];
@@ -1036,7 +1086,7 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
         // in the form symmetric in the radii (a = lower id, b = higher id).
         const R aa = (R)pi.w, ab = (R)pj.w;  // LO_ONLY: i is a
         const R sR = aa + ab, i5s2 = (R)0.2 * rrcp<R>(sR * sR), isR = rrcp<R>(sR);
-        const R pie = (R)kPi * (R)P.eta;
+        const R pie = BOXC ? C.pieta : (R)kPi * (R)P.eta;
         const R YB11 = -(R)4 * pie * aa * aa * ab * ((R)4 * aa + ab) * i5s2 * lgv;
         const R YB21 = -(R)4 * pie * ab * ab * aa * ((R)4 * ab + aa) * i5s2 * lgv;
         const R YC11 = (R)3.2 * pie * aa * aa * aa * ab * isR * lgv;
@@ -1226,44 +1276,35 @@ __device__ __forceinline__ void load_vw(const Bufs& b, uint32_t i, typename Eval
     }
 }
 
-// stores the force and torque of particle i, applies kick 2, flags non-finite values
-template <bool MIX, bool MASKS = true>
-__device__ __forceinline__ void store_particle(const Bufs& b, const RepParams& P, int kick, uint32_t i,
-                                               const double* Ft, const double* Tt, uint64_t cm, uint64_t sm,
-                                               bool& bad, double4* vf_out = nullptr, double4* wf_out = nullptr,
-                                               bool store = true) {
-    bad = !(isfinite(Ft[0]) && isfinite(Ft[1]) && isfinite(Ft[2]) && isfinite(Tt[0]) && isfinite(Tt[1]) &&
-            isfinite(Tt[2]));
-    if (MASKS) {
-        b.cmask[i] = cm;
-        b.smask[i] = sm;
-    }
-    if (!store) {
-    } else if (MIX) {
+__device__ __forceinline__ bool nonfinite(const double* Ft, const double* Tt) {
+    return !(isfinite(Ft[0]) && isfinite(Ft[1]) && isfinite(Ft[2]) && isfinite(Tt[0]) && isfinite(Tt[1]) &&
+             isfinite(Tt[2]));
+}
+template <bool MIX>
+__device__ __forceinline__ void store_ft(const Bufs& b, uint32_t i, const double* Ft, const double* Tt) {
+    if (MIX) {
         ((float4*)b.F)[i] = make_float4((float)Ft[0], (float)Ft[1], (float)Ft[2], 0.0f);
         ((float4*)b.T)[i] = make_float4((float)Tt[0], (float)Tt[1], (float)Tt[2], 0.0f);
     } else {
         ((double4*)b.F)[i] = make_double4(Ft[0], Ft[1], Ft[2], 0.0);
         ((double4*)b.T)[i] = make_double4(Tt[0], Tt[1], Tt[2], 0.0);
     }
+}
+// stores the force and torque of particle i and its masks, applies kick 2, flags
+// non-finite values
+template <bool MIX>
+__device__ __forceinline__ void store_particle(const Bufs& b, const RepParams& P, int kick, uint32_t i,
+                                               const double* Ft, const double* Tt, uint64_t cm, uint64_t sm,
+                                               bool& bad) {
+    bad = nonfinite(Ft, Tt);
+    b.cmask[i] = cm;
+    b.smask[i] = sm;
+    store_ft<MIX>(b, i, Ft, Tt);
     // kick 2 of velocity-Verlet
     double4 vf = b.vh[i], wf = b.wh[i];
-    if (kick) {
-        const double a = b.pos[i].w;
-        const double m = (4.0 / 3.0) * kPi * P.rho * a * a * a;
-        const double I = 0.4 * m * a * a;
-        const double hm = P.half_dt / m, hI = P.half_dt / I;
-        vf.x += hm * Ft[0]; vf.y += hm * Ft[1]; vf.z += hm * Ft[2];
-        wf.x += hI * Tt[0]; wf.y += hI * Tt[1]; wf.z += hI * Tt[2];
-    }
-    if (store) {
-        b.vf[i] = vf;
-        b.wf[i] = wf;
-    }
-    if (vf_out) {
-        *vf_out = vf;
-        *wf_out = wf;
-    }
+    if (kick) half_kick(b.pos[i].w, P.rho, P.half_dt, Ft, Tt, vf, wf);
+    b.vf[i] = vf;
+    b.wf[i] = wf;
 }
 
 // block partial of the 27 stress sums held in thread-private LDS slots sacc[c][thread]
@@ -1760,7 +1801,8 @@ __global__ __launch_bounds__(256, (MIX || OCC) ? 3 : 2) void k_half(Bufs b, int 
         else in.s[0] = in.s[1] = in.s[2] = (R)0;
         R f[3], t[3], tb[3];  // tb: written by eval_item where it is used (contact, or the couplings)
         bool contact, slid;
-        eval_item<MIX, true, EXT>(b, P, C, ii, e, pi, idi, vi, wi, had, f, t, contact, slid, maxov, addS, tb, &in);
+        eval_item<MIX, true, EXT, MIX || !OCC>(b, P, C, ii, e, pi, idi, vi, wi, had, f, t, contact, slid, maxov, addS,
+                                                tb, &in);
         pf[k] = PairRec<R>::make(f[0], f[1], f[2]);
         if (EXT && C.do_rot) {  // torques on the lower- and the higher-id particle
             pt[k] = PairRec<R>::make(t[0], t[1], t[2]);
@@ -1865,87 +1907,97 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
     using V3 = typename PairRec<R>::T;
     EvalCtx<MIX> C;
     make_ctx<MIX, true>(C, P, D.s_slot[q], D.step_slot[q]);
-    const uint32_t npad = b.npad;
+    const DriftPar dp = drift_par(P, D, 1 - q);  // the next step's (fused steps)
+    const uint32_t npad = b.npad, cap = b.cap;
     const double4 pi = b.pos[i];
     const uint32_t idi = b.id[i];
     const R ai = (R)pi.w;
     R vi[3], wi[3];
     load_vw<MIX>(b, i, vi, wi);
     Acc<R> F, T;
-    const uint32_t cnt = b.ncnt[i], e0 = b.lo0[i];
+    const uint32_t e0 = b.lo0[i];
     const uint64_t im = b.imask[i], cm = b.cmask[i];
-    // pair k of the wave owning particle p sits at (p & ~(NP - 1)) * cap + k, NP = 64 / lanes
     const uint32_t wmask = ~(64u / (uint32_t)b.lanes - 1u);
-    size_t klo = (size_t)(i & wmask) * b.cap + b.qoff[i];
-    // entries in groups of GB: the loads of a group's stages (list, partner masks,
-    // pair records) are issued together; the sums still run in entry order
+    const size_t kw = (size_t)(i & wmask) * cap, k0 = kw + b.qoff[i];
+    // Pair k of the wave owning particle p sits at (p & ~(NP - 1)) * cap + k, NP = 64 /
+    // lanes.  First the entries [0, e0), whose partner j has the lower id: entry m of j's
+    // list holds the pair, and j's records run in the order of its interacting entries.
+    // Groups of GB entries, each stage's loads issued together.  No load sits behind a
+    // branch (a lane without an item reads its wave's first record instead), nor does a sum:
+    // such a lane adds +0, which leaves a sum that starts at +0 unchanged.
     constexpr uint32_t GB = 4;
-    for (uint32_t c0 = 0; c0 < cnt; c0 += GB) {
+    for (uint32_t c0 = 0; c0 < e0; c0 += GB) {
         uint32_t jj[GB], mm[GB], qj[GB];
         uint64_t imj[GB], cmj[GB];
 #pragma unroll
         for (uint32_t u = 0; u < GB; ++u) {
-            const uint32_t e = c0 + u;
-            jj[u] = 0u;
-            mm[u] = 0u;
-            if (e < cnt && e < e0) {  // lower-id partner j: its entry m holds the pair
-                jj[u] = b.nbr[e * npad + i];
-                mm[u] = b.mir[e * npad + i];
-            }
+            const uint32_t e = min(c0 + u, e0 - 1u);
+            jj[u] = b.nbr[e * npad + i];
+            mm[u] = b.mir[e * npad + i];
         }
 #pragma unroll
         for (uint32_t u = 0; u < GB; ++u) {
-            const uint32_t e = c0 + u;
-            imj[u] = 0ull;
-            cmj[u] = 0ull;
-            qj[u] = 0u;
-            if (e < cnt && e < e0) {
-                imj[u] = b.imask[jj[u]];
-                cmj[u] = b.cmask[jj[u]];
-                qj[u] = b.qoff[jj[u]];
-            }
+            imj[u] = b.imask[jj[u]];
+            cmj[u] = ROT ? 0ull : b.cmask[jj[u]];
+            qj[u] = b.qoff[jj[u]];
         }
-        size_t slot[GB];
+        V3 fv[GB], tv[GB];
         bool use[GB], ct[GB];
 #pragma unroll
         for (uint32_t u = 0; u < GB; ++u) {
-            const uint32_t e = c0 + u;
-            slot[u] = 0;
-            use[u] = false;
-            ct[u] = false;
-            if (e >= cnt) continue;
-            if (e < e0) {
-                use[u] = (imj[u] >> mm[u]) & 1ull;
-                slot[u] = (size_t)(jj[u] & wmask) * b.cap + qj[u] +
-                          (uint32_t)__popcll(imj[u] & ((1ull << mm[u]) - 1ull));
-                ct[u] = use[u] && (ROT || ((cmj[u] >> mm[u]) & 1ull));
-            } else if ((im >> e) & 1ull) {
-                use[u] = true;
-                slot[u] = klo++;
-                ct[u] = ROT || ((cm >> e) & 1ull);
-            }
+            use[u] = c0 + u < e0 && ((imj[u] >> mm[u]) & 1ull);
+            ct[u] = use[u] && (ROT || ((cmj[u] >> mm[u]) & 1ull));
+            const size_t slot =
+                (size_t)(jj[u] & wmask) * cap + qj[u] + (uint32_t)__popcll(imj[u] & ((1ull << mm[u]) - 1ull));
+            fv[u] = ((const V3*)b.pf)[use[u] ? slot : kw];
+            // with ROT the record of the torque on the higher-id particle
+            tv[u] = ((const V3*)(ROT ? b.pt2 : b.pt))[ct[u] ? slot : kw];
         }
+#pragma unroll
+        for (uint32_t u = 0; u < GB; ++u) {
+            F.add(0, use[u] ? (R)-1 * fv[u].x : (R)0);
+            F.add(1, use[u] ? (R)-1 * fv[u].y : (R)0);
+            F.add(2, use[u] ? (R)-1 * fv[u].z : (R)0);
+            // without ROT the record is n x (k_t s): each side scales it by its radius
+            T.add(0, ct[u] ? (ROT ? tv[u].x : ai * tv[u].x) : (R)0);
+            T.add(1, ct[u] ? (ROT ? tv[u].y : ai * tv[u].y) : (R)0);
+            T.add(2, ct[u] ? (ROT ? tv[u].z : ai * tv[u].z) : (R)0);
+        }
+    }
+    // then the particle's own pairs (entries from e0 on that interact): a contiguous run
+    // from k0, in entry order
+    const uint32_t nown = (uint32_t)__popcll(im);
+    uint64_t rest = im;
+    for (uint32_t c0 = 0; c0 < nown; c0 += GB) {
         V3 fv[GB], tv[GB];
+        bool use[GB], ct[GB];
 #pragma unroll
         for (uint32_t u = 0; u < GB; ++u) {
-            if (use[u]) fv[u] = ((const V3*)b.pf)[slot[u]];
-            // with ROT the torque record of the particle's own side of the pair
-            if (ct[u]) tv[u] = ((const V3*)(ROT && c0 + u < e0 ? b.pt2 : b.pt))[slot[u]];
+            use[u] = c0 + u < nown;
+            const uint32_t e = rest ? (uint32_t)__builtin_ctzll(rest) : 0u;
+            rest &= rest - 1ull;
+            ct[u] = use[u] && (ROT || ((cm >> e) & 1ull));
+            fv[u] = ((const V3*)b.pf)[use[u] ? k0 + c0 + u : kw];
+            tv[u] = ((const V3*)b.pt)[ct[u] ? k0 + c0 + u : kw];
         }
 #pragma unroll
         for (uint32_t u = 0; u < GB; ++u) {
-            if (!use[u]) continue;
-            const R sg = c0 + u < e0 ? (R)-1 : (R)1;
-            F.add(0, sg * fv[u].x);
-            F.add(1, sg * fv[u].y);
-            F.add(2, sg * fv[u].z);
-            if (ct[u]) {
-                const R sc = ROT ? (R)1 : ai;  // without ROT the record is n x (k_t s)
-                T.add(0, ROT ? tv[u].x : sc * tv[u].x);
-                T.add(1, ROT ? tv[u].y : sc * tv[u].y);
-                T.add(2, ROT ? tv[u].z : sc * tv[u].z);
-            }
+            F.add(0, use[u] ? fv[u].x : (R)0);
+            F.add(1, use[u] ? fv[u].y : (R)0);
+            F.add(2, use[u] ? fv[u].z : (R)0);
+            T.add(0, ct[u] ? (ROT ? tv[u].x : ai * tv[u].x) : (R)0);
+            T.add(1, ct[u] ? (ROT ? tv[u].y : ai * tv[u].y) : (R)0);
+            T.add(2, ct[u] ? (ROT ? tv[u].z : ai * tv[u].z) : (R)0);
         }
+    }
+    // what the kicks and the drift read, issued here (before any store of the launch)
+    // so that the one-body terms hide the wait
+    const double4 vh = b.vh[i], wh = b.wh[i];
+    double4 da = make_double4(0.0, 0.0, 0.0, 0.0);
+    double dacc = 0.0;
+    if (fuse) {
+        da = b.disp[i];
+        dacc = b.dacc[i];
     }
     if (C.do_one) {
 #pragma unroll
@@ -1964,11 +2016,16 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
     double Ft[3], Tt[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) { Ft[d] = F.get(d); Tt[d] = T.get(d); }
-    // a fused step keeps the full-step values in registers: only the last step of a
-    // launch sequence (never fused) leaves them in memory for the state readers
-    double4 vf, wf;
-    store_particle<MIX, false>(b, P, kick, i, Ft, Tt, 0ull, 0ull, bad, &vf, &wf, !fuse);
-    if (fuse) {
+    bad = nonfinite(Ft, Tt);
+    // kick 2; a fused step keeps the full-step values in registers: only the last step
+    // of a launch sequence (never fused) leaves them in memory for the state readers
+    double4 vf = vh, wf = wh;
+    if (kick) half_kick(pi.w, dp.rho, dp.half_dt, Ft, Tt, vf, wf);
+    if (!fuse) {
+        store_ft<MIX>(b, i, Ft, Tt);
+        b.vf[i] = vf;
+        b.wf[i] = wf;
+    } else {
         if (MIX) {  // the next kick uses the force as stored
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
@@ -1976,7 +2033,7 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
                 Tt[d] = (double)(float)Tt[d];
             }
         }
-        integrate_particle<MIX>(b, P, D, 1 - q, i, pi, vf, wf, Ft, Tt, dblk, expire);
+        integrate_particle<MIX>(b, dp, i, pi, vf, wf, Ft, Tt, da, dacc, dblk, expire);
     }
 }
 

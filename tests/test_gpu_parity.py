@@ -229,7 +229,9 @@ def test_mixed_precision_create(P):
 
 
 def test_ragged_and_tiny_systems(P):
-    for n, phi in ((2, 0.001), (37, 0.3), (257, 0.45), (1000, 0.55)):
+    """A lone sphere (one-body terms only), one pair in contact, and sizes that leave
+    ragged tiles: the first evaluation, then five steps, against the oracle."""
+    for n, phi in ((1, 0.001), (2, 0.001), (37, 0.3), (257, 0.45), (1000, 0.55)):
         _say(f"case: ragged n={n} phi={phi}")
         w = gen.Workload("t", n, phi, 1.0, kT=1.0, seed=n)
         a = gen.radii_bidisperse(n, n)
@@ -243,6 +245,15 @@ def test_ragged_and_tiny_systems(P):
         sim = P.Sim(_cfg(P, st), a, x, v, om)
         orc = O.Oracle(O.Params(L=st["L"], **st["params"]), a, x, v, om)
         _compare_eval(P, sim, orc, TOL_F64)
+        sim.step(5)
+        orc.step(5)
+        gs, os_ = sim.get_state(), orc.state()
+        dx = np.abs(gs["x"] - os_["x"]).max()
+        dv = np.abs(gs["v"] - os_["v"]).max() / np.abs(os_["v"]).max()
+        _say(f"  after 5 steps: |dx| {dx:.2e} |dv|/|v| {dv:.2e}")
+        assert gs["step"] == os_["step"] and gs["s_le"] == os_["s_le"]
+        assert dx < 1e-11 and dv < 1e-9
+        assert np.array_equal(sim.pairs(), orc.pairs())
 
 
 def test_batched_replicas_match_single(P):
