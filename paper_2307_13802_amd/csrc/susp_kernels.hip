@@ -1728,9 +1728,11 @@ __global__ __launch_bounds__(256, (MIX || OCC) ? 3 : 2) void k_half(Bufs b, int 
         }
     }
 
-    if (!go()) return;
+    // (the constants are read before the bookkeeping's stores: after them the
+    // compiler would read them again from memory)
     EvalCtx<MIX> C;
     make_ctx<MIX, true>(C, P, s_le, step);
+    if (!go()) return;
 
     // The queue holds up to qc items of a wave at a time: all of them (NP * 64), or with
     // OCC b.qcap <= 2048 (a wave's interacting pairs seldom exceed a few hundred; more
@@ -1877,13 +1879,16 @@ __global__ __launch_bounds__(256, (MIX || OCC) ? 3 : 2) void k_half(Bufs b, int 
 
 template <bool MIX, bool ROT>
 __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& P, const RepDyn& D, int q, int kick,
-                                                int fuse, uint32_t i, float& dblk, bool& expire, bool& bad);
+                                                int fuse, uint32_t i, float& dblk, bool& expire, bool& bad,
+                                                uint32_t halted);
 
 // fuse: also take kick 1 and the drift of the next step (parity 1 - q) from the
-// new forces, as the integrate launch of that step would
+// new forces, as the integrate launch of that step would.  The halted test follows
+// the particle's own loads (all in bounds whatever the step's state), so that they
+// are in flight beside the flag's.
 template <bool MIX, bool ROT>
 __global__ __launch_bounds__(256) void k_gather(Bufs b, int q, int kick, int fuse, uint32_t only_rep) {
-    if (b.sys->halted) return;
+    const uint32_t halted = b.sys->halted;
     const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t i = tile * 256 + threadIdx.x;
     const uint32_t r = __builtin_amdgcn_readfirstlane(b.blk_rep[tile]);
@@ -1892,7 +1897,8 @@ __global__ __launch_bounds__(256) void k_gather(Bufs b, int q, int kick, int fus
     RepDyn& D = b.dyn[r];
     float dblk = 0.0f;
     bool expire = false, bad = false;
-    if (i - P.p_begin < P.n) gather_particle<MIX, ROT>(b, P, D, q, kick, fuse, i, dblk, expire, bad);
+    if (i - P.p_begin < P.n) gather_particle<MIX, ROT>(b, P, D, q, kick, fuse, i, dblk, expire, bad, halted);
+    if (halted) return;
     if (bad) atomicOr(&D.health, H_NAN);
     if (fuse) {
         if (expire) atomicOr(&b.sys->expire[1 - q], 1u);
@@ -1902,7 +1908,8 @@ __global__ __launch_bounds__(256) void k_gather(Bufs b, int q, int kick, int fus
 
 template <bool MIX, bool ROT>
 __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& P, const RepDyn& D, int q, int kick,
-                                                int fuse, uint32_t i, float& dblk, bool& expire, bool& bad) {
+                                                int fuse, uint32_t i, float& dblk, bool& expire, bool& bad,
+                                                uint32_t halted) {
     using R = typename std::conditional<MIX, float, double>::type;
     using V3 = typename PairRec<R>::T;
     EvalCtx<MIX> C;
@@ -1919,6 +1926,7 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
     const uint64_t im = b.imask[i], cm = b.cmask[i];
     const uint32_t wmask = ~(64u / (uint32_t)b.lanes - 1u);
     const size_t kw = (size_t)(i & wmask) * cap, k0 = kw + b.qoff[i];
+    if (halted) return;
     // Pair k of the wave owning particle p sits at (p & ~(NP - 1)) * cap + k, NP = 64 /
     // lanes.  First the entries [0, e0), whose partner j has the lower id: entry m of j's
     // list holds the pair, and j's records run in the order of its interacting entries.
