@@ -76,6 +76,17 @@ struct SysDyn {
 
 // Device buffers of one handle.  Particle arrays have npad entries, in
 // Morton-cell order; replicas are contiguous and padded to kTile.
+// Per particle, for the half-pair kernel and its gather (one 16-byte record, so
+// that a partner's lookup touches one line): bit e of im = entry e (a higher-id
+// partner) interacts in the last evaluation; qoff = the particle's first pair within
+// its wave's run (queue order); lo0 = first entry whose partner has the higher id
+// (lists are sorted by id).
+struct alignas(16) PairIdx {
+    uint64_t im;
+    uint32_t qoff;
+    uint32_t lo0;
+};
+
 struct Bufs {
     uint32_t npad, nrep, nkeys_total, cap;   // cap = neighbour slots per particle
     int mixed;
@@ -101,10 +112,8 @@ struct Bufs {
     // half-pair evaluation: each interacting pair is evaluated once, by its
     // lower-id particle, into its list entry; the higher-id particle reads it
     // through the mirror index
-    uint8_t* lo0;     // first entry whose partner has the higher id (lists are sorted by id)
+    PairIdx* pidx;    // per particle: interaction mask, queue offset, first higher-id entry
     uint8_t* mir;     // [e * npad + i], entry with a lower-id partner j: the entry of i in j's list
-    uint64_t* imask;  // bit e: entry e (higher-id partner) interacts in the last evaluation
-    uint16_t* qoff;   // first of particle i's pairs within its wave's run (queue order)
     void* pf;         // 3 doubles / 4 floats per pair: force on the lower-id particle; the pairs of
                       // the wave owning particles [64 w, 64 w + 64) sit in queue order
                       // (particles in order, entries in order) from 64 w * cap

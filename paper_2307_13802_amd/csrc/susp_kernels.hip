@@ -713,17 +713,17 @@ __global__ __launch_bounds__(256) void k_rb_nlist(Bufs b, int q, int in_step) {
     b.smask[i] = sm;
 }
 
-// Mirror index of the half-pair variant: lo0[i] = first entry whose partner
-// has the higher id; for an entry with a lower-id partner j, the position of
-// i in j's list (lists are symmetric: the range test is symmetric in i, j).
+// Mirror index of the half-pair variant: lo0 = first entry whose partner has
+// the higher id (in pidx, whose mask it clears); for an entry with a lower-id
+// partner j, the position of i in j's list (lists are symmetric: the range test
+// is symmetric in i, j).
 __global__ __launch_bounds__(256) void k_rb_mirror(Bufs b) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t r = __builtin_amdgcn_readfirstlane(b.blk_rep[i / kTile]);
     const RepParams& P = b.reps[r];
     const uint32_t npad = b.npad;
     if (i - P.p_begin >= P.n) {
-        b.lo0[i] = 0;
-        b.imask[i] = 0ull;
+        b.pidx[i] = PairIdx{0ull, 0u, 0u};
         return;
     }
     const uint32_t idi = b.id[i], cnt = b.ncnt[i];
@@ -747,8 +747,7 @@ __global__ __launch_bounds__(256) void k_rb_mirror(Bufs b) {
         }
         b.mir[e * npad + i] = (uint8_t)m;
     }
-    b.lo0[i] = (uint8_t)e0;
-    b.imask[i] = 0ull;
+    b.pidx[i] = PairIdx{0ull, 0u, e0};
 }
 
 // after a build every list holds all pairs within range plus the full skin;
@@ -1665,7 +1664,7 @@ __global__ __launch_bounds__(256, (MIX || OCC) ? 3 : 2) void k_half(Bufs b, int 
     // the replica's parameters, such as the noise keys, in scalar registers)
     const uint32_t r = __builtin_amdgcn_readfirstlane(b.blk_rep[base / kTile]);
     const uint32_t halted = b.sys->halted, expired = b.sys->expire[q] & (advance ? ~0u : 0u);
-    const uint32_t cnt = min(b.ncnt[i], b.cap), e_lo = b.lo0[i];
+    const uint32_t cnt = min(b.ncnt[i], b.cap), e_lo = b.pidx[i].lo0;
     const double4 pi = b.pos[i];
     const uint64_t cm_i = b.cmask[i];
     // the first group of partners as well in FP64 (in mixed precision, where the
@@ -1760,8 +1759,7 @@ __global__ __launch_bounds__(256, (MIX || OCC) ? 3 : 2) void k_half(Bufs b, int 
     const uint32_t total = __shfl(incl, 63);
     const uint32_t qk0 = incl - cnt_i;  // the particle's first position in the wave's queue order
     if (sub == 0 && valid) {
-        b.imask[i] = im;
-        b.qoff[i] = (uint16_t)qk0;
+        b.pidx[i] = PairIdx{im, qk0, e_lo};
     }
     // results of this wave's pairs: a contiguous run in queue order
     V3* const pf = (V3*)b.pf + (size_t)base * b.cap;
@@ -1922,10 +1920,11 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
     R vi[3], wi[3];
     load_vw<MIX>(b, i, vi, wi);
     Acc<R> F, T;
-    const uint32_t e0 = b.lo0[i];
-    const uint64_t im = b.imask[i], cm = b.cmask[i];
+    const PairIdx pq = b.pidx[i];
+    const uint32_t e0 = pq.lo0;
+    const uint64_t im = pq.im, cm = b.cmask[i];
     const uint32_t wmask = ~(64u / (uint32_t)b.lanes - 1u);
-    const size_t kw = (size_t)(i & wmask) * cap, k0 = kw + b.qoff[i];
+    const size_t kw = (size_t)(i & wmask) * cap, k0 = kw + pq.qoff;
     if (halted) return;
     // Pair k of the wave owning particle p sits at (p & ~(NP - 1)) * cap + k, NP = 64 /
     // lanes.  First the entries [0, e0), whose partner j has the lower id: entry m of j's
@@ -1945,9 +1944,10 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
         }
 #pragma unroll
         for (uint32_t u = 0; u < GB; ++u) {
-            imj[u] = b.imask[jj[u]];
+            const PairIdx pj = b.pidx[jj[u]];
+            imj[u] = pj.im;
+            qj[u] = pj.qoff;
             cmj[u] = ROT ? 0ull : b.cmask[jj[u]];
-            qj[u] = b.qoff[jj[u]];
         }
         V3 fv[GB], tv[GB];
         bool use[GB], ct[GB];

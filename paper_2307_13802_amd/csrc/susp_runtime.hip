@@ -585,10 +585,8 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         b.hs = s->dalloc(np * cap * 3 * (s->mixed ? sizeof(float) : sizeof(double)));
         b.cmask = s->alloc<uint64_t>(np);
         b.smask = s->alloc<uint64_t>(np);
-        b.lo0 = s->alloc<uint8_t>(np);
+        b.pidx = s->alloc<PairIdx>(np);
         b.mir = s->alloc<uint8_t>(np * cap);
-        b.imask = s->alloc<uint64_t>(np);
-        b.qoff = s->alloc<uint16_t>(np);
         b.pf = s->dalloc(np * cap * (s->mixed ? 4 * sizeof(float) : 3 * sizeof(double)));
         b.pt = s->dalloc(np * cap * (s->mixed ? 4 * sizeof(float) : 3 * sizeof(double)));
         b.pt2 = s->dalloc(np * cap * (s->mixed ? 4 * sizeof(float) : 3 * sizeof(double)));
