@@ -122,6 +122,51 @@ def test_injected_contacts_and_offset(P):
         _compare_eval(P, sim, orc, TOL_F64)
 
 
+def _cut_boundary(x0, a1, a2, xi_cut):
+    """The largest x with (x0 - x)^2 <= ((a1 + a2)(1 + xi_cut / 2))^2 in FP64, the range test's own arithmetic
+    (Sec. II.B, cut-off inclusive), and the next double above it: the last position in range and the first out."""
+    rc = (a1 + a2) * (1.0 + 0.5 * xi_cut)
+    inside = lambda x: (x0 - x) * (x0 - x) <= rc * rc
+    x = x0 + rc
+    while inside(x):
+        x = float(np.nextafter(x, np.inf))
+    while not inside(x):
+        x = float(np.nextafter(x, -np.inf))
+    return x, float(np.nextafter(x, np.inf))
+
+
+def test_adversarial_pairs(P):
+    """Hand-built pairs, each far from the others: one exactly at the cut-off (in range), one an ulp beyond it,
+    one at a gap far below xi_min (the regularised lubrication), one in shallow contact across the sheared
+    y boundary, and one in contact across the x boundary; offsets 0, L/3 and L minus 1e-9."""
+    L = (30.0, 30.0, 30.0)
+    prm = dict(rho=0.1, eta=0.1, kn=1e4, kt=2e4 / 7, mu=0.5, kT=0.5, gammadot=0.4, dt=1e-4, xi_cut=0.05,
+               xi_min=1e-3, seed=5)
+    x_in, x_out = _cut_boundary(5.0, 1.0, 1.4, prm["xi_cut"])
+    rng = np.random.default_rng(12)
+    for s_le in (0.0, L[0] / 3.0, L[0] - 1e-9):
+        a = np.array([1.0, 1.4, 1.0, 1.4, 1.0, 1.0, 1.4, 1.0, 1.0, 1.4])
+        x = np.array([
+            [5.0, 5.0, 5.0], [x_in, 5.0, 5.0],                       # gap exactly at the cut-off: in range
+            [5.0, 15.0, 5.0], [x_out, 15.0, 5.0],                    # an ulp beyond: out of range
+            [15.0, 5.0, 20.0], [15.0 + 2.0 + 1e-6, 5.0, 20.0],       # gap 1e-6 << xi_min
+            [12.0, 0.3, 12.0], [(12.0 + s_le) % L[0], L[1] - 2.09, 12.0],  # contact through y = 0 / Ly
+            [0.2, 20.0, 25.0], [L[0] - 1.9, 20.0, 25.0],             # contact through x = 0 / Lx
+        ])
+        v = rng.normal(size=(10, 3)) * 0.3
+        w = rng.normal(size=(10, 3)) * 0.3
+        _say(f"case: adversarial pairs s_le={s_le:.9f} (cut-off at x={x_in!r}, first out {x_out!r})")
+        orc = O.Oracle(O.Params(L=L, **prm), a, x, v, w, s_le=s_le)
+        sim = P.Sim(P.Config(box=L, **prm, max_overlap=1.0), a, x, v, w)
+        sim.set_state(0, x, v, w, s_le=s_le, step=0)
+        _compare_eval(P, sim, orc, TOL_F64)
+        pairs = {tuple(p) for p in np.asarray(sim.pairs()).tolist()}
+        assert (0, 1) in pairs and (2, 3) not in pairs and (4, 5) in pairs
+        assert (6, 7) in pairs and (8, 9) in pairs
+        contacts = {tuple(c) for c in np.asarray(sim.contacts()[0]).tolist()}
+        assert (6, 7) in contacts and (8, 9) in contacts and (4, 5) not in contacts
+
+
 def test_step_trajectory_fp64(P):
     """Short trajectory: the same state after each step (chaos sets in only later)."""
     st = _state(n=500, phi=0.5)
@@ -273,6 +318,29 @@ def test_batched_replicas_match_single(P):
         _say(f"  replica {k}: max |dx| {np.abs(a['x'] - b['x']).max():.2e}")
         for key in ("x", "v", "w", "F", "T"):
             assert np.array_equal(a[key], b[key]), key
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batched_sweep_replicas_match_single(P, prec):
+    """Eight replicas of a flow-curve sweep in one handle (uneven N, four volume fractions, Pe from 1e-2 to 1e3,
+    own seeds), half-pair kernel: each bit-identical to the same replica run alone, in both precisions."""
+    spec = [(300, 0.45, 1e-2), (777, 0.50, 0.1), (512, 0.54, 1.0), (1200, 0.58, 10.0), (450, 0.45, 1e2),
+            (900, 0.50, 1e3), (600, 0.54, 0.3), (1024, 0.58, 30.0)]
+    sts = [gen.make_state(gen.Workload(f"sweep{k}", n, phi, pe, seed=20 + k)) for k, (n, phi, pe) in enumerate(spec)]
+    cfgs = [P.Config(box=st["L"], precision=prec, pair_kernel=P.KERNEL_HALF, **st["params"]) for st in sts]
+    _say(f"case: 8 sweep replicas batched vs alone, 25 steps, precision {prec}")
+    multi = P.Sim(cfgs, [s["radii"] for s in sts], [s["x"] for s in sts], [s["v"] for s in sts],
+                  [s["w"] for s in sts])
+    multi.step(25)
+    for k, st in enumerate(sts):
+        one = P.Sim(cfgs[k], st["radii"], st["x"], st["v"], st["w"])
+        one.step(25)
+        a, b = multi.get_state(k), one.get_state()
+        for key in ("x", "v", "w", "F", "T"):
+            assert np.array_equal(a[key], b[key]), (k, key)
+        assert np.array_equal(multi.stress_series(k), one.stress_series())
+        one.close()
+    multi.close()
 
 
 @pytest.mark.parametrize("kernel, lanes", [(0, 1), (0, 2), (3, 1), (3, 4)])
