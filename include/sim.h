@@ -188,8 +188,9 @@ typedef struct sim_stats_t {
 int sim_validate(const sim_config* cfg, const double* radii);
 
 /* Creates a handle with n_replicas systems.  For replica r: radii[r] -> n
- * doubles; x0[r] -> 3n doubles inside [0, L); v0[r], w0[r] -> 3n doubles of
- * velocities and angular velocities, or NULL for U^inf(x) and Omega^inf.
+ * doubles; x0[r] -> 3n doubles inside [0, L); v0[r], w0[r] -> 3n finite doubles
+ * of velocities and angular velocities, or NULL for U^inf(x) and Omega^inf
+ * (a coordinate outside [0, L) or a NaN or infinity: SIM_EINVAL).
  * hip_stream is a hipStream_t (NULL = the null stream).  Evaluates the forces
  * of every replica at its initial state (Sec. II force law at step step0,
  * using v0 and w0), so the first sim_step starts a velocity-Verlet step.
@@ -267,7 +268,8 @@ int sim_positions(sim* s, int32_t replica, double* out_3n);
 int sim_get_state(sim* s, int32_t replica, double* x, double* v, double* w, double* F, double* T,
                   double* le_offset, uint64_t* step);
 
-/* Replaces the state of one replica.  x, v, w: 3n doubles (required).
+/* Replaces the state of one replica.  x, v, w: 3n doubles (required; x inside
+ * [0, L), every value given here finite, else SIM_EINVAL).
  * c_ij: n_contacts (id_i, id_j) pairs with id_i < id_j and c_s their springs
  * (3 doubles each); pairs that are not overlapping are ignored.  If F and T
  * are given they are taken as the forces of the state (a restart); if both

@@ -472,6 +472,14 @@ int sim_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, v
     return SIM_OK;
 }
 
+// index of the first NaN or infinity among n values (-1: none, or no array)
+static int64_t first_nonfinite(const double* a, uint64_t n) {
+    if (!a) return -1;
+    for (uint64_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return (int64_t)i;
+    return -1;
+}
+
 int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* radii, const double* const* x0,
                const double* const* v0, const double* const* w0, void* hip_stream, sim** out) {
     if (!out) return fail(nullptr, SIM_EINVAL, "null output handle");
@@ -489,6 +497,11 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
             if (!(x0[r][i] >= 0.0 && x0[r][i] < L))
                 return fail(nullptr, SIM_EINVAL, fmt("replica %d: coordinate %u outside [0, L)", r, i));
         }
+        const int64_t bv = first_nonfinite(v0 ? v0[r] : nullptr, 3ull * cfgs[r].n);
+        const int64_t bw = first_nonfinite(w0 ? w0[r] : nullptr, 3ull * cfgs[r].n);
+        if (bv >= 0 || bw >= 0)
+            return fail(nullptr, SIM_EINVAL, fmt("replica %d: %s value %lld is not finite", r, bv >= 0 ? "velocity" :
+                                                 "angular velocity", (long long)(bv >= 0 ? bv : bw)));
     }
     sim* s = new sim();
     try {
@@ -1107,6 +1120,12 @@ int sim_set_state(sim* s, int32_t r, const double* x, const double* v, const dou
     const RepParams& P = s->P[r];
     for (uint32_t i = 0; i < 3 * P.n; ++i)
         if (!(x[i] >= 0.0 && x[i] < P.L[i % 3])) return fail(s, SIM_EINVAL, fmt("coordinate %u outside [0, L)", i));
+    const char* names[5] = {"velocity", "angular velocity", "force", "torque", "spring"};
+    const double* arrays[5] = {v, w, F, T, c_s};
+    const uint64_t counts[5] = {3ull * P.n, 3ull * P.n, 3ull * P.n, 3ull * P.n, 3ull * (uint64_t)n_contacts};
+    for (int k = 0; k < 5; ++k)
+        if (const int64_t b = first_nonfinite(arrays[k], counts[k]); b >= 0)
+            return fail(s, SIM_EINVAL, fmt("%s value %lld is not finite", names[k], (long long)b));
     try {
         upload_state(s, r, x, v, w, F, T, c_ij, c_s, n_contacts);
         set_dyn(s, r, le_offset, step);

@@ -97,3 +97,25 @@ def test_strerror_and_null_handles():
         assert L.sim_strerror(code)
     assert L.sim_step(None, 1) == S.EINVAL
     assert L.sim_destroy(None) == S.OK
+
+
+def test_create_rejects_bad_state_on_the_host():
+    """sim_create checks its host inputs before any device work (this runs without a GPU): a coordinate
+    outside [0, L), a NaN velocity or an infinite angular velocity is SIM_EINVAL with a message."""
+    n = 8
+    arr = (S._Config * 1)(_cfg().c(n))
+    a = np.full(n, 1.0)
+    x = np.random.default_rng(0).random((n, 3)) * 19.0
+    v, w = np.zeros((n, 3)), np.zeros((n, 3))
+
+    def ptr(m):
+        return (C.POINTER(C.c_double) * 1)(m.ctypes.data_as(C.POINTER(C.c_double)))
+
+    for key, val, needle in (("x", 20.0, "outside [0, L)"), ("x", np.nan, "outside [0, L)"),
+                             ("v", np.nan, "velocity value"), ("w", np.inf, "angular velocity value")):
+        arrs = dict(x=x.copy(), v=v.copy(), w=w.copy())
+        arrs[key][2, 1] = val
+        h = C.c_void_p()
+        rc = P.lib().sim_create(arr, 1, ptr(a), ptr(arrs["x"]), ptr(arrs["v"]), ptr(arrs["w"]), None, C.byref(h))
+        assert rc == S.EINVAL and not h.value
+        assert needle in S.last_error(), S.last_error()

@@ -384,6 +384,26 @@ def test_health_errors(P):
     with pytest.raises(P.SimError) as e:
         P.Sim(_cfg(P, st, nlist_cap=2), st["radii"], st["x"], st["v"], st["w"])
     assert e.value.code == -5
+    # inputs the host rejects before anything reaches the GPU
+    bad = [("NaN coordinate", "x", (3, 1), np.nan), ("coordinate equal to L", "x", (4, 2), st["L"][2]),
+           ("infinite velocity", "v", (5, 0), np.inf), ("NaN angular velocity", "w", (6, 1), np.nan)]
+    for what, key, (i, d), val in bad:
+        _say(f"case: {what} rejected at creation")
+        arr = {k: st[k].copy() for k in ("x", "v", "w")}
+        arr[key][i, d] = val
+        with pytest.raises(P.SimError) as e:
+            P.Sim(_cfg(P, st), st["radii"], arr["x"], arr["v"], arr["w"])
+        assert e.value.code == -1  # SIM_EINVAL
+    sim = P.Sim(_cfg(P, st), st["radii"], st["x"], st["v"], st["w"])
+    zero = np.zeros_like(st["x"])
+    for what, F, T in (("NaN force", np.where(np.arange(3) == 1, np.nan, zero), zero),
+                       ("infinite torque", zero, np.where(np.arange(3) == 2, np.inf, zero))):
+        _say(f"case: {what} rejected by set_state")
+        with pytest.raises(P.SimError) as e:
+            sim.set_state(0, st["x"], st["v"], st["w"], F=F, T=T)
+        assert e.value.code == -1  # SIM_EINVAL
+    sim.step(2)  # the handle is unchanged and still steps
+    assert np.isfinite(sim.get_state()["x"]).all()
 
 
 def test_large_sampled_fp64(P):
