@@ -273,6 +273,35 @@ def test_mixed_precision_create(P):
     _compare_eval(P, sim, orc, TOL_MIX, exact=False)
 
 
+@pytest.mark.parametrize("pe", [0.1, 10.0])
+def test_mixed_viscosity_shadow(P, pe):
+    """The shadow protocol on a small system: eight states along an FP64 trajectory (5,000 bidisperse spheres,
+    phi = 0.55) are evaluated by an FP64 and a mixed handle; the relative viscosity of each (contact +
+    lubrication + drag shear stress over eta gammadot, Sec. II.E) and its mean agree within 1e-4.  (These are
+    the first 400 steps from a relaxed packing: at Pe = 0.1, where gammadot is small, the values themselves swing
+    widely, even in sign; the test compares the two precisions at identical states.)"""
+    st = gen.make_state(gen.Workload("shadow", 5000, 0.55, pe, seed=3))
+    p = st["params"]
+    mk = lambda prec: P.Sim(P.Config(box=st["L"], precision=prec, **p), st["radii"], st["x"], st["v"], st["w"])
+    traj, p64, p32 = mk(P.FP64), mk(P.FP64), mk(P.MIXED)
+    _say(f"case: shadow protocol N=5000 phi=0.55 Pe={pe}, 8 states 50 steps apart")
+    e64, e32 = [], []
+    for _ in range(8):
+        traj.step(50)
+        s = traj.get_state()
+        cij, cs, _ = traj.contacts()
+        for pr, acc in ((p64, e64), (p32, e32)):
+            pr.set_state(0, s["x"], s["v"], s["w"], s_le=s["s_le"], step=s["step"], contacts=(cij, cs))
+            acc.append(pr.stress(0, P.STRESS_TOTAL, P.STRESS_LAST)[0, 1] / (p["eta"] * p["gammadot"]))
+    e64, e32 = np.array(e64), np.array(e32)
+    rel = np.abs(e32 - e64) / np.abs(e64)
+    mean_rel = abs(e32.mean() - e64.mean()) / abs(e64.mean())
+    _say(f"  eta_r FP64 {e64.mean():.6f}; mixed vs FP64: max rel {rel.max():.2e}, mean rel {mean_rel:.2e}")
+    assert rel.max() <= 1e-4 and mean_rel <= 1e-4
+    for h in (traj, p64, p32):
+        h.close()
+
+
 def test_ragged_and_tiny_systems(P):
     """A lone sphere (one-body terms only), one pair in contact, and sizes that leave
     ragged tiles: the first evaluation, then five steps, against the oracle."""
