@@ -14,6 +14,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 import subprocess
+import threading
 from dataclasses import dataclass
 
 import numpy as np
@@ -49,37 +50,52 @@ class _Params(C.Structure):
 
 
 _lib = None
+_lib_lock = threading.Lock()
 
 
 def lib():
     global _lib
-    if _lib is None:
-        _lib = C.CDLL(build())
-        dp = C.POINTER(C.c_double)
-        up = C.POINTER(C.c_uint32)
-        _lib.orc_new.restype = C.c_void_p
-        _lib.orc_new.argtypes = [C.POINTER(_Params), C.c_int, dp, dp, dp, dp, C.c_double, C.c_uint64,
-                                 C.c_int, up, dp, dp, dp]
-        _lib.orc_free.argtypes = [C.c_void_p]
-        _lib.orc_step.argtypes = [C.c_void_p, C.c_long, dp]
-        _lib.orc_eval.argtypes = [C.c_void_p]
-        _lib.orc_get_state.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, dp, C.POINTER(C.c_uint64)]
-        _lib.orc_get_norms.argtypes = [C.c_void_p, dp, dp]
-        _lib.orc_get_stress.argtypes = [C.c_void_p, dp]
-        _lib.orc_structural_stress.argtypes = [C.c_void_p, dp]
-        _lib.orc_get_disp.argtypes = [C.c_void_p, dp]
-        _lib.orc_rdf.argtypes = [C.c_void_p, C.c_double, C.c_int, C.POINTER(C.c_uint64)]
-        _lib.orc_lub_rot_scalars.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, dp]
-        _lib.orc_get_contacts.restype = C.c_int
-        _lib.orc_get_contacts.argtypes = [C.c_void_p, C.c_int, up, dp, C.POINTER(C.c_int32)]
-        _lib.orc_get_pairs.restype = C.c_int
-        _lib.orc_get_pairs.argtypes = [C.c_void_p, C.c_int, up]
-        _lib.orc_verlet_pairs.restype = C.c_long
-        _lib.orc_verlet_pairs.argtypes = [C.c_void_p, C.c_double, C.c_long, up]
-        _lib.orc_particle_force.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, dp]
-        _lib.orc_philox4x32_10.argtypes = [up, up, up]
-        _lib.orc_gauss3.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, dp]
-        _lib.orc_lub_scalars.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, dp, dp]
+    if _lib is not None:
+        return _lib
+    with _lib_lock:
+        if _lib is None:
+            _lib = _load()
+    return _lib
+
+
+def _load():
+    """Loads the compiled oracle and declares its C signatures."""
+    _lib = C.CDLL(build())
+    dp = C.POINTER(C.c_double)
+    up = C.POINTER(C.c_uint32)
+    _lib.orc_new.restype = C.c_void_p
+    _lib.orc_new.argtypes = [C.POINTER(_Params), C.c_int, dp, dp, dp, dp, C.c_double, C.c_uint64,
+                             C.c_int, up, dp, dp, dp]
+    _lib.orc_free.argtypes = [C.c_void_p]
+    _lib.orc_step.argtypes = [C.c_void_p, C.c_long, dp]
+    _lib.orc_eval.argtypes = [C.c_void_p]
+    _lib.orc_get_state.argtypes = [C.c_void_p, dp, dp, dp, dp, dp, dp, C.POINTER(C.c_uint64)]
+    _lib.orc_get_norms.argtypes = [C.c_void_p, dp, dp]
+    _lib.orc_get_stress.argtypes = [C.c_void_p, dp]
+    _lib.orc_get_stress_all.argtypes = [C.c_void_p, dp]
+    _lib.orc_eta_r.restype = C.c_double
+    _lib.orc_eta_r.argtypes = [C.c_void_p]
+    _lib.orc_acf.argtypes = [dp, C.c_long, C.c_long, dp]
+    _lib.orc_run_rdf.argtypes = [C.c_void_p, C.c_long, C.c_long, C.c_double, C.c_int, C.POINTER(C.c_uint64)]
+    _lib.orc_structural_stress.argtypes = [C.c_void_p, dp]
+    _lib.orc_get_disp.argtypes = [C.c_void_p, dp]
+    _lib.orc_rdf.argtypes = [C.c_void_p, C.c_double, C.c_int, C.POINTER(C.c_uint64)]
+    _lib.orc_lub_rot_scalars.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, dp]
+    _lib.orc_get_contacts.restype = C.c_int
+    _lib.orc_get_contacts.argtypes = [C.c_void_p, C.c_int, up, dp, C.POINTER(C.c_int32)]
+    _lib.orc_get_pairs.restype = C.c_int
+    _lib.orc_get_pairs.argtypes = [C.c_void_p, C.c_int, up]
+    _lib.orc_verlet_pairs.restype = C.c_long
+    _lib.orc_verlet_pairs.argtypes = [C.c_void_p, C.c_double, C.c_long, up]
+    _lib.orc_particle_force.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, dp]
+    _lib.orc_philox4x32_10.argtypes = [up, up, up]
+    _lib.orc_gauss3.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, dp]
+    _lib.orc_lub_scalars.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, dp, dp]
     return _lib
 
 
@@ -139,6 +155,14 @@ def lub_scalars(eta, ai, aj, xi):
     ya = np.zeros(1)
     lib().orc_lub_scalars(eta, ai, aj, xi, _d(xa), _d(ya))
     return float(xa[0]), float(ya[0])
+
+
+def acf(series, nlag):
+    """Time autocorrelation out[k] = mean_t s(t) s(t + k), k < nlag (Sec. IV.B)."""
+    s = np.ascontiguousarray(series, dtype=np.float64).reshape(-1)
+    out = np.zeros(int(nlag))
+    lib().orc_acf(_d(s), len(s), int(nlag), _d(out))
+    return out
 
 
 def lub_rot_scalars(eta, ai, aj, xi):
@@ -211,6 +235,24 @@ class Oracle:
         out = np.zeros(27)
         lib().orc_get_stress(self._h, _d(out))
         return out.reshape(3, 3, 3)
+
+    def stress_all(self):
+        """(5, 3, 3): contact, lubrication, Brownian, drag stresslet and total (hydrodynamic +
+        contact), Sec. II.A-II.D, IV.D."""
+        out = np.zeros(45)
+        lib().orc_get_stress_all(self._h, _d(out))
+        return out.reshape(5, 3, 3)
+
+    def eta_r(self):
+        """Relative viscosity of the last evaluation, Sec. II.E."""
+        return float(lib().orc_eta_r(self._h))
+
+    def run_rdf(self, nsteps, every, r_max, nbins, counts=None):
+        """Runs nsteps steps, adding the pair-distance histogram after every `every`-th step."""
+        out = np.zeros(nbins, np.uint64) if counts is None else counts
+        lib().orc_run_rdf(self._h, int(nsteps), int(every), float(r_max), int(nbins),
+                          out.ctypes.data_as(C.POINTER(C.c_uint64)))
+        return out
 
     def displacement(self):
         """(n, 3) accumulated non-affine displacement (drift minus the imposed flow)."""

@@ -25,7 +25,14 @@
  *   Sec. II.C, eq. (force_brownian_drag), (torque_brownian_drag),
  *       (force_brownian_lub): one-body and pairwise Brownian forces with
  *       amplitude sqrt(2 kT / dt) times the square root of the resistance.
+ *   Sec. II.B (after eq. torque_drag): drag stresslet (20/3) pi eta a^3 E per
+ *       particle, summed and divided by V.
  *   Sec. II.D: instantaneous Brownian stress -F^{B,L} (x) r / V.
+ *   Sec. IV.D: total stress = hydrodynamic (lubrication + drag) + contact;
+ *       Sec. II.E: relative viscosity eta_r = Sigma_xy / (eta gammadot).
+ *   Sec. IV.F: short-ranged repulsion A/kappa exp(-h/kappa) n (switch rep_A).
+ *   Sec. III.A, IV.B: pair-distance histograms and stress autocorrelations
+ *       (the observables of g(r) and of the Green-Kubo integral).
  *   Sec. II.E: sheared periodic box; the tilted-box remap is represented by a
  *       Lees-Edwards offset (same image lattice, no effect on forces).
  *
@@ -46,6 +53,8 @@
  *       +F^{B,L}, on the higher id -F^{B,L}.
  *   U^inf = gammadot (y - Ly/2) e_x, Omega^inf = (0, 0, -gammadot/2).
  *   Stress is divided by the volume only.
+ *   The repulsion (no cut-off in the paper) acts on pairs with gap up to 16
+ *       kappa, where it has decayed to exp(-16) of its contact value.
  */
 #include <math.h>
 #include <stdint.h>
@@ -93,6 +102,7 @@ typedef struct {
     orc_contact *c; int nc, capc; /* contact history, sorted by (i, j)       */
     uint32_t *pairs; int npairs, cappairs; /* interaction set of last eval   */
     double stress[27];            /* contact, lubrication, Brownian 3x3     */
+    double drag[9];               /* drag stresslet (1/V) sum 20/3 pi eta a^3 E */
     double *disp;                 /* 3n: accumulated non-affine displacement */
 } orc_state;
 
@@ -264,6 +274,21 @@ typedef struct {
     int overflow;
 } contact_io;
 
+/* Range of the short-ranged repulsion of Sec. IV.F: it acts on every pair with
+ * gap h <= ORC_REP_RANGE * kappa, kappa = 0.01 (a_i + a_j), where it has decayed
+ * to exp(-16) ~ 1e-7 of its contact value (the paper states no cut-off), i.e.
+ * |r| <= (a_i + a_j) (1 + ORC_REP_RANGE * 0.01). */
+#define ORC_REP_RANGE 16.0
+
+static void repulsion_force(const orc_params *p, double sa, double dist, const double n[3], double FC[3])
+{
+    /* Sec. IV.F: A/kappa exp((a_i + a_j - |r|)/kappa) n, kappa = 0.01 (a_i + a_j); an
+       interparticle force, kept with the contact force (and the contact stress) */
+    double kappa = 0.01 * sa;
+    double fr = p->rep_A / kappa * exp((sa - dist) / kappa);
+    for (int d = 0; d < 3; ++d) FC[d] += fr * n[d];
+}
+
 static void pair_force(orc_state *S, int i, int j, contact_io *io)
 {
     const orc_params *p = &S->p;
@@ -272,7 +297,26 @@ static void pair_force(orc_state *S, int i, int j, contact_io *io)
     double d2 = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
     double sa = S->a[i] + S->a[j];
     double rc = sa * (1.0 + 0.5 * p->xi_cut);
-    if (!(d2 <= rc * rc)) return;                 /* gap xi > xi_cut: no lubrication pair */
+    if (!(d2 <= rc * rc)) {
+        /* gap xi > xi_cut: no lubrication pair; only the repulsion may act */
+        double rr = sa * (1.0 + ORC_REP_RANGE * 0.01);
+        if (!(p->rep_A > 0.0) || !(d2 <= rr * rr)) return;
+        double dist = sqrt(d2);
+        double n[3] = {r[0] / dist, r[1] / dist, r[2] / dist};
+        double FC[3] = {0, 0, 0};
+        repulsion_force(p, sa, dist, n, FC);
+        double V = p->L[0] * p->L[1] * p->L[2];
+        for (int d = 0; d < 3; ++d) {
+            S->F[3 * i + d] += FC[d];
+            S->F[3 * j + d] -= FC[d];
+        }
+        double fn = sqrt(dot3(FC, FC));
+        S->Fabs[i] += fn;
+        S->Fabs[j] += fn;
+        for (int al = 0; al < 3; ++al)
+            for (int be = 0; be < 3; ++be) S->stress[0 + 3 * al + be] -= FC[al] * r[be] / V;
+        return;
+    }
 
     if (S->npairs >= S->cappairs) {
         S->cappairs = S->cappairs ? 2 * S->cappairs : 1024;
@@ -425,14 +469,7 @@ static void pair_force(orc_state *S, int i, int j, contact_io *io)
         S->Tabs[j] += S->a[j] * tnorm;
     }
 
-    if (p->rep_A > 0.0) {
-        /* short-ranged repulsion of Sec. IV.B, A/kappa exp((a_i + a_j - |r|)/kappa) n,
-           kappa = 0.01 (a_i + a_j), on the pairs within the lubrication cut-off; an
-           interparticle force, kept with the contact force (and the contact stress) */
-        double kappa = 0.01 * sa;
-        double fr = p->rep_A / kappa * exp((sa - dist) / kappa);
-        for (int d = 0; d < 3; ++d) FC[d] += fr * n[d];
-    }
+    if (p->rep_A > 0.0) repulsion_force(p, sa, dist, n, FC);
     double V = p->L[0] * p->L[1] * p->L[2];
     for (int d = 0; d < 3; ++d) {
         double f = FL[d] + FB[d] + FC[d];
@@ -469,7 +506,9 @@ static void all_pairs(orc_state *S, contact_io *io)
      * shift bookkeeping is needed; pairs are taken once with i < j. */
     double amax = 0.0;
     for (int i = 0; i < n; ++i) if (S->a[i] > amax) amax = S->a[i];
-    double rmax = 2.0 * amax * (1.0 + 0.5 * S->p.xi_cut);
+    double c = 1.0 + 0.5 * S->p.xi_cut;
+    if (S->p.rep_A > 0.0 && 1.0 + ORC_REP_RANGE * 0.01 > c) c = 1.0 + ORC_REP_RANGE * 0.01;
+    double rmax = 2.0 * amax * c;
     int nc[3];
     for (int d = 0; d < 3; ++d) nc[d] = cells_dim(S->p.L[d], rmax);
     int ncell = nc[0] * nc[1] * nc[2];
@@ -521,6 +560,7 @@ static void forces(orc_state *S)
     memset(S->Fabs, 0, sizeof(double) * (size_t)n);
     memset(S->Tabs, 0, sizeof(double) * (size_t)n);
     memset(S->stress, 0, sizeof(S->stress));
+    memset(S->drag, 0, sizeof(S->drag));
     S->npairs = 0;
 
     contact_io io = {NULL, 0, 0, S->c, S->nc, 0};
@@ -553,6 +593,16 @@ static void forces(orc_state *S)
             S->Fabs[i] += norm3(fd);
             S->Tabs[i] += norm3(td);
         }
+        /* Sec. II.B: the drag force gives particle i the stress (20/3) pi eta a_i^3 E, with
+           E the symmetric part of grad U^inf (only dU_x/dy = gammadot is nonzero) */
+        double G[9] = {0, p->gammadot, 0, 0, 0, 0, 0, 0, 0};   /* G[3a+b] = dU_a/dx_b */
+        double V = p->L[0] * p->L[1] * p->L[2];
+        for (int i = 0; i < n; ++i) {
+            double c = (20.0 / 3.0) * ORC_PI * p->eta * S->a[i] * S->a[i] * S->a[i];
+            for (int al = 0; al < 3; ++al)
+                for (int be = 0; be < 3; ++be) S->drag[3 * al + be] += c * 0.5 * (G[3 * al + be] + G[3 * be + al]);
+        }
+        for (int k = 0; k < 9; ++k) S->drag[k] /= V;
     }
 }
 
@@ -695,6 +745,37 @@ void orc_get_norms(const orc_state *S, double *Fabs, double *Tabs)
 
 void orc_get_stress(const orc_state *S, double out[27]) { memcpy(out, S->stress, sizeof(S->stress)); }
 
+/* Five 3x3 stresses of the last evaluation: contact (with the repulsion),
+ * lubrication, instantaneous Brownian, drag stresslet, and the total of Sec.
+ * IV.D, hydrodynamic (lubrication + drag) plus contact; the Brownian stress
+ * averages to zero and is not part of the total. */
+void orc_get_stress_all(const orc_state *S, double out[45])
+{
+    memcpy(out, S->stress, sizeof(S->stress));
+    memcpy(out + 27, S->drag, sizeof(S->drag));
+    for (int k = 0; k < 9; ++k) out[36 + k] = S->stress[k] + S->stress[9 + k] + S->drag[k];
+}
+
+/* Relative viscosity of the last evaluation, Sec. II.E: Sigma_xy / (eta gammadot)
+ * of the total stress (NaN without shear). */
+double orc_eta_r(const orc_state *S)
+{
+    double t = S->stress[1] + S->stress[9 + 1] + S->drag[1];
+    return t / (S->p.eta * S->p.gammadot);
+}
+
+/* Time autocorrelation of a per-step series, the integrand of the Green-Kubo
+ * integral of Sec. IV.B: out[k] = mean over t of s(t) s(t + k), for k < nlag,
+ * over the count - k available pairs of records (0 where none). */
+void orc_acf(const double *s, long count, long nlag, double *out)
+{
+    for (long k = 0; k < nlag; ++k) {
+        double acc = 0.0;
+        for (long t = 0; t + k < count; ++t) acc += s[t] * s[t + k];
+        out[k] = k < count ? acc / (double)(count - k) : 0.0;
+    }
+}
+
 void orc_get_disp(const orc_state *S, double *out_3n) { memcpy(out_3n, S->disp, sizeof(double) * 3 * (size_t)S->n); }
 
 /* Histogram of pair distances r < r_max (each pair once, minimum image in the sheared
@@ -712,6 +793,20 @@ void orc_rdf(const orc_state *S, double r_max, int nbins, uint64_t *counts)
             if (k >= nbins) k = nbins - 1;
             counts[k] += 1;
         }
+}
+
+/* Runs nsteps steps and adds the pair-distance histogram of the configuration
+   after every `every`-th step to counts (the g(r) sampling of Sec. III.A). */
+void orc_run_rdf(orc_state *S, long nsteps, long every, double r_max, int nbins, uint64_t *counts)
+{
+    uint64_t *c = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)nbins);
+    for (long t = 1; t <= nsteps; ++t) {
+        step(S);
+        if (t % every) continue;
+        orc_rdf(S, r_max, nbins, c);
+        for (int k = 0; k < nbins; ++k) counts[k] += c[k];
+    }
+    free(c);
 }
 
 /* Structural Brownian stress of the current configuration, Sec. II.D:

@@ -571,7 +571,7 @@ def test_table1_peclet_numbers():
 
 
 # --------------------------------------------------------------------------
-# Short-ranged repulsion (Sec. IV.B) and the structural Brownian stress (Sec. II.D)
+# Short-ranged repulsion (Sec. IV.F) and the structural Brownian stress (Sec. II.D)
 # --------------------------------------------------------------------------
 ONLY_REP = O.NO_LUB | O.NO_PAIR_BROWN | O.NO_CONTACT | O.NO_ONEBODY
 
@@ -579,7 +579,7 @@ ONLY_REP = O.NO_LUB | O.NO_PAIR_BROWN | O.NO_CONTACT | O.NO_ONEBODY
 def test_repulsion_two_spheres_closed_form():
     A = 0.7
     for a in ((1.0, 1.0), (1.0, 1.4)):
-        for xi in (-4e-3, 0.0, 0.01, 0.049):
+        for xi in (-4e-3, 0.0, 0.01, 0.049, 0.06, 0.2, 0.3199):
             o, n, dist = _two(xi, a=a, flags=ONLY_REP | O.FREEZE_X, rep_A=A, direction=(0.3, -0.5, 0.8))
             F = o.state()["F"]
             sa = sum(a)
@@ -595,9 +595,17 @@ def test_repulsion_two_spheres_closed_form():
             assert np.abs(S[1]).max() == 0.0 and np.abs(S[2]).max() == 0.0
 
 
-def test_repulsion_off_beyond_cutoff_and_adds_to_contact():
-    o, n, dist = _two(0.0501, flags=ONLY_REP, rep_A=1.0)
+def test_repulsion_range_and_adds_to_contact():
+    """The repulsion acts up to a gap of 16 kappa = 0.16 (a_i + a_j) (xi = 0.32), where it has
+    decayed to exp(-16) of its contact value, beyond the lubrication cut-off; those pairs are
+    not lubrication pairs (no interaction-set entry, no pair noise)."""
+    o, n, dist = _two(0.3201, flags=ONLY_REP, rep_A=1.0)
     assert np.abs(o.state()["F"]).max() == 0.0
+    o, n, dist = _two(0.3199, flags=O.NO_CONTACT | O.NO_ONEBODY, rep_A=1.0, kT=1.0)
+    F = o.state()["F"][0]
+    assert len(o.pairs()) == 0
+    assert np.allclose(F, 1.0 / 0.02 * math.exp(-(dist - 2.0) / 0.02) * n, rtol=1e-12, atol=0)
+    assert F @ n / (1.0 / 0.02) < 1.2e-7
     # with contact on: Hookean part plus the repulsion, both along n
     kn = 1e4
     o, n, dist = _two(-2e-3, flags=O.NO_LUB | O.NO_PAIR_BROWN | O.NO_ONEBODY, rep_A=0.5, kn=kn, mu=0.0)
@@ -795,3 +803,172 @@ def test_rdf_histogram_brute_force():
     ref, _ = np.histogram(r[r < r_max], bins=nb, range=(0.0, r_max))
     assert h.sum() == ref.sum() > 100
     assert np.abs(h.astype(np.int64) - ref).sum() <= 2   # a distance on a bin edge may round either way
+
+
+# --------------------------------------------------------------------------
+# Drag stresslet, total stress and relative viscosity (Sec. II.B, II.E, IV.D)
+# --------------------------------------------------------------------------
+def test_drag_stresslet_is_einstein_viscosity():
+    """Sec. II.B gives each particle the drag stress (20/3) pi eta a^3 E with E_xy = gammadot/2;
+    summed over a volume V this is 2.5 phi eta gammadot, Einstein's dilute-suspension result
+    (phi = sum (4/3) pi a^3 / V).  A dilute system without pairs in range has no pair stress, so
+    its total stress (Sec. IV.D) is the drag stresslet and eta_r = 2.5 phi exactly."""
+    for n, L, gd in ((40, (60.0, 55.0, 70.0), 0.3), (500, (19.9, 19.9, 19.9), 0.53)):
+        a = gen.radii_bidisperse(n, 1)
+        V = float(np.prod(L))
+        phi = float(np.sum(4.0 / 3.0 * PI * a ** 3) / V)
+        if n == 40:   # spheres on a coarse lattice: no pair within the cut-off
+            g = np.stack(np.meshgrid(np.arange(4), np.arange(2), np.arange(5), indexing="ij"), -1).reshape(-1, 3)
+            x = (g + 0.5) * np.array([L[0] / 4, L[1] / 2, L[2] / 5])
+        else:
+            x = gen.relaxed_positions(a, L[0], 3)
+        v = np.zeros((n, 3))
+        w = np.zeros((n, 3))
+        o = O.Oracle(_params(L, gammadot=gd, kT=0.0, eta=0.1), a, x, v, w)
+        S = o.stress_all()
+        eta = 0.1
+        assert S[3][0, 1] / (eta * gd) == pytest.approx(2.5 * phi, rel=1e-12)
+        assert S[3][1, 0] == S[3][0, 1]
+        mask = np.ones((3, 3), bool)
+        mask[0, 1] = mask[1, 0] = False
+        assert np.all(S[3][mask] == 0.0)
+        # total = hydrodynamic (lubrication + drag) + contact; Brownian excluded
+        assert np.allclose(S[4], S[0] + S[1] + S[3], rtol=1e-15, atol=0)
+        assert o.eta_r() == pytest.approx(S[4][0, 1] / (eta * gd), rel=1e-15)
+        if n == 40:
+            assert len(o.pairs()) == 0 and np.all(S[:3] == 0.0)
+            assert o.eta_r() == pytest.approx(2.5 * phi, rel=1e-12)
+    # no one-body terms, no drag stresslet
+    o = O.Oracle(_params(L, gammadot=0.3, flags=O.NO_ONEBODY), a, x, v, w)
+    assert np.all(o.stress_all()[3] == 0.0)
+
+
+def test_single_sphere_relaxes_to_imposed_flow():
+    """One sphere, kT = 0, at rest in shear flow.  With the drag of eq. (force_drag) and
+    (torque_drag) evaluated at the half-step velocities of velocity-Verlet, the departure
+    u = v - U^inf(x) of the full-step velocity obeys u_n = (1 - c)^2 (1 - 2c)^(n-1) u_0 with
+    c = zeta dt / (2 m), zeta = 6 pi eta a, m = (4/3) pi rho a^3 (Sec. II), and likewise the
+    spin relaxes towards Omega^inf = (1/2) curl U^inf with c_r = zeta_r dt / (2 I), zeta_r =
+    8 pi eta a^3, I = (2/5) m a^2.  The limits pin the gauge U^inf = gammadot (y - Ly/2) e_x and
+    the sign of Omega^inf; the rates pin zeta, zeta_r, m and I; the discrete law pins the
+    kick-drift-kick order.  (Continuous-time limit: exp(-zeta t / m).)"""
+    L = (12.0, 10.0, 11.0)
+    gd, eta, rho, dt, a = 0.7, 0.1, 0.1, 1e-4, 1.3
+    y0 = 0.8 * L[1]
+    x = np.array([[3.0, y0, 5.0]])
+    v0 = np.array([[0.05, 0.0, -0.02]])
+    w0 = np.array([[0.1, -0.3, 0.2]])
+    o = O.Oracle(_params(L, gammadot=gd, kT=0.0, eta=eta, rho=rho, dt=dt), np.array([a]), x, v0, w0)
+    # imposed flow at the sphere and its vorticity, from U^inf(x) = gammadot (y - Ly/2) e_x
+    U = np.array([gd * (y0 - 0.5 * L[1]), 0.0, 0.0])
+    dUx_dy, dUy_dx = gd, 0.0
+    Om = np.array([0.0, 0.0, 0.5 * (dUy_dx - dUx_dy)])
+    m = 4.0 / 3.0 * PI * rho * a ** 3
+    I = 0.4 * m * a ** 2
+    c = 6 * PI * eta * a * dt / (2 * m)
+    cr = 8 * PI * eta * a ** 3 * dt / (2 * I)
+    done = 0
+    for nsteps in (1, 10, 300, 2000):
+        o.step(nsteps - done)
+        done = nsteps
+        st = o.state()
+        fac = (1 - c) ** 2 * (1 - 2 * c) ** (nsteps - 1)
+        facr = (1 - cr) ** 2 * (1 - 2 * cr) ** (nsteps - 1)
+        assert np.allclose(st["v"][0] - U, fac * (v0[0] - U), rtol=1e-11, atol=1e-17)
+        assert np.allclose(st["w"][0] - Om, facr * (w0[0] - Om), rtol=1e-11, atol=1e-17)
+        assert st["x"][0, 1] == y0    # no gradient-direction motion
+    assert abs(st["w"][0, 2] - Om[2]) < 0.25 * abs(w0[0, 2] - Om[2])   # relaxed towards -gammadot / 2
+
+
+# --------------------------------------------------------------------------
+# Two-sphere potential of mean force (Sec. III.A)
+# --------------------------------------------------------------------------
+_PMF_EDGES = np.linspace(0.0, 2.5, 251)
+
+
+def _pmf_counts(flags, seeds, kn, nsteps=2_000_000):
+    """Two spheres of radius 1 in a periodic box of side 5 without flow; pair-distance
+    histogram every 5 steps over independent runs (threads: the oracle releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    x = np.array([[1.0, 1.0, 1.0], [3.5, 3.5, 3.5]])
+    z = np.zeros((2, 3))
+    O.lib()
+
+    def one(seed):
+        o = O.Oracle(_params((5.0, 5.0, 5.0), kn=kn, kt=2 * kn / 7, kT=1.0, gammadot=0.0, seed=seed, flags=flags),
+                     np.ones(2), x, z, z)
+        return o.run_rdf(nsteps, 5, 2.5, len(_PMF_EDGES) - 1)
+
+    with ThreadPoolExecutor(8) as ex:
+        return sum(ex.map(one, seeds))
+
+
+def _pmf_ratios(counts, kn, regions):
+    """Observed counts over those of g(r) = exp(-U(r)/kT), U = (1/2) k_n delta^2 in contact and
+    0 outside (the potential of mean force the paper reports), per region of r; the
+    histogram is normalised on 2.05 <= r <= 2.45 (r < L/2: whole spherical shells)."""
+    def shell(lo, hi):
+        r = np.linspace(lo, hi, 201)
+        return np.trapezoid(4 * PI * r ** 2 * np.exp(-0.5 * kn * np.clip(2.0 - r, 0, None) ** 2), r)
+
+    lo_e, hi_e = _PMF_EDGES[:-1], _PMF_EDGES[1:]
+
+    def region(lo, hi):
+        k = np.where((lo_e >= lo - 1e-12) & (hi_e <= hi + 1e-12))[0]
+        return counts[k].sum(), sum(shell(lo_e[q], hi_e[q]) for q in k)
+
+    c0, e0 = region(2.05, 2.45)
+    out = []
+    for lo, hi in regions:
+        c, e = region(lo, hi)
+        out.append(float(c / (e * c0 / e0)))
+    return out
+
+
+@pytest.mark.slow
+def test_two_sphere_pmf_contact_potential():
+    """Contact force and one-body thermostat alone (Sec. III.A): inside contact -ln g(r) =
+    (1/2) k_n delta^2 / kT, outside it g is flat (k_n = 300, kT = 1: delta_rms ~ 0.06)."""
+    kn = 300.0
+    rat = _pmf_ratios(_pmf_counts(O.NO_LUB | O.NO_PAIR_BROWN, range(16), kn), kn,
+                      [(1.8, 1.9), (1.9, 2.0), (2.0, 2.05), (2.05, 2.25), (2.25, 2.45)])
+    assert abs(rat[0] - 1) < 0.3 and abs(rat[1] - 1) < 0.15, rat
+    assert all(abs(t - 1) < 0.08 for t in rat[2:]), rat
+
+
+@pytest.mark.slow
+def test_two_sphere_pmf_flat_outside_contact():
+    """All forces (Sec. III.A): lubrication and the pairwise Brownian force introduce no net
+    potential outside contact, so g(r) is flat for r > 2a, also inside the lubrication range
+    2a < r < 2.05a where they act.  (Inside contact, with dt = 1e-4, the lubricated pair
+    samples its overlap in long, rare episodes: that region is not asserted.)"""
+    kn = 300.0
+    rat = _pmf_ratios(_pmf_counts(0, range(100, 116), kn), kn, [(2.0, 2.05), (2.05, 2.25), (2.25, 2.45)])
+    assert all(abs(t - 1) < 0.04 for t in rat), rat
+
+
+# --------------------------------------------------------------------------
+# Stress autocorrelation (the Green-Kubo integrand of Sec. IV.B)
+# --------------------------------------------------------------------------
+def test_acf_closed_forms():
+    """Series with closed-form autocorrelations: a constant c gives c^2 at every lag; the
+    alternating series (-1)^t gives (-1)^k exactly; a series and its time reverse give the
+    same estimator; lag 0 is the mean square; AR(1) noise decays as phi^k."""
+    assert np.array_equal(O.acf(np.full(50, 3.0), 10), np.full(10, 9.0))
+    alt = np.array([(-1.0) ** t for t in range(101)])
+    assert np.array_equal(O.acf(alt, 20), np.array([(-1.0) ** k for k in range(20)]))
+    rng = np.random.default_rng(5)
+    s = rng.normal(size=300)
+    c = O.acf(s, 40)
+    assert np.allclose(c, O.acf(s[::-1], 40), rtol=1e-13, atol=1e-15)
+    assert c[0] == pytest.approx(np.mean(s * s), rel=1e-14)
+    assert np.array_equal(O.acf(s, 400)[300:], np.zeros(100))
+    # AR(1): s_t = phi s_(t-1) + e_t, stationary variance 1 / (1 - phi^2)
+    ph, n = 0.8, 400_000
+    e = rng.normal(size=n)
+    ar = np.empty(n)
+    ar[0] = e[0] / math.sqrt(1 - ph * ph)
+    for t in range(1, n):
+        ar[t] = ph * ar[t - 1] + e[t]
+    c = O.acf(ar, 8)
+    assert np.allclose(c, ph ** np.arange(8) / (1 - ph * ph), rtol=0.05)
