@@ -23,7 +23,8 @@
  *     (force_brownian_drag), (torque_brownian_drag);
  *   - velocity-Verlet for translation and rotation (Sec. II, I = 2/5 m a^2);
  *   - the virial stresses -F (x) r / V of contact, lubrication and Brownian
- *     pair forces (Sec. II.A, II.B, II.D), accumulated in FP64.
+ *     pair forces (Sec. II.A, II.B, II.D), accumulated in FP64, the drag
+ *     stresslet (Sec. II.B) and the total stress (Sec. IV.D).
  *
  * Conventions
  *   Units are the paper's (Sec. II.E): lengths in a, masses in rho a^3, time
@@ -40,8 +41,18 @@
  *   into caller-sized buffers.  The library owns the handle and all device
  *   memory (through the allocator set by sim_set_allocator, else hipMalloc).
  *   All GPU work is ordered on the stream given at creation.  A handle is not
- *   thread safe; different handles are independent.  The same build, inputs
- *   and configuration give bit-identical results (no floating-point atomics).
+ *   thread safe; different handles are independent.
+ *
+ * Determinism
+ *   No floating-point atomics are used.  Trajectories (positions, velocities,
+ *   forces, torques, springs, interaction sets) are bit-identical for the same
+ *   build, inputs and configuration whatever launch parameters the tuner picks
+ *   (lanes per particle, kernel form, skin, cell size): each particle's terms
+ *   are summed in a fixed item order.  The stress sums run over the pairs in an
+ *   order that follows the launch shape, so with tuned parameters their last
+ *   bits can differ between two creations; they are bit-identical when the
+ *   parameters are the same (fixed in the configuration, or read from the
+ *   cache set by sim_set_tune_cache; sim_stats reports the set in use).
  *
  * Errors
  *   Every function returns an int32 status: 0 = SIM_OK, negative = error.
@@ -85,11 +96,11 @@ extern "C" {
                                         torque_brownian_lub2); half-pair kernel only       */
 #define SIM_REBUILD_EACH_STEP 0x100u /* rebuild the neighbour list every step        */
 #define SIM_NO_GRAPH          0x200u /* launch kernels directly, no HIP graph        */
-#define SIM_HALF_OCC_ON       0x400u /* half-pair kernel, FP64, no model switch: use its
-                                        form for occupancy (the pair queue in rounds, part
-                                        of the stress sums in LDS, 3 waves per SIMD) rather
+#define SIM_HALF_OCC_ON       0x400u /* FP64, no model switch: use the pair kernel's form
+                                        for occupancy (the pair queue in rounds, part of
+                                        the stress sums in LDS, 3 waves per SIMD) rather
                                         than choosing by timing at creation; the same
-                                        results bit for bit                             */
+                                        trajectories bit for bit                        */
 #define SIM_HALF_OCC_OFF      0x800u /* ... never use that form                       */
 #define SIM_SMALL_QUEUE      0x1000u /* test switch: that form processes its pair queue
                                         64 items per round (instead of 2048), so that
@@ -97,11 +108,13 @@ extern "C" {
 
 /* sim_stress components and modes */
 #define SIM_STRESS_CONTACT 0      /* -(F^C + F^R) (x) r / V: contact and
-                                     short-ranged repulsion       (Sec. II.A, IV.B) */
+                                     short-ranged repulsion       (Sec. II.A, IV.F) */
 #define SIM_STRESS_LUB     1      /* -F^{H,L} (x) r / V                 (Sec. II.B) */
 #define SIM_STRESS_BROWN   2      /* -F^{B,L} (x) r / V, instantaneous  (Sec. II.D) */
-#define SIM_STRESS_DRAG    3      /* (1/V) sum 20/3 pi eta a^3 E        (Sec. II.B) */
-#define SIM_STRESS_TOTAL   4      /* contact + lubrication + drag       (Sec. IV.D) */
+#define SIM_STRESS_DRAG    3      /* (1/V) sum 20/3 pi eta a^3 E        (Sec. II.B);
+                                     0 under SIM_NO_ONEBODY (no drag)                */
+#define SIM_STRESS_TOTAL   4      /* contact + lubrication + drag       (Sec. IV.D);
+                                     its xy entry / (eta gammadot) is eta_r (II.E)  */
 #define SIM_STRESS_LAST    0      /* value at the last evaluated step               */
 #define SIM_STRESS_MEAN    1      /* mean over steps since sim_reset_stress/create  */
 
@@ -121,40 +134,36 @@ typedef struct sim_config {
     double   dt;            /* time step                                             */
     double   xi_cut;        /* no lubrication for dimensionless gaps xi > xi_cut     */
     double   xi_min;        /* xi is replaced by xi_min when smaller (Sec. II.B)     */
-    double   skin;          /* Verlet skin, length; <= 0 selects 0.2 * min radius    */
+    double   skin;          /* Verlet skin, length; 0 selects 0.2 * min radius; < 0:
+                               the tuner picks 0.1 ... 0.4 * min radius              */
     double   le_offset0;    /* initial Lees-Edwards offset (x shift of the y image)  */
     double   max_overlap;   /* health limit on the overlap; <= 0 selects 0.1 * min a */
     double   repulsion;     /* A >= 0 of the short-ranged repulsion (A / kappa)
-                               exp(-h / kappa) n, kappa = 0.01 (a_i + a_j), on the
-                               pairs within the lubrication cut-off (Sec. IV.B);
-                               0 = none; > 0 needs the half-pair kernel              */
+                               exp(-h / kappa) n, kappa = 0.01 (a_i + a_j) (Sec.
+                               IV.F), on the pairs with gap h <= 16 kappa (where it
+                               has decayed to e^-16; the paper states no cut-off);
+                               0 = none                                              */
+    double   cell_factor;   /* search cells at least cell_factor times the list range
+                               wide: 0 selects 1, < 0 the tuner picks 1, 1.5 or 2;
+                               else in [1, 4]                                        */
     uint64_t seed;          /* key of the counter-based noise generator             */
     uint64_t step0;         /* step counter of the initial state                     */
     int32_t  precision;     /* SIM_FP64 or SIM_MIXED, identical for all replicas     */
     uint32_t flags;         /* SIM_* flags, identical for all replicas               */
     uint32_t nlist_cap;     /* neighbour list capacity per particle; 0 selects 48    */
-    uint32_t lanes;         /* lanes sharing one particle in the pair kernel: 1, 2, 4
-                               or 8 (at most 4 for SIM_KERNEL_WAVE and
-                               SIM_KERNEL_HALF); 0 = chosen by timing at creation    */
-    uint32_t pair_kernel;   /* SIM_KERNEL_AUTO, _LANES, _WAVE or _HALF                */
+    uint32_t lanes;         /* lanes sharing one particle's list in the pair kernel
+                               (1, 2 or 4: 64, 32 or 16 particles per wave); 0 =
+                               chosen by timing at creation                          */
+    uint32_t pair_kernel;   /* SIM_KERNEL_AUTO or SIM_KERNEL_HALF (the same kernel)   */
     uint32_t reserved;      /* must be 0                                             */
 } sim_config;
 
-/* sim_config.pair_kernel: all evaluate the same pair terms (Sec. II.A-II.D,
- * in canonical orientation, lower id first) and sum each particle's terms in
- * the same item order, so forces, torques and springs are bit-identical
- * between them (with one lane per particle); they differ in how lanes share
- * the work */
-#define SIM_KERNEL_AUTO  0  /* the fastest at creation (timed)                        */
-#define SIM_KERNEL_LANES 1  /* each particle's items split over `lanes` lanes;
-                               every pair is evaluated by both of its particles       */
-#define SIM_KERNEL_WAVE  2  /* a wave tests its particles' list entries, then packs
-                               their interacting pairs into full 64-lane batches      */
-#define SIM_KERNEL_HALF  3  /* every pair evaluated once, by its lower-id particle
-                               (`lanes` lanes per particle test its list), packed 64
-                               to a wave; a second launch sums each particle's pair
-                               terms and one-body terms in item order, so forces
-                               are bit-identical for every `lanes`                    */
+/* sim_config.pair_kernel: every interacting pair is evaluated once, by its
+ * lower-id particle (`lanes` lanes per particle test its list), packed 64 to a
+ * wave; a second launch sums each particle's pair terms and one-body terms in
+ * item order */
+#define SIM_KERNEL_AUTO  0
+#define SIM_KERNEL_HALF  3
 
 typedef struct sim_stats_t {
     double  contacts_per_particle;  /* Z = 2 * contacts / n                          */
@@ -168,24 +177,37 @@ typedef struct sim_stats_t {
     uint64_t step;                  /* current step counter                            */
     double  le_offset;              /* current Lees-Edwards offset                     */
     int32_t lanes;                  /* lanes per particle used by the pair kernel       */
-    int32_t pair_kernel;            /* SIM_KERNEL_LANES, _WAVE or _HALF in use             */
-    int32_t occupancy_form;         /* 1: the half-pair kernel's form for occupancy is in
-                                       use (see SIM_HALF_OCC_ON), 0 otherwise            */
+    int32_t pair_kernel;            /* SIM_KERNEL_HALF                                   */
+    int32_t occupancy_form;         /* 1: the pair kernel's form for occupancy is in use
+                                       (see SIM_HALF_OCC_ON), 0 otherwise               */
+    int32_t tune_source;            /* launch and list parameters: 0 configured or
+                                       default, 1 measured at creation, 2 read from the
+                                       cache (sim_set_tune_cache)                        */
+    double  skin;                   /* Verlet skin of the replica (length)               */
+    double  cell_factor;            /* search cells >= cell_factor x the list range      */
+    int32_t cells_x, cells_y, cells_z; /* search cells per box side                     */
     int32_t reserved;               /* 0                                                 */
 } sim_stats_t;
 
 /* Checks a configuration and its radii on the host (no GPU needed).
  * radii: n doubles, host memory.  Returns SIM_EINVAL for both SIM_HALF_OCC_ON
- * and SIM_HALF_OCC_OFF, SIM_HALF_OCC_ON with SIM_MIXED, SIM_LUB_ROT,
- * repulsion > 0 or a pair_kernel other than 0 and SIM_KERNEL_HALF, n = 0, a <= 0,
+ * and SIM_HALF_OCC_OFF, SIM_HALF_OCC_ON with SIM_MIXED, SIM_LUB_ROT or
+ * repulsion > 0, a pair_kernel other than 0 and SIM_KERNEL_HALF, n = 0, a <= 0,
  * dt <= 0, rho/eta <= 0, kn/kt < 0, mu < 0, kT < 0, repulsion < 0, xi_min <= 0,
  * xi_min >= xi_cut, a box side not larger than twice the largest
- * interaction range plus skin (the minimum image must be unique), a wrong
- * struct_size, nlist_cap > 64, lanes not in {0, 1, 2, 4, 8}, an unknown
- * pair_kernel, SIM_KERNEL_WAVE with lanes 8 or nlist_cap > 62,
- * SIM_KERNEL_HALF with lanes 8, SIM_LUB_ROT or repulsion > 0 with
- * SIM_KERNEL_LANES or SIM_KERNEL_WAVE, or a nonzero reserved field. */
+ * interaction range plus skin (the minimum image must be unique; with a tuned
+ * skin, the smallest candidate), a wrong struct_size, nlist_cap > 64, lanes
+ * not in {0, 1, 2, 4}, cell_factor in (0, 1) or above 4, or a nonzero
+ * reserved field. */
 int sim_validate(const sim_config* cfg, const double* radii);
+
+/* Tuned launch and list parameters are read from and added to the cache file at
+ * path (a JSON object keyed by device, precision, model switches, the fixed
+ * parameters and buckets of particle count, volume fraction, size ratio and
+ * Peclet number) by the creations that follow; NULL or "" = no cache (the
+ * default).  A cached set is used without measuring, so that a rerun has the same
+ * parameters; a cache that cannot be read or written is ignored. */
+int sim_set_tune_cache(const char* path);
 
 /* Creates a handle with n_replicas systems.  For replica r: radii[r] -> n
  * doubles; x0[r] -> 3n doubles inside [0, L); v0[r], w0[r] -> 3n finite doubles
@@ -255,7 +277,7 @@ int sim_rdf(sim* s, int32_t replica, double r_max, int32_t nbins, uint64_t* coun
  * SIM_STRESS_CONTACT, _LUB or _BROWN, entry alpha, beta in 0..2) over the
  * per-step records since sim_reset_stress (at most the last 8192):
  * out[k] = mean over t of S(t) S(t + k), k < nlag, for Green-Kubo integrals
- * (Sec. III.C).  SIM_ERANGE if fewer than nlag records are available. */
+ * (Sec. IV.B).  SIM_ERANGE if fewer than nlag records are available. */
 int sim_stress_acf(sim* s, int32_t replica, int32_t component, int32_t alpha, int32_t beta, int64_t nlag,
                    double* out);
 

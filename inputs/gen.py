@@ -33,6 +33,7 @@ LIB = os.path.join(HERE, "libpack.so")
 CACHE = os.environ.get("SUSP_INPUT_CACHE", "/tmp/susp_inputs")
 
 _lib = None
+PACK_VERSION = 3   # part of the cache key: packings of an older packer are not reused
 
 
 def build(force=False):
@@ -89,7 +90,8 @@ def relaxed_positions(radii, L, seed, tol=None, maxiter=20000, alpha=1.2):
     n = len(radii)
     if tol is None:
         tol = 1e-4 * float(np.min(radii))
-    key = hashlib.sha1(np.ascontiguousarray(radii).tobytes() + repr((L, seed, tol, alpha)).encode()).hexdigest()[:20]
+    key = hashlib.sha1(np.ascontiguousarray(radii).tobytes() + repr((L, seed, tol, alpha, PACK_VERSION)).encode()
+                       ).hexdigest()[:20]
     path = os.path.join(CACHE, f"pack_{n}_{key}.npy")
     if os.path.exists(path):
         try:
@@ -104,6 +106,8 @@ def relaxed_positions(radii, L, seed, tol=None, maxiter=20000, alpha=1.2):
     dp = C.POINTER(C.c_double)
     mo = _pack().pack_relax(n, a.ctypes.data_as(dp), x.ctypes.data_as(dp), Lb.ctypes.data_as(dp),
                             float(tol), int(maxiter), float(alpha), C.byref(it))
+    if mo < 0:
+        raise RuntimeError(f"packing: more than 64 neighbours of one sphere within the list range")
     if mo > tol:
         raise RuntimeError(f"packing did not relax: max overlap {mo:.3e} > {tol:.3e} after {it.value} sweeps")
     try:

@@ -28,10 +28,12 @@ struct RepParams {
     double rep_A;             // short-ranged repulsion scale A (0 = none)
     double kT;
     double bamp;              // sqrt(2 kT / dt)
-    double c1;                // 1 + xi_cut / 2
+    double c1;                // 1 + xi_cut / 2: lubrication range factor
+    double c_int;             // range factor of the pairs evaluated: c1, or with the repulsion
+                              // on, max(c1, 1 + 16 * 0.01) (its range of 16 kappa)
     double xi_min;
     double skin;
-    double rc_max;            // largest interaction range (2 a_max c1)
+    double rc_max;            // largest interaction range (2 a_max c_int)
     double rl_max;            // rc_max + skin
     double invV;
     double cw[3];             // cell widths
@@ -142,12 +144,10 @@ struct Bufs {
     // stress: per pair-kernel block partial sums (two parities), ring of per-step values
     double* partial;      // [parity][27][blk]
     float* ovpart;        // [parity][blk]: largest overlap seen by each pair-kernel block
-    uint32_t nblk_max;    // pair-kernel blocks at 8 lanes per particle (partials per parity)
+    uint32_t nblk_max;    // pair-kernel blocks at 4 lanes per particle (partials per parity)
     double* ring;         // [rep][kRing][27]
     double* last;         // [rep][27]
-    int lanes;            // pair kernel: lanes per particle (1, 2, 4, 8)
-    int kern;             // pair kernel: 0 = lanes split each particle's items, 1 = wave-cooperative,
-                          // 2 = half-pair evaluation + gather
+    int lanes;            // pair kernel: lanes per particle (1, 2, 4)
     int ppb;              // particles per pair-kernel block (for the stress partials)
     int occ;              // half-pair kernel in FP64 without extensions: 1 = its form for occupancy
     uint32_t qcap;        // queue items per round of that form (2048; 64 under SIM_SMALL_QUEUE)

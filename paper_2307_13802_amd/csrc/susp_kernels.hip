@@ -19,8 +19,6 @@
 
 namespace susp {
 
-constexpr int kPairBlock = 128;  // threads per pair-force block
-
 // ---------------------------------------------------------------------------
 // Counter-based noise: Philox4x32 with 10 rounds (Salmon, Moraes, Dror, Shaw,
 // SC'11), Box-Muller normals.  Counter words: (step_lo, id_a, id_b,
@@ -183,11 +181,6 @@ __device__ __forceinline__ void spring_f64(const Bufs& b, uint32_t k, double* s)
     } else {
         load_spring<double>(b, k, s);
     }
-}
-
-// thread-private accumulation in LDS (each slot has one writer)
-__device__ __forceinline__ void lds_add(double* p, double v) {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // inclusive sum over each 16-lane row; lane 15 of a row then holds the row total
@@ -713,7 +706,7 @@ __global__ __launch_bounds__(256) void k_rb_nlist(Bufs b, int q, int in_step) {
     b.smask[i] = sm;
 }
 
-// Mirror index of the half-pair variant: lo0 = first entry whose partner has
+// Mirror index of the half-pair evaluation: lo0 = first entry whose partner has
 // the higher id (in pidx, whose mask it clears); for an entry with a lower-id
 // partner j, the position of i in j's list (lists are symmetric: the range test
 // is symmetric in i, j).
@@ -806,16 +799,14 @@ template <> __device__ __forceinline__ float rrcp<float>(float x) { return __bui
 
 // ---------------------------------------------------------------------------
 // Forces of a step with parity q: Sec. II.A-II.D pair terms, Sec. II.B-II.C
-// one-body terms, kick 2.  The work of particle i is a list of items: its
+// one-body terms, kick 2.  The terms of particle i are a list of items: its
 // interacting list entries in entry order (partner ids ascending), then a
 // one-body force item (drag + noise) and a one-body torque item.  Every item
-// draws one Philox block and three normals through the same code.  Pairs are
-// evaluated in canonical orientation (lower id = "a", higher id = "b",
-// r = x_a - x_b), so both sides compute bit-identical pair terms and the pair
-// forces are exactly antisymmetric; the stress of a pair is added on the
-// lower-id side.  The force and torque on i are summed over its items in item
-// order (FP64, or FP32 with Neumaier compensation), so every kernel variant
-// below gives the same bits.
+// draws one Philox block and three normals.  Pairs are evaluated once, in
+// canonical orientation (r = x_i - x_j with i the lower id), so the pair
+// forces are exactly antisymmetric; the stress of a pair is added once.  The
+// force and torque on i are summed over its items in item order (FP64, or FP32
+// with Neumaier compensation), so they do not depend on the launch shape.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kItemForce = 64u;   // item code of the one-body force (list entries are < 64)
 constexpr uint32_t kItemTorque = 65u;  // item code of the one-body torque
@@ -824,7 +815,7 @@ template <bool MIX> struct EvalCtx {
     using R = typename std::conditional<MIX, float, double>::type;
     double s_le, c1, invV;
     // the box: a pair loop that stores its results would otherwise read these from the
-    // parameters again in every pass (eval_item's BOXC; the FP64 occupancy form of the
+    // parameters again in every pass (eval_pair's BOXC; the FP64 occupancy form of the
     // half-pair kernel has no scalar registers to spare and reads them)
     double L[3], invL[3], gdLy;
     uint32_t k0, k1, ctr_lo, ctr_hi;
@@ -853,21 +844,6 @@ __device__ __forceinline__ void eval_record(const Bufs& b, int q, int advance, c
         D.eval_id[q] = D.eval_seq;
         D.rec[q] = 0u;
     }
-}
-
-// Returns false when the launch must do nothing (a list may have expired: the
-// list-validity test of the step's integrate failed for some replica, and one
-// failure halts the whole launch sequence until the host has rebuilt).
-__device__ __forceinline__ bool eval_begin(const Bufs& b, int q, int advance, const RepParams& P, RepDyn& D,
-                                           bool first, double& s_le, uint64_t& step) {
-    if (advance && b.sys->expire[q]) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) b.sys->halted = 1u;
-        return false;
-    }
-    s_le = advance ? next_offset(P, D.s_slot[1 - q]) : D.s_slot[q];
-    step = advance ? D.step_slot[1 - q] + 1 : D.step_slot[q];
-    eval_record(b, q, advance, P, D, first, s_le, step, blockIdx.x == 0);
-    return true;
 }
 
 // values uniform over the wave (the evaluation's constants): readfirstlane keeps
@@ -915,12 +891,14 @@ __device__ __forceinline__ void make_ctx(EvalCtx<MIX>& C, const RepParams& P, do
     C.do_rot = (P.flags & F_LUB_ROT) != 0;
 }
 
-// interaction predicate of list entry j of particle i: gap xi <= xi_cut (exact FP64 test)
+// interaction predicate of list entry j of particle i (exact FP64 test): gap xi <=
+// xi_cut, or with the repulsion on, gap h <= 16 kappa (P.c_int = the larger range
+// factor of the two)
 __device__ __forceinline__ bool interacting(const RepParams& P, double s_le, const double4& pi, const double4& pj) {
     double dx, dy, dz;
     min_image(P, s_le, pi, pj, dx, dy, dz);
     const double d2 = (dx * dx + dy * dy) + dz * dz;
-    const double rc = (pi.w + pj.w) * P.c1;
+    const double rc = (pi.w + pj.w) * P.c_int;
     return d2 <= rc * rc;
 }
 
@@ -957,25 +935,25 @@ template <class R> struct PairIn {
     R vj[3], wj[3], s[3];  // half-step velocities of j, stored spring of the entry
 };
 
-// One item of particle i: contribution f to its force and t to its torque.
-// Pair items also update the stored spring (entry e of i), the contact and
-// sliding bits, the largest overlap and the lower-id stress sums (addS).
-// tb_out (LO_ONLY): without ROT, n x (k_t s) of a contact (the torque per unit
-// lever arm of both spheres); with ROT, the pair's torque on the higher-id
-// partner.
-// Returns false for a pair that does not interact (nothing contributed).
-// LO_ONLY: the item is a pair whose partner has the higher id.  EXT: the
-// model extensions are compiled in (the short-ranged repulsion, and the
-// rotational lubrication couplings with the pairwise Brownian torques, which
-// need LO_ONLY and preloaded partner data), each on when its parameter says.
-template <bool MIX, bool LO_ONLY = false, bool EXT = false, bool BOXC = true, class AddS>
-__device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, const EvalCtx<MIX>& C, uint32_t i,
+// One interacting pair (i, j), i the lower id (canonical orientation, r = x_i -
+// x_j), from the partner data preloaded in `in`: the force f on i (j gets -f),
+// the torque t on i, the spring update of list entry e of i, the contact and
+// sliding bits, the largest overlap and the stress sums (addS).  tb_out: without
+// ROT, n x (k_t s) of a contact (the torque per unit lever arm of both spheres);
+// with ROT, the pair's torque on j.  EXT: the model extensions are compiled in
+// (the short-ranged repulsion, which reaches beyond the lubrication cut-off, and
+// the rotational lubrication couplings with the pairwise Brownian torques), each
+// on when its parameter says.  BOXC: the box from the context (else from P).
+// Returns false for a pair out of range (only when !BOXC; the half-pair kernel's
+// cull tested the range with the same arithmetic otherwise).
+template <bool MIX, bool EXT = false, bool BOXC = true, class AddS>
+__device__ __forceinline__ bool eval_pair(const Bufs& b, const RepParams& P, const EvalCtx<MIX>& C, uint32_t i,
                                           uint32_t e, const double4& pi, uint32_t idi,
                                           const typename EvalCtx<MIX>::R* vi, const typename EvalCtx<MIX>::R* wi,
                                           bool had_contact, typename EvalCtx<MIX>::R* f,
                                           typename EvalCtx<MIX>::R* t, bool& contact, bool& slid, float& maxov,
-                                          AddS addS, typename EvalCtx<MIX>::R* tb_out = nullptr,
-                                          const PairIn<typename EvalCtx<MIX>::R>* pre = nullptr) {
+                                          AddS addS, typename EvalCtx<MIX>::R* tb_out,
+                                          const PairIn<typename EvalCtx<MIX>::R>& in) {
     using R = typename EvalCtx<MIX>::R;
     const uint32_t npad = b.npad;
     const R ai = (R)pi.w;
@@ -983,85 +961,55 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
     for (int d = 0; d < 3; ++d) { f[d] = (R)0; t[d] = (R)0; }
     contact = false;
     slid = false;
-    const bool pair = LO_ONLY || e < kItemForce;
-    // ---- geometry of a pair item (FP64)
-    uint32_t j = 0, idj = 0;
-    double4 pj = make_double4(0.0, 0.0, 0.0, 0.0);
-    bool lo = true;
-    double dx = 0.0, dy = 0.0, dz = 0.0, h = 0.0;
-    int ky = 0;
-    R n[3] = {(R)0, (R)0, (R)0}, XA = (R)0, YA = (R)0, lgv = (R)0;
-    if (pair) {
-        if (pre) {
-            j = pre->j;
-            pj = pre->pj;
-            idj = pre->idj;
-        } else {
-            j = b.nbr[e * npad + i];
-            pj = b.pos[j];
-            idj = b.id[j];
-        }
-        lo = LO_ONLY || idi < idj;  // i holds the lower id
-        const double* L = BOXC ? C.L : P.L;
-        const double* invL = BOXC ? C.invL : P.invL;
-        ky = lo ? min_image(L, invL, C.s_le, pi, pj, dx, dy, dz) : min_image(L, invL, C.s_le, pj, pi, dx, dy, dz);
-        const double d2 = (dx * dx + dy * dy) + dz * dz;
-        const double sa = pi.w + pj.w;
-        const double rc = sa * C.c1;
-        // (the half-pair kernel evaluates only pairs its cull found in range, with the
-        // same arithmetic)
-        if (!(LO_ONLY && BOXC) && !(d2 <= rc * rc)) return false;
-        const double dist = sqrt(d2);
-        h = dist - sa;
-        const R inv = rrcp<R>((R)dist);
-        n[0] = (R)dx * inv; n[1] = (R)dy * inv; n[2] = (R)dz * inv;
-        const R aj = (R)pj.w;
-        const R aa = lo ? ai : aj, ab = lo ? aj : ai;
+    // ---- geometry (FP64)
+    const uint32_t idj = in.idj;
+    const double4 pj = in.pj;
+    double dx, dy, dz;
+    const double* L = BOXC ? C.L : P.L;
+    const double* invL = BOXC ? C.invL : P.invL;
+    const int ky = min_image(L, invL, C.s_le, pi, pj, dx, dy, dz);
+    const double d2 = (dx * dx + dy * dy) + dz * dz;
+    const double sa = pi.w + pj.w;
+    const double rc = sa * C.c1;
+    if (!BOXC && !(d2 <= rc * rc)) return false;
+    // a pair the cull admitted for the repulsion alone (beyond the lubrication cut-off)
+    const bool lubp = !(EXT && C.do_rep) || d2 <= rc * rc;
+    const double dist = sqrt(d2);
+    const double h = dist - sa;
+    R n[3];
+    const R inv = rrcp<R>((R)dist);
+    n[0] = (R)dx * inv; n[1] = (R)dy * inv; n[2] = (R)dz * inv;
+    const R aj = (R)pj.w;
+    R XA = (R)0, YA = (R)0, lgv = (R)0;
+    if (lubp) {
         const R xi = (R)(2.0 * h) * rrcp<R>((R)sa);
         const R xie = xi < C.xi_min ? C.xi_min : xi;
         // resistance scalars X^A_11, Y^A_11 (Sec. II.B) in the symmetric form
-        const R pab = aa * ab, qab = aa * aa + ab * ab;
-        const R sR = aa + ab;
+        const R pab = ai * aj, qab = ai * ai + aj * aj;
+        const R sR = ai + aj;
         const R pre = C.eta6pi * rrcp<R>(sR * sR * sR);
         const R lg = -rlog<R>(xie);
         lgv = lg;
         XA = pre * ((R)2 * pab * pab * rrcp<R>(xie) + pab * (qab + (R)7 * pab) * (R)0.2 * lg);
         YA = pre * ((R)4 * pab * ((R)2 * qab + pab) * (R)(1.0 / 15.0) * lg);
     }
-    // ---- one Philox block -> three normals (shared by both kinds of item)
+    // ---- one Philox block -> three normals
     R th[3] = {(R)0, (R)0, (R)0};
-    if (pair ? C.do_br : true) {
-        const uint32_t ida = pair ? (lo ? idi : idj) : idi;
-        const uint32_t idb = pair ? (lo ? idj : idi) : 0xFFFFFFFFu;
-        const uint32_t stream = pair ? 0u : (e == kItemForce ? 2u : 3u);
-        const uint4 w = philox10(C.ctr_lo, ida, idb, C.ctr_hi | stream, C.k0, C.k1);
+    if (C.do_br && lubp) {
+        const uint4 w = philox10(C.ctr_lo, idi, idj, C.ctr_hi, C.k0, C.k1);  // stream 0
         normals3(w, th);
     }
-    if (!pair) {
-        onebody_terms<MIX>(P, C, pi, e, vi, wi, th, f, t);
-        return true;
-    }
 
-    // ---- pair item: velocities in canonical orientation; b's image moves with +k_y gammadot Ly
-    R va[3], vb[3], vj[3];
+    // ---- velocities; j's image moves with +k_y gammadot Ly
+    R va[3], vb[3];
     const R shiftv = (R)((double)ky * (BOXC ? C.gdLy : P.gdLy));
-    if (pre) {
 #pragma unroll
-        for (int d = 0; d < 3; ++d) vj[d] = pre->vj[d];
-    } else if (MIX) {
-        const float4 v4 = b.vsh[j];
-        vj[0] = v4.x; vj[1] = v4.y; vj[2] = v4.z;
-    } else {
-        const double4 v4 = b.vh[j];
-        vj[0] = (R)v4.x; vj[1] = (R)v4.y; vj[2] = (R)v4.z;
-    }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) { va[d] = lo ? vi[d] : vj[d]; vb[d] = lo ? vj[d] : vi[d]; }
+    for (int d = 0; d < 3; ++d) { va[d] = vi[d]; vb[d] = in.vj[d]; }
     vb[0] = vb[0] + shiftv;
 
     R fl[3] = {(R)0, (R)0, (R)0}, fb[3] = {(R)0, (R)0, (R)0}, fc[3] = {(R)0, (R)0, (R)0};
-    if (C.do_lub) {
-        // eq. (force_lub): (X^A N + Y^A T)(U_b - U_a)
+    if (C.do_lub && lubp) {
+        // eq. (force_lub): (X^A N + Y^A T)(U_j - U_i)
         R ur[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) ur[d] = vb[d] - va[d];
@@ -1069,21 +1017,21 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
 #pragma unroll
         for (int d = 0; d < 3; ++d) fl[d] = XA * (un * n[d]) + YA * (ur[d] - un * n[d]);
     }
-    if (C.do_br) {
+    if (C.do_br && lubp) {
         // eq. (force_brownian_lub): sqrt(2kT/dt) (sqrt(X^A) N + sqrt(Y^A) T) theta
         const R tn = (n[0] * th[0] + n[1] * th[1]) + n[2] * th[2];
         const R sx = rsqrt_<R>(XA), sy = rsqrt_<R>(YA);
 #pragma unroll
         for (int d = 0; d < 3; ++d) fb[d] = C.bamp * (sx * (tn * n[d]) + sy * (th[d] - tn * n[d]));
     }
-    const bool ROT = EXT && C.do_rot;
+    const bool ROT = EXT && C.do_rot && lubp;
     R trot_a[3] = {(R)0, (R)0, (R)0}, trot_b[3] = {(R)0, (R)0, (R)0};
     if (ROT) {
         // Rotational couplings, eq. (force_lub), (torque_lub1), (torque_lub2), and pairwise
         // Brownian torques, eq. (torque_brownian_lub1), (torque_brownian_lub2).  The printed
-        // signs hold for the unit vector from a to b, which is -n here; the scalars Y^B, Y^C
-        // in the form symmetric in the radii (a = lower id, b = higher id).
-        const R aa = (R)pi.w, ab = (R)pj.w;  // LO_ONLY: i is a
+        // signs hold for the unit vector from i to j, which is -n here; the scalars Y^B, Y^C
+        // in the form symmetric in the radii.
+        const R aa = ai, ab = aj;
         const R sR = aa + ab, i5s2 = (R)0.2 * rrcp<R>(sR * sR), isR = rrcp<R>(sR);
         const R pie = BOXC ? C.pieta : (R)kPi * (R)P.eta;
         const R YB11 = -(R)4 * pie * aa * aa * ab * ((R)4 * aa + ab) * i5s2 * lgv;
@@ -1093,7 +1041,7 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
         const R YC22 = (R)3.2 * pie * ab * ab * ab * aa * isR * lgv;
         const R nab[3] = {-n[0], -n[1], -n[2]};
         const R* wa = wi;
-        const R* wb = pre->wj;
+        const R* wb = in.wj;
         if (C.do_lub) {
             R ca[3], cb[3], urn[3], oa[3], ob[3];
             cross3r(wa, nab, ca);
@@ -1136,46 +1084,27 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
         }
 #pragma unroll
         for (int d = 0; d < 3; ++d) t[d] = trot_a[d];
-        if (tb_out) {
 #pragma unroll
-            for (int d = 0; d < 3; ++d) tb_out[d] = trot_b[d];
-        }
+        for (int d = 0; d < 3; ++d) tb_out[d] = trot_b[d];
     }
     if (h < 0.0 && C.do_ct) {
         // eq. (force_contact), (torque_contact); the spring s lives in canonical orientation
-        const R aj = (R)pj.w;
-        const R aa = lo ? ai : aj, ab = lo ? aj : ai;
+        const R aa = ai, ab = aj;
         const R delta = (R)(-h);
         if ((float)(-h) > maxov) maxov = (float)(-h);
         if (!MIX) {
             // the spring is updated with the correctly rounded normal (bit-reproducible history)
-            const double dist = sqrt((dx * dx + dy * dy) + dz * dz);
-            n[0] = (R)(dx / dist); n[1] = (R)(dy / dist); n[2] = (R)(dz / dist);
+            const double dd = sqrt((dx * dx + dy * dy) + dz * dz);
+            n[0] = (R)(dx / dd); n[1] = (R)(dy / dd); n[2] = (R)(dz / dd);
         }
         R s[3] = {(R)0, (R)0, (R)0};
-        if (had_contact && pre) {
+        if (had_contact) {
 #pragma unroll
-            for (int d = 0; d < 3; ++d) s[d] = pre->s[d];
-        } else if (had_contact) {
-            load_spring<R>(b, e * npad + i, s);
-        }
-        R wj[3];
-        if (pre) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) wj[d] = pre->wj[d];
-        } else if (MIX) {
-            const float4 w4 = b.wsh[j];
-            wj[0] = w4.x; wj[1] = w4.y; wj[2] = w4.z;
-        } else {
-            const double4 w4 = b.wh[j];
-            wj[0] = (R)w4.x; wj[1] = (R)w4.y; wj[2] = (R)w4.z;
+            for (int d = 0; d < 3; ++d) s[d] = in.s[d];
         }
         R aw[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const R wa = lo ? wi[d] : wj[d], wb = lo ? wj[d] : wi[d];
-            aw[d] = aa * wa + ab * wb;
-        }
+        for (int d = 0; d < 3; ++d) aw[d] = aa * wi[d] + ab * in.wj[d];
         const R awn[3] = {aw[1] * n[2] - aw[2] * n[1], aw[2] * n[0] - aw[0] * n[2], aw[0] * n[1] - aw[1] * n[0]};
         R vc[3];
 #pragma unroll
@@ -1216,23 +1145,20 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
         const R nks[3] = {n[1] * ks[2] - n[2] * ks[1], n[2] * ks[0] - n[0] * ks[2], n[0] * ks[1] - n[1] * ks[0]};
         if (ROT) {
 #pragma unroll
-            for (int d = 0; d < 3; ++d) t[d] = t[d] + ai * nks[d];
+            for (int d = 0; d < 3; ++d) {
+                t[d] = t[d] + ai * nks[d];
+                tb_out[d] = tb_out[d] + aj * nks[d];
+            }
         } else {
 #pragma unroll
-            for (int d = 0; d < 3; ++d) t[d] = ai * nks[d];
-        }
-        if (tb_out) {
-            if (ROT) {
-#pragma unroll
-                for (int d = 0; d < 3; ++d) tb_out[d] = tb_out[d] + aj * nks[d];
-            } else {
-#pragma unroll
-                for (int d = 0; d < 3; ++d) tb_out[d] = nks[d];
+            for (int d = 0; d < 3; ++d) {
+                t[d] = ai * nks[d];
+                tb_out[d] = nks[d];
             }
         }
     }
     if (EXT && C.do_rep) {
-        // short-ranged repulsion (A / kappa) exp(-h / kappa) n, kappa = 0.01 (a_a + a_b) (Sec. IV.B),
+        // short-ranged repulsion (A / kappa) exp(-h / kappa) n, kappa = 0.01 (a_i + a_j) (Sec. IV.F),
         // an interparticle force like contact: it joins fc (and the contact stress)
         const R kappa = (R)(0.01 * (pi.w + pj.w));
         const R fr = C.repA * rrcp<R>(kappa) * rexp<R>(-(R)h * rrcp<R>(kappa));
@@ -1240,22 +1166,17 @@ __device__ __forceinline__ bool eval_item(const Bufs& b, const RepParams& P, con
         for (int d = 0; d < 3; ++d) fc[d] = fc[d] + fr * n[d];
     }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const R fs = fl[d] + fb[d] + fc[d];
-        f[d] = lo ? fs : -fs;
-    }
-    if (lo) {
-        // Sec. II.A, II.B, II.D: Sigma^X_ab -= F^X_a r_b / V, FP64
-        const double rr[3] = {dx * C.invV, dy * C.invV, dz * C.invV};
+    for (int d = 0; d < 3; ++d) f[d] = fl[d] + fb[d] + fc[d];
+    // Sec. II.A, II.B, II.D: Sigma^X_ab -= F^X_a r_b / V, FP64
+    const double rr[3] = {dx * C.invV, dy * C.invV, dz * C.invV};
 #pragma unroll
-        for (int al = 0; al < 3; ++al)
+    for (int al = 0; al < 3; ++al)
 #pragma unroll
-            for (int be = 0; be < 3; ++be) {
-                addS(3 * al + be, -(double)fc[al] * rr[be]);
-                addS(9 + 3 * al + be, -(double)fl[al] * rr[be]);
-                addS(18 + 3 * al + be, -(double)fb[al] * rr[be]);
-            }
-    }
+        for (int be = 0; be < 3; ++be) {
+            addS(3 * al + be, -(double)fc[al] * rr[be]);
+            addS(9 + 3 * al + be, -(double)fl[al] * rr[be]);
+            addS(18 + 3 * al + be, -(double)fb[al] * rr[be]);
+        }
     return true;
 }
 
@@ -1289,335 +1210,8 @@ __device__ __forceinline__ void store_ft(const Bufs& b, uint32_t i, const double
         ((double4*)b.T)[i] = make_double4(Tt[0], Tt[1], Tt[2], 0.0);
     }
 }
-// stores the force and torque of particle i and its masks, applies kick 2, flags
-// non-finite values
-template <bool MIX>
-__device__ __forceinline__ void store_particle(const Bufs& b, const RepParams& P, int kick, uint32_t i,
-                                               const double* Ft, const double* Tt, uint64_t cm, uint64_t sm,
-                                               bool& bad) {
-    bad = nonfinite(Ft, Tt);
-    b.cmask[i] = cm;
-    b.smask[i] = sm;
-    store_ft<MIX>(b, i, Ft, Tt);
-    // kick 2 of velocity-Verlet
-    double4 vf = b.vh[i], wf = b.wh[i];
-    if (kick) half_kick(b.pos[i].w, P.rho, P.half_dt, Ft, Tt, vf, wf);
-    b.vf[i] = vf;
-    b.wf[i] = wf;
-}
-
-// block partial of the 27 stress sums held in thread-private LDS slots sacc[c][thread]
-// (fixed order), stored for the reduction by a later launch; blockDim = NT
-template <int NT>
-__device__ __forceinline__ void write_block_partial(const Bufs& b, int q, double (*sacc)[NT], uint32_t tile) {
-    __syncthreads();
-    __shared__ double quarter[108];
-    if (threadIdx.x < 108) {
-        const int c = threadIdx.x >> 2, k0 = (threadIdx.x & 3) * (NT / 4);
-        double t = 0.0;
-        for (int k = 0; k < NT / 4; ++k) t += sacc[c][k0 + k];
-        quarter[threadIdx.x] = t;
-    }
-    __syncthreads();
-    if (threadIdx.x < 27) {
-        const int c = threadIdx.x;
-        const double t = ((quarter[4 * c] + quarter[4 * c + 1]) + quarter[4 * c + 2]) + quarter[4 * c + 3];
-        b.partial[((size_t)q * 27 + c) * b.nblk_max + tile] = t;
-    }
-}
-
-// thread-private accumulation in LDS (each slot has one writer)
-struct LdsStress {
-    double* row0;  // &sacc[0][threadIdx.x]
-    int stride;
-    __device__ __forceinline__ void operator()(int c, double v) const { lds_add(row0 + c * stride, v); }
-};
-
 // ---------------------------------------------------------------------------
-// Variant 1: LN consecutive lanes share one particle and split its items
-// (e = sub, sub + LN, ...); lanes combine in a fixed butterfly.  With LN = 1
-// the items of a particle are summed by one lane in item order.
-// ---------------------------------------------------------------------------
-template <bool MIX, int LN>
-__global__ __launch_bounds__(kPairBlock) void k_pair(Bufs b, int q, int kick, int advance, uint32_t only_rep) {
-    using R = typename std::conditional<MIX, float, double>::type;
-    if (b.sys->halted) return;  // the host rebuilds the lists and repeats this launch
-    // the first blocks also reduce the stress of the previous evaluation (its partials
-    // have the other parity); with more blocks than compute units this costs little
-    finalize_all(b, 1 - q);
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t i = (tile * kPairBlock + threadIdx.x) / LN;
-    const uint32_t sub = threadIdx.x % LN;
-    const uint32_t r = __builtin_amdgcn_readfirstlane(b.blk_rep[i / kTile]);
-    if (only_rep != 0xFFFFFFFFu && r != only_rep) return;  // whole block belongs to one replica
-    const RepParams& P = b.reps[r];
-    RepDyn& D = b.dyn[r];
-    double s_le;
-    uint64_t step;
-    if (!eval_begin(b, q, advance, P, D, tile == P.p_begin * LN / kPairBlock, s_le, step)) return;
-    EvalCtx<MIX> C;
-    make_ctx<MIX>(C, P, s_le, step);
-
-    __shared__ double sacc[27][kPairBlock];
-#pragma unroll
-    for (int t = 0; t < 27; ++t) sacc[t][threadIdx.x] = 0.0;
-    const LdsStress addS{&sacc[0][threadIdx.x], kPairBlock};
-    float maxov = 0.0f;
-    bool bad = false;
-
-    if (i - P.p_begin < P.n) {
-        const double4 pi = b.pos[i];
-        const uint32_t idi = b.id[i];
-        R vi[3], wi[3];
-        load_vw<MIX>(b, i, vi, wi);
-        Acc<R> F, T;
-        const uint32_t cnt = b.ncnt[i];
-        const uint32_t items = cnt + (C.do_one ? 2u : 0u);
-        const uint64_t cm_old = b.cmask[i];
-        uint64_t cm = 0ull, sm = 0ull;
-        for (uint32_t k = sub; k < items; k += LN) {
-            const uint32_t e = k < cnt ? k : kItemForce + (k - cnt);
-            R f[3], t[3];
-            bool contact, slid;
-            if (!eval_item<MIX>(b, P, C, i, e, pi, idi, vi, wi, k < cnt && ((cm_old >> k) & 1ull), f, t, contact,
-                                slid, maxov, addS))
-                continue;
-            if (contact) {
-                cm |= 1ull << k;
-                if (slid) sm |= 1ull << k;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) T.add(d, t[d]);
-            } else if (e == kItemTorque) {
-#pragma unroll
-                for (int d = 0; d < 3; ++d) T.add(d, t[d]);
-            }
-            if (e != kItemTorque) {
-#pragma unroll
-                for (int d = 0; d < 3; ++d) F.add(d, f[d]);
-            }
-        }
-        // combine the LN lanes of the particle (fixed butterfly order)
-        double Ft[3], Tt[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) { Ft[d] = F.get(d); Tt[d] = T.get(d); }
-        if (LN >= 2) {  // neighbouring lanes (quad_perm 1,0,3,2)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                Ft[d] += dpp_f64<0xB1>(Ft[d]);
-                Tt[d] += dpp_f64<0xB1>(Tt[d]);
-            }
-            cm |= dpp_u64<0xB1>(cm);
-            sm |= dpp_u64<0xB1>(sm);
-        }
-        if (LN >= 4) {  // lane pairs (quad_perm 2,3,0,1)
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                Ft[d] += dpp_f64<0x4E>(Ft[d]);
-                Tt[d] += dpp_f64<0x4E>(Tt[d]);
-            }
-            cm |= dpp_u64<0x4E>(cm);
-            sm |= dpp_u64<0x4E>(sm);
-        }
-        if (LN >= 8) {  // quads
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                Ft[d] += __shfl_xor(Ft[d], 4);
-                Tt[d] += __shfl_xor(Tt[d], 4);
-            }
-            cm |= __shfl_xor(cm, 4);
-            sm |= __shfl_xor(sm, 4);
-        }
-        if (sub == 0) store_particle<MIX>(b, P, kick, i, Ft, Tt, cm, sm, bad);
-    }
-
-    // health: non-finite forces (relaxed atomic; read after the launch), largest overlap
-    if (bad) atomicOr(&D.health, H_NAN);
-    block_max_store(maxov, &b.ovpart[(size_t)q * b.nblk_max + tile]);
-    write_block_partial<kPairBlock>(b, q, sacc, tile);
-}
-
-// ---------------------------------------------------------------------------
-// Variant 2 (wave-cooperative): a wave owns NP = 64 / LN particles.  Its lanes
-// first test the list entries (LN lanes per particle) and build, per
-// particle, the list of its items; the wave packs these lists into chunks of
-// 64 items without splitting a particle across chunks, then evaluates one
-// chunk at a time with every lane on one item, so lanes stay busy whatever
-// the spread of neighbour counts and interactions.  The last lane of each
-// particle's run sums the run's contributions from LDS in item order.
-// ---------------------------------------------------------------------------
-template <bool MIX, int LN>
-__global__ __launch_bounds__(256) void k_pairq(Bufs b, int q, int kick, int advance, uint32_t only_rep) {
-    using R = typename std::conditional<MIX, float, double>::type;
-    constexpr int NP = 64 / LN;  // particles per wave
-    if (b.sys->halted) return;
-    finalize_all(b, 1 - q);
-    const int w = threadIdx.x >> 6, p = threadIdx.x & 63;
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    const uint32_t base = (tile * 4 + w) * NP;  // first particle of this wave
-    const uint32_t r = __builtin_amdgcn_readfirstlane(b.blk_rep[base / kTile]);       // a block (4 NP <= 256 particles) is inside one tile
-    if (only_rep != 0xFFFFFFFFu && r != only_rep) return;
-    const RepParams& P = b.reps[r];
-    RepDyn& D = b.dyn[r];
-    double s_le;
-    uint64_t step;
-    if (!eval_begin(b, q, advance, P, D, tile == P.p_begin / (4 * NP), s_le, step)) return;
-    EvalCtx<MIX> C;
-    make_ctx<MIX>(C, P, s_le, step);
-    const uint32_t npad = b.npad;
-
-    __shared__ uint16_t queue[4][NP * 64];   // items: particle slot << 8 | item code; 0xFFFF = empty
-    __shared__ uint32_t seg0[4][NP], nitems[4][NP];
-    __shared__ unsigned long long cmq[4][NP], smq[4][NP];
-    __shared__ R fbuf[4][6][64];
-    __shared__ uint8_t isct[4][64];
-    __shared__ uint32_t total_[4];
-
-    // ---- cull: which list entries interact (LN lanes per particle)
-    const uint32_t l = p / LN, sub = p % LN;
-    const uint32_t i = base + l;
-    const bool valid = i - P.p_begin < P.n;
-    uint64_t im = 0ull;
-    if (valid) {
-        const double4 pi = b.pos[i];
-        const uint32_t cnt = b.ncnt[i];
-        for (uint32_t e = sub; e < cnt; e += LN)
-            if (interacting(P, s_le, pi, b.pos[b.nbr[e * npad + i]])) im |= 1ull << e;
-    }
-    if (LN >= 2) im |= dpp_u64<0xB1>(im);
-    if (LN >= 4) im |= dpp_u64<0x4E>(im);
-    if (LN >= 8) im |= __shfl_xor(im, 4);
-    const uint32_t npair = (uint32_t)__popcll(im);
-    const uint32_t nk = valid ? npair + (C.do_one ? 2u : 0u) : 0u;
-    if (sub == 0) {
-        nitems[w][l] = nk;
-        cmq[w][l] = 0ull;
-        smq[w][l] = 0ull;
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    // ---- pack: runs of items, never split across a 64-item chunk
-    if (p == 0) {
-        uint32_t off = 0;
-        for (int l2 = 0; l2 < NP; ++l2) {
-            const uint32_t len = nitems[w][l2];
-            if ((off & 63u) + len > 64u) off = (off + 63u) & ~63u;
-            seg0[w][l2] = off;
-            off += len;
-        }
-        total_[w] = off;
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    const uint32_t total = total_[w];
-    for (uint32_t s = p; s < total; s += 64) queue[w][s] = 0xFFFFu;
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    if (valid) {
-        const uint32_t s0 = seg0[w][l];
-        uint64_t m = im;
-        uint32_t k = 0;
-        while (m) {
-            const uint32_t e = (uint32_t)__builtin_ctzll(m);
-            if (k % LN == sub) queue[w][s0 + k] = (uint16_t)((l << 8) | e);
-            m &= m - 1ull;
-            ++k;
-        }
-        if (C.do_one) {
-            if (k % LN == sub) queue[w][s0 + k] = (uint16_t)((l << 8) | kItemForce);
-            if ((k + 1) % LN == sub) queue[w][s0 + k + 1] = (uint16_t)((l << 8) | kItemTorque);
-        }
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-
-    // ---- evaluate chunk by chunk
-    double acc[27];
-#pragma unroll
-    for (int c = 0; c < 27; ++c) acc[c] = 0.0;
-    auto addS = [&](int c, double v) { acc[c] += v; };
-    float maxov = 0.0f;
-    bool bad = false;
-    for (uint32_t c0 = 0; c0 < total; c0 += 64) {
-        const uint32_t code = c0 + p < total ? (uint32_t)queue[w][c0 + p] : 0xFFFFu;
-        R f[3] = {(R)0, (R)0, (R)0}, t[3] = {(R)0, (R)0, (R)0};
-        uint32_t li = 0;
-        uint8_t ct = 0;
-        if (code != 0xFFFFu) {
-            li = code >> 8;
-            const uint32_t e = code & 0xFFu;
-            const uint32_t ii = base + li;
-            const double4 pi = b.pos[ii];
-            const uint32_t idi = b.id[ii];
-            R vi[3], wi[3];
-            load_vw<MIX>(b, ii, vi, wi);
-            const bool had = e < kItemForce && ((b.cmask[ii] >> e) & 1ull);
-            bool contact, slid;
-            eval_item<MIX>(b, P, C, ii, e, pi, idi, vi, wi, had, f, t, contact, slid, maxov, addS);
-            if (contact) {
-                ct = 1;
-                atomicOr(&cmq[w][li], 1ull << e);
-                if (slid) atomicOr(&smq[w][li], 1ull << e);
-            }
-        }
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            fbuf[w][d][p] = f[d];
-            fbuf[w][3 + d][p] = t[d];
-        }
-        isct[w][p] = ct;
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        if (code != 0xFFFFu) {
-            const uint32_t first = seg0[w][li] - c0, len = nitems[w][li];
-            if (p == first + len - 1) {
-                // last item of the particle's run: sum the run in item order
-                Acc<R> F, T;
-                for (uint32_t k = first; k <= (uint32_t)p; ++k) {
-                    const uint32_t ck = queue[w][c0 + k] & 0xFFu;
-                    if (ck != kItemTorque) {
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) F.add(d, fbuf[w][d][k]);
-                    }
-                    if (ck == kItemTorque || isct[w][k]) {
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) T.add(d, fbuf[w][3 + d][k]);
-                    }
-                }
-                double Ft[3], Tt[3];
-#pragma unroll
-                for (int d = 0; d < 3; ++d) { Ft[d] = F.get(d); Tt[d] = T.get(d); }
-                store_particle<MIX>(b, P, kick, base + li, Ft, Tt, cmq[w][li], smq[w][li], bad);
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    }
-    // particles without any item (all terms switched off, no interacting pair)
-    if (valid && sub == 0 && nk == 0) {
-        const double z[3] = {0.0, 0.0, 0.0};
-        store_particle<MIX>(b, P, kick, i, z, z, 0ull, 0ull, bad);
-    }
-
-    if (bad) atomicOr(&D.health, H_NAN);
-    block_max_store(maxov, &b.ovpart[(size_t)q * b.nblk_max + tile]);
-    // block partial of the stress: fixed-order sum over the block's lanes (DPP rows, then LDS)
-    __shared__ double rows[16][27];
-#pragma unroll
-    for (int c = 0; c < 27; ++c) {
-        const double v = row_sum_f64(acc[c]);
-        if ((p & 15) == 15) rows[threadIdx.x >> 4][c] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < 27) {
-        const int c = threadIdx.x;
-        double tsum = 0.0;
-        for (int k = 0; k < 16; ++k) tsum += rows[k][c];
-        b.partial[((size_t)q * 27 + c) * b.nblk_max + tile] = tsum;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Variant 3 (half-pair): every interacting pair is evaluated once, by its
+// Half-pair evaluation: every interacting pair is evaluated once, by its
 // lower-id particle.  k_half: a wave owns NP = 64 / LN particles; LN lanes
 // per particle test the entries whose partner has the higher id (a suffix of
 // the id-sorted list), the wave packs the interacting ones into a queue and
@@ -1626,9 +1220,9 @@ __global__ __launch_bounds__(256) void k_pairq(Bufs b, int q, int kick, int adva
 // particle suit systems too small to fill the GPU with one.  k_gather: each
 // lane sums its particle's pair terms in entry order (reading a lower-id
 // partner's result through the mirror index, negated), then the one-body
-// force and torque, then applies kick 2.  The sums run in the same item order
-// as the other variants, and the pair terms are the same bits, so forces,
-// torques and springs equal those of variant 1 with one lane per particle.
+// force and torque, then applies kick 2.  The sums run in item order whatever
+// the lanes per particle, the queue rounds or the particle layout, so forces,
+// torques and springs do not depend on them.
 // ---------------------------------------------------------------------------
 
 // OCC (FP64 without the model extensions): the form for occupancy -- the queue is
@@ -1684,12 +1278,12 @@ __global__ __launch_bounds__(256, (MIX || OCC) ? 3 : 2) void k_half(Bufs b, int 
     }
     const RepParams& P = b.reps[r];
     RepDyn& D = b.dyn[r];
-    // offset and step counter of this evaluation (the bookkeeping of eval_begin
-    // without its writes, which follow the exit tests)
+    // offset and step counter of this evaluation (its bookkeeping writes follow the
+    // exit tests)
     const double s_le = advance ? next_offset(P, D.s_slot[1 - q]) : D.s_slot[q];
     const uint64_t step = advance ? D.step_slot[1 - q] + 1 : D.step_slot[q];
 
-    // exit tests and the step's bookkeeping (the writes of eval_begin), after the cull
+    // exit tests and the step's bookkeeping, after the cull
     auto go = [&]() -> bool {
         if (halted) return false;
         if (only_rep != 0xFFFFFFFFu && r != only_rep) return false;
@@ -1782,7 +1376,7 @@ __global__ __launch_bounds__(256, (MIX || OCC) ? 3 : 2) void k_half(Bufs b, int 
     };
     float maxov = 0.0f;
     // one pair: item k of the wave's queue order, code (particle slot << 6) | entry
-    auto eval_pair = [&](uint32_t k, uint32_t code) {
+    auto do_pair = [&](uint32_t k, uint32_t code) {
         const uint32_t l = code >> 6, e = code & 63u;
         const uint32_t ii = base + l;
         const bool had = (cmo[w][l] >> e) & 1ull;
@@ -1799,10 +1393,10 @@ __global__ __launch_bounds__(256, (MIX || OCC) ? 3 : 2) void k_half(Bufs b, int 
         load_vw<MIX>(b, in.j, in.vj, in.wj);
         if (had) load_spring<R>(b, e * npad + ii, in.s);
         else in.s[0] = in.s[1] = in.s[2] = (R)0;
-        R f[3], t[3], tb[3];  // tb: written by eval_item where it is used (contact, or the couplings)
+        R f[3], t[3], tb[3];  // tb: written by eval_pair where it is used (contact, or the couplings)
         bool contact, slid;
-        eval_item<MIX, true, EXT, MIX || !OCC>(b, P, C, ii, e, pi, idi, vi, wi, had, f, t, contact, slid, maxov, addS,
-                                                tb, &in);
+        eval_pair<MIX, EXT, MIX || !OCC>(b, P, C, ii, e, pi, idi, vi, wi, had, f, t, contact, slid, maxov, addS, tb,
+                                         in);
         pf[k] = PairRec<R>::make(f[0], f[1], f[2]);
         if (EXT && C.do_rot) {  // torques on the lower- and the higher-id particle
             pt[k] = PairRec<R>::make(t[0], t[1], t[2]);
@@ -1828,7 +1422,7 @@ __global__ __launch_bounds__(256, (MIX || OCC) ? 3 : 2) void k_half(Bufs b, int 
         for (uint32_t r0 = 0; r0 < total; r0 += qc) {
             fill(r0);
             const uint32_t nq = min(total - r0, qc);
-            for (uint32_t kq = p; kq < nq; kq += 64) eval_pair(r0 + kq, queue[w][kq]);
+            for (uint32_t kq = p; kq < nq; kq += 64) do_pair(r0 + kq, queue[w][kq]);
             __builtin_amdgcn_wave_barrier();  // the queue is refilled by the next round
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         }
@@ -1839,7 +1433,7 @@ __global__ __launch_bounds__(256, (MIX || OCC) ? 3 : 2) void k_half(Bufs b, int 
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        for (uint32_t k = p; k < total; k += 64) eval_pair(k, queue[w][k]);
+        for (uint32_t k = p; k < total; k += 64) do_pair(k, queue[w][k]);
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -2260,49 +1854,29 @@ static void launch_pair_t(const Bufs& b, hipStream_t st, int q, int kick, int ad
                           const hipEvent_t* kev, int fuse) {
     const hipEvent_t* ev0 = kev;                        // pair kernel
     const hipEvent_t* ev1 = kev ? kev + 2 : nullptr;    // gather
-    if (b.kern == 2) {  // half-pair evaluation, then the per-particle gather
-        const uint32_t g = b.npad / 256, fin = (27u * b.nrep + 7u) & ~7u;  // finalize blocks, then pair blocks
-        if (b.ext) {
-            switch (b.lanes) {
-                case 1: launch_k(k_half<MIX, 1, true>, dim3(g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
-                case 2: launch_k(k_half<MIX, 2, true>, dim3(2 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
-                default: launch_k(k_half<MIX, 4, true>, dim3(4 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
-            }
-        } else if (!MIX && b.occ) {
-            switch (b.lanes) {
-                case 1: launch_k(k_half<false, 1, false, true>, dim3(g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
-                case 2: launch_k(k_half<false, 2, false, true>, dim3(2 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
-                default: launch_k(k_half<false, 4, false, true>, dim3(4 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
-            }
-        } else {
-            switch (b.lanes) {
-                case 1: launch_k(k_half<MIX, 1, false>, dim3(g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
-                case 2: launch_k(k_half<MIX, 2, false>, dim3(2 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
-                default: launch_k(k_half<MIX, 4, false>, dim3(4 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
-            }
-        }
-        if (b.rot) launch_k(k_gather<MIX, true>, dim3(b.npad / 256), dim3(256), st, ev1, b, q, kick, fuse, only_rep);
-        else launch_k(k_gather<MIX, false>, dim3(b.npad / 256), dim3(256), st, ev1, b, q, kick, fuse, only_rep);
-        return;
-    }
-    if (b.kern == 1) {  // wave-cooperative; 256-thread blocks of 4 * 64 / lanes particles
-        const dim3 blk(256);
-        const uint32_t g = b.npad / 256;
+    // half-pair evaluation, then the per-particle gather
+    const uint32_t g = b.npad / 256, fin = (27u * b.nrep + 7u) & ~7u;  // finalize blocks, then pair blocks
+    if (b.ext) {
         switch (b.lanes) {
-            case 1: launch_k(k_pairq<MIX, 1>, dim3(g), blk, st, ev0, b, q, kick, advance, only_rep); break;
-            case 2: launch_k(k_pairq<MIX, 2>, dim3(2 * g), blk, st, ev0, b, q, kick, advance, only_rep); break;
-            default: launch_k(k_pairq<MIX, 4>, dim3(4 * g), blk, st, ev0, b, q, kick, advance, only_rep); break;
+            case 1: launch_k(k_half<MIX, 1, true>, dim3(g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
+            case 2: launch_k(k_half<MIX, 2, true>, dim3(2 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
+            default: launch_k(k_half<MIX, 4, true>, dim3(4 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
         }
-        return;
+    } else if (!MIX && b.occ) {
+        switch (b.lanes) {
+            case 1: launch_k(k_half<false, 1, false, true>, dim3(g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
+            case 2: launch_k(k_half<false, 2, false, true>, dim3(2 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
+            default: launch_k(k_half<false, 4, false, true>, dim3(4 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
+        }
+    } else {
+        switch (b.lanes) {
+            case 1: launch_k(k_half<MIX, 1, false>, dim3(g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
+            case 2: launch_k(k_half<MIX, 2, false>, dim3(2 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
+            default: launch_k(k_half<MIX, 4, false>, dim3(4 * g + fin), dim3(256), st, ev0, b, q, advance, only_rep); break;
+        }
     }
-    const dim3 blk(kPairBlock);
-    const uint32_t g = b.npad / kPairBlock;
-    switch (b.lanes) {
-        case 1: launch_k(k_pair<MIX, 1>, dim3(g), blk, st, ev0, b, q, kick, advance, only_rep); break;
-        case 2: launch_k(k_pair<MIX, 2>, dim3(2 * g), blk, st, ev0, b, q, kick, advance, only_rep); break;
-        case 4: launch_k(k_pair<MIX, 4>, dim3(4 * g), blk, st, ev0, b, q, kick, advance, only_rep); break;
-        default: launch_k(k_pair<MIX, 8>, dim3(8 * g), blk, st, ev0, b, q, kick, advance, only_rep); break;
-    }
+    if (b.rot) launch_k(k_gather<MIX, true>, dim3(b.npad / 256), dim3(256), st, ev1, b, q, kick, fuse, only_rep);
+    else launch_k(k_gather<MIX, false>, dim3(b.npad / 256), dim3(256), st, ev1, b, q, kick, fuse, only_rep);
 }
 
 void launch_pair_force(const Bufs& b, hipStream_t st, int q, int kick, int advance, uint32_t only_rep,

@@ -26,6 +26,25 @@ void (*g_free)(void*, void*) = nullptr;
 void* g_alloc_ctx = nullptr;
 
 constexpr uint32_t kDefaultCap = 48;
+// Verlet skin of a replica: the configured one, or (skin <= 0) skin_frac times the
+// smallest radius (0.2 by default; the tuner chooses among kSkinFracs for skin < 0)
+constexpr double kSkinDefault = 0.2;
+constexpr double kSkinFracs[] = {0.1, 0.15, 0.2, 0.3, 0.4};
+constexpr double kCellFactors[] = {1.0, 1.5, 2.0};
+constexpr double kRepRange = 16.0;   // the repulsion acts up to a gap of 16 kappa, kappa = 0.01 (a_i + a_j)
+
+// Tunable launch and list parameters (one set per handle).  None of them changes a
+// trajectory: each particle's force is summed over its interacting partners in id
+// order whatever the lanes per particle, the kernel form, the skin of the list or the
+// cell size of the layout.  The stress sums run over pairs in an order that follows
+// the launch shape, so their last bits can differ between parameter sets.
+struct Tune {
+    int lanes = 1, occ = 0;
+    double skin_frac = kSkinDefault;  // skin = skin_frac * a_min (when not configured)
+    double cell = 1.0;                // search cells at least cell * list range wide
+    int source = 0;                   // 0 configured / default, 1 measured, 2 cache
+};
+
 constexpr int kGraphSteps = 8;     // step graphs of kGraphLong, kGraphSteps and 1 steps
 constexpr int kGraphLong = 64;
 
@@ -89,6 +108,8 @@ struct sim {
     int64_t plan_hint = 16;      // first chunk after a build
     double* struct_part = nullptr;  // block sums of the structural Brownian stress
     uint32_t struct_cap = 0;
+    uint32_t keys_cap = 0;       // cell keys allocated (the finest layout a parameter set can ask for)
+    Tune tune;                   // parameter set in use
 
     void* dalloc(size_t bytes) {
         if (bytes == 0) bytes = 256;
@@ -156,8 +177,24 @@ double max_radius(const double* a, uint32_t n) {
     return m;
 }
 
-double eff_skin(const sim_config& c, const double* radii) {
-    return c.skin > 0.0 ? c.skin : 0.2 * min_radius(radii, c.n);
+
+double eff_skin(const sim_config& c, const double* radii, double frac) {
+    return c.skin > 0.0 ? c.skin : frac * min_radius(radii, c.n);
+}
+
+// range factor of the pairs evaluated: the lubrication cut-off, or the repulsion's range
+double range_factor(const sim_config& c) {
+    const double c1 = 1.0 + 0.5 * c.xi_cut;
+    const double cr = 1.0 + kRepRange * 0.01;
+    return c.repulsion > 0.0 && cr > c1 ? cr : c1;
+}
+
+// the minimum image is unique when every box side exceeds twice the list range
+bool box_fits(const sim_config& c, const double* radii, double skin) {
+    const double rl = 2.0 * max_radius(radii, c.n) * range_factor(c) + skin;
+    for (int d = 0; d < 3; ++d)
+        if (!(c.box[d] > 2.0 * rl)) return false;
+    return true;
 }
 
 int validate(const sim_config* c, const double* radii, std::string& why) {
@@ -166,35 +203,27 @@ int validate(const sim_config* c, const double* radii, std::string& why) {
         why = fmt("struct_size %u != sizeof(sim_config) %zu", c->struct_size, sizeof(sim_config));
         return SIM_EINVAL;
     }
-    if (c->lanes != 0 && c->lanes != 1 && c->lanes != 2 && c->lanes != 4 && c->lanes != 8) {
-        why = "lanes must be 0, 1, 2, 4 or 8";
+    if (c->lanes != 0 && c->lanes != 1 && c->lanes != 2 && c->lanes != 4) {
+        why = "lanes must be 0, 1, 2 or 4";
         return SIM_EINVAL;
     }
-    if (c->pair_kernel > SIM_KERNEL_HALF) { why = "unknown pair_kernel"; return SIM_EINVAL; }
-    if (((c->flags & SIM_LUB_ROT) || c->repulsion > 0.0) &&
-        (c->pair_kernel == SIM_KERNEL_LANES || c->pair_kernel == SIM_KERNEL_WAVE)) {
-        why = "SIM_LUB_ROT and the repulsion need the half-pair kernel (pair_kernel 0 or SIM_KERNEL_HALF)";
+    if (c->pair_kernel != SIM_KERNEL_AUTO && c->pair_kernel != SIM_KERNEL_HALF) {
+        why = "pair_kernel must be SIM_KERNEL_AUTO or SIM_KERNEL_HALF";
         return SIM_EINVAL;
     }
     if ((c->flags & SIM_HALF_OCC_ON) && (c->flags & SIM_HALF_OCC_OFF)) {
         why = "SIM_HALF_OCC_ON and SIM_HALF_OCC_OFF exclude each other";
         return SIM_EINVAL;
     }
-    if ((c->flags & SIM_HALF_OCC_ON) &&
-        (c->precision != SIM_FP64 || (c->flags & SIM_LUB_ROT) || c->repulsion > 0.0 ||
-         (c->pair_kernel != SIM_KERNEL_AUTO && c->pair_kernel != SIM_KERNEL_HALF))) {
-        why = "SIM_HALF_OCC_ON needs FP64, no model switch and the half-pair kernel";
-        return SIM_EINVAL;
-    }
-    if (c->pair_kernel == SIM_KERNEL_HALF && c->lanes == 8) {
-        why = "the half-pair kernel needs lanes <= 4";
-        return SIM_EINVAL;
-    }
-    if (c->pair_kernel == SIM_KERNEL_WAVE && (c->lanes == 8 || c->nlist_cap > 62)) {
-        why = "the wave kernel needs lanes <= 4 and nlist_cap <= 62";
+    if ((c->flags & SIM_HALF_OCC_ON) && (c->precision != SIM_FP64 || (c->flags & SIM_LUB_ROT) || c->repulsion > 0.0)) {
+        why = "SIM_HALF_OCC_ON needs FP64 and no model switch";
         return SIM_EINVAL;
     }
     if (c->reserved != 0) { why = "reserved field must be 0"; return SIM_EINVAL; }
+    if (!(c->cell_factor == 0.0 || c->cell_factor < 0.0 || (c->cell_factor >= 1.0 && c->cell_factor <= 4.0))) {
+        why = "cell_factor must be 0 (1.0), negative (tuned) or in [1, 4]";
+        return SIM_EINVAL;
+    }
     if (c->n == 0 || c->n >= 0xFFFFFFFFu) { why = "n must be in [1, 2^32-2]"; return SIM_EINVAL; }
     if (!radii) { why = "null radii"; return SIM_EINVAL; }
     for (uint32_t i = 0; i < c->n; ++i)
@@ -211,13 +240,13 @@ int validate(const sim_config* c, const double* radii, std::string& why) {
     if (!(c->xi_min > 0.0) || !(c->xi_min < c->xi_cut)) { why = "need 0 < xi_min < xi_cut"; return SIM_EINVAL; }
     if (c->precision != SIM_FP64 && c->precision != SIM_MIXED) { why = "unknown precision"; return SIM_EINVAL; }
     if (c->nlist_cap > 64) { why = "nlist_cap must be <= 64"; return SIM_EINVAL; }
-    const double amax = max_radius(radii, c->n);
-    const double rl = 2.0 * amax * (1.0 + 0.5 * c->xi_cut) + eff_skin(*c, radii);
-    for (int d = 0; d < 3; ++d)
-        if (!(c->box[d] > 2.0 * rl)) {
-            why = fmt("box side %d (%g) must exceed twice the list range %g", d, c->box[d], rl);
-            return SIM_EINVAL;
-        }
+    // with a tuned skin the smallest candidate must fit
+    const double skin = eff_skin(*c, radii, c->skin < 0.0 ? kSkinFracs[0] : kSkinDefault);
+    if (!box_fits(*c, radii, skin)) {
+        const double rl = 2.0 * max_radius(radii, c->n) * range_factor(*c) + skin;
+        why = fmt("every box side must exceed twice the list range %g", rl);
+        return SIM_EINVAL;
+    }
     return SIM_OK;
 }
 
@@ -245,11 +274,10 @@ template <class T> std::vector<T> d2h(sim* s, const T* dev, size_t off, size_t c
 // this run of steps starts a sequence; fuse_last: it does not end one (the next
 // run continues it without an integrate).
 void enqueue_steps(sim* s, hipStream_t st, int nsteps, int q0, bool integrate_first = true, bool fuse_last = false) {
-    const bool fuse = s->b.kern == 2;
     for (int k = 0; k < nsteps; ++k) {
         const int q = q0 ^ (k & 1);
-        if ((k == 0 && integrate_first) || !fuse) launch_integrate(s->b, st, q);
-        launch_pair_force(s->b, st, q, 1, 1, 0xFFFFFFFFu, nullptr, fuse && (k + 1 < nsteps || fuse_last));
+        if (k == 0 && integrate_first) launch_integrate(s->b, st, q);
+        launch_pair_force(s->b, st, q, 1, 1, 0xFFFFFFFFu, nullptr, k + 1 < nsteps || fuse_last);
     }
 }
 
@@ -316,6 +344,22 @@ void upload_state(sim* s, int r, const double* x, const double* v, const double*
         Tf[i] = make_float4((float)TT[i].x, (float)TT[i].y, (float)TT[i].z, 0.f);
         id[i] = i;
     }
+    // compact contact table (both sides of each contact), host-input half; checked before
+    // anything is uploaded, so that a rejected state leaves the replica as it was
+    std::vector<uint32_t> cnt(np, 0), cid((size_t)kCtCap * np, 0);
+    std::vector<double> cvs((size_t)kCtCap * 3 * np, 0.0);
+    for (int64_t k = 0; k < nc; ++k) {
+        const uint32_t i = cij[2 * k], j = cij[2 * k + 1];
+        if (i >= n || j >= n || i == j) throw std::string(fmt("contact %lld has invalid ids (%u, %u)", (long long)k, i, j));
+        if (!(i < j)) throw std::string(fmt("contact %lld must list the lower id first", (long long)k));
+        for (int side = 0; side < 2; ++side) {
+            const uint32_t me = side ? j : i, other = side ? i : j;
+            if (cnt[me] >= (uint32_t)kCtCap) throw std::string(fmt("particle %u has more than %d contacts", me, kCtCap));
+            const uint32_t c = cnt[me]++;
+            cid[(size_t)c * np + me] = other;
+            for (int d = 0; d < 3; ++d) cvs[((size_t)c * 3 + d) * np + me] = cs[3 * k + d];
+        }
+    }
     hipStream_t st = s->st;
     auto up = [&](void* dst, const void* src, size_t bytes) {
         HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
@@ -334,21 +378,6 @@ void upload_state(sim* s, int r, const double* x, const double* v, const double*
     } else {
         up((double4*)s->b.F + p0, FF.data(), np * sizeof(double4));
         up((double4*)s->b.T + p0, TT.data(), np * sizeof(double4));
-    }
-    // compact contact table (both sides of each contact), host-input half
-    std::vector<uint32_t> cnt(np, 0), cid((size_t)kCtCap * np, 0);
-    std::vector<double> cvs((size_t)kCtCap * 3 * np, 0.0);
-    for (int64_t k = 0; k < nc; ++k) {
-        const uint32_t i = cij[2 * k], j = cij[2 * k + 1];
-        if (i >= n || j >= n || i == j) throw std::string(fmt("contact %lld has invalid ids (%u, %u)", (long long)k, i, j));
-        if (!(i < j)) throw std::string(fmt("contact %lld must list the lower id first", (long long)k));
-        for (int side = 0; side < 2; ++side) {
-            const uint32_t me = side ? j : i, other = side ? i : j;
-            if (cnt[me] >= (uint32_t)kCtCap) throw std::string(fmt("particle %u has more than %d contacts", me, kCtCap));
-            const uint32_t c = cnt[me]++;
-            cid[(size_t)c * np + me] = other;
-            for (int d = 0; d < 3; ++d) cvs[((size_t)c * 3 + d) * np + me] = cs[3 * k + d];
-        }
     }
     up(s->b.ct_n + npad + p0, cnt.data(), np * sizeof(uint32_t));
     for (int c = 0; c < kCtCap; ++c) {
@@ -373,77 +402,273 @@ void set_dyn(sim* s, int r, double s_le, uint64_t step) {
     s->ring_tail[r] = 0;
 }
 
-// Pair-kernel variant and lanes per particle: the fastest candidate over a
-// few real time steps of the actual system (few lanes suit large systems,
-// more lanes hide gather latency when particles are too few to fill the GPU;
-// the half-pair variant also saves the integrate launch of fused steps).
-// The trial steps change the state: the caller restores it afterwards.
-// want_kern / want_lanes: 0 = free.
-void set_variant(sim* s, int kern, int lanes, int occ = 0) {
-    s->b.kern = kern;
+void set_variant(sim* s, int lanes, int occ) {
     s->b.lanes = lanes;
     s->b.occ = occ;
-    s->b.ppb = kern == 0 ? 128 / lanes : 256 / lanes;
+    s->b.ppb = 256 / lanes;
 }
 
-void tune_pair(sim* s, int want_kern, int want_lanes) {
-    struct Cand {
-        int kern, lanes, occ;
-    };
-    std::vector<Cand> cand;
-    for (int kern : {2, 0, 1}) {
-        if (want_kern && want_kern - 1 != kern) continue;
-        if (s->b.ext && kern != 2) continue;  // the model extensions live in the half-pair kernel
-        if (kern == 1 && s->b.cap > 62) continue;
-        for (int L : {1, 2, 4, 8}) {
-            if (want_lanes && want_lanes != L) continue;
-            if (kern != 0 && L == 8) continue;
-            // the half-pair kernel's form for occupancy (FP64, no extensions), unless forced
-            const bool occ_ok = kern == 2 && !s->mixed && !s->b.ext && !(s->flags & SIM_HALF_OCC_OFF);
-            if (!(occ_ok && (s->flags & SIM_HALF_OCC_ON))) cand.push_back({kern, L, 0});
-            if (occ_ok) cand.push_back({kern, L, 1});
-        }
+// Per-replica parameters for a skin fraction and cell factor; p_begin, blocks and
+// key offsets are filled by the caller.
+RepParams rep_params(const sim_config& c, const double* radii, double skin_frac, double cell) {
+    RepParams P{};
+    for (int d = 0; d < 3; ++d) {
+        P.L[d] = c.box[d];
+        P.invL[d] = 1.0 / c.box[d];
     }
-    if (cand.size() == 1) {
-        set_variant(s, cand[0].kern, cand[0].lanes, cand[0].occ);
+    P.gd = c.gammadot;
+    P.gdLy = c.gammadot * c.box[1];
+    P.dt = c.dt;
+    P.half_dt = 0.5 * c.dt;
+    P.rho = c.rho; P.eta = c.eta; P.kn = c.kn; P.kt = c.kt; P.mu = c.mu;
+    P.rep_A = c.repulsion;
+    P.kT = c.kT;
+    P.bamp = std::sqrt(2.0 * c.kT / c.dt);
+    P.c1 = 1.0 + 0.5 * c.xi_cut;
+    P.c_int = range_factor(c);
+    P.xi_min = c.xi_min;
+    P.skin = eff_skin(c, radii, skin_frac);
+    const double amax = max_radius(radii, c.n), amin = min_radius(radii, c.n);
+    P.rc_max = 2.0 * amax * P.c_int;
+    P.rl_max = P.rc_max + P.skin;
+    P.invV = 1.0 / (c.box[0] * c.box[1] * c.box[2]);
+    const double cf = c.cell_factor > 0.0 ? c.cell_factor : cell;
+    int mx = 1;
+    for (int d = 0; d < 3; ++d) {
+        int nc = (int)std::floor(c.box[d] / (P.rl_max * cf));
+        if (nc < 3) nc = 1;
+        if (nc > 1024) nc = 1024;
+        P.nc[d] = nc;
+        P.cw[d] = c.box[d] / nc;
+        mx = std::max(mx, nc);
+    }
+    P.mbits = morton_bits(mx);
+    P.nkeys = (1u << (3 * P.mbits)) + 1u;
+    P.max_overlap = c.max_overlap > 0.0 ? c.max_overlap : 0.1 * amin;
+    P.n = c.n;
+    P.n_pad = (c.n + kTile - 1) / kTile * kTile;
+    P.flags = c.flags;
+    P.nblk = P.n_pad / kTile;
+    P.seed = c.seed;
+    return P;
+}
+
+// Parameter table of every replica for one parameter set (key offsets laid out in
+// replica order); total cell keys in *keys.
+std::vector<RepParams> layout(const sim* s, const Tune& t, uint32_t* keys) {
+    std::vector<RepParams> out;
+    uint32_t p = 0, key = 0;
+    for (int r = 0; r < s->nrep; ++r) {
+        RepParams P = rep_params(s->cfg[r], s->radii[r].data(), t.skin_frac, t.cell);
+        P.p_begin = p;
+        P.blk_begin = p / kTile;
+        P.key_off = key;
+        key += P.nkeys;
+        p += P.n_pad;
+        out.push_back(P);
+    }
+    *keys = key;
+    return out;
+}
+
+// Makes t the handle's parameter set (tables on the device; the lists are rebuilt by
+// the caller before the next evaluation).
+void apply_tune(sim* s, const Tune& t) {
+    uint32_t keys = 0;
+    s->P = layout(s, t, &keys);
+    if (keys > s->keys_cap) throw std::string(fmt("%u cell keys exceed the %u allocated", keys, s->keys_cap));
+    s->b.nkeys_total = keys;
+    HIPCHK(hipMemcpyAsync(s->b.reps, s->P.data(), sizeof(RepParams) * s->nrep, hipMemcpyHostToDevice, s->st));
+    set_variant(s, t.lanes, t.occ);
+    s->tune = t;
+}
+
+// whether a parameter set keeps every replica's minimum image unique
+bool tune_fits(const sim* s, const Tune& t) {
+    for (int r = 0; r < s->nrep; ++r)
+        if (!box_fits(s->cfg[r], s->radii[r].data(), eff_skin(s->cfg[r], s->radii[r].data(), t.skin_frac)))
+            return false;
+    return true;
+}
+
+// ---- cache of tuned parameter sets: a JSON object, one entry per line,
+// "key": {"lanes": L, "occ": O, "skin": F, "cell": C}
+std::string g_tune_cache;  // path; empty = no cache (guarded by g_mu)
+
+std::string tune_key(const sim* s) {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipGetDeviceProperties(&prop, dev);
+    const sim_config& c0 = s->cfg[0];
+    double ntot = 0.0, phi = 0.0, poly = 1.0, pe = 0.0;
+    for (int r = 0; r < s->nrep; ++r) {
+        const sim_config& c = s->cfg[r];
+        const double* a = s->radii[r].data();
+        double v = 0.0;
+        for (uint32_t i = 0; i < c.n; ++i) v += (4.0 / 3.0) * kPi * a[i] * a[i] * a[i];
+        phi += v / (c.box[0] * c.box[1] * c.box[2]) / s->nrep;
+        ntot += c.n;
+        poly = std::max(poly, max_radius(a, c.n) / min_radius(a, c.n));
+        const double am = min_radius(a, c.n);
+        const double p = c.kT > 0.0 ? 6.0 * kPi * c.eta * am * am * am * std::fabs(c.gammadot) / c.kT : 1e30;
+        pe += std::log10(std::max(p, 1e-30)) / s->nrep;
+    }
+    return fmt("%s/%d|%s|flags%x|rep%d|nrep%d|log2n%.1f|phi%.2f|poly%.1f|log10pe%.0f|skin%g|cell%g|lanes%u|kern%u",
+               prop.gcnArchName, prop.multiProcessorCount, s->mixed ? "mixed" : "fp64", s->flags,
+               c0.repulsion > 0.0 ? 1 : 0, std::min(s->nrep, 64), std::round(2.0 * std::log2(ntot)) / 2.0,
+               std::round(phi * 50.0) / 50.0, std::round(poly * 10.0) / 10.0, std::min(pe, 12.0),
+               c0.skin < 0.0 ? -1.0 : c0.skin, c0.cell_factor < 0.0 ? -1.0 : c0.cell_factor, c0.lanes,
+               c0.pair_kernel);
+}
+
+std::vector<std::pair<std::string, Tune>> cache_read(const std::string& path) {
+    std::vector<std::pair<std::string, Tune>> out;
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return out;
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+        const char* q0 = std::strchr(line, '"');
+        const char* q1 = q0 ? std::strchr(q0 + 1, '"') : nullptr;
+        const char* br = q1 ? std::strchr(q1, '{') : nullptr;
+        if (!br) continue;
+        Tune t;
+        if (std::sscanf(br, "{\"lanes\": %d, \"occ\": %d, \"skin\": %lf, \"cell\": %lf}", &t.lanes, &t.occ,
+                        &t.skin_frac, &t.cell) == 4)
+            out.push_back({std::string(q0 + 1, q1), t});
+    }
+    std::fclose(f);
+    return out;
+}
+
+void cache_write(const std::string& path, const std::string& key, const Tune& t) {
+    auto all = cache_read(path);
+    bool found = false;
+    for (auto& e : all)
+        if (e.first == key) { e.second = t; found = true; }
+    if (!found) all.push_back({key, t});
+    const std::string tmp = path + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;  // a cache that cannot be written is not an error
+    std::fprintf(f, "{\n");
+    for (size_t k = 0; k < all.size(); ++k)
+        std::fprintf(f, "\"%s\": {\"lanes\": %d, \"occ\": %d, \"skin\": %.17g, \"cell\": %.17g}%s\n",
+                     all[k].first.c_str(), all[k].second.lanes, all[k].second.occ, all[k].second.skin_frac,
+                     all[k].second.cell, k + 1 < all.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    (void)std::rename(tmp.c_str(), path.c_str());
+}
+
+// One measured trial of a parameter set on the actual system: rebuild, 2 warm-up
+// steps, rebuild (timed), then two runs of kTrial steps (the faster counts: one
+// run can catch a stall).  Returns the expected time per step including the
+// rebuilds, from the growth of the displacement bound over the trial (the rule the
+// step planner uses): +inf when a list expired during the trial.  The trial steps
+// change the state; the caller restores it.
+double trial(sim* s, const Tune& t, hipEvent_t* e) {
+    constexpr int kTrial = 4;
+    apply_tune(s, t);
+    const int q = 1 - s->par;
+    launch_rebuild(s->b, s->st, q, 0, 0xFFFFFFFFu);
+    enqueue_steps(s, s->st, 2, q);
+    HIPCHK(hipEventRecord(e[0], s->st));
+    launch_rebuild(s->b, s->st, q, 0, 0xFFFFFFFFu);
+    HIPCHK(hipEventRecord(e[1], s->st));
+    enqueue_steps(s, s->st, kTrial, q);
+    HIPCHK(hipEventRecord(e[2], s->st));
+    enqueue_steps(s, s->st, kTrial, q ^ (kTrial & 1));
+    HIPCHK(hipEventRecord(e[3], s->st));
+    HIPCHK(hipEventSynchronize(e[3]));
+    float mr = 0.f, m1 = 0.f, m2 = 0.f;
+    HIPCHK(hipEventElapsedTime(&mr, e[0], e[1]));
+    HIPCHK(hipEventElapsedTime(&m1, e[1], e[2]));
+    HIPCHK(hipEventElapsedTime(&m2, e[2], e[3]));
+    SysDyn sy;
+    HIPCHK(hipMemcpy(&sy, s->b.sys, sizeof sy, hipMemcpyDeviceToHost));
+    if (sy.halted) return 1e30;
+    // fraction of the skin used per step (largest over replicas) after 2 kTrial steps
+    const int last = q ^ ((2 * kTrial - 1) & 1);
+    const uint32_t nt = s->b.npad / kTile;
+    std::vector<float> dp(nt);
+    std::vector<RepDyn> dyn(s->nrep);
+    HIPCHK(hipMemcpy(dp.data(), s->b.dpart + (size_t)last * nt, nt * sizeof(float), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(dyn.data(), s->b.dyn, sizeof(RepDyn) * s->nrep, hipMemcpyDeviceToHost));
+    double used = 0.0;
+    for (int r = 0; r < s->nrep; ++r) {
+        const RepParams& P = s->P[r];
+        double dmax = 0.0;
+        for (uint32_t k = P.blk_begin; k < P.blk_begin + P.nblk; ++k) dmax = std::max(dmax, (double)dp[k]);
+        const double u = 2.0 * dmax + std::fabs(P.gd) * dyn[r].t_slot[last] * (P.rc_max + 2.0 * P.skin);
+        used = std::max(used, u / P.skin / (2.0 * kTrial));
+    }
+    const double steps_per_build = used > 0.0 ? std::max(1.0, 0.8 / used) : 1e30;
+    return std::min(m1, m2) / kTrial + mr / steps_per_build;
+}
+
+// Chooses the parameter set: what the configuration fixes is kept; the rest is read
+// from the cache or measured, one parameter at a time (lanes and kernel form, then
+// the skin, then the cell factor), each by trial() on the actual system.
+void tune(sim* s) {
+    const sim_config& c0 = s->cfg[0];
+    const bool occ_ok = !s->mixed && !s->b.ext && !(s->flags & SIM_HALF_OCC_OFF);
+    std::vector<std::pair<int, int>> forms;  // (lanes, occ)
+    for (int L : {1, 2, 4}) {
+        if (c0.lanes && (int)c0.lanes != L) continue;
+        if (!(occ_ok && (s->flags & SIM_HALF_OCC_ON))) forms.push_back({L, 0});
+        if (occ_ok) forms.push_back({L, 1});
+    }
+    std::vector<double> skins, cells;
+    if (c0.skin < 0.0) skins.assign(std::begin(kSkinFracs), std::end(kSkinFracs));
+    else skins.push_back(kSkinDefault);
+    if (c0.cell_factor < 0.0) cells.assign(std::begin(kCellFactors), std::end(kCellFactors));
+    else cells.push_back(1.0);
+    Tune best;
+    best.lanes = forms[0].first;
+    best.occ = forms[0].second;
+    best.skin_frac = skins.size() == 1 ? skins[0] : kSkinDefault;
+    best.cell = 1.0;
+    if (forms.size() == 1 && skins.size() == 1 && cells.size() == 1) {
+        apply_tune(s, best);
         return;
     }
-    constexpr int kTrial = 4;
-    hipEvent_t e0, e1, e2;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    HIPCHK(hipEventCreate(&e2));
-    float best = 1e30f;
-    Cand pick = cand[0];
-    for (auto c : cand) {
-        set_variant(s, c.kern, c.lanes, c.occ);
-        int q = 1 - s->par;
-        launch_rebuild(s->b, s->st, q, 0, 0xFFFFFFFFu);
-        enqueue_steps(s, s->st, 2, q);  // warm-up
-        launch_rebuild(s->b, s->st, q, 0, 0xFFFFFFFFu);
-        // two timed runs of kTrial steps (the faster counts: one run can catch a stall)
-        HIPCHK(hipEventRecord(e0, s->st));
-        enqueue_steps(s, s->st, kTrial, q);
-        HIPCHK(hipEventRecord(e1, s->st));
-        enqueue_steps(s, s->st, kTrial, q ^ (kTrial & 1));
-        HIPCHK(hipEventRecord(e2, s->st));
-        HIPCHK(hipEventSynchronize(e2));
-        float ms1 = 0.f, ms2 = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms1, e0, e1));
-        HIPCHK(hipEventElapsedTime(&ms2, e1, e2));
-        float ms = std::min(ms1, ms2);
-        SysDyn sy;
-        HIPCHK(hipMemcpy(&sy, s->b.sys, sizeof sy, hipMemcpyDeviceToHost));
-        if (sy.halted) ms = 1e30f;  // a list expired during the trial: no valid timing
-        if (ms < best) {
-            best = ms;
-            pick = c;
+    std::string path;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        path = g_tune_cache;
+    }
+    const std::string key = path.empty() ? std::string() : tune_key(s);
+    if (!path.empty()) {
+        for (auto& e : cache_read(path)) {
+            Tune t = e.second;
+            if (e.first != key || !tune_fits(s, t)) continue;
+            t.source = 2;
+            apply_tune(s, t);
+            return;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipEventDestroy(e2);
-    set_variant(s, pick.kern, pick.lanes, pick.occ);
+    hipEvent_t ev[4];
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    auto scan = [&](std::vector<Tune> cand) {
+        double bt = 1e31;
+        for (const Tune& t : cand) {
+            if (!tune_fits(s, t)) continue;
+            const double ms = trial(s, t, ev);
+            if (ms < bt) { bt = ms; best = t; }
+        }
+    };
+    std::vector<Tune> cand;
+    for (auto f : forms) { Tune t = best; t.lanes = f.first; t.occ = f.second; cand.push_back(t); }
+    if (cand.size() > 1) scan(cand);
+    cand.clear();
+    for (double sf : skins) { Tune t = best; t.skin_frac = sf; cand.push_back(t); }
+    if (cand.size() > 1) scan(cand);
+    cand.clear();
+    for (double cf : cells) { Tune t = best; t.cell = cf; cand.push_back(t); }
+    if (cand.size() > 1) scan(cand);
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    best.source = 1;
+    apply_tune(s, best);
+    if (!path.empty()) cache_write(path, key, best);
 }
 
 int check_rep(sim* s, int32_t r) {
@@ -472,6 +697,12 @@ int sim_set_allocator(void* (*alloc_fn)(size_t, void*), void (*free_fn)(void*, v
     return SIM_OK;
 }
 
+int sim_set_tune_cache(const char* path) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tune_cache = path ? path : "";
+    return SIM_OK;
+}
+
 // index of the first NaN or infinity among n values (-1: none, or no array)
 static int64_t first_nonfinite(const double* a, uint64_t n) {
     if (!a) return -1;
@@ -489,8 +720,10 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         std::string why;
         if (validate(&cfgs[r], radii[r], why) != SIM_OK) return fail(nullptr, SIM_EINVAL, fmt("replica %d: %s", r, why.c_str()));
         if (cfgs[r].precision != cfgs[0].precision || cfgs[r].flags != cfgs[0].flags ||
-            cfgs[r].lanes != cfgs[0].lanes || cfgs[r].pair_kernel != cfgs[0].pair_kernel)
-            return fail(nullptr, SIM_EINVAL, "precision, flags, lanes and pair_kernel must be equal for all replicas");
+            cfgs[r].lanes != cfgs[0].lanes || cfgs[r].pair_kernel != cfgs[0].pair_kernel ||
+            (cfgs[r].skin < 0.0) != (cfgs[0].skin < 0.0) || (cfgs[r].cell_factor < 0.0) != (cfgs[0].cell_factor < 0.0))
+            return fail(nullptr, SIM_EINVAL, "precision, flags, lanes, pair_kernel and which of skin and cell_factor "
+                                             "are tuned must be equal for all replicas");
         if (!x0[r]) return fail(nullptr, SIM_EINVAL, fmt("replica %d: null positions", r));
         for (uint32_t i = 0; i < 3 * cfgs[r].n; ++i) {
             const double L = cfgs[r].box[i % 3];
@@ -520,59 +753,29 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         s->ring_tail.assign(n_replicas, 0);
         uint32_t cap = cfgs[0].nlist_cap ? cfgs[0].nlist_cap : kDefaultCap;
         for (int r = 1; r < n_replicas; ++r) cap = std::max(cap, cfgs[r].nlist_cap ? cfgs[r].nlist_cap : kDefaultCap);
-        uint32_t p = 0, key = 0;
+        for (int r = 0; r < n_replicas; ++r) s->radii.emplace_back(radii[r], radii[r] + cfgs[r].n);
+        // cell keys for the finest layout any parameter set can ask for (the smallest skin, cells
+        // of one list range)
+        uint32_t key = 0;
+        {
+            Tune t;
+            t.skin_frac = cfgs[0].skin < 0.0 ? kSkinFracs[0] : kSkinDefault;
+            s->P = layout(s, t, &key);
+            s->keys_cap = key;
+        }
+        uint32_t p = 0;
         std::vector<uint32_t> blk_rep;
         for (int r = 0; r < n_replicas; ++r) {
             const sim_config& c = cfgs[r];
-            s->radii.emplace_back(radii[r], radii[r] + c.n);
-            RepParams P{};
-            for (int d = 0; d < 3; ++d) {
-                P.L[d] = c.box[d];
-                P.invL[d] = 1.0 / c.box[d];
-            }
-            P.gd = c.gammadot;
-            P.gdLy = c.gammadot * c.box[1];
-            P.dt = c.dt;
-            P.half_dt = 0.5 * c.dt;
-            P.rho = c.rho; P.eta = c.eta; P.kn = c.kn; P.kt = c.kt; P.mu = c.mu;
-            P.rep_A = c.repulsion;
-            P.kT = c.kT;
-            P.bamp = std::sqrt(2.0 * c.kT / c.dt);
-            P.c1 = 1.0 + 0.5 * c.xi_cut;
-            P.xi_min = c.xi_min;
-            P.skin = eff_skin(c, radii[r]);
-            const double amax = max_radius(radii[r], c.n), amin = min_radius(radii[r], c.n);
-            P.rc_max = 2.0 * amax * P.c1;
-            P.rl_max = P.rc_max + P.skin;
-            P.invV = 1.0 / (c.box[0] * c.box[1] * c.box[2]);
-            int mx = 1;
-            for (int d = 0; d < 3; ++d) {
-                int nc = (int)std::floor(c.box[d] / P.rl_max);
-                if (nc < 3) nc = 1;
-                if (nc > 1024) nc = 1024;
-                P.nc[d] = nc;
-                P.cw[d] = c.box[d] / nc;
-                mx = std::max(mx, nc);
-            }
-            P.mbits = morton_bits(mx);
-            P.key_off = key;
-            P.nkeys = (1u << (3 * P.mbits)) + 1u;
-            key += P.nkeys;
-            P.max_overlap = c.max_overlap > 0.0 ? c.max_overlap : 0.1 * amin;
-            P.p_begin = p;
-            P.n = c.n;
-            P.n_pad = (c.n + kTile - 1) / kTile * kTile;
-            P.flags = c.flags;
-            P.blk_begin = p / kTile;
-            P.nblk = P.n_pad / kTile;
-            P.seed = c.seed;
+            const RepParams& P = s->P[r];
             for (uint32_t k = 0; k < P.nblk; ++k) blk_rep.push_back((uint32_t)r);
             p += P.n_pad;
-            s->P.push_back(P);
             double sa3 = 0.0;
             for (uint32_t i = 0; i < c.n; ++i) sa3 += radii[r][i] * radii[r][i] * radii[r][i];
-            // Sec. II.B: per-particle drag stresslet 20/3 pi eta a^3 E, E_xy = gammadot / 2
-            s->drag_xy.push_back(P.invV * (20.0 / 3.0) * kPi * c.eta * sa3 * 0.5 * c.gammadot);
+            // Sec. II.B: per-particle drag stresslet 20/3 pi eta a^3 E, E_xy = gammadot / 2 (a
+            // stress of the one-body drag: none when that is switched off)
+            const double on = (c.flags & SIM_NO_ONEBODY) ? 0.0 : 1.0;
+            s->drag_xy.push_back(on * P.invV * (20.0 / 3.0) * kPi * c.eta * sa3 * 0.5 * c.gammadot);
         }
         Bufs& b = s->b;
         b.npad = p;
@@ -621,7 +824,7 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         for (int a = 0; a < 8; ++a) b.alt4[a] = s->alloc<double4>(np);
         b.disp = s->alloc<double4>(np);
         b.alt_id = s->alloc<uint32_t>(np);
-        b.nblk_max = (uint32_t)(np / 128 * 8);               // 128-thread pair blocks, up to 8 lanes
+        b.nblk_max = (uint32_t)(np / 256 * 4);               // 256-thread pair blocks, up to 4 lanes
         b.partial = s->alloc<double>((size_t)2 * b.nblk_max * 27);
         b.ovpart = s->alloc<float>((size_t)2 * b.nblk_max);
         b.ring = s->alloc<double>((size_t)n_replicas * kRing * 27);
@@ -645,10 +848,17 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
             s->step_now = cfgs[0].step0;
             launch_rebuild(b, s->st, 1 - s->par, 0, 0xFFFFFFFEu);
         };
+        {
+            Tune t0;
+            t0.lanes = cfgs[0].lanes ? (int)cfgs[0].lanes : 1;
+            t0.occ = 0;
+            t0.skin_frac = kSkinDefault;
+            if (cfgs[0].skin < 0.0) t0.skin_frac = kSkinFracs[0];
+            apply_tune(s, t0);
+        }
         load_initial();
-        set_variant(s, 0, 1);
         launch_pair_force(b, s->st, s->par, 0, 0, 0xFFFFFFFFu);
-        tune_pair(s, (int)cfgs[0].pair_kernel, (int)cfgs[0].lanes);
+        tune(s);
         // the trial steps moved the state: start again from the initial one
         load_initial();
         launch_pair_force(b, s->st, s->par, 0, 0, 0xFFFFFFFFu);
@@ -703,7 +913,7 @@ void launch_steps(sim* s, int64_t m) {
             HIPCHK(hipEventCreate(&e));
             s->ev.push_back(e);
         }
-        const bool half = s->b.kern == 2;
+        const bool half = true;  // the gathers integrate every step of a batch but the first
         while (m > 0) {
             const int nb = (int)std::min<int64_t>(m, kBatch);
             for (int k = 0; k < nb; ++k) {
@@ -1256,8 +1466,14 @@ int sim_stats(sim* s, int32_t r, sim_stats_t* out) {
         out->step = d[0].step_slot[s->par];
         out->le_offset = d[0].s_slot[s->par];
         out->lanes = s->b.lanes;
-        out->pair_kernel = s->b.kern + 1;  // SIM_KERNEL_LANES, _WAVE, _HALF
-        out->occupancy_form = s->b.kern == 2 && s->b.occ && !s->mixed && !s->b.ext ? 1 : 0;
+        out->pair_kernel = SIM_KERNEL_HALF;
+        out->occupancy_form = s->b.occ && !s->mixed && !s->b.ext ? 1 : 0;
+        out->tune_source = s->tune.source;
+        out->skin = s->P[r].skin;
+        out->cell_factor = s->cfg[r].cell_factor > 0.0 ? s->cfg[r].cell_factor : s->tune.cell;
+        out->cells_x = s->P[r].nc[0];
+        out->cells_y = s->P[r].nc[1];
+        out->cells_z = s->P[r].nc[2];
         out->reserved = 0;
         return SIM_OK;
     } catch (const HipError& e) {

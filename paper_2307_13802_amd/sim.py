@@ -23,7 +23,7 @@ FREEZE_X, NO_LUB, NO_PAIR_BROWN, NO_CONTACT, NO_ONEBODY, LUB_ROT = 0x1, 0x2, 0x4
 REBUILD_EACH_STEP, NO_GRAPH = 0x100, 0x200
 HALF_OCC_ON, HALF_OCC_OFF = 0x400, 0x800  # half-pair kernel, FP64: force or forbid its form for occupancy
 SMALL_QUEUE = 0x1000  # test switch: that form's pair queue in rounds of 64 items
-KERNEL_AUTO, KERNEL_LANES, KERNEL_WAVE, KERNEL_HALF = 0, 1, 2, 3
+KERNEL_AUTO, KERNEL_HALF = 0, 3
 STRESS_CONTACT, STRESS_LUB, STRESS_BROWN, STRESS_DRAG, STRESS_TOTAL = range(5)
 STRESS_LAST, STRESS_MEAN = 0, 1
 
@@ -42,7 +42,8 @@ class _Config(C.Structure):
                 ("eta", C.c_double), ("kn", C.c_double), ("kt", C.c_double), ("mu", C.c_double),
                 ("kT", C.c_double), ("gammadot", C.c_double), ("dt", C.c_double), ("xi_cut", C.c_double),
                 ("xi_min", C.c_double), ("skin", C.c_double), ("le_offset0", C.c_double),
-                ("max_overlap", C.c_double), ("repulsion", C.c_double), ("seed", C.c_uint64), ("step0", C.c_uint64),
+                ("max_overlap", C.c_double), ("repulsion", C.c_double), ("cell_factor", C.c_double),
+                ("seed", C.c_uint64), ("step0", C.c_uint64),
                 ("precision", C.c_int32), ("flags", C.c_uint32), ("nlist_cap", C.c_uint32),
                 ("lanes", C.c_uint32), ("pair_kernel", C.c_uint32), ("reserved", C.c_uint32)]
 
@@ -52,7 +53,9 @@ class _Stats(C.Structure):
                 ("max_overlap", C.c_double), ("neighbours_per_particle", C.c_double),
                 ("interacting_per_particle", C.c_double), ("contacts", C.c_int64), ("rebuilds", C.c_int64),
                 ("steps", C.c_int64), ("step", C.c_uint64), ("le_offset", C.c_double), ("lanes", C.c_int32),
-                ("pair_kernel", C.c_int32), ("occupancy_form", C.c_int32), ("reserved", C.c_int32)]
+                ("pair_kernel", C.c_int32), ("occupancy_form", C.c_int32), ("tune_source", C.c_int32),
+                ("skin", C.c_double), ("cell_factor", C.c_double), ("cells_x", C.c_int32), ("cells_y", C.c_int32),
+                ("cells_z", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SimError(RuntimeError):
@@ -106,6 +109,7 @@ def lib():
         "sim_destroy": [vp],
         "sim_last_error": [vp, C.c_char_p, C.c_size_t],
         "sim_set_allocator": [_ALLOC_CB, _FREE_CB, vp],
+        "sim_set_tune_cache": [C.c_char_p],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -154,6 +158,7 @@ class Config:
     le_offset0: float = 0.0
     max_overlap: float = 0.0
     repulsion: float = 0.0
+    cell_factor: float = 0.0
     seed: int = 0
     step0: int = 0
     precision: int = FP64
@@ -169,7 +174,7 @@ class Config:
         for d in range(3):
             c.box[d] = float(self.box[d])
         for f in ("rho", "eta", "kn", "kt", "mu", "kT", "gammadot", "dt", "xi_cut", "xi_min", "skin",
-                  "le_offset0", "max_overlap", "repulsion"):
+                  "le_offset0", "max_overlap", "repulsion", "cell_factor"):
             setattr(c, f, float(getattr(self, f)))
         c.seed, c.step0 = int(self.seed), int(self.step0)
         c.precision, c.flags, c.nlist_cap = int(self.precision), int(self.flags), int(self.nlist_cap)
@@ -183,6 +188,11 @@ def validate(cfg: Config, radii) -> int:
     a = np.ascontiguousarray(radii, dtype=np.float64)
     c = cfg.c(len(a))
     return lib().sim_validate(C.byref(c), _dp(a))
+
+
+def set_tune_cache(path):
+    """Cache file of tuned launch and list parameters for later handles (None = none)."""
+    _check(lib().sim_set_tune_cache(None if path is None else str(path).encode()))
 
 
 def last_error() -> str:
@@ -202,6 +212,11 @@ def use_torch_allocator():
     a, f = _ALLOC_CB(_alloc), _FREE_CB(_free)
     _keep.extend([a, f])
     _check(lib().sim_set_allocator(a, f, None))
+
+
+def use_default_allocator():
+    """Routes device allocations of later handles to hipMalloc / hipFree again."""
+    _check(lib().sim_set_allocator(_ALLOC_CB(), _FREE_CB(), None))
 
 
 def _current_stream():

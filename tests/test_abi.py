@@ -48,6 +48,10 @@ def _cfg(**kw):
 def test_validate_accepts_good_config():
     a = np.full(10, 1.0)
     assert S.validate(_cfg(), a) == S.OK
+    # list range 2 * 1.025 + 0.2 = 2.25 (< 5 / 2), or 2.05 + 0.1 with the smallest tuned skin
+    assert S.validate(_cfg(box=(5.0, 20.0, 20.0)), a) == S.OK
+    assert S.validate(_cfg(box=(4.4, 20.0, 20.0), skin=-1.0), a) == S.OK
+    assert S.validate(_cfg(cell_factor=-1.0, lanes=4, pair_kernel=3), a) == S.OK
 
 
 @pytest.mark.parametrize("kw, radii, needle", [
@@ -64,17 +68,21 @@ def test_validate_accepts_good_config():
     (dict(), np.array([1.0, 0.0]), "radius"),
     (dict(rho=0.0), None, "rho"),
     (dict(lanes=3), None, "lanes"),
+    (dict(lanes=8), None, "lanes"),
     (dict(pair_kernel=4), None, "pair_kernel"),
-    (dict(pair_kernel=2, lanes=8), None, "wave kernel"),
-    (dict(pair_kernel=3, lanes=8), None, "half-pair"),
-    (dict(flags=0x20, pair_kernel=1), None, "SIM_LUB_ROT"),
-    (dict(repulsion=1.0, pair_kernel=2), None, "half-pair kernel"),
+    (dict(pair_kernel=1), None, "pair_kernel"),
+    (dict(pair_kernel=2), None, "pair_kernel"),
     (dict(repulsion=-1.0), None, "non-negative"),
+    (dict(cell_factor=0.5), None, "cell_factor"),
+    (dict(cell_factor=5.0), None, "cell_factor"),
+    # the repulsion reaches a gap of 16 kappa: its list range is 2 * 1.16 + skin
+    (dict(box=(5.0, 20.0, 20.0), repulsion=1.0), None, "twice the list range"),
+    # a tuned skin must fit with its smallest candidate (0.1 a_min)
+    (dict(box=(4.3, 20.0, 20.0), skin=-1.0), None, "twice the list range"),
     (dict(flags=0x400 | 0x800), None, "exclude each other"),
     (dict(flags=0x400, precision=1), None, "SIM_HALF_OCC_ON"),
     (dict(flags=0x400 | 0x20), None, "SIM_HALF_OCC_ON"),
     (dict(flags=0x400, repulsion=1.0), None, "SIM_HALF_OCC_ON"),
-    (dict(flags=0x400, pair_kernel=1), None, "SIM_HALF_OCC_ON"),
 ])
 def test_validate_rejects(kw, radii, needle):
     a = np.full(4, 1.0) if radii is None else radii

@@ -7,11 +7,10 @@ dynamics, change the interaction set.  At each checkpoint: the interaction set
 end, the mean pair shear stress (contact + lubrication + Brownian, xy) against
 the oracle's, beside its block standard error.
 
-The 1,000-step run of the 500-sphere workload runs with the GPU tests; the
-2,000-step prefix of the 50,000-sphere workload takes the oracle about two
-minutes and runs when SUSP_LONG_TESTS=1.
+The 1,000-step run of the 500-sphere workload and the 2,000-step prefix of the
+50,000-sphere workload (about two minutes of oracle time) both run with the GPU
+tests.
 """
-import os
 import sys
 
 import numpy as np
@@ -87,8 +86,6 @@ def test_c1_trajectory_1000_steps(P):
     _run(P, gen.C1, 10, 100, cells=False)
 
 
-@pytest.mark.skipif(os.environ.get("SUSP_LONG_TESTS") != "1",
-                    reason="the oracle takes about two minutes; set SUSP_LONG_TESTS=1")
 def test_c2_prefix_2000_steps(P):
     """50,000 bidisperse spheres, phi = 0.55, Pe = 10: the first 2,000 steps."""
     _say("case: trajectory N=50000 phi=0.55 Pe=10, 2000 steps in chunks of 200")
