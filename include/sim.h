@@ -266,20 +266,41 @@ int sim_reset_displacement(sim* s);
 
 /* Histogram of the pair distances r = |r_ij| < r_max of the current
  * configuration of one replica (each pair once; minimum image in the sheared
- * box), nbins bins of width r_max / nbins, added to nothing: counts receives
- * nbins integers.  Dividing by the ideal-gas count of each shell gives g(r)
- * (Sec. III.A).  Rebuilds the neighbour lists first (which changes no
- * trajectory).  SIM_EINVAL for nbins outside [1, 2^24] or r_max outside
- * (0, 2 a_min (1 + xi_cut/2) + skin], the range every list covers. */
+ * box), nbins bins of width r_max / nbins, from a cell pass of its own (not the
+ * neighbour lists): counts receives nbins integers.  Dividing by the ideal-gas
+ * count of each shell gives g(r) (Sec. III.A), e.g. out to the flat region of
+ * the potential of mean force.  Rebuilds the neighbour lists first (which
+ * changes no trajectory).  SIM_EINVAL for nbins outside [1, 2^24] or r_max
+ * outside (0, L/2), L the smallest box side. */
 int sim_rdf(sim* s, int32_t replica, double r_max, int32_t nbins, uint64_t* counts);
 
+/* Slice of the pair distribution through the flow-gradient (xy) plane of one
+ * replica (Sec. IV.D, the microstructure under shear): pairs with
+ * |r_z| < slab / 2 and |r_x|, |r_y| < r_max, counted at r_ij and at -r_ij on an
+ * nbins x nbins grid over [-r_max, r_max)^2; counts[ix * nbins + iy], ix along
+ * x (flow), iy along y (gradient).  Dividing by the ideal-gas count of a bin
+ * (n (n - 1) / V x bin area x slab) gives g in the slice.  Rebuilds the lists
+ * first.  SIM_EINVAL for nbins outside [1, 4096], slab <= 0 or
+ * sqrt(2 r_max^2 + slab^2 / 4) not in (0, L/2). */
+int sim_rdf_xy(sim* s, int32_t replica, double r_max, double slab, int32_t nbins, uint64_t* counts);
+
 /* Time autocorrelation of one recorded stress component (component
- * SIM_STRESS_CONTACT, _LUB or _BROWN, entry alpha, beta in 0..2) over the
- * per-step records since sim_reset_stress (at most the last 8192):
- * out[k] = mean over t of S(t) S(t + k), k < nlag, for Green-Kubo integrals
- * (Sec. IV.B).  SIM_ERANGE if fewer than nlag records are available. */
+ * SIM_STRESS_CONTACT, _LUB or _BROWN, entry alpha, beta in 0..2) for Green-Kubo
+ * integrals (Sec. IV.B): out[k] = mean over t of S(t) S(t + k), k < nlag, over
+ * the count - k pairs of records.  If sim_stress_acf_stream is accumulating
+ * this entry with at least nlag lags, the sums cover every record since the
+ * stream started or sim_reset_stress (no limit on the count); otherwise the
+ * records since sim_reset_stress in the ring (at most the last 8192).
+ * SIM_ERANGE if fewer than nlag records are available. */
 int sim_stress_acf(sim* s, int32_t replica, int32_t component, int32_t alpha, int32_t beta, int64_t nlag,
                    double* out);
+
+/* Starts accumulating the autocorrelation of one stress entry (as in
+ * sim_stress_acf) for every replica on the device, at every recorded step, for
+ * lags 0..nlag-1 (nlag <= 2^20): no record ring bounds the run length.  The
+ * sums restart with sim_reset_stress; nlag = 0 stops the stream.  Each lag's sum
+ * runs in time order. */
+int sim_stress_acf_stream(sim* s, int32_t component, int32_t alpha, int32_t beta, int64_t nlag);
 
 /* Positions of one replica in id order, wrapped into [0, L), FP64, 3n doubles. */
 int sim_positions(sim* s, int32_t replica, double* out_3n);
@@ -308,8 +329,9 @@ int sim_forces(sim* s, int32_t replica, double* F_3n, double* T_3n);
  * dimensionless gap xi <= xi_cut, sorted.  cap is in pairs. */
 int sim_pairs(sim* s, int32_t replica, uint32_t* ij_2m, int64_t cap, int64_t* count);
 
-/* Verlet set of the current neighbour list (gap within xi_cut plus skin at
- * the last rebuild), pairs (id_i < id_j), sorted. */
+/* Verlet set of the current neighbour list (|r| <= (a_i + a_j)(1 + xi_cut/2)
+ * + skin at the last rebuild; with the repulsion on, (a_i + a_j)(1 + 16 x 0.01)
+ * + skin when that is larger), pairs (id_i < id_j), sorted. */
 int sim_nlist(sim* s, int32_t replica, uint32_t* ij_2m, int64_t cap, int64_t* count);
 
 /* Contact history: pairs (id_i < id_j) in contact at the last evaluation,

@@ -85,6 +85,7 @@ def _load():
     _lib.orc_structural_stress.argtypes = [C.c_void_p, dp]
     _lib.orc_get_disp.argtypes = [C.c_void_p, dp]
     _lib.orc_rdf.argtypes = [C.c_void_p, C.c_double, C.c_int, C.POINTER(C.c_uint64)]
+    _lib.orc_rdf_xy.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_uint64)]
     _lib.orc_lub_rot_scalars.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, dp]
     _lib.orc_get_contacts.restype = C.c_int
     _lib.orc_get_contacts.argtypes = [C.c_void_p, C.c_int, up, dp, C.POINTER(C.c_int32)]
@@ -265,6 +266,12 @@ class Oracle:
         out = np.zeros(nbins, np.uint64)
         lib().orc_rdf(self._h, float(r_max), int(nbins), out.ctypes.data_as(C.POINTER(C.c_uint64)))
         return out
+
+    def rdf_xy(self, r_max, slab, nbins):
+        """Pair counts in the flow-gradient slice |r_z| < slab/2, (nbins, nbins) over [-r_max, r_max)^2."""
+        out = np.zeros(nbins * nbins, np.uint64)
+        lib().orc_rdf_xy(self._h, float(r_max), float(slab), int(nbins), out.ctypes.data_as(C.POINTER(C.c_uint64)))
+        return out.reshape(nbins, nbins)
 
     def structural_stress(self):
         """(3, 3) structural Brownian stress of the current configuration, Sec. II.D."""

@@ -795,6 +795,29 @@ void orc_rdf(const orc_state *S, double r_max, int nbins, uint64_t *counts)
         }
 }
 
+/* Slice of the pair distribution through the flow-gradient plane (Sec. IV.D):
+   pairs with |r_z| < slab/2 and |r_x|, |r_y| < r_max, counted at r and at -r on
+   an nbins x nbins grid over [-r_max, r_max)^2 (counts[ix * nbins + iy]);
+   brute force over all pairs, minimum image in the sheared box. */
+void orc_rdf_xy(const orc_state *S, double r_max, double slab, int nbins, uint64_t *counts)
+{
+    for (long k = 0; k < (long)nbins * nbins; ++k) counts[k] = 0;
+    for (int i = 0; i < S->n; ++i)
+        for (int j = i + 1; j < S->n; ++j) {
+            double r[3];
+            min_image(&S->p, S->s_le, &S->x[3 * i], &S->x[3 * j], r);
+            if (!(fabs(r[2]) < 0.5 * slab) || !(fabs(r[0]) < r_max) || !(fabs(r[1]) < r_max)) continue;
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                double ux = sgn ? -r[0] : r[0], uy = sgn ? -r[1] : r[1];
+                int ix = (int)((ux + r_max) / (2.0 * r_max) * (double)nbins);
+                int iy = (int)((uy + r_max) / (2.0 * r_max) * (double)nbins);
+                if (ix >= nbins) ix = nbins - 1;
+                if (iy >= nbins) iy = nbins - 1;
+                counts[(long)ix * nbins + iy] += 1;
+            }
+        }
+}
+
 /* Runs nsteps steps and adds the pair-distance histogram of the configuration
    after every `every`-th step to counts (the g(r) sampling of Sec. III.A). */
 void orc_run_rdf(orc_state *S, long nsteps, long every, double r_max, int nbins, uint64_t *counts)

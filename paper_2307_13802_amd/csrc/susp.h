@@ -152,6 +152,16 @@ struct Bufs {
     int occ;              // half-pair kernel in FP64 without extensions: 1 = its form for occupancy
     uint32_t qcap;        // queue items per round of that form (2048; 64 under SIM_SMALL_QUEUE)
 
+    // streaming autocorrelation of one recorded stress entry (Green-Kubo, Sec. IV.B):
+    // acf_comp = entry 0..26 or -1 (off); per replica the last acf_nlag samples
+    // (acf_hist, circular), the lag sums acf_sum[k] = sum_t s(t) s(t - k) and the
+    // sample count acf_n
+    int acf_comp;
+    uint32_t acf_nlag;
+    double* acf_hist;     // [rep][acf_nlag]
+    double* acf_sum;      // [rep][acf_nlag]
+    unsigned long long* acf_n;  // [rep]
+
     double* dacc;         // per particle: bound on its non-affine displacement since the last build
     double4* disp;        // per particle: accumulated non-affine displacement (x, y, z) since the
                           // creation, the last state upload or sim_reset_displacement
@@ -188,9 +198,13 @@ void launch_finalize(const Bufs& b, hipStream_t st, int q);
 void launch_rebuild(const Bufs& b, hipStream_t st, int q, int in_step, uint32_t ct_input_rep);
 // mean-square displacement sums of one replica: nblk = n_pad / 256 blocks, 3 doubles each
 void launch_msd(const Bufs& b, hipStream_t st, uint32_t rep, uint32_t nblk, double* part);
-// pair-distance histogram of one replica at parity p (each pair once, r < r_max)
-void launch_rdf(const Bufs& b, hipStream_t st, int p, uint32_t rep, uint32_t nblk, double r_max, uint32_t nbins,
-                unsigned long long* counts);
+// pair histograms of one replica at parity p from a cell pass reaching `reach`:
+// mode 0 = distances r < r_max in nbins bins; mode 1 = the flow-gradient slice
+// |r_z| < slab / 2 on an nbins x nbins grid over [-r_max, r_max)^2 (each pair at r and -r)
+void launch_rdf(const Bufs& b, hipStream_t st, int p, uint32_t rep, uint32_t nblk, int mode, double r_max,
+                double slab, double reach, uint32_t nbins, unsigned long long* counts);
+// zeroes n 64-bit words with a kernel
+void launch_zero64(hipStream_t st, unsigned long long* a, uint32_t n);
 // autocorrelation of one recorded stress component of one replica over the records
 // [first, first + count) of the ring: out[lag] = mean_t s(t) s(t + lag), lag < nlag
 void launch_acf(const Bufs& b, hipStream_t st, uint32_t rep, int comp, uint32_t first, uint32_t count,

@@ -235,11 +235,13 @@ __device__ void finalize_unit(const Bufs& b, uint32_t r, int c, int x) {
         if ((threadIdx.x & 15) == 15) mrows[threadIdx.x >> 4] = m;
     }
     __syncthreads();
+    __shared__ double total;
+    const uint32_t rec = D.rec[x];
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int k = 0; k < (int)(blockDim.x >> 4); ++k) t += rows[k];
+        total = t;
         b.last[r * 27 + c] = t;
-        const uint32_t rec = D.rec[x];
         if (rec) {
             b.ring[((size_t)r * kRing + (rec - 1) % kRing) * 27 + c] = t;
             D.stress_sum[c] += t;
@@ -253,6 +255,23 @@ __device__ void finalize_unit(const Bufs& b, uint32_t r, int c, int x) {
         D.done_id[x][c] = id;
     }
     __syncthreads();
+    if (rec && c == b.acf_comp) {
+        // streaming autocorrelation: each lag's sum gains s(t) s(t - k), one thread per lag,
+        // the terms of every lag in time order
+        const uint32_t W = b.acf_nlag;
+        const unsigned long long ns = b.acf_n[r];
+        double* hist = b.acf_hist + (size_t)r * W;
+        double* sum = b.acf_sum + (size_t)r * W;
+        const double v = total;
+        for (uint32_t k = threadIdx.x; k < W && (unsigned long long)k <= ns; k += blockDim.x)
+            sum[k] += (k == 0 ? v : hist[(ns - k) % W]) * v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            hist[ns % W] = v;
+            b.acf_n[r] = ns + 1;
+        }
+        __syncthreads();
+    }
 }
 
 // units (replica, component) handled by the blocks of a grid, in turn
@@ -609,7 +628,8 @@ __global__ __launch_bounds__(256) void k_rb_copyback(Bufs b) {
     }
 }
 
-// Verlet list: every j with |r| <= (a_i + a_j)(1 + xi_cut/2) + skin, sorted by
+// Verlet list: every j with |r| <= (a_i + a_j) c_int + skin (c_int = 1 + xi_cut/2, or the
+// repulsion's range factor when that is larger), sorted by
 // partner id (so force sums do not depend on the cell layout), then the
 // carried contact history is attached to its list entry.
 __global__ __launch_bounds__(256) void k_rb_nlist(Bufs b, int q, int in_step) {
@@ -626,8 +646,8 @@ __global__ __launch_bounds__(256) void k_rb_nlist(Bufs b, int q, int in_step) {
     const double4 pi = b.pos[i];
     const double s_base = b.dyn[r].s_slot[1 - q];
     const double s_le = in_step ? next_offset(P, s_base) : s_base;
-    const double amax = P.rc_max / (2.0 * P.c1);
-    const double rli = (pi.w + amax) * P.c1 + P.skin;           // largest list radius of i
+    const double amax = P.rc_max / (2.0 * P.c_int);
+    const double rli = (pi.w + amax) * P.c_int + P.skin;        // largest list radius of i
     const double margin = rli * (1.0 + 1e-12) + 1e-12 * P.L[0];
     const int cy = cell_coord(pi.y, P.cw[1], P.nc[1]);
     const int cz = cell_coord(pi.z, P.cw[2], P.nc[2]);
@@ -656,7 +676,7 @@ __global__ __launch_bounds__(256) void k_rb_nlist(Bufs b, int q, int in_step) {
                     double dx, dy, dz;
                     min_image(P, s_le, pi, pj, dx, dy, dz);
                     const double d2 = (dx * dx + dy * dy) + dz * dz;
-                    const double rl = (pi.w + pj.w) * P.c1 + P.skin;
+                    const double rl = (pi.w + pj.w) * P.c_int + P.skin;
                     if (d2 <= rl * rl) {
                         if (cnt < cap) b.nbr[cnt * npad + i] = j;
                         ++cnt;
@@ -959,6 +979,10 @@ __device__ __forceinline__ bool eval_pair(const Bufs& b, const RepParams& P, con
     const R ai = (R)pi.w;
 #pragma unroll
     for (int d = 0; d < 3; ++d) { f[d] = (R)0; t[d] = (R)0; }
+    if (EXT) {  // with the couplings every pair has a torque record on j (zero for a repulsion-only pair)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) tb_out[d] = (R)0;
+    }
     contact = false;
     slid = false;
     // ---- geometry (FP64)
@@ -1667,35 +1691,96 @@ void launch_msd(const Bufs& b, hipStream_t st, uint32_t rep, uint32_t nblk, doub
     hipLaunchKernelGGL(k_msd, dim3(nblk), dim3(256), 0, st, b, rep, part);
 }
 
-// Histogram of pair distances r < r_max of one replica at parity p (each pair
-// once, from its lower-id side; the list holds every pair within its range),
-// nbins bins of width r_max / nbins; integer counts, so the order of the
-// atomic increments does not matter.
-__global__ __launch_bounds__(256) void k_rdf(Bufs b, uint32_t rep, int p, double r_max, uint32_t nbins,
-                                             unsigned long long* counts) {
+// Pair histograms of one replica at parity p from its own cell pass (any range
+// below half the box, independent of the lists): every particle scans the cells
+// within `reach` of it -- across the sheared y boundary the x range is shifted by
+// the Lees-Edwards offset -- and takes each partner with a higher id once, over
+// the minimum image r = x_i - x_j.
+//   mode 0 (g(r), Sec. III.A): |r| < r_max into nbins bins of width r_max / nbins;
+//   mode 1 (slice of g through the flow-gradient plane, Sec. IV.D): pairs with
+//     |r_z| < slab / 2 and |r_x|, |r_y| < r_max, binned by (r_x, r_y) on an
+//     nbins x nbins grid over [-r_max, r_max)^2, each pair at r and at -r;
+//     counts[ix * nbins + iy].
+// Integer counts, so the order of the atomic increments does not matter.
+__device__ __forceinline__ void rdf_bin(double dx, double dy, double dz, int mode, double r_max, double slab,
+                                        uint32_t nbins, unsigned long long* counts) {
+    if (mode == 0) {
+        const double r = sqrt((dx * dx + dy * dy) + dz * dz);
+        if (!(r < r_max)) return;
+        uint32_t k = (uint32_t)(r / r_max * (double)nbins);
+        if (k >= nbins) k = nbins - 1;
+        atomicAdd(&counts[k], 1ull);
+    } else {
+        if (!(fabs(dz) < 0.5 * slab) || !(fabs(dx) < r_max) || !(fabs(dy) < r_max)) return;
+        const double w = 2.0 * r_max;
+        for (int sgn = 0; sgn < 2; ++sgn) {
+            const double ux = sgn ? -dx : dx, uy = sgn ? -dy : dy;
+            uint32_t ix = (uint32_t)((ux + r_max) / w * (double)nbins), iy = (uint32_t)((uy + r_max) / w * (double)nbins);
+            if (ix >= nbins) ix = nbins - 1;
+            if (iy >= nbins) iy = nbins - 1;
+            atomicAdd(&counts[(size_t)ix * nbins + iy], 1ull);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rdf(Bufs b, uint32_t rep, int p, int mode, double r_max, double slab,
+                                             double reach, uint32_t nbins, unsigned long long* counts) {
     const RepParams& P = b.reps[rep];
     const uint32_t i = P.p_begin + blockIdx.x * 256 + threadIdx.x;
     if (i - P.p_begin >= P.n) return;
     const double4 pi = b.pos[i];
     const uint32_t idi = b.id[i];
     const double s_le = b.dyn[rep].s_slot[p];
-    const uint32_t cnt = b.ncnt[i];
-    for (uint32_t e = 0; e < cnt; ++e) {
-        const uint32_t j = b.nbr[e * b.npad + i];
-        if (!(idi < b.id[j])) continue;
-        double dx, dy, dz;
-        min_image(P, s_le, pi, b.pos[j], dx, dy, dz);
-        const double r = sqrt((dx * dx + dy * dy) + dz * dz);
-        if (!(r < r_max)) continue;
-        uint32_t k = (uint32_t)(r / r_max * (double)nbins);
-        if (k >= nbins) k = nbins - 1;
-        atomicAdd(&counts[k], 1ull);
+    const double margin = reach * (1.0 + 1e-12) + 1e-12 * P.L[0];
+    const int cy = cell_coord(pi.y, P.cw[1], P.nc[1]);
+    const int cz = cell_coord(pi.z, P.cw[2], P.nc[2]);
+    int ly = (int)ceil(margin / P.cw[1]), lz = (int)ceil(margin / P.cw[2]);
+    // rows (y) or layers (z) scanned all at once when the layers would wrap onto themselves
+    const bool all_y = 2 * ly + 1 >= P.nc[1], all_z = 2 * lz + 1 >= P.nc[2];
+    const int oy0 = all_y ? 0 : -ly, oy1 = all_y ? P.nc[1] - 1 : ly;
+    const int oz0 = all_z ? 0 : -lz, oz1 = all_z ? P.nc[2] - 1 : lz;
+    for (int oz = oz0; oz <= oz1; ++oz) {
+        const int zz = all_z ? oz : ((cz + oz) % P.nc[2] + P.nc[2]) % P.nc[2];
+        for (int oy = oy0; oy <= oy1; ++oy) {
+            int yy = all_y ? oy : cy + oy;
+            double shift = 0.0;
+            if (!all_y) {
+                if (yy < 0) { yy += P.nc[1]; shift = s_le; }             // j's image sits at y - Ly, x - s
+                else if (yy >= P.nc[1]) { yy -= P.nc[1]; shift = -s_le; }
+            }
+            const double xs = pi.x + shift;
+            int xlo = (int)floor((xs - margin) / P.cw[0]);
+            int xhi = (int)floor((xs + margin) / P.cw[0]);
+            if (all_y || xhi - xlo + 1 >= P.nc[0]) { xlo = 0; xhi = P.nc[0] - 1; }
+            for (int xc = xlo; xc <= xhi; ++xc) {
+                const int xx = ((xc % P.nc[0]) + P.nc[0]) % P.nc[0];
+                const uint32_t key = P.key_off + morton3((uint32_t)xx, (uint32_t)yy, (uint32_t)zz);
+                const uint32_t st = b.cell_start[key], en = st + b.cell_cnt[key];
+                for (uint32_t j = st; j < en; ++j) {
+                    if (!(idi < b.id[j])) continue;
+                    double dx, dy, dz;
+                    min_image(P, s_le, pi, b.pos[j], dx, dy, dz);
+                    rdf_bin(dx, dy, dz, mode, r_max, slab, nbins, counts);
+                }
+            }
+        }
     }
 }
 
-void launch_rdf(const Bufs& b, hipStream_t st, int p, uint32_t rep, uint32_t nblk, double r_max, uint32_t nbins,
-                unsigned long long* counts) {
-    hipLaunchKernelGGL(k_rdf, dim3(nblk), dim3(256), 0, st, b, rep, p, r_max, nbins, counts);
+void launch_rdf(const Bufs& b, hipStream_t st, int p, uint32_t rep, uint32_t nblk, int mode, double r_max,
+                double slab, double reach, uint32_t nbins, unsigned long long* counts) {
+    hipLaunchKernelGGL(k_rdf, dim3(nblk), dim3(256), 0, st, b, rep, p, mode, r_max, slab, reach, nbins, counts);
+}
+
+// zeroes n 64-bit words (a kernel, not a memset node, so that the call can sit in
+// a captured graph)
+__global__ __launch_bounds__(256) void k_zero64(unsigned long long* a, uint32_t n) {
+    for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) a[k] = 0ull;
+}
+
+void launch_zero64(hipStream_t st, unsigned long long* a, uint32_t n) {
+    const uint32_t g = std::min<uint32_t>((n + 255) / 256, 1024u);
+    hipLaunchKernelGGL(k_zero64, dim3(g), dim3(256), 0, st, a, n);
 }
 
 // Time autocorrelation of recorded stress component comp (0..26) of one

@@ -264,6 +264,18 @@ template <class T> std::vector<T> d2h(sim* s, const T* dev, size_t off, size_t c
     return h;
 }
 
+// Destroys the captured step graphs (they are captured again on the next step).
+void drop_graphs(sim* s) {
+    for (auto& a : s->gc)
+        for (auto& b2 : a)
+            for (auto& c : b2)
+                for (auto& g : c)
+                    if (g) {
+                        (void)hipGraphExecDestroy(g);
+                        g = nullptr;
+                    }
+}
+
 // nsteps time steps, the first with parity q0, without a list rebuild; every
 // launch does nothing once the expiry test of an earlier one has halted the
 // chunk.  With the half-pair variant the gather of each step but the last
@@ -807,6 +819,8 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         b.pt = s->dalloc(np * cap * (s->mixed ? 4 * sizeof(float) : 3 * sizeof(double)));
         b.pt2 = s->dalloc(np * cap * (s->mixed ? 4 * sizeof(float) : 3 * sizeof(double)));
         b.qcap = (s->flags & SIM_SMALL_QUEUE) ? 64u : 2048u;
+        b.acf_comp = -1;   // no streaming autocorrelation until asked for
+        b.acf_nlag = 0;
         b.rot = (s->flags & SIM_LUB_ROT) ? 1 : 0;
         b.ext = b.rot;
         for (int r = 0; r < n_replicas; ++r)
@@ -1099,6 +1113,10 @@ int sim_reset_stress(sim* s) {
         HIPCHK(hipMemcpyAsync(dyn.data(), s->b.dyn, sizeof(RepDyn) * s->nrep, hipMemcpyDeviceToHost, s->st));
         HIPCHK(hipStreamSynchronize(s->st));
         const double z[27] = {0};
+        if (s->b.acf_hist) {   // the streaming autocorrelation starts again
+            launch_zero64(s->st, (unsigned long long*)s->b.acf_sum, (uint32_t)((size_t)s->nrep * s->b.acf_nlag));
+            launch_zero64(s->st, s->b.acf_n, (uint32_t)s->nrep);
+        }
         for (int r = 0; r < s->nrep; ++r) {
             HIPCHK(hipMemcpyAsync((char*)(s->b.dyn + r) + offsetof(RepDyn, stress_sum), z, sizeof z,
                                   hipMemcpyHostToDevice, s->st));
@@ -1231,25 +1249,86 @@ int sim_msd(sim* s, int32_t r, double out[3]) {
     }
 }
 
+namespace {
+// Pair histogram of replica r into the device array dc (nwords 64-bit counts, zeroed here
+// by a kernel), copied to counts: mode 0 = g(r) bins, mode 1 = the flow-gradient slice.
+int rdf_into(sim* s, int32_t r, int mode, double r_max, double slab, int32_t nbins, unsigned long long* dc,
+             uint64_t* counts) {
+    const RepParams& P = s->P[r];
+    const uint32_t nwords = mode == 0 ? (uint32_t)nbins : (uint32_t)nbins * (uint32_t)nbins;
+    const double reach = mode == 0 ? r_max : std::sqrt(2.0 * r_max * r_max + 0.25 * slab * slab);
+    launch_rebuild(s->b, s->st, 1 - s->par, 0, 0xFFFFFFFFu);   // current cells (changes no trajectory)
+    s->since_build = 0;
+    s->plan = s->plan_hint;
+    launch_zero64(s->st, dc, nwords);
+    launch_rdf(s->b, s->st, s->par, (uint32_t)r, P.n_pad / 256, mode, r_max, slab, reach, (uint32_t)nbins, dc);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(counts, dc, sizeof(uint64_t) * nwords, hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    return check_health(s);
+}
+
+// the minimum image of every pair within reach must be unique
+bool reach_ok(const RepParams& P, double reach) {
+    return reach > 0.0 && reach < 0.5 * std::min(P.L[0], std::min(P.L[1], P.L[2]));
+}
+}  // namespace
+
 int sim_rdf(sim* s, int32_t r, double r_max, int32_t nbins, uint64_t* counts) {
     if (int rc = check_rep(s, r)) return rc;
     if (!counts || nbins <= 0 || nbins > (1 << 24)) return fail(s, SIM_EINVAL, "need counts and 0 < nbins <= 2^24");
-    const RepParams& P = s->P[r];
-    const double amin = min_radius(s->radii[r].data(), P.n);
-    const double rl_min = 2.0 * amin * P.c1 + P.skin;  // every list holds all pairs within this range
-    if (!(r_max > 0.0) || r_max > rl_min)
-        return fail(s, SIM_EINVAL, fmt("r_max must be in (0, %g], the smallest list range", rl_min));
+    if (!reach_ok(s->P[r], r_max)) return fail(s, SIM_EINVAL, "r_max must be in (0, L/2) for the smallest box side L");
     try {
-        launch_rebuild(s->b, s->st, 1 - s->par, 0, 0xFFFFFFFFu);
-        s->since_build = 0;
-        s->plan = s->plan_hint;
-        unsigned long long* dc = s->alloc<unsigned long long>((size_t)nbins);  // zeroed
-        launch_rdf(s->b, s->st, s->par, (uint32_t)r, P.n_pad / 256, r_max, (uint32_t)nbins, dc);
-        HIPCHK(hipGetLastError());
-        auto h = d2h(s, dc, 0, (size_t)nbins);
-        for (int k = 0; k < nbins; ++k) counts[k] = h[k];
+        unsigned long long* dc = s->alloc<unsigned long long>((size_t)nbins);
+        const int rc = rdf_into(s, r, 0, r_max, 0.0, nbins, dc, counts);
         s->release(dc);
-        return check_health(s);
+        return rc;
+    } catch (const HipError& e) {
+        return hip_fail(s, e);
+    }
+}
+
+int sim_rdf_xy(sim* s, int32_t r, double r_max, double slab, int32_t nbins, uint64_t* counts) {
+    if (int rc = check_rep(s, r)) return rc;
+    if (!counts || nbins <= 0 || nbins > 4096) return fail(s, SIM_EINVAL, "need counts and 0 < nbins <= 4096");
+    if (!(slab > 0.0) || !reach_ok(s->P[r], std::sqrt(2.0 * r_max * r_max + 0.25 * slab * slab)))
+        return fail(s, SIM_EINVAL, "need slab > 0, r_max > 0 and sqrt(2 r_max^2 + slab^2 / 4) < L/2");
+    try {
+        unsigned long long* dc = s->alloc<unsigned long long>((size_t)nbins * (size_t)nbins);
+        const int rc = rdf_into(s, r, 1, r_max, slab, nbins, dc, counts);
+        s->release(dc);
+        return rc;
+    } catch (const HipError& e) {
+        return hip_fail(s, e);
+    }
+}
+
+int sim_stress_acf_stream(sim* s, int32_t component, int32_t alpha, int32_t beta, int64_t nlag) {
+    if (!s) return fail(nullptr, SIM_EINVAL, "null handle");
+    if (nlag < 0 || nlag > (1 << 20)) return fail(s, SIM_EINVAL, "nlag must be in [0, 2^20]");
+    if (nlag > 0 && (component < 0 || component > SIM_STRESS_BROWN || alpha < 0 || alpha > 2 || beta < 0 || beta > 2))
+        return fail(s, SIM_EINVAL, "bad component or index");
+    try {
+        HIPCHK(hipStreamSynchronize(s->st));
+        if (s->b.acf_hist) {
+            s->release(s->b.acf_hist);
+            s->release(s->b.acf_sum);
+            s->release(s->b.acf_n);
+            s->b.acf_hist = s->b.acf_sum = nullptr;
+            s->b.acf_n = nullptr;
+        }
+        s->b.acf_comp = -1;
+        s->b.acf_nlag = 0;
+        if (nlag > 0) {
+            s->b.acf_hist = s->alloc<double>((size_t)s->nrep * nlag);   // zeroed
+            s->b.acf_sum = s->alloc<double>((size_t)s->nrep * nlag);
+            s->b.acf_n = s->alloc<unsigned long long>((size_t)s->nrep);
+            s->b.acf_comp = component * 9 + alpha * 3 + beta;
+            s->b.acf_nlag = (uint32_t)nlag;
+        }
+        drop_graphs(s);   // captured launches hold the buffer table by value
+        HIPCHK(hipStreamSynchronize(s->st));
+        return SIM_OK;
     } catch (const HipError& e) {
         return hip_fail(s, e);
     }
@@ -1261,6 +1340,16 @@ int sim_stress_acf(sim* s, int32_t r, int32_t component, int32_t alpha, int32_t 
         nlag <= 0)
         return fail(s, SIM_EINVAL, "bad component, index, lag count or output");
     try {
+        const int comp = component * 9 + alpha * 3 + beta;
+        if (comp == s->b.acf_comp && nlag <= (int64_t)s->b.acf_nlag) {
+            // the streaming sums: every record since the stream started or the stress was reset
+            auto n = d2h(s, s->b.acf_n, (size_t)r, 1);
+            auto sum = d2h(s, s->b.acf_sum, (size_t)r * s->b.acf_nlag, (size_t)nlag);
+            if ((int64_t)n[0] < nlag) return fail(s, SIM_ERANGE, fmt("%llu records streamed, %lld lags asked",
+                                                                      (unsigned long long)n[0], (long long)nlag));
+            for (int64_t k = 0; k < nlag; ++k) out[k] = sum[k] / (double)(n[0] - (uint64_t)k);
+            return SIM_OK;
+        }
         auto d = d2h(s, s->b.dyn, (size_t)r, 1);
         const uint32_t head = d[0].nrec;  // records 1..head; record k sits in slot (k - 1) % kRing
         uint32_t first = d[0].rec_base;
@@ -1268,8 +1357,7 @@ int sim_stress_acf(sim* s, int32_t r, int32_t component, int32_t alpha, int32_t 
         const uint32_t count = head - first;
         if ((int64_t)count < nlag) return fail(s, SIM_ERANGE, fmt("%u records since the reset, %lld lags asked", count, (long long)nlag));
         double* dout = s->alloc<double>((size_t)nlag);
-        launch_acf(s->b, s->st, (uint32_t)r, component * 9 + alpha * 3 + beta, first % kRing, count,
-                   (uint32_t)nlag, dout);
+        launch_acf(s->b, s->st, (uint32_t)r, comp, first % kRing, count, (uint32_t)nlag, dout);
         HIPCHK(hipGetLastError());
         auto h = d2h(s, dout, 0, (size_t)nlag);
         std::copy(h.begin(), h.end(), out);
@@ -1286,7 +1374,7 @@ int sim_structural_stress(sim* s, int32_t r, double out[9]) {
     const RepParams& P = s->P[r];
     // the list (range (a_i + a_j)(1 + xi_cut/2) + skin) must hold every shell partner
     const double amin = min_radius(s->radii[r].data(), P.n), amax = max_radius(s->radii[r].data(), P.n);
-    if (P.skin + amin * (2.0 * (P.c1 - 1.0)) < 0.05 * amax)
+    if (P.skin + amin * (2.0 * (P.c_int - 1.0)) < 0.05 * amax)
         return fail(s, SIM_EINVAL, "the neighbour list range does not cover the 0.05 a shell");
     try {
         launch_rebuild(s->b, s->st, 1 - s->par, 0, 0xFFFFFFFFu);

@@ -95,6 +95,8 @@ def lib():
         "sim_msd": [vp, C.c_int32, dp],
         "sim_reset_displacement": [vp],
         "sim_rdf": [vp, C.c_int32, C.c_double, C.c_int32, C.POINTER(C.c_uint64)],
+        "sim_rdf_xy": [vp, C.c_int32, C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_uint64)],
+        "sim_stress_acf_stream": [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int64],
         "sim_stress_acf": [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int64, dp],
         "sim_get_state": [vp, C.c_int32, dp, dp, dp, dp, dp, dp, C.POINTER(C.c_uint64)],
         "sim_set_state": [vp, C.c_int32, dp, dp, dp, dp, dp, C.c_double, C.c_uint64, up, dp, C.c_int64],
@@ -330,6 +332,17 @@ class Sim:
         _check(lib().sim_rdf(self.h, replica, float(r_max), int(nbins), out.ctypes.data_as(C.POINTER(C.c_uint64))),
                self.h)
         return out
+
+    def rdf_xy(self, r_max, slab, nbins, replica=0):
+        """Pair counts in the flow-gradient slice |r_z| < slab/2, (nbins, nbins) over [-r_max, r_max)^2."""
+        out = np.zeros(nbins * nbins, np.uint64)
+        _check(lib().sim_rdf_xy(self.h, replica, float(r_max), float(slab), int(nbins),
+                                out.ctypes.data_as(C.POINTER(C.c_uint64))), self.h)
+        return out.reshape(nbins, nbins)
+
+    def stress_acf_stream(self, component, alpha, beta, nlag):
+        """Accumulates the autocorrelation of a stress entry on the device at every recorded step."""
+        _check(lib().sim_stress_acf_stream(self.h, component, alpha, beta, int(nlag)), self.h)
 
     def stress_acf(self, component, alpha, beta, nlag, replica=0):
         """Time autocorrelation of a recorded stress entry over the records since the reset."""

@@ -52,7 +52,7 @@ def _bench_cfg(P, st, precision):
     return P.Config(box=st["L"], precision=precision, skin=-1.0, cell_factor=-1.0, lanes=0, **st["params"])
 
 
-def _compare(P, sim, orc, label):
+def _compare(P, sim, orc, label, exact_springs=True):
     p = sim.configs[0]
     pg, po = sim.pairs(), orc.pairs()
     cg, co = sim.contacts(), orc.contacts()
@@ -68,7 +68,11 @@ def _compare(P, sim, orc, label):
     _say(f"  {label}: pairs {len(pg)}/{len(po)} contacts {len(cg[0])}/{len(co[0])} F err {ef:.2e} "
          f"T err {et:.2e} stress err {es:.2e} eta_r {eg:.10g} / {eo:.10g}")
     assert np.array_equal(pg, po)
-    assert np.array_equal(cg[0], co[0]) and np.array_equal(cg[1], co[1]) and np.array_equal(cg[2], co[2])
+    assert np.array_equal(cg[0], co[0])
+    if exact_springs:   # from an identical state: the same bits
+        assert np.array_equal(cg[1], co[1]) and np.array_equal(cg[2], co[2])
+    else:               # after steps the positions differ in the last bits (force sums in another order)
+        assert np.abs(cg[1] - co[1]).max() <= 1e-9 * np.abs(co[1]).max()
     assert ef <= TOL_F64 and et <= TOL_F64 and es <= TOL_F64
     assert abs(eg - eo) <= TOL_F64 * abs(eo)
 
@@ -88,7 +92,14 @@ def test_c3_relaxed_fp64_matches_oracle(P, c3):
     dx = float(np.abs(g["x"] - o["x"]).max())
     _say(f"  after 2 steps: max |dx| {dx:.2e}")
     assert g["step"] == o["step"] and g["s_le"] == o["s_le"] and dx < 1e-12
-    _compare(P, sim, orc, "step 2")
+    _compare(P, sim, orc, "step 2", exact_springs=False)
+    # and from the oracle's state injected into the library, one evaluation: bit-exact again
+    cij, cs, _ = orc.contacts()
+    sim.set_state(0, o["x"], o["v"], o["w"], s_le=o["s_le"], step=o["step"], contacts=(cij, cs))
+    del orc
+    ref = O.Oracle(O.Params(L=st["L"], **st["params"], flags=O.CELLS), st["radii"], o["x"], o["v"], o["w"],
+                   s_le=o["s_le"], step=o["step"], contacts=(cij, cs))
+    _compare(P, sim, ref, "injected state at step 2")
     sim.close()
 
 

@@ -972,3 +972,25 @@ def test_acf_closed_forms():
         ar[t] = ph * ar[t - 1] + e[t]
     c = O.acf(ar, 8)
     assert np.allclose(c, ph ** np.arange(8) / (1 - ph * ph), rtol=0.05)
+
+
+def test_rdf_xy_slice_brute_force():
+    """The flow-gradient slice of the pair distribution against a numpy enumeration of all pairs
+    in an unsheared box: identical counts (up to bin-edge rounding), point-symmetric."""
+    n, L = 250, (12.0, 12.5, 13.0)
+    a = gen.radii_bidisperse(n, 5)
+    x, v, w = gen.random_state(n, L, a, seed=7)
+    o = O.Oracle(_params(L), a, x, v, w)
+    r_max, slab, nb = 4.0, 1.5, 16
+    h = o.rdf_xy(r_max, slab, nb)
+    d = x[:, None, :] - x[None, :, :]
+    d -= np.asarray(L) * np.rint(d / np.asarray(L))
+    iu = np.triu_indices(n, 1)
+    r = d[iu]
+    sel = (np.abs(r[:, 2]) < slab / 2) & (np.abs(r[:, 0]) < r_max) & (np.abs(r[:, 1]) < r_max)
+    r = r[sel]
+    both = np.concatenate([r[:, :2], -r[:, :2]])
+    ref, _, _ = np.histogram2d(both[:, 0], both[:, 1], bins=nb, range=((-r_max, r_max), (-r_max, r_max)))
+    assert h.sum() == ref.sum() > 200
+    assert np.abs(h.astype(np.int64) - ref.astype(np.int64)).sum() <= 4
+    assert np.array_equal(h, h[::-1, ::-1])
