@@ -4,7 +4,8 @@ Default workload (the metric's configuration): 1,000,000 bidisperse spheres
 (radii 1.0 / 1.4, 50:50 by number), phi = 0.56, Pe = 10 (gammadot = 0.009,
 kT = 6 pi eta 0.009 / 10), mu = 0.5, k_n = 1e4, k_t = 2/7 k_n, dt = 1e-4,
 xi_cut = 0.05, xi_min = 1e-3, FP64, seeded relaxed packing, all inputs resident
-in HBM before timing, launch and list parameters from the tuner.
+in HBM before timing, launch and list parameters from the tuner (read from the
+cache of parameters it measured on an MI355X, so that reruns time the same launch).
 
 Prints one JSON line: the FP64 throughput (headline), the mixed-precision form on
 the same workload with its viscosity error under the shadow protocol (FP64 states
@@ -425,7 +426,9 @@ def main():
                     help="profiler driver: a 256 MiB elementwise kernel (the calibration of the byte counters), "
                          "then --steps steps of the workload in FP64 and in mixed precision with the launch "
                          "parameters the tuner picks (cached in --tune-cache)")
-    ap.add_argument("--tune-cache", default=None, help="file of tuned launch and list parameters")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2307_13802_amd", "tune_cache_mi355x.json"),
+                    help="file of tuned launch and list parameters (default: the parameters the tuner measured for "
+                         "these workloads on an MI355X; a workload or device not in it is tuned at creation)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the engine has no multi-GPU path",

@@ -591,7 +591,7 @@ def test_displacement_msd_rdf_match_oracle(P):
     sim.reset_displacement()
     assert np.abs(sim.displacement()).max() == 0.0
     with pytest.raises(P.SimError):
-        sim.rdf(10.0, 50)   # not below half the box side (19.9): the minimum image would not be unique
+        sim.rdf(0.5 * st["L"][0], 50)   # not below half the box side: the minimum image would not be unique
 
 
 def test_rdf_beyond_list_range_and_xy_slice(P):
@@ -616,7 +616,7 @@ def test_rdf_beyond_list_range_and_xy_slice(P):
         assert hg.sum() > 1000 and np.array_equal(hg, ho)
         assert np.array_equal(hg, hg[::-1, ::-1])   # each pair at r and -r
     with pytest.raises(P.SimError):
-        sim.rdf_xy(7.0, 1.0, 10)   # sqrt(2) 7 > L/2
+        sim.rdf_xy(0.5 * L / math.sqrt(2.0) + 0.01, 1.0, 10)   # its reach would exceed half the box
 
 
 def test_stress_acf_stream_unbounded_matches_oracle(P):
