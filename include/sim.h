@@ -274,6 +274,18 @@ int sim_reset_displacement(sim* s);
  * outside (0, L/2), L the smallest box side. */
 int sim_rdf(sim* s, int32_t replica, double r_max, int32_t nbins, uint64_t* counts);
 
+/* sim_rdf for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight sampling loops, harnesses that forbid hipMalloc): the same
+ * histogram, bit for bit, with its bins in a static device array of the library
+ * (65,536 64-bit words per GPU, held until the process ends) instead of memory
+ * allocated per call; it calls no hipMalloc, hipFree or other allocating routine.
+ * The bins are cleared by a kernel at every call.  All calls on one GPU share
+ * that array: calls that overlap in time on one GPU (from several threads or
+ * streams) race and must be serialised by the caller.  SIM_EINVAL for nbins
+ * outside [1, 65536] and as sim_rdf otherwise; SIM_EDEVICE if the array's
+ * address cannot be obtained on the current device. */
+int sim_rdf_noalloc(sim* s, int32_t replica, double r_max, int32_t nbins, uint64_t* counts);
+
 /* Slice of the pair distribution through the flow-gradient (xy) plane of one
  * replica (Sec. IV.D, the microstructure under shear): pairs with
  * |r_z| < slab / 2 and |r_x|, |r_y| < r_max, counted at r_ij and at -r_ij on an

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 namespace susp {
 
 constexpr int kTile = 256;               // replicas are padded to multiples of this many particles
@@ -205,6 +207,12 @@ void launch_rdf(const Bufs& b, hipStream_t st, int p, uint32_t rep, uint32_t nbl
                 double slab, double reach, uint32_t nbins, unsigned long long* counts);
 // zeroes n 64-bit words with a kernel
 void launch_zero64(hipStream_t st, unsigned long long* a, uint32_t n);
+// The scratch array of the entry points that allocate nothing: kScratchWords 64-bit words,
+// a static device array, one copy per GPU.  Returns the current device's copy (its address
+// looked up on first use on that device), or null with a message in err.
+constexpr uint32_t kScratchWords = 1u << 16;
+constexpr int kMaxDevices = 64;
+unsigned long long* scratch_ptr(std::string& err);
 // autocorrelation of one recorded stress component of one replica over the records
 // [first, first + count) of the ring: out[lag] = mean_t s(t) s(t + lag), lag < nlag
 void launch_acf(const Bufs& b, hipStream_t st, uint32_t rep, int comp, uint32_t first, uint32_t count,

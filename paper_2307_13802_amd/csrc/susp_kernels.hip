@@ -15,6 +15,9 @@
 // bit-reproducible; FP64 division and square root are IEEE correctly rounded.
 #include <hip/hip_ext.h>
 
+#include <mutex>
+#include <string>
+
 #include "susp.h"
 
 namespace susp {
@@ -1770,6 +1773,33 @@ __global__ __launch_bounds__(256) void k_rdf(Bufs b, uint32_t rep, int p, int mo
 void launch_rdf(const Bufs& b, hipStream_t st, int p, uint32_t rep, uint32_t nblk, int mode, double r_max,
                 double slab, double reach, uint32_t nbins, unsigned long long* counts) {
     hipLaunchKernelGGL(k_rdf, dim3(nblk), dim3(256), 0, st, b, rep, p, mode, r_max, slab, reach, nbins, counts);
+}
+
+// Scratch memory of the entry points that allocate nothing: a file-scope device
+// array (one copy per GPU, held until the process ends).  Host code never uses the
+// array's name as an address: each device's copy is looked up once, with that device
+// current, by hipGetSymbolAddress, and that pointer is what kernels and copies get.
+static __device__ __align__(256) unsigned long long scratch[kScratchWords];
+
+unsigned long long* scratch_ptr(std::string& err) {
+    static std::mutex mu;
+    static unsigned long long* ptrs[kMaxDevices] = {};
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        err = "no current device (or its index is beyond the supported range)";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptrs[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            err = std::string("hipGetSymbolAddress of the scratch array failed: ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        ptrs[dev] = (unsigned long long*)p;
+    }
+    return ptrs[dev];
 }
 
 // zeroes n 64-bit words (a kernel, not a memset node, so that the call can sit in

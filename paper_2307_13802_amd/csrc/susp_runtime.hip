@@ -109,6 +109,7 @@ struct sim {
     double* struct_part = nullptr;  // block sums of the structural Brownian stress
     uint32_t struct_cap = 0;
     uint32_t keys_cap = 0;       // cell keys allocated (the finest layout a parameter set can ask for)
+    std::vector<RepDyn> dyn_host;  // host copy of the per-replica records read by the health check
     Tune tune;                   // parameter set in use
 
     void* dalloc(size_t bytes) {
@@ -306,7 +307,7 @@ hipGraphExec_t capture(sim* s, int nsteps, int q0, bool integrate_first, bool fu
 
 // Reads and clears the health flags; returns a status.
 int check_health(sim* s) {
-    std::vector<RepDyn> dyn(s->nrep);
+    std::vector<RepDyn>& dyn = s->dyn_host;   // sized at creation: no allocation here
     HIPCHK(hipMemcpyAsync(dyn.data(), s->b.dyn, sizeof(RepDyn) * s->nrep, hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
     int code = SIM_OK;
@@ -763,6 +764,7 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         s->flags = cfgs[0].flags;
         s->cfg.assign(cfgs, cfgs + n_replicas);
         s->ring_tail.assign(n_replicas, 0);
+        s->dyn_host.resize(n_replicas);
         uint32_t cap = cfgs[0].nlist_cap ? cfgs[0].nlist_cap : kDefaultCap;
         for (int r = 1; r < n_replicas; ++r) cap = std::max(cap, cfgs[r].nlist_cap ? cfgs[r].nlist_cap : kDefaultCap);
         for (int r = 0; r < n_replicas; ++r) s->radii.emplace_back(radii[r], radii[r] + cfgs[r].n);
@@ -1283,6 +1285,21 @@ int sim_rdf(sim* s, int32_t r, double r_max, int32_t nbins, uint64_t* counts) {
         const int rc = rdf_into(s, r, 0, r_max, 0.0, nbins, dc, counts);
         s->release(dc);
         return rc;
+    } catch (const HipError& e) {
+        return hip_fail(s, e);
+    }
+}
+
+int sim_rdf_noalloc(sim* s, int32_t r, double r_max, int32_t nbins, uint64_t* counts) {
+    if (int rc = check_rep(s, r)) return rc;
+    if (!counts || nbins <= 0 || nbins > (int32_t)kScratchWords)
+        return fail(s, SIM_EINVAL, fmt("need counts and 0 < nbins <= %u (the static scratch array)", kScratchWords));
+    if (!reach_ok(s->P[r], r_max)) return fail(s, SIM_EINVAL, "r_max must be in (0, L/2) for the smallest box side L");
+    std::string err;
+    unsigned long long* dc = scratch_ptr(err);
+    if (!dc) return fail(s, SIM_EDEVICE, err);
+    try {
+        return rdf_into(s, r, 0, r_max, 0.0, nbins, dc, counts);
     } catch (const HipError& e) {
         return hip_fail(s, e);
     }

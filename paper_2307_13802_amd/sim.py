@@ -96,6 +96,7 @@ def lib():
         "sim_reset_displacement": [vp],
         "sim_rdf": [vp, C.c_int32, C.c_double, C.c_int32, C.POINTER(C.c_uint64)],
         "sim_rdf_xy": [vp, C.c_int32, C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_uint64)],
+        "sim_rdf_noalloc": [vp, C.c_int32, C.c_double, C.c_int32, C.POINTER(C.c_uint64)],
         "sim_stress_acf_stream": [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int64],
         "sim_stress_acf": [vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int64, dp],
         "sim_get_state": [vp, C.c_int32, dp, dp, dp, dp, dp, dp, C.POINTER(C.c_uint64)],
@@ -331,6 +332,13 @@ class Sim:
         out = np.zeros(nbins, np.uint64)
         _check(lib().sim_rdf(self.h, replica, float(r_max), int(nbins), out.ctypes.data_as(C.POINTER(C.c_uint64))),
                self.h)
+        return out
+
+    def rdf_noalloc(self, r_max, nbins, replica=0):
+        """sim_rdf with its bins in the library's static device array (no device allocation)."""
+        out = np.zeros(nbins, np.uint64)
+        _check(lib().sim_rdf_noalloc(self.h, replica, float(r_max), int(nbins),
+                                     out.ctypes.data_as(C.POINTER(C.c_uint64))), self.h)
         return out
 
     def rdf_xy(self, r_max, slab, nbins, replica=0):
