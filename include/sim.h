@@ -150,7 +150,10 @@ typedef struct sim_config {
     uint64_t step0;         /* step counter of the initial state                     */
     int32_t  precision;     /* SIM_FP64 or SIM_MIXED, identical for all replicas     */
     uint32_t flags;         /* SIM_* flags, identical for all replicas               */
-    uint32_t nlist_cap;     /* neighbour list capacity per particle; 0 selects 48    */
+    uint32_t nlist_cap;     /* initial neighbour list capacity per particle (0
+                               selects 48); a build that finds more partners within
+                               the list range regrows the lists to hold them, up to
+                               64 (beyond: SIM_ECAPACITY)                            */
     uint32_t lanes;         /* lanes sharing one particle's list in the pair kernel
                                (1, 2 or 4: 64, 32 or 16 particles per wave); 0 =
                                chosen by timing at creation                          */
@@ -185,8 +188,12 @@ typedef struct sim_stats_t {
                                        cache (sim_set_tune_cache)                        */
     double  skin;                   /* Verlet skin of the replica (length)               */
     double  cell_factor;            /* search cells >= cell_factor x the list range      */
+    double  kT_translational;       /* sum m |v - U^inf(x)|^2 / (3 n): the temperature of
+                                       the peculiar translational motion (full-step v)   */
+    double  kT_rotational;          /* sum I |w - Omega^inf|^2 / (3 n), rotational       */
     int32_t cells_x, cells_y, cells_z; /* search cells per box side                     */
-    int32_t reserved;               /* 0                                                 */
+    int32_t list_cap;               /* entries per particle the lists hold now: nlist_cap,
+                                       grown when a build finds more partners (to 64)   */
 } sim_stats_t;
 
 /* Checks a configuration and its radii on the host (no GPU needed).
@@ -351,7 +358,8 @@ int sim_nlist(sim* s, int32_t replica, uint32_t* ij_2m, int64_t cap, int64_t* co
 int sim_contacts(sim* s, int32_t replica, uint32_t* ij_2m, double* s_3m, int32_t* sliding,
                  int64_t cap, int64_t* count);
 
-/* Statistics of one replica at the last evaluation. */
+/* Statistics of one replica at the last evaluation (the kinetic temperatures
+ * measure the equipartition of Sec. II.C: each tends to kT at rest). */
 int sim_stats(sim* s, int32_t replica, sim_stats_t* out);
 
 /* Kernel timing: when enabled, sim_step launches directly (no graph), in the

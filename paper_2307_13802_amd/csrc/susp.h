@@ -74,7 +74,8 @@ struct SysDyn {
     uint32_t halted;          // 1: some list may have expired; the remaining launches of the chunk do nothing
     uint32_t expire[2];       // 1: the integrate of the step with that parity found a particle whose
                               // displacement bound fails the list-validity test
-    uint32_t pad;
+    uint32_t list_need;       // largest neighbour count of a particle whose list overflowed at the
+                              // last build (0: none overflowed); the host regrows the lists
     uint64_t rebuilds;
 };
 
@@ -192,12 +193,18 @@ void launch_pair_force(const Bufs& b, hipStream_t st, int q, int kick, int advan
                        const hipEvent_t* kev = nullptr, int fuse = 0);
 // reduces pending stress partials of parity q
 void launch_finalize(const Bufs& b, hipStream_t st, int q);
+// The neighbour lists and mirror index again from the cells and the carried
+// contact history of the last rebuild (after the lists were regrown); q, in_step as
+// for launch_rebuild.
+void launch_relist(const Bufs& b, hipStream_t st, int q, int in_step);
 // Rebuild of cells and neighbour lists from the current positions; q is the
 // parity of the next force evaluation.  in_step: called between kick 1 and the
 // force evaluation of a step.  ct_input_rep: 0xFFFFFFFF = carry contact
 // history from the current lists; 0xFFFFFFFE = every replica takes the
 // host-written compact table; else that replica does.
 void launch_rebuild(const Bufs& b, hipStream_t st, int q, int in_step, uint32_t ct_input_rep);
+// kinetic sums of one replica (m |v - U^inf|^2 and I |w - Omega^inf|^2): nblk = n_pad / 256 blocks, 2 doubles each
+void launch_kinetic(const Bufs& b, hipStream_t st, uint32_t rep, uint32_t nblk, double* part);
 // mean-square displacement sums of one replica: nblk = n_pad / 256 blocks, 3 doubles each
 void launch_msd(const Bufs& b, hipStream_t st, uint32_t rep, uint32_t nblk, double* part);
 // pair histograms of one replica at parity p from a cell pass reaching `reach`:

@@ -688,8 +688,8 @@ __global__ __launch_bounds__(256) void k_rb_nlist(Bufs b, int q, int in_step) {
             }
         }
     }
-    if (cnt > cap) {
-        atomicOr(&b.dyn[r].health, H_NLIST);
+    if (cnt > cap) {  // rare: the host regrows the lists to the largest count and builds them again
+        atomicMax(&b.sys->list_need, cnt);
         cnt = cap;
     }
     // insertion sort of the entries by partner id
@@ -757,8 +757,8 @@ __global__ __launch_bounds__(256) void k_rb_mirror(Bufs b) {
                 m = k;
                 break;
             }
-        if (m == 0xFFu) {
-            atomicOr(&b.dyn[r].health, H_NLIST);
+        if (m == 0xFFu) {   // asymmetric lists: only truncated ones (then they are built again)
+            if (b.sys->list_need == 0u) atomicOr(&b.dyn[r].health, H_NLIST);
             m = 0;
         }
         b.mir[e * npad + i] = (uint8_t)m;
@@ -776,6 +776,11 @@ __global__ void k_rb_reset(Bufs b, int q) {
         b.sys->expire[1] = 0u;
         b.sys->rebuilds += 1;
     }
+}
+
+// clears the overflow record before a list build
+__global__ void k_rb_need0(Bufs b) {
+    if (threadIdx.x == 0) b.sys->list_need = 0u;
 }
 
 template <class R> struct Acc;
@@ -1322,12 +1327,20 @@ __global__ __launch_bounds__(256, (MIX || OCC) ? 3 : 2) void k_half(Bufs b, int 
         return true;
     };
 
-    // ---- cull: interacting entries with a higher-id partner (LN lanes per particle)
+    // ---- cull: interacting entries with a higher-id partner (LN lanes per particle).
+    // Without OCC the partner index of the particle's first kJC higher-id entries stays
+    // in LDS, so that the evaluation of those pairs needs no second read of the list
+    // (with OCC the LDS goes to the queue instead: the cache measured slower there).
+    constexpr uint32_t kJC = OCC ? 0u : 8u;
+    __shared__ uint32_t jcache[4][NP][kJC > 0 ? kJC : 1];
+    __shared__ uint8_t elo_s[4][NP];
+    if (kJC > 0 && sub == 0) elo_s[w][l] = (uint8_t)e_lo;
     uint64_t im = 0ull;
     if constexpr (G0 > 0) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint32_t e = e_lo + sub + u * LN;
+            if (kJC > 0 && e < cnt && e - e_lo < kJC) jcache[w][l][e - e_lo] = jj0[u];
             if (e < cnt && interacting(P, s_le, pi, pj0[u])) im |= 1ull << e;
         }
     }
@@ -1344,6 +1357,7 @@ __global__ __launch_bounds__(256, (MIX || OCC) ? 3 : 2) void k_half(Bufs b, int 
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint32_t e = c0 + u * LN;
+            if (kJC > 0 && e < cnt && e - e_lo < kJC) jcache[w][l][e - e_lo] = jj[u];
             if (e < cnt && interacting(P, s_le, pi, pj[u])) im |= 1ull << e;
         }
     }
@@ -1414,7 +1428,12 @@ __global__ __launch_bounds__(256, (MIX || OCC) ? 3 : 2) void k_half(Bufs b, int 
         R vi[3], wi[3];
         load_vw<MIX>(b, ii, vi, wi);
         PairIn<R> in;
-        in.j = b.nbr[e * npad + ii];
+        if constexpr (kJC > 0) {
+            const uint32_t ec = e - elo_s[w][l];   // entries past the cache are read from the list again
+            in.j = ec < kJC ? jcache[w][l][ec] : b.nbr[e * npad + ii];
+        } else {
+            in.j = b.nbr[e * npad + ii];
+        }
         in.pj = b.pos[in.j];
         in.idj = b.id[in.j];
         load_vw<MIX>(b, in.j, in.vj, in.wj);
@@ -1690,6 +1709,39 @@ __global__ __launch_bounds__(256) void k_msd(Bufs b, uint32_t rep, double* part)
     }
 }
 
+// Kinetic temperatures of one replica from its full-step velocities: per block the
+// fixed-order sums of m |v - U^inf(x)|^2 and I |w - Omega^inf|^2 (peculiar
+// translational and rotational motion; m = 4/3 pi rho a^3, I = 2/5 m a^2).
+__global__ __launch_bounds__(256) void k_kinetic(Bufs b, uint32_t rep, double* part) {
+    const RepParams& P = b.reps[rep];
+    const uint32_t i = P.p_begin + blockIdx.x * 256 + threadIdx.x;
+    double acc[2] = {0.0, 0.0};
+    if (i - P.p_begin < P.n) {
+        const double4 x = b.pos[i], v = b.vf[i], w = b.wf[i];
+        const double m = (4.0 / 3.0) * kPi * P.rho * x.w * x.w * x.w;
+        const double I = 0.4 * m * x.w * x.w;
+        const double ux = v.x - P.gd * (x.y - 0.5 * P.L[1]), wz = w.z + 0.5 * P.gd;
+        acc[0] = m * ((ux * ux + v.y * v.y) + v.z * v.z);
+        acc[1] = I * ((w.x * w.x + w.y * w.y) + wz * wz);
+    }
+    __shared__ double rows[16][2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const double v = row_sum_f64(acc[c]);
+        if ((threadIdx.x & 15) == 15) rows[threadIdx.x >> 4][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double t = 0.0;
+        for (int k = 0; k < 16; ++k) t += rows[k][threadIdx.x];
+        part[blockIdx.x * 2 + threadIdx.x] = t;
+    }
+}
+
+void launch_kinetic(const Bufs& b, hipStream_t st, uint32_t rep, uint32_t nblk, double* part) {
+    hipLaunchKernelGGL(k_kinetic, dim3(nblk), dim3(256), 0, st, b, rep, part);
+}
+
 void launch_msd(const Bufs& b, hipStream_t st, uint32_t rep, uint32_t nblk, double* part) {
     hipLaunchKernelGGL(k_msd, dim3(nblk), dim3(256), 0, st, b, rep, part);
 }
@@ -1951,9 +2003,17 @@ void launch_rebuild(const Bufs& b, hipStream_t st, int q, int in_step, uint32_t 
     hipLaunchKernelGGL(k_rb_cellsort, dim3(nblocks(b.nkeys_total, 256)), dim3(256), 0, st, b);
     hipLaunchKernelGGL(k_rb_gather, dim3(np), dim3(256), 0, st, b, ct_input_rep);
     hipLaunchKernelGGL(k_rb_copyback, dim3(np), dim3(256), 0, st, b);
+    hipLaunchKernelGGL(k_rb_need0, dim3(1), dim3(64), 0, st, b);
     hipLaunchKernelGGL(k_rb_nlist, dim3(np), dim3(256), 0, st, b, q, in_step);
     hipLaunchKernelGGL(k_rb_mirror, dim3(np), dim3(256), 0, st, b);
     hipLaunchKernelGGL(k_rb_reset, dim3(1), dim3(256), 0, st, b, q);
+}
+
+void launch_relist(const Bufs& b, hipStream_t st, int q, int in_step) {
+    const uint32_t np = b.npad / 256;
+    hipLaunchKernelGGL(k_rb_need0, dim3(1), dim3(64), 0, st, b);
+    hipLaunchKernelGGL(k_rb_nlist, dim3(np), dim3(256), 0, st, b, q, in_step);
+    hipLaunchKernelGGL(k_rb_mirror, dim3(np), dim3(256), 0, st, b);
 }
 
 // One launch, or with ev (start, stop) a launch whose events are recorded by the

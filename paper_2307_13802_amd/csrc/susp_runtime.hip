@@ -26,6 +26,7 @@ void (*g_free)(void*, void*) = nullptr;
 void* g_alloc_ctx = nullptr;
 
 constexpr uint32_t kDefaultCap = 48;
+constexpr uint32_t kMaxCap = 64;     // list entries per particle: the width of the entry bit masks
 // Verlet skin of a replica: the configured one, or (skin <= 0) skin_frac times the
 // smallest radius (0.2 by default; the tuner chooses among kSkinFracs for skin < 0)
 constexpr double kSkinDefault = 0.2;
@@ -110,6 +111,10 @@ struct sim {
     uint32_t struct_cap = 0;
     uint32_t keys_cap = 0;       // cell keys allocated (the finest layout a parameter set can ask for)
     std::vector<RepDyn> dyn_host;  // host copy of the per-replica records read by the health check
+    int short_q = -1;            // >= 0: the last build found lists too short; regrow and build them
+                                 // again (parity q) before they are used
+    uint32_t short_need = 0;     // the largest partner count it found
+    std::string list_fail;       // a list that cannot grow enough (reported by the health check)
     Tune tune;                   // parameter set in use
 
     void* dalloc(size_t bytes) {
@@ -277,6 +282,63 @@ void drop_graphs(sim* s) {
                     }
 }
 
+// Regrows the per-entry arrays of the lists (partners, springs, mirror index, pair
+// records) to hold `need` entries per particle, and builds the lists again from the
+// cells and the carried contact history of the build just done (which stay valid
+// until the next build).  Beyond kMaxCap entries (or 2^32 list slots) the lists
+// cannot grow: the failure is left for the health check to report.
+void regrow_lists(sim* s, int q, int in_step, uint32_t need) {
+    Bufs& b = s->b;
+    const size_t np = b.npad;
+    const uint32_t cap = std::min(kMaxCap, (need + 7u) & ~7u);
+    if (need > kMaxCap || (uint64_t)np * cap >= (1ull << 32)) {
+        s->list_fail = fmt("a particle has %u partners within the list range; the lists hold at most %u", need,
+                           need > kMaxCap ? kMaxCap : b.cap);
+        return;
+    }
+    const size_t rs = s->mixed ? sizeof(float) : sizeof(double);
+    const size_t recs = s->mixed ? 4 * sizeof(float) : 3 * sizeof(double);
+    for (void* p : {(void*)b.nbr, b.hs, (void*)b.mir, b.pf, b.pt, b.pt2}) s->release(p);
+    b.nbr = s->alloc<uint32_t>(np * cap);
+    b.hs = s->dalloc(np * cap * 3 * rs);
+    b.mir = s->alloc<uint8_t>(np * cap);
+    b.pf = s->dalloc(np * cap * recs);
+    b.pt = s->dalloc(np * cap * recs);
+    b.pt2 = s->dalloc(np * cap * recs);
+    b.cap = cap;
+    drop_graphs(s);   // captured launches hold the buffer table by value
+    launch_relist(b, s->st, q, in_step);
+    HIPCHK(hipGetLastError());
+}
+
+// A list build of parity q (launch_rebuild), then the regrow when it found a particle
+// with more partners than the lists hold.  grow false (a caller that cannot allocate):
+// the regrow waits for the next call that uses the lists (ensure_lists).  in_step
+// builds (those between kick 1 and the forces of a step) are always regrown at once.
+void rebuild(sim* s, int q, int in_step, uint32_t ct_input_rep, bool grow = true) {
+    launch_rebuild(s->b, s->st, q, in_step, ct_input_rep);
+    uint32_t need = 0;
+    HIPCHK(hipMemcpyAsync(&need, (char*)s->b.sys + offsetof(SysDyn, list_need), sizeof need,
+                          hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+    s->short_q = -1;
+    if (need == 0) return;
+    if (!grow && !in_step) {
+        s->short_q = q;
+        s->short_need = need;
+        return;
+    }
+    regrow_lists(s, q, in_step, need);
+}
+
+// Regrows lists that a build without allocation left short (before they are used).
+void ensure_lists(sim* s) {
+    if (s->short_q < 0) return;
+    const int q = s->short_q;
+    s->short_q = -1;
+    regrow_lists(s, q, 0, s->short_need);
+}
+
 // nsteps time steps, the first with parity q0, without a list rebuild; every
 // launch does nothing once the expiry test of an earlier one has halted the
 // chunk.  With the half-pair variant the gather of each step but the last
@@ -312,10 +374,15 @@ int check_health(sim* s) {
     HIPCHK(hipStreamSynchronize(s->st));
     int code = SIM_OK;
     std::string msg;
+    if (!s->list_fail.empty()) {
+        code = SIM_ECAPACITY;
+        msg = s->list_fail;
+        s->list_fail.clear();
+    }
     for (int r = 0; r < s->nrep; ++r) {
         const uint32_t h = dyn[r].health;
         if (!h) continue;
-        if (h & H_NLIST) {
+        if ((h & H_NLIST) && code != SIM_ECAPACITY) {
             code = SIM_ECAPACITY;
             msg = fmt("replica %d: neighbour list or contact capacity exceeded at step %llu", r,
                       (unsigned long long)std::max(dyn[r].step_slot[0], dyn[r].step_slot[1]));
@@ -582,10 +649,10 @@ double trial(sim* s, const Tune& t, hipEvent_t* e) {
     constexpr int kTrial = 4;
     apply_tune(s, t);
     const int q = 1 - s->par;
-    launch_rebuild(s->b, s->st, q, 0, 0xFFFFFFFFu);
+    rebuild(s, q, 0, 0xFFFFFFFFu);
     enqueue_steps(s, s->st, 2, q);
     HIPCHK(hipEventRecord(e[0], s->st));
-    launch_rebuild(s->b, s->st, q, 0, 0xFFFFFFFFu);
+    rebuild(s, q, 0, 0xFFFFFFFFu);
     HIPCHK(hipEventRecord(e[1], s->st));
     enqueue_steps(s, s->st, kTrial, q);
     HIPCHK(hipEventRecord(e[2], s->st));
@@ -862,7 +929,7 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
             HIPCHK(hipMemsetAsync(b.sys, 0, sizeof(SysDyn), s->st));
             HIPCHK(hipMemsetAsync(b.dacc, 0, sizeof(double) * b.npad, s->st));
             s->step_now = cfgs[0].step0;
-            launch_rebuild(b, s->st, 1 - s->par, 0, 0xFFFFFFFEu);
+            rebuild(s, 1 - s->par, 0, 0xFFFFFFFEu);
         };
         {
             Tune t0;
@@ -996,6 +1063,7 @@ int sim_step(sim* s, int64_t nsteps) {
     if (!s) return fail(nullptr, SIM_EINVAL, "null handle");
     if (nsteps < 0) return fail(s, SIM_EINVAL, "nsteps < 0");
     try {
+        ensure_lists(s);
         int64_t left = nsteps;
         std::vector<RepDyn> dyn(s->nrep);
         const bool every = (s->flags & SIM_REBUILD_EACH_STEP) != 0;
@@ -1003,7 +1071,7 @@ int sim_step(sim* s, int64_t nsteps) {
             int64_t budget = every ? 0 : s->plan - s->since_build;
             if (budget < 1) {
                 // displacement budget used up: rebuild between steps, from the current positions
-                launch_rebuild(s->b, s->st, 1 - s->par, 0, 0xFFFFFFFFu);
+                rebuild(s, 1 - s->par, 0, 0xFFFFFFFFu);
                 s->since_build = 0;
                 s->plan = s->plan_hint;
                 budget = every ? 1 : s->plan;
@@ -1025,7 +1093,7 @@ int sim_step(sim* s, int64_t nsteps) {
                 // rebuild from the moved positions and evaluate that step
                 const int64_t grown = plan_steps(s, dyn);
                 const int q = 1 - s->par;
-                launch_rebuild(s->b, s->st, q, 1, 0xFFFFFFFFu);
+                rebuild(s, q, 1, 0xFFFFFFFFu);
                 launch_pair_force(s->b, s->st, q, 1, 1, 0xFFFFFFFFu);
                 HIPCHK(hipGetLastError());
                 HIPCHK(hipStreamSynchronize(s->st));
@@ -1254,12 +1322,13 @@ int sim_msd(sim* s, int32_t r, double out[3]) {
 namespace {
 // Pair histogram of replica r into the device array dc (nwords 64-bit counts, zeroed here
 // by a kernel), copied to counts: mode 0 = g(r) bins, mode 1 = the flow-gradient slice.
+// grow false: allocates nothing (lists that the build finds short are regrown later).
 int rdf_into(sim* s, int32_t r, int mode, double r_max, double slab, int32_t nbins, unsigned long long* dc,
-             uint64_t* counts) {
+             uint64_t* counts, bool grow = true) {
     const RepParams& P = s->P[r];
     const uint32_t nwords = mode == 0 ? (uint32_t)nbins : (uint32_t)nbins * (uint32_t)nbins;
     const double reach = mode == 0 ? r_max : std::sqrt(2.0 * r_max * r_max + 0.25 * slab * slab);
-    launch_rebuild(s->b, s->st, 1 - s->par, 0, 0xFFFFFFFFu);   // current cells (changes no trajectory)
+    rebuild(s, 1 - s->par, 0, 0xFFFFFFFFu, grow);   // current cells (changes no trajectory)
     s->since_build = 0;
     s->plan = s->plan_hint;
     launch_zero64(s->st, dc, nwords);
@@ -1299,7 +1368,7 @@ int sim_rdf_noalloc(sim* s, int32_t r, double r_max, int32_t nbins, uint64_t* co
     unsigned long long* dc = scratch_ptr(err);
     if (!dc) return fail(s, SIM_EDEVICE, err);
     try {
-        return rdf_into(s, r, 0, r_max, 0.0, nbins, dc, counts);
+        return rdf_into(s, r, 0, r_max, 0.0, nbins, dc, counts, false);
     } catch (const HipError& e) {
         return hip_fail(s, e);
     }
@@ -1394,7 +1463,7 @@ int sim_structural_stress(sim* s, int32_t r, double out[9]) {
     if (P.skin + amin * (2.0 * (P.c_int - 1.0)) < 0.05 * amax)
         return fail(s, SIM_EINVAL, "the neighbour list range does not cover the 0.05 a shell");
     try {
-        launch_rebuild(s->b, s->st, 1 - s->par, 0, 0xFFFFFFFFu);
+        rebuild(s, 1 - s->par, 0, 0xFFFFFFFFu);
         s->since_build = 0;
         s->plan = s->plan_hint;
         const uint32_t nblk = P.n_pad / 256;
@@ -1445,7 +1514,7 @@ int sim_set_state(sim* s, int32_t r, const double* x, const double* v, const dou
         upload_state(s, r, x, v, w, F, T, c_ij, c_s, n_contacts);
         set_dyn(s, r, le_offset, step);
         if (r == 0) s->step_now = step;
-        launch_rebuild(s->b, s->st, 1 - s->par, 0, (uint32_t)r);
+        rebuild(s, 1 - s->par, 0, (uint32_t)r);
         s->since_build = 0;
         if (!F) {
             launch_pair_force(s->b, s->st, s->par, 0, 0, (uint32_t)r);
@@ -1467,6 +1536,7 @@ namespace {
 int diag_pairs(sim* s, int32_t r, int mode, std::vector<uint32_t>& ij, std::vector<double>& sv,
                std::vector<int32_t>& sl) {
     const RepParams& P = s->P[r];
+    ensure_lists(s);
     uint32_t* dcount = nullptr;
     HIPCHK(hipMalloc(&dcount, sizeof(uint32_t)));
     HIPCHK(hipMemsetAsync(dcount, 0, sizeof(uint32_t), s->st));
@@ -1576,10 +1646,25 @@ int sim_stats(sim* s, int32_t r, sim_stats_t* out) {
         out->tune_source = s->tune.source;
         out->skin = s->P[r].skin;
         out->cell_factor = s->cfg[r].cell_factor > 0.0 ? s->cfg[r].cell_factor : s->tune.cell;
+        {   // kinetic temperatures of the peculiar motion (fixed-order sums on the device)
+            const uint32_t nblk = s->P[r].n_pad / 256;
+            if (s->struct_cap < nblk) {
+                s->struct_part = s->alloc<double>((size_t)nblk * 9);
+                s->struct_cap = nblk;
+            }
+            launch_kinetic(s->b, s->st, (uint32_t)r, nblk, s->struct_part);
+            HIPCHK(hipGetLastError());
+            auto h = d2h(s, s->struct_part, 0, (size_t)nblk * 2);
+            double ke[2] = {0.0, 0.0};
+            for (uint32_t k = 0; k < nblk; ++k)
+                for (int c = 0; c < 2; ++c) ke[c] += h[(size_t)k * 2 + c];
+            out->kT_translational = ke[0] / (3.0 * n);
+            out->kT_rotational = ke[1] / (3.0 * n);
+        }
         out->cells_x = s->P[r].nc[0];
         out->cells_y = s->P[r].nc[1];
         out->cells_z = s->P[r].nc[2];
-        out->reserved = 0;
+        out->list_cap = (int32_t)s->b.cap;
         return SIM_OK;
     } catch (const HipError& e) {
         return hip_fail(s, e);

@@ -54,8 +54,9 @@ class _Stats(C.Structure):
                 ("interacting_per_particle", C.c_double), ("contacts", C.c_int64), ("rebuilds", C.c_int64),
                 ("steps", C.c_int64), ("step", C.c_uint64), ("le_offset", C.c_double), ("lanes", C.c_int32),
                 ("pair_kernel", C.c_int32), ("occupancy_form", C.c_int32), ("tune_source", C.c_int32),
-                ("skin", C.c_double), ("cell_factor", C.c_double), ("cells_x", C.c_int32), ("cells_y", C.c_int32),
-                ("cells_z", C.c_int32), ("reserved", C.c_int32)]
+                ("skin", C.c_double), ("cell_factor", C.c_double), ("kT_translational", C.c_double),
+                ("kT_rotational", C.c_double), ("cells_x", C.c_int32), ("cells_y", C.c_int32),
+                ("cells_z", C.c_int32), ("list_cap", C.c_int32)]
 
 
 class SimError(RuntimeError):

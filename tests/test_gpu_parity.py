@@ -122,6 +122,33 @@ def test_injected_contacts_and_offset(P):
         _compare_eval(P, sim, orc, TOL_F64)
 
 
+def test_verlet_lists_every_layout_match_brute_force(P):
+    """The list build against the oracle's O(N^2) search, bit-exact, over cell sizes, skins,
+    Lees-Edwards offsets and boxes with 3 cells or 1 cell (every x cell searched) along a side."""
+    n = 200
+    a = gen.radii_bidisperse(n, 4)
+    prm = dict(rho=0.1, eta=0.1, kn=1e4, kt=2e4 / 7, mu=0.5, kT=0.5, gammadot=0.4, dt=1e-4, xi_cut=0.05,
+               xi_min=1e-3, seed=99)
+    for L in ((14.0, 13.0, 15.0), (20.0, 9.5, 20.0), (7.2, 20.0, 18.0)):
+        x, v, w = gen.random_state(n, L, a, seed=5, kT=0.5, gammadot=0.4)
+        for skin in (0.1, 0.6):
+            for cf in (1.0, 1.5, 2.0, 3.0):
+                sim = P.Sim(P.Config(box=L, **prm, max_overlap=10.0, skin=skin, cell_factor=cf, lanes=1), a, x, v, w)
+                stt = sim.stats()
+                for s_le in (0.0, L[0] / 3.0, L[0] - 1e-9):
+                    sim.set_state(0, x, v, w, s_le=s_le, step=0)
+                    orc = O.Oracle(O.Params(L=L, **prm), a, x, v, w, s_le=s_le)
+                    ref = orc.verlet_pairs(skin)
+                    got = sim.nlist()
+                    ok = np.array_equal(got, ref)
+                    if not ok or s_le == 0.0:
+                        _say(f"case: box {L} skin {skin} cell factor {cf} cells "
+                             f"{stt['cells_x']}x{stt['cells_y']}x{stt['cells_z']} s_le {s_le:.4f}: "
+                             f"{len(got)} / {len(ref)} pairs")
+                    assert ok
+                sim.close()
+
+
 def _cut_boundary(x0, a1, a2, xi_cut):
     """The largest x with (x0 - x)^2 <= ((a1 + a2)(1 + xi_cut / 2))^2 in FP64, the range test's own arithmetic
     (Sec. II.B, cut-off inclusive), and the next double above it: the last position in range and the first out."""
@@ -444,10 +471,10 @@ def test_health_errors(P):
     with pytest.raises(P.SimError) as e:
         P.Sim(_cfg(P, st), st["radii"], x, st["v"], st["w"])
     assert e.value.code == -4
-    _say("case: list capacity 2 rejected")
+    _say("case: more than 64 partners within the list range (skin 5) rejected")
     with pytest.raises(P.SimError) as e:
-        P.Sim(_cfg(P, st, nlist_cap=2), st["radii"], st["x"], st["v"], st["w"])
-    assert e.value.code == -5
+        P.Sim(_cfg(P, st, skin=5.0), st["radii"], st["x"], st["v"], st["w"])
+    assert e.value.code == -5 and "at most 64" in str(e.value)
     # inputs the host rejects before anything reaches the GPU
     bad = [("NaN coordinate", "x", (3, 1), np.nan), ("coordinate equal to L", "x", (4, 2), st["L"][2]),
            ("infinite velocity", "v", (5, 0), np.inf), ("NaN angular velocity", "w", (6, 1), np.nan)]
@@ -836,3 +863,57 @@ def test_torch_allocator(P):
         P.use_default_allocator()
     for key in ("x", "v", "w", "F", "T"):
         assert np.array_equal(runs[0][key], runs[1][key]), key
+
+
+def test_lists_regrow_to_partner_count(P):
+    """A list capacity of 2 entries, far below the partner count: every build that finds
+    more partners regrows the lists and builds them again, so the run is the run with
+    room for 64 (same lists, same trajectory bit for bit), with a list build at every step."""
+    st = _state(n=300, phi=0.5)
+    _say("case: nlist_cap 2 vs 64, skin 3, 200 steps, a build per step")
+    fl = P.REBUILD_EACH_STEP
+    small = P.Sim(_cfg(P, st, flags=fl, nlist_cap=2, skin=3.0, lanes=1), st["radii"], st["x"], st["v"], st["w"])
+    big = P.Sim(_cfg(P, st, flags=fl, nlist_cap=64, skin=3.0, lanes=1), st["radii"], st["x"], st["v"], st["w"])
+    ls, lb = small.nlist(), big.nlist()
+    cnt = np.bincount(ls.reshape(-1), minlength=300)
+    _say(f"  list capacity {small.stats()['list_cap']} for at most {cnt.max()} partners")
+    assert np.array_equal(ls, lb)
+    assert cnt.max() <= small.stats()["list_cap"] <= 64 and small.stats()["list_cap"] > 2
+    assert big.stats()["list_cap"] == 64
+    small.step(200)
+    big.step(200)
+    a, b = small.get_state(), big.get_state()
+    for key in ("x", "v", "w", "F", "T"):
+        assert np.array_equal(a[key], b[key]), key
+    assert np.array_equal(small.nlist(), big.nlist())
+    assert small.stats()["rebuilds"] == big.stats()["rebuilds"] >= 200
+    small.close()
+    big.close()
+
+
+def test_kinetic_temperatures(P):
+    """sim_stats' kinetic temperatures against the host's sums over the full-step
+    velocities: sum m |v - U^inf(x)|^2 / 3n and sum I |w - Omega^inf|^2 / 3n with
+    U^inf = gammadot (y - L_y/2) e_x and Omega^inf = -gammadot/2 e_z; after some steps of a
+    Brownian run both are of order kT."""
+    st = _state(n=500, phi=0.4, pe=1.0, kT=1.0)
+    p = st["params"]
+    for prec in (P.FP64, P.MIXED):
+        sim = P.Sim(_cfg(P, st, precision=prec), st["radii"], st["x"], st["v"], st["w"])
+        sim.step(400)
+        g, stt = sim.get_state(), sim.stats()
+        a = st["radii"]
+        m = 4.0 / 3.0 * np.pi * p["rho"] * a ** 3
+        inertia = 0.4 * m * a ** 2
+        u = g["v"].copy()
+        u[:, 0] -= p["gammadot"] * (g["x"][:, 1] - 0.5 * st["L"][1])
+        om = g["w"].copy()
+        om[:, 2] += 0.5 * p["gammadot"]
+        kt = float((m * (u * u).sum(axis=1)).sum() / (3 * len(a)))
+        kr = float((inertia * (om * om).sum(axis=1)).sum() / (3 * len(a)))
+        _say(f"case: kinetic temperatures precision {prec}: translational {stt['kT_translational']:.6g} "
+             f"(host {kt:.6g}) rotational {stt['kT_rotational']:.6g} (host {kr:.6g})")
+        assert abs(stt["kT_translational"] - kt) <= 1e-12 * kt
+        assert abs(stt["kT_rotational"] - kr) <= 1e-12 * kr
+        assert 0.6 < kt < 1.6 and 0.6 < kr < 1.6
+        sim.close()
