@@ -493,8 +493,27 @@ def test_health_errors(P):
         with pytest.raises(P.SimError) as e:
             sim.set_state(0, st["x"], st["v"], st["w"], F=F, T=T)
         assert e.value.code == -1  # SIM_EINVAL
-    sim.step(2)  # the handle is unchanged and still steps
-    assert np.isfinite(sim.get_state()["x"]).all()
+    # contact tables the host rejects (partner id out of range, higher id first, more than 16 contacts
+    # on one particle): nothing is uploaded, so the handle steps exactly as an untouched one
+    n = len(st["radii"])
+    moved = {k: st[k] + 0.0 for k in ("v", "w")}
+    moved["v"][:, 0] += 0.25
+    for what, cij in (("partner id out of range", np.array([[0, n]], np.uint32)),
+                      ("higher id first", np.array([[5, 2]], np.uint32)),
+                      ("17 contacts on one particle", np.array([[0, j] for j in range(1, 18)], np.uint32))):
+        _say(f"case: contact table with {what} rejected by set_state")
+        with pytest.raises(P.SimError) as e:
+            sim.set_state(0, st["x"] * 0.5, moved["v"], moved["w"], contacts=(cij, np.zeros((len(cij), 3))))
+        assert e.value.code == -1  # SIM_EINVAL
+    ref = P.Sim(_cfg(P, st), st["radii"], st["x"], st["v"], st["w"])
+    sim.step(20)
+    ref.step(20)
+    a, b = sim.get_state(), ref.get_state()
+    for key in ("x", "v", "w", "F", "T"):
+        assert np.array_equal(a[key], b[key]), key
+    assert np.array_equal(sim.stress_series(), ref.stress_series())
+    sim.close()
+    ref.close()
 
 
 def test_large_sampled_fp64(P):
