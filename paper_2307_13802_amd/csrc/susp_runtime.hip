@@ -685,9 +685,28 @@ double trial(sim* s, const Tune& t, hipEvent_t* e) {
     return std::min(m1, m2) / kTrial + mr / steps_per_build;
 }
 
+// Time of one list build under t, the fastest of three from the same positions: the cell
+// factor changes nothing but the build (and the analysis passes), so it is chosen by this.
+double build_time(sim* s, const Tune& t, hipEvent_t* e) {
+    apply_tune(s, t);
+    const int q = 1 - s->par;
+    rebuild(s, q, 0, 0xFFFFFFFFu);   // regrows the lists if these cells find more partners
+    float best = 1e30f;
+    for (int k = 0; k < 3; ++k) {
+        HIPCHK(hipEventRecord(e[0], s->st));
+        launch_rebuild(s->b, s->st, q, 0, 0xFFFFFFFFu);   // the same positions: the same lists
+        HIPCHK(hipEventRecord(e[1], s->st));
+        HIPCHK(hipEventSynchronize(e[1]));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e[0], e[1]));
+        best = std::min(best, ms);
+    }
+    return best;
+}
+
 // Chooses the parameter set: what the configuration fixes is kept; the rest is read
-// from the cache or measured, one parameter at a time (lanes and kernel form, then
-// the skin, then the cell factor), each by trial() on the actual system.
+// from the cache or measured on the actual system, one parameter at a time: lanes and
+// kernel form, then the skin, by trial(); then the cell factor, by build_time().
 void tune(sim* s) {
     const sim_config& c0 = s->cfg[0];
     const bool occ_ok = !s->mixed && !s->b.ext && !(s->flags & SIM_HALF_OCC_OFF);
@@ -742,9 +761,18 @@ void tune(sim* s) {
     cand.clear();
     for (double sf : skins) { Tune t = best; t.skin_frac = sf; cand.push_back(t); }
     if (cand.size() > 1) scan(cand);
-    cand.clear();
-    for (double cf : cells) { Tune t = best; t.cell = cf; cand.push_back(t); }
-    if (cand.size() > 1) scan(cand);
+    if (cells.size() > 1) {
+        double bt = 1e31;
+        Tune pick = best;
+        for (double cf : cells) {
+            Tune t = best;
+            t.cell = cf;
+            if (!tune_fits(s, t)) continue;
+            const double ms = build_time(s, t, ev);
+            if (ms < bt) { bt = ms; pick = t; }
+        }
+        best = pick;
+    }
     for (auto& e : ev) (void)hipEventDestroy(e);
     best.source = 1;
     apply_tune(s, best);
