@@ -1565,19 +1565,28 @@ int diag_pairs(sim* s, int32_t r, int mode, std::vector<uint32_t>& ij, std::vect
                std::vector<int32_t>& sl) {
     const RepParams& P = s->P[r];
     ensure_lists(s);
-    uint32_t* dcount = nullptr;
-    HIPCHK(hipMalloc(&dcount, sizeof(uint32_t)));
-    HIPCHK(hipMemsetAsync(dcount, 0, sizeof(uint32_t), s->st));
+    // device buffers through the handle's allocator (the hook, when one is set), freed on every path
+    std::vector<void*> held;
+    struct Release {
+        sim* s;
+        std::vector<void*>& p;
+        ~Release() {
+            for (void* q : p) s->release(q);
+        }
+    } rel{s, held};
+    auto get = [&](size_t bytes) {
+        void* q = s->dalloc(bytes);   // zeroed
+        held.push_back(q);
+        return q;
+    };
+    uint32_t* dcount = (uint32_t*)get(sizeof(uint32_t));
     launch_diag(s->b, s->st, s->par, (uint32_t)r, P.n, nullptr, nullptr, nullptr, dcount, 0, mode);
     uint32_t cnt = 0;
     HIPCHK(hipMemcpyAsync(&cnt, dcount, 4, hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
-    uint32_t* dij = nullptr;
-    double* ds = nullptr;
-    int32_t* dsl = nullptr;
-    HIPCHK(hipMalloc(&dij, sizeof(uint32_t) * 2 * (cnt + 1)));
-    HIPCHK(hipMalloc(&ds, sizeof(double) * 3 * (cnt + 1)));
-    HIPCHK(hipMalloc(&dsl, sizeof(int32_t) * (cnt + 1)));
+    uint32_t* dij = (uint32_t*)get(sizeof(uint32_t) * 2 * ((size_t)cnt + 1));
+    double* ds = (double*)get(sizeof(double) * 3 * ((size_t)cnt + 1));
+    int32_t* dsl = (int32_t*)get(sizeof(int32_t) * ((size_t)cnt + 1));
     HIPCHK(hipMemsetAsync(dcount, 0, sizeof(uint32_t), s->st));
     launch_diag(s->b, s->st, s->par, (uint32_t)r, P.n, dij, ds, dsl, dcount, cnt, mode);
     std::vector<uint32_t> hij(2 * (size_t)cnt);
@@ -1587,7 +1596,6 @@ int diag_pairs(sim* s, int32_t r, int mode, std::vector<uint32_t>& ij, std::vect
     HIPCHK(hipMemcpyAsync(hs.data(), ds, hs.size() * 8, hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipMemcpyAsync(hsl.data(), dsl, hsl.size() * 4, hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipStreamSynchronize(s->st));
-    (void)hipFree(dcount); (void)hipFree(dij); (void)hipFree(ds); (void)hipFree(dsl);
     std::vector<uint32_t> order(cnt);
     for (uint32_t k = 0; k < cnt; ++k) order[k] = k;
     std::sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
