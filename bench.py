@@ -503,7 +503,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic: seeded relaxed bidisperse packing (stands in for the paper's packings)",
         "config": {"workload": name, "n": n, "phi": wl.phi, "pe": wl.pe, "gammadot": st["params"]["gammadot"],
-                   "kT": st["params"]["kT"], "mu": wl.mu, "dt": wl.dt, "hip_graph": True,
+                   "kT": st["params"]["kT"], "mu": wl.mu, "dt": wl.dt, "hip_graph": True, "track_displacement": False,
                    "lanes_per_particle": f64["stats"]["lanes"], "occupancy_form": f64["stats"]["occupancy_form"],
                    "skin": f64["stats"]["skin"], "cell_factor": f64["stats"]["cell_factor"],
                    "tune_source": f64["stats"]["tune_source"]},

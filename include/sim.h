@@ -102,6 +102,10 @@ extern "C" {
                                         than choosing by timing at creation; the same
                                         trajectories bit for bit                        */
 #define SIM_HALF_OCC_OFF      0x800u /* ... never use that form                       */
+#define SIM_TRACK_DISPLACEMENT 0x2000u /* accumulate each particle's non-affine
+                                        displacement (sim_displacement, sim_msd): 64
+                                        bytes of HBM traffic per particle and step, so
+                                        off unless asked for; no trajectory changes     */
 #define SIM_SMALL_QUEUE      0x1000u /* test switch: that form processes its pair queue
                                         64 items per round (instead of 2048), so that
                                         every wave takes several rounds                 */
@@ -266,7 +270,8 @@ int sim_structural_stress(sim* s, int32_t replica, double out[9]);
  * sim_set_state of its replica or sim_reset_displacement; id order, 3n
  * doubles.  sim_msd: its mean square per axis, out[3] = <dx^2>, <dy^2>,
  * <dz^2> over the replica's particles (the MSD of Sec. III.B).
- * sim_reset_displacement: zero for every replica. */
+ * sim_reset_displacement: zero for every replica.  All three need a handle
+ * created with SIM_TRACK_DISPLACEMENT (else SIM_EINVAL). */
 int sim_displacement(sim* s, int32_t replica, double* out_3n);
 int sim_msd(sim* s, int32_t replica, double out[3]);
 int sim_reset_displacement(sim* s);

@@ -16,6 +16,7 @@ constexpr double kPi = 3.14159265358979323846;
 enum : uint32_t {
     F_FREEZE_X = 0x001u, F_NO_LUB = 0x002u, F_NO_PAIR_BROWN = 0x004u, F_NO_CONTACT = 0x008u,
     F_NO_ONEBODY = 0x010u, F_LUB_ROT = 0x020u, F_REBUILD_EACH_STEP = 0x100u, F_NO_GRAPH = 0x200u,
+    F_TRACK_DISP = 0x2000u,
 };
 
 enum : uint32_t { H_NAN = 1u, H_OVERLAP = 2u, H_NLIST = 4u };

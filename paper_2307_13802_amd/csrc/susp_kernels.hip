@@ -343,7 +343,8 @@ __device__ __forceinline__ void half_kick(double a, double rho, double half_dt, 
 
 // Kick 1, drift and wrap of particle i (parameters dp of the step), from its
 // full-step velocities v, w, position x and the force and torque F, T of the
-// last evaluation (as stored); da, dacc: its displacement records as read;
+// last evaluation (as stored); da, dacc: its displacement records as read (da only
+// with F_TRACK_DISP);
 // accumulates its displacement bound (dblk) and applies the list-validity test
 // (expire).
 template <bool MIX>
@@ -376,8 +377,10 @@ __device__ __forceinline__ void integrate_particle(const Bufs& b, const DriftPar
         const double ex = dp.dt * (vdx - ux), ey = dp.dt * vdy, ez = dp.dt * vdz;
         disp = sqrt(ex * ex + ey * ey + ez * ez) * (1.0 + 1e-6) + 1e-30;
         b.pos[i] = x;
-        da.x += ex; da.y += ey; da.z += ez;
-        b.disp[i] = da;
+        if (dp.flags & F_TRACK_DISP) {
+            da.x += ex; da.y += ey; da.z += ez;
+            b.disp[i] = da;
+        }
     }
     b.vh[i] = v;
     b.wh[i] = w;
@@ -413,7 +416,8 @@ __global__ __launch_bounds__(256) void k_integrate(Bufs b, int q) {
             const double4 f = ((const double4*)b.F)[i], t = ((const double4*)b.T)[i];
             F[0] = f.x; F[1] = f.y; F[2] = f.z; T[0] = t.x; T[1] = t.y; T[2] = t.z;
         }
-        integrate_particle<MIX>(b, dp, i, b.pos[i], b.vf[i], b.wf[i], F, T, b.disp[i], b.dacc[i], dblk, expire);
+        const double4 da = (dp.flags & F_TRACK_DISP) ? b.disp[i] : make_double4(0.0, 0.0, 0.0, 0.0);
+        integrate_particle<MIX>(b, dp, i, b.pos[i], b.vf[i], b.wf[i], F, T, da, b.dacc[i], dblk, expire);
     }
     if (expire) atomicOr(&b.sys->expire[q], 1u);  // rare: the lists are rebuilt before that
     block_max_store(dblk, &b.dpart[(size_t)q * (b.npad / kTile) + tile]);
@@ -1644,7 +1648,7 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
     double4 da = make_double4(0.0, 0.0, 0.0, 0.0);
     double dacc = 0.0;
     if (fuse) {
-        da = b.disp[i];
+        if (dp.flags & F_TRACK_DISP) da = b.disp[i];
         dacc = b.dacc[i];
     }
     if (C.do_one) {

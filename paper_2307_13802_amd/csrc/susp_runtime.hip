@@ -1295,6 +1295,8 @@ int sim_get_state(sim* s, int32_t r, double* x, double* v, double* w, double* F,
 }
 
 int sim_reset_displacement(sim* s) {
+    if (s && !(s->flags & SIM_TRACK_DISPLACEMENT))
+        return fail(s, SIM_EINVAL, "displacements are kept only by a handle created with SIM_TRACK_DISPLACEMENT");
     if (!s) return fail(nullptr, SIM_EINVAL, "null handle");
     try {
         HIPCHK(hipMemsetAsync(s->b.disp, 0, sizeof(double4) * s->b.npad, s->st));
@@ -1306,6 +1308,8 @@ int sim_reset_displacement(sim* s) {
 }
 
 int sim_displacement(sim* s, int32_t r, double* out_3n) {
+    if (s && !(s->flags & SIM_TRACK_DISPLACEMENT))
+        return fail(s, SIM_EINVAL, "displacements are kept only by a handle created with SIM_TRACK_DISPLACEMENT");
     if (int rc = check_rep(s, r)) return rc;
     if (!out_3n) return fail(s, SIM_EINVAL, "null output");
     try {
@@ -1326,6 +1330,8 @@ int sim_displacement(sim* s, int32_t r, double* out_3n) {
 
 int sim_msd(sim* s, int32_t r, double out[3]) {
     if (int rc = check_rep(s, r)) return rc;
+    if (!(s->flags & SIM_TRACK_DISPLACEMENT))
+        return fail(s, SIM_EINVAL, "displacements are kept only by a handle created with SIM_TRACK_DISPLACEMENT");
     if (!out) return fail(s, SIM_EINVAL, "null output");
     try {
         const RepParams& P = s->P[r];

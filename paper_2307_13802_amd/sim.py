@@ -23,6 +23,7 @@ FREEZE_X, NO_LUB, NO_PAIR_BROWN, NO_CONTACT, NO_ONEBODY, LUB_ROT = 0x1, 0x2, 0x4
 REBUILD_EACH_STEP, NO_GRAPH = 0x100, 0x200
 HALF_OCC_ON, HALF_OCC_OFF = 0x400, 0x800  # half-pair kernel, FP64: force or forbid its form for occupancy
 SMALL_QUEUE = 0x1000  # test switch: that form's pair queue in rounds of 64 items
+TRACK_DISPLACEMENT = 0x2000  # keep each particle's non-affine displacement (sim_displacement, sim_msd)
 KERNEL_AUTO, KERNEL_HALF = 0, 3
 STRESS_CONTACT, STRESS_LUB, STRESS_BROWN, STRESS_DRAG, STRESS_TOTAL = range(5)
 STRESS_LAST, STRESS_MEAN = 0, 1

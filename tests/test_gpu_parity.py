@@ -618,9 +618,15 @@ def test_displacement_msd_rdf_match_oracle(P):
     """Accumulated non-affine displacement and its mean square, and the pair-distance histogram of
     the sheared state, against the oracle (histogram bit-exact on the GPU's own state)."""
     st = _state(n=600, phi=0.5, seed=15)
-    sim = P.Sim(_cfg(P, st), st["radii"], st["x"], st["v"], st["w"])
+    untracked = P.Sim(_cfg(P, st), st["radii"], st["x"], st["v"], st["w"])
+    for call in (untracked.displacement, untracked.msd, untracked.reset_displacement):
+        with pytest.raises(P.SimError) as e:   # kept only when asked for at creation
+            call()
+        assert e.value.code == -1
+    sim = P.Sim(_cfg(P, st, flags=P.TRACK_DISPLACEMENT), st["radii"], st["x"], st["v"], st["w"])
     orc = O.Oracle(O.Params(L=st["L"], **st["params"]), st["radii"], st["x"], st["v"], st["w"])
     _say("case: displacement, MSD and g(r) after 40 sheared steps, N=600")
+    untracked.step(40)
     sim.step(40)
     orc.step(40)
     dg, do = sim.displacement(), orc.displacement()
@@ -634,6 +640,11 @@ def test_displacement_msd_rdf_match_oracle(P):
     hg, ho = sim.rdf(r_max, 50), ref.rdf(r_max, 50)
     _say(f"  g(r) pairs {hg.sum()} / {ho.sum()}")
     assert np.array_equal(hg, ho)
+    # the tracking changes no trajectory
+    gu = untracked.get_state()
+    for key in ("x", "v", "w", "F", "T"):
+        assert np.array_equal(gs[key], gu[key]), key
+    untracked.close()
     sim.reset_displacement()
     assert np.abs(sim.displacement()).max() == 0.0
     with pytest.raises(P.SimError):
@@ -718,7 +729,8 @@ def test_dilute_msd_closed_form_gpu(P):
     m = 4.0 / 3.0 * math.pi * rho * a ** 3
     v = rng.standard_normal((n, 3)) * math.sqrt(kT / m)
     w = rng.standard_normal((n, 3)) * math.sqrt(kT / (0.4 * m * a * a))
-    cfg = P.Config(box=(Lb, Lb, Lb), rho=rho, eta=eta, kT=kT, gammadot=0.0, dt=1e-4, seed=5)
+    cfg = P.Config(box=(Lb, Lb, Lb), rho=rho, eta=eta, kT=kT, gammadot=0.0, dt=1e-4, seed=5,
+                   flags=P.TRACK_DISPLACEMENT)
     sim = P.Sim(cfg, radii, x, v, w)
     gamma = 6 * math.pi * eta * a
     _say("case: dilute MSD, N=3000 phi=0.001")
