@@ -1561,8 +1561,10 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
     const double4 pi = b.pos[i];
     const uint32_t idi = b.id[i];
     const R ai = (R)pi.w;
-    R vi[3], wi[3];
-    load_vw<MIX>(b, i, vi, wi);
+    // the half-step velocities for the one-body terms and the kicks (in mixed precision the
+    // FP32 copies are these values rounded, so they are not read again)
+    const double4 vh = b.vh[i], wh = b.wh[i];
+    const R vi[3] = {(R)vh.x, (R)vh.y, (R)vh.z}, wi[3] = {(R)wh.x, (R)wh.y, (R)wh.z};
     Acc<R> F, T;
     const PairIdx pq = b.pidx[i];
     const uint32_t e0 = pq.lo0;
@@ -1642,9 +1644,8 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
             T.add(2, ct[u] ? (ROT ? tv[u].z : ai * tv[u].z) : (R)0);
         }
     }
-    // what the kicks and the drift read, issued here (before any store of the launch)
-    // so that the one-body terms hide the wait
-    const double4 vh = b.vh[i], wh = b.wh[i];
+    // what the drift reads, issued here (before any store of the launch) so that the
+    // one-body terms hide the wait
     double4 da = make_double4(0.0, 0.0, 0.0, 0.0);
     double dacc = 0.0;
     if (fuse) {
