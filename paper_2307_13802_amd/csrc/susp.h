@@ -42,9 +42,9 @@ struct RepParams {
     double cw[3];             // cell widths
     double max_overlap;
     int32_t nc[3];            // cells per dimension (1 or >= 3)
-    int32_t mbits;            // Morton bits per dimension
+    int32_t mbits;            // cell-key bits per dimension (Hilbert order)
     uint32_t key_off;         // first cell key of this replica
-    uint32_t nkeys;           // Morton cells + 1 padding cell
+    uint32_t nkeys;           // 2^(3 mbits) cell keys + 1 padding cell
     uint32_t p_begin, n, n_pad;
     uint32_t flags;
     uint32_t blk_begin, nblk; // pair-kernel blocks of this replica
@@ -81,7 +81,7 @@ struct SysDyn {
 };
 
 // Device buffers of one handle.  Particle arrays have npad entries, in
-// Morton-cell order; replicas are contiguous and padded to kTile.
+// Hilbert cell order; replicas are contiguous and padded to kTile.
 // Per particle, for the half-pair kernel and its gather (one 16-byte record, so
 // that a partner's lookup touches one line): bit e of im = entry e (a higher-id
 // partner) interacts in the last evaluation; qoff = the particle's first pair within

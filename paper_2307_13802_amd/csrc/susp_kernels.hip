@@ -4,7 +4,7 @@
 // Lees-Edwards wrap, bound on the displacement since the last list build,
 // list-expiry test) and pair force (all pair and one-body terms, kick 2,
 // stress with a fixed-order reduction, advance of the step counter).  The
-// cell/list rebuild (Morton cell keys, scan, scatter, in-cell ordering,
+// cell/list rebuild (Hilbert-ordered cell keys, scan, scatter, in-cell ordering,
 // reorder, Verlet list with contact-history carry-over) is launched by the
 // host only when its displacement budget is used up, or when the expiry test
 // halted a step.  Paper references are to Li, Royer & Ness, arXiv 2307.13802.
@@ -105,8 +105,41 @@ __device__ __forceinline__ uint32_t part1by2(uint32_t v) {
     return v;
 }
 
-__device__ __forceinline__ uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
-    return part1by2(x) | (part1by2(y) << 1) | (part1by2(z) << 2);
+// Cell key along a 3D Hilbert curve over [0, 2^b)^3 (J. Skilling, "Programming the
+// Hilbert curve", AIP Conf. Proc. 707 (2004): the coordinates are transformed in place,
+// then their bits interleaved, the first coordinate most significant).  Consecutive keys
+// are face neighbours, so particles in key order keep their neighbours near in memory
+// (without the long jumps of Morton order at its block boundaries).
+__device__ __forceinline__ uint32_t hilbert3(uint32_t x, uint32_t y, uint32_t z, int b) {
+    if (b == 0) return 0u;
+    uint32_t X[3] = {x, y, z};
+    const uint32_t M = 1u << (b - 1);
+    for (uint32_t Q = M; Q > 1u; Q >>= 1) {   // undo excess work
+        const uint32_t P = Q - 1u;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;   // invert the low bits of the first
+            } else {
+                const uint32_t t = (X[0] ^ X[i]) & P;   // exchange the low bits
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    X[1] ^= X[0];   // Gray encode
+    X[2] ^= X[1];
+    uint32_t t = 0u;
+    for (uint32_t Q = M; Q > 1u; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1u;
+    X[0] ^= t;
+    X[1] ^= t;
+    X[2] ^= t;
+    return part1by2(X[2]) | (part1by2(X[1]) << 1) | (part1by2(X[0]) << 2);
+}
+
+__device__ __forceinline__ uint32_t cell_key(const RepParams& P, int x, int y, int z) {
+    return P.key_off + hilbert3((uint32_t)x, (uint32_t)y, (uint32_t)z, P.mbits);
 }
 
 __device__ __forceinline__ int cell_coord(double x, double w, int n) {
@@ -118,7 +151,7 @@ __device__ __forceinline__ float as_posf(uint32_t b) { return __uint_as_float(b)
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  Particle kernels map block b to tile xcd_tile(b, g) so that every XCD
-// walks one contiguous range of Morton-ordered tiles: neighbours' data then
+// walks one contiguous range of Hilbert-ordered tiles: neighbours' data then
 // sits in the L2 of the XCD that reads it.  A bijection of [0, g).
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t g) {
     const uint32_t x = b & 7u, k = b >> 3, per = g >> 3, rem = g & 7u;
@@ -424,7 +457,7 @@ __global__ __launch_bounds__(256) void k_integrate(Bufs b, int q) {
 }
 
 // ---------------------------------------------------------------------------
-// Rebuild: Morton-ordered cells, deterministic order inside a cell (by id),
+// Rebuild: Hilbert-ordered cells, deterministic order inside a cell (by id),
 // reorder of all particle data, neighbour list with history carry-over.
 // ---------------------------------------------------------------------------
 __global__ void k_rb_zero(Bufs b) {
@@ -445,7 +478,7 @@ __global__ __launch_bounds__(256) void k_rb_keys(Bufs b) {
         const int cx = cell_coord(x.x, P.cw[0], P.nc[0]);
         const int cy = cell_coord(x.y, P.cw[1], P.nc[1]);
         const int cz = cell_coord(x.z, P.cw[2], P.nc[2]);
-        const uint32_t key = P.key_off + morton3((uint32_t)cx, (uint32_t)cy, (uint32_t)cz);
+        const uint32_t key = cell_key(P, cx, cy, cz);
         b.key[q] = key;
         atomicAdd(&b.cell_cnt[key], 1u);
     } else if (lq == P.n && P.n_pad > P.n) {
@@ -675,7 +708,7 @@ __global__ __launch_bounds__(256) void k_rb_nlist(Bufs b, int q, int in_step) {
             if (all_x || xhi - xlo + 1 >= P.nc[0]) { xlo = 0; xhi = P.nc[0] - 1; }
             for (int xc = xlo; xc <= xhi; ++xc) {
                 const int xx = ((xc % P.nc[0]) + P.nc[0]) % P.nc[0];
-                const uint32_t key = P.key_off + morton3((uint32_t)xx, (uint32_t)yy, (uint32_t)zz);
+                const uint32_t key = cell_key(P, xx, yy, zz);
                 const uint32_t st = b.cell_start[key], en = st + b.cell_cnt[key];
                 for (uint32_t j = st; j < en; ++j) {
                     if (j == i) continue;
@@ -1814,7 +1847,7 @@ __global__ __launch_bounds__(256) void k_rdf(Bufs b, uint32_t rep, int p, int mo
             if (all_y || xhi - xlo + 1 >= P.nc[0]) { xlo = 0; xhi = P.nc[0] - 1; }
             for (int xc = xlo; xc <= xhi; ++xc) {
                 const int xx = ((xc % P.nc[0]) + P.nc[0]) % P.nc[0];
-                const uint32_t key = P.key_off + morton3((uint32_t)xx, (uint32_t)yy, (uint32_t)zz);
+                const uint32_t key = cell_key(P, xx, yy, zz);
                 const uint32_t st = b.cell_start[key], en = st + b.cell_cnt[key];
                 for (uint32_t j = st; j < en; ++j) {
                     if (!(idi < b.id[j])) continue;

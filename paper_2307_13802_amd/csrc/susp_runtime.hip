@@ -256,7 +256,7 @@ int validate(const sim_config* c, const double* radii, std::string& why) {
     return SIM_OK;
 }
 
-int morton_bits(int n) {
+int key_bits(int n) {
     int b = 0;
     while ((1 << b) < n) ++b;
     return b;
@@ -522,7 +522,7 @@ RepParams rep_params(const sim_config& c, const double* radii, double skin_frac,
         P.cw[d] = c.box[d] / nc;
         mx = std::max(mx, nc);
     }
-    P.mbits = morton_bits(mx);
+    P.mbits = key_bits(mx);
     P.nkeys = (1u << (3 * P.mbits)) + 1u;
     P.max_overlap = c.max_overlap > 0.0 ? c.max_overlap : 0.1 * amin;
     P.n = c.n;
