@@ -37,7 +37,7 @@ def pair_bytes_per_particle(mixed, k, c):
     table counts them: own state (x, a, v, w, id: 84 B FP64, 56 B mixed), the list (4 B per
     entry, k entries), the contact history read and written (52 B per contact FP64, 28 B
     mixed; c contacts per particle) and F, T written (48 B / 24 B).  Partner gathers are
-    not counted (Morton order serves them from cache)."""
+    not counted (the cell order serves them from cache)."""
     return (56 + 4 * k + 28 * c + 24) if mixed else (84 + 4 * k + 52 * c + 48)
 
 

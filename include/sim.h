@@ -9,7 +9,7 @@
  *   - the Lees-Edwards offset and the wrap of particles into the sheared
  *     periodic box (Sec. II.E: the tilted box remapped at strain +-1/2 is the
  *     same image lattice as a Lees-Edwards offset);
- *   - a Verlet neighbour list from Morton-ordered cells, rebuilt on device when
+ *   - a Verlet neighbour list from Hilbert-ordered cells, rebuilt on device when
  *     the accumulated non-affine displacement can have used up the skin
  *     (Sec. II, footnote on the skin);
  *   - per pair: the squeeze and shear lubrication force of eq. (force_lub)
