@@ -290,8 +290,10 @@ int sim_rdf(sim* s, int32_t replica, double r_max, int32_t nbins, uint64_t* coun
  * capture, tight sampling loops, harnesses that forbid hipMalloc): the same
  * histogram, bit for bit, with its bins in a static device array of the library
  * (65,536 64-bit words per GPU, held until the process ends) instead of memory
- * allocated per call; it calls no hipMalloc, hipFree or other allocating routine.
- * The bins are cleared by a kernel at every call.  All calls on one GPU share
+ * allocated per call; it calls no hipMalloc, hipFree or other allocating routine
+ * (a list build of the call that finds more partners than the lists hold leaves
+ * their regrow to the next call that uses them).  The bins are cleared by a
+ * kernel at every call.  All calls on one GPU share
  * that array: calls that overlap in time on one GPU (from several threads or
  * streams) race and must be serialised by the caller.  SIM_EINVAL for nbins
  * outside [1, 65536] and as sim_rdf otherwise; SIM_EDEVICE if the array's

@@ -298,13 +298,28 @@ void regrow_lists(sim* s, int q, int in_step, uint32_t need) {
     }
     const size_t rs = s->mixed ? sizeof(float) : sizeof(double);
     const size_t recs = s->mixed ? 4 * sizeof(float) : 3 * sizeof(double);
-    for (void* p : {(void*)b.nbr, b.hs, (void*)b.mir, b.pf, b.pt, b.pt2}) s->release(p);
-    b.nbr = s->alloc<uint32_t>(np * cap);
-    b.hs = s->dalloc(np * cap * 3 * rs);
-    b.mir = s->alloc<uint8_t>(np * cap);
-    b.pf = s->dalloc(np * cap * recs);
-    b.pt = s->dalloc(np * cap * recs);
-    b.pt2 = s->dalloc(np * cap * recs);
+    // the new arrays first, so that a failed allocation leaves the handle's lists as they were
+    void* const old[6] = {b.nbr, b.hs, b.mir, b.pf, b.pt, b.pt2};
+    void* nw[6] = {};
+    try {
+        nw[0] = s->dalloc(np * cap * sizeof(uint32_t));
+        nw[1] = s->dalloc(np * cap * 3 * rs);
+        nw[2] = s->dalloc(np * cap);
+        nw[3] = s->dalloc(np * cap * recs);
+        nw[4] = s->dalloc(np * cap * recs);
+        nw[5] = s->dalloc(np * cap * recs);
+    } catch (...) {
+        for (void* p : nw)
+            if (p) s->release(p);
+        throw;
+    }
+    b.nbr = (uint32_t*)nw[0];
+    b.hs = nw[1];
+    b.mir = (uint8_t*)nw[2];
+    b.pf = nw[3];
+    b.pt = nw[4];
+    b.pt2 = nw[5];
+    for (void* p : old) s->release(p);
     b.cap = cap;
     drop_graphs(s);   // captured launches hold the buffer table by value
     launch_relist(b, s->st, q, in_step);
