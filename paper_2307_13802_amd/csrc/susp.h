@@ -166,7 +166,8 @@ struct Bufs {
     double* acf_sum;      // [rep][acf_nlag]
     unsigned long long* acf_n;  // [rep]
 
-    double* dacc;         // per particle: bound on its non-affine displacement since the last build
+    float* dacc;          // per particle: bound on its non-affine displacement since the last build
+                          // (FP32, rounded up)
     double4* disp;        // per particle: accumulated non-affine displacement (x, y, z) since the
                           // creation, the last state upload or sim_reset_displacement
     float* dpart;         // [parity][kTile-block]: largest dacc of the block after that step's drift

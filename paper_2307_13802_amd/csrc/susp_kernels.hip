@@ -422,7 +422,7 @@ __device__ __forceinline__ void integrate_particle(const Bufs& b, const DriftPar
         b.wsh[i] = make_float4((float)w.x, (float)w.y, (float)w.z, 0.0f);
     }
     const double d = dacc + disp;
-    b.dacc[i] = d;
+    b.dacc[i] = __double2float_ru(d);   // rounded up: the stored bound stays a bound
     expire = list_expired(dp.gd, dp.rcs, dp.skin, d, dp.t_next);
     dblk = (float)d * (1.0f + 1e-6f);
 }
@@ -647,7 +647,7 @@ __global__ __launch_bounds__(256) void k_rb_gather(Bufs b, uint32_t ct_input_rep
 
 __global__ __launch_bounds__(256) void k_rb_copyback(Bufs b) {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    b.dacc[q] = 0.0;
+    b.dacc[q] = 0.0f;
     b.id[q] = b.alt_id[q];
     b.pos[q] = b.alt4[0][q];
     const double4 vh = b.alt4[1][q], wh = b.alt4[2][q];
@@ -859,7 +859,16 @@ template <class R> __device__ __forceinline__ R rsqrt_(R x);
 template <> __device__ __forceinline__ double rsqrt_<double>(double x) { return sqrt(x); }
 template <> __device__ __forceinline__ float rsqrt_<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <class R> __device__ __forceinline__ R rrcp(R x);
-template <> __device__ __forceinline__ double rrcp<double>(double x) { return 1.0 / x; }
+// FP64: the hardware reciprocal refined by two Newton steps (within an ulp of 1/x; the
+// springs, which the parity with the oracle needs to the bit, use correctly rounded
+// divisions instead)
+template <> __device__ __forceinline__ double rrcp<double>(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
 template <> __device__ __forceinline__ float rrcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ---------------------------------------------------------------------------

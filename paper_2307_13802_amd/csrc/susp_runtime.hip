@@ -956,7 +956,7 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
         b.ring = s->alloc<double>((size_t)n_replicas * kRing * 27);
         b.last = s->alloc<double>((size_t)n_replicas * 27);
         b.blk_rep = s->alloc<uint32_t>(blk_rep.size());
-        b.dacc = s->alloc<double>(np);
+        b.dacc = s->alloc<float>(np);
         b.dpart = s->alloc<float>(2 * (np / kTile));
         b.reps = s->alloc<RepParams>(n_replicas);
         b.dyn = s->alloc<RepDyn>(n_replicas);
@@ -970,7 +970,7 @@ int sim_create(const sim_config* cfgs, int32_t n_replicas, const double* const* 
                 set_dyn(s, r, cfgs[r].le_offset0, cfgs[r].step0);
             }
             HIPCHK(hipMemsetAsync(b.sys, 0, sizeof(SysDyn), s->st));
-            HIPCHK(hipMemsetAsync(b.dacc, 0, sizeof(double) * b.npad, s->st));
+            HIPCHK(hipMemsetAsync(b.dacc, 0, sizeof(float) * b.npad, s->st));
             s->step_now = cfgs[0].step0;
             rebuild(s, 1 - s->par, 0, 0xFFFFFFFEu);
         };
