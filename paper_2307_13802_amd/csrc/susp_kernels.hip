@@ -157,6 +157,16 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t g) {
     const uint32_t x = b & 7u, k = b >> 3, per = g >> 3, rem = g & 7u;
     return x * per + (x < rem ? x : rem) + k;
 }
+// The same ranges walked from their ends: the gather, which follows the pair kernel,
+// starts where that kernel finished, so the pair records and particle data it wrote
+// last are still in the XCD's L2 (and the next pair kernel starts where the gather
+// finished).  A bijection of [0, g): block b's position k in its XCD's range is below
+// that range's length.
+__device__ __forceinline__ uint32_t xcd_tile_rev(uint32_t b, uint32_t g) {
+    const uint32_t x = b & 7u, k = b >> 3, per = g >> 3, rem = g & 7u;
+    const uint32_t len = per + (x < rem ? 1u : 0u);
+    return x * per + (x < rem ? x : rem) + (len - 1u - k);
+}
 
 // Lees-Edwards offset one step after the stored one (same arithmetic everywhere)
 __device__ __forceinline__ double next_offset(const RepParams& P, double s_le) {
@@ -1573,7 +1583,7 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
 template <bool MIX, bool ROT>
 __global__ __launch_bounds__(256) void k_gather(Bufs b, int q, int kick, int fuse, uint32_t only_rep) {
     const uint32_t halted = b.sys->halted;
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t tile = xcd_tile_rev(blockIdx.x, gridDim.x);
     const uint32_t i = tile * 256 + threadIdx.x;
     const uint32_t r = __builtin_amdgcn_readfirstlane(b.blk_rep[tile]);
     if (only_rep != 0xFFFFFFFFu && r != only_rep) return;
