@@ -655,13 +655,14 @@ void cache_write(const std::string& path, const std::string& key, const Tune& t)
 }
 
 // One measured trial of a parameter set on the actual system: rebuild, 2 warm-up
-// steps, rebuild (timed), then two runs of kTrial steps (the faster counts: one
-// run can catch a stall).  Returns the expected time per step including the
+// steps, rebuild (timed), then kRuns runs of kTrial steps (the fastest counts: a run
+// can catch a stall).  Returns the expected time per step including the
 // rebuilds, from the growth of the displacement bound over the trial (the rule the
 // step planner uses): +inf when a list expired during the trial.  The trial steps
 // change the state; the caller restores it.
+constexpr int kTrial = 8, kRuns = 3;   // steps per timed run of a trial, timed runs
+
 double trial(sim* s, const Tune& t, hipEvent_t* e) {
-    constexpr int kTrial = 4;
     apply_tune(s, t);
     const int q = 1 - s->par;
     rebuild(s, q, 0, 0xFFFFFFFFu);
@@ -669,20 +670,23 @@ double trial(sim* s, const Tune& t, hipEvent_t* e) {
     HIPCHK(hipEventRecord(e[0], s->st));
     rebuild(s, q, 0, 0xFFFFFFFFu);
     HIPCHK(hipEventRecord(e[1], s->st));
-    enqueue_steps(s, s->st, kTrial, q);
-    HIPCHK(hipEventRecord(e[2], s->st));
-    enqueue_steps(s, s->st, kTrial, q ^ (kTrial & 1));
-    HIPCHK(hipEventRecord(e[3], s->st));
-    HIPCHK(hipEventSynchronize(e[3]));
-    float mr = 0.f, m1 = 0.f, m2 = 0.f;
+    for (int k = 0; k < kRuns; ++k) {
+        enqueue_steps(s, s->st, kTrial, q ^ ((k * kTrial) & 1));
+        HIPCHK(hipEventRecord(e[2 + k], s->st));
+    }
+    HIPCHK(hipEventSynchronize(e[1 + kRuns]));
+    float mr = 0.f, mbest = 1e30f;
     HIPCHK(hipEventElapsedTime(&mr, e[0], e[1]));
-    HIPCHK(hipEventElapsedTime(&m1, e[1], e[2]));
-    HIPCHK(hipEventElapsedTime(&m2, e[2], e[3]));
+    for (int k = 0; k < kRuns; ++k) {
+        float m = 0.f;
+        HIPCHK(hipEventElapsedTime(&m, e[1 + k], e[2 + k]));
+        mbest = std::min(mbest, m);
+    }
     SysDyn sy;
     HIPCHK(hipMemcpy(&sy, s->b.sys, sizeof sy, hipMemcpyDeviceToHost));
     if (sy.halted) return 1e30;
-    // fraction of the skin used per step (largest over replicas) after 2 kTrial steps
-    const int last = q ^ ((2 * kTrial - 1) & 1);
+    // fraction of the skin used per step (largest over replicas) over the timed steps
+    const int last = q ^ ((kRuns * kTrial - 1) & 1);
     const uint32_t nt = s->b.npad / kTile;
     std::vector<float> dp(nt);
     std::vector<RepDyn> dyn(s->nrep);
@@ -694,10 +698,10 @@ double trial(sim* s, const Tune& t, hipEvent_t* e) {
         double dmax = 0.0;
         for (uint32_t k = P.blk_begin; k < P.blk_begin + P.nblk; ++k) dmax = std::max(dmax, (double)dp[k]);
         const double u = 2.0 * dmax + std::fabs(P.gd) * dyn[r].t_slot[last] * (P.rc_max + 2.0 * P.skin);
-        used = std::max(used, u / P.skin / (2.0 * kTrial));
+        used = std::max(used, u / P.skin / (double)(kRuns * kTrial));
     }
     const double steps_per_build = used > 0.0 ? std::max(1.0, 0.8 / used) : 1e30;
-    return std::min(m1, m2) / kTrial + mr / steps_per_build;
+    return mbest / kTrial + mr / steps_per_build;
 }
 
 // Time of one list build under t, the fastest of three from the same positions: the cell
@@ -760,7 +764,7 @@ void tune(sim* s) {
             return;
         }
     }
-    hipEvent_t ev[4];
+    hipEvent_t ev[kRuns + 2];
     for (auto& e : ev) HIPCHK(hipEventCreate(&e));
     auto scan = [&](std::vector<Tune> cand) {
         double bt = 1e31;
