@@ -424,7 +424,7 @@ def main():
                          "sweep: 64 batched replicas; large: 4,000,000 log-normal spheres")
     ap.add_argument("--sample-every", type=int, default=250, help="c3-all: steps between shadow samples")
     ap.add_argument("--trace", action="store_true",
-                    help="profiler driver: a 256 MiB elementwise kernel (the calibration of the byte counters), "
+                    help="profiling mode: a 256 MiB elementwise kernel (the calibration of the byte counters), "
                          "then --steps steps of the workload in FP64 and in mixed precision with the launch "
                          "parameters the tuner picks (cached in --tune-cache)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_2307_13802_amd", "tune_cache_mi355x.json"),
