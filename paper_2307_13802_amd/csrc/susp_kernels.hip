@@ -218,6 +218,21 @@ template <class R> __device__ __forceinline__ void load_spring(const Bufs& b, ui
 template <class R> __device__ __forceinline__ void store_spring(const Bufs& b, uint32_t k, const R* s) {
     ((Spring<R>*)b.hs)[k] = Spring<R>{s[0], s[1], s[2]};
 }
+// the pair kernel's read of a stored spring: once per step, so not kept in the L2
+template <class R> __device__ __forceinline__ void load_spring_nt(const Bufs& b, uint32_t k, R* s) {
+    const R* p = (const R*)((const Spring<R>*)b.hs + k);
+    s[0] = __builtin_nontemporal_load(p);
+    s[1] = __builtin_nontemporal_load(p + 1);
+    s[2] = __builtin_nontemporal_load(p + 2);
+}
+// the pair kernel's spring update: read again only by the next step's pair kernel, so
+// stored past the L2 (non-temporal), which keeps the L2 for the records the gather reads
+template <class R> __device__ __forceinline__ void store_spring_nt(const Bufs& b, uint32_t k, const R* s) {
+    R* p = (R*)((Spring<R>*)b.hs + k);
+    __builtin_nontemporal_store(s[0], p);
+    __builtin_nontemporal_store(s[1], p + 1);
+    __builtin_nontemporal_store(s[2], p + 2);
+}
 // in FP64 whatever the precision of the handle (rebuild carry, diagnostics)
 __device__ __forceinline__ void spring_f64(const Bufs& b, uint32_t k, double* s) {
     if (b.mixed) {
@@ -432,7 +447,9 @@ __device__ __forceinline__ void integrate_particle(const Bufs& b, const DriftPar
         b.wsh[i] = make_float4((float)w.x, (float)w.y, (float)w.z, 0.0f);
     }
     const double d = dacc + disp;
-    b.dacc[i] = __double2float_ru(d);   // rounded up: the stored bound stays a bound
+    // rounded up: the stored bound stays a bound; read again only by the next step's
+    // integrate, so stored past the L2
+    __builtin_nontemporal_store(__double2float_ru(d), &b.dacc[i]);
     expire = list_expired(dp.gd, dp.rcs, dp.skin, d, dp.t_next);
     dblk = (float)d * (1.0f + 1e-6f);
 }
@@ -1225,7 +1242,7 @@ __device__ __forceinline__ bool eval_pair(const Bufs& b, const RepParams& P, con
             for (int d = 0; d < 3; ++d) s[d] = s[d] * fac;
             slid = true;
         }
-        store_spring<R>(b, e * npad + i, s);
+        store_spring_nt<R>(b, e * npad + i, s);
         contact = true;
         const R ks[3] = {C.kt * s[0], C.kt * s[1], C.kt * s[2]};
 #pragma unroll
@@ -1493,7 +1510,7 @@ __global__ __launch_bounds__(256, (MIX || OCC) ? 3 : 2) void k_half(Bufs b, int 
         in.pj = b.pos[in.j];
         in.idj = b.id[in.j];
         load_vw<MIX>(b, in.j, in.vj, in.wj);
-        if (had) load_spring<R>(b, e * npad + ii, in.s);
+        if (had) load_spring_nt<R>(b, e * npad + ii, in.s);
         else in.s[0] = in.s[1] = in.s[2] = (R)0;
         R f[3], t[3], tb[3];  // tb: written by eval_pair where it is used (contact, or the couplings)
         bool contact, slid;
@@ -1541,7 +1558,7 @@ __global__ __launch_bounds__(256, (MIX || OCC) ? 3 : 2) void k_half(Bufs b, int 
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (valid && sub == 0) {
         b.cmask[i] = cmq[w][l];
-        b.smask[i] = smq[w][l];
+        __builtin_nontemporal_store((unsigned long long)smq[w][l], (unsigned long long*)&b.smask[i]);   // read at list builds
     }
 
     // block partial of the stress (fixed-order sum over the block's lanes: DPP rows,
@@ -1702,7 +1719,7 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
     double dacc = 0.0;
     if (fuse) {
         if (dp.flags & F_TRACK_DISP) da = b.disp[i];
-        dacc = b.dacc[i];
+        dacc = __builtin_nontemporal_load(&b.dacc[i]);   // read once per step
     }
     if (C.do_one) {
 #pragma unroll
