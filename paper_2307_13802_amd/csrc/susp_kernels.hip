@@ -218,6 +218,17 @@ template <class R> __device__ __forceinline__ void load_spring(const Bufs& b, ui
 template <class R> __device__ __forceinline__ void store_spring(const Bufs& b, uint32_t k, const R* s) {
     ((Spring<R>*)b.hs)[k] = Spring<R>{s[0], s[1], s[2]};
 }
+// non-temporal double4 access (one access, not kept in the L2), for data that no kernel
+// reads soon after
+typedef double nt_d4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ double4 ld_nt(const double4* p) {
+    const nt_d4 v = __builtin_nontemporal_load((const nt_d4*)p);
+    return make_double4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st_nt(double4* p, const double4& v) {
+    const nt_d4 t = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(t, (nt_d4*)p);
+}
 // the pair kernel's read of a stored spring: once per step, so not kept in the L2
 template <class R> __device__ __forceinline__ void load_spring_nt(const Bufs& b, uint32_t k, R* s) {
     const R* p = (const R*)((const Spring<R>*)b.hs + k);
@@ -440,8 +451,13 @@ __device__ __forceinline__ void integrate_particle(const Bufs& b, const DriftPar
             b.disp[i] = da;
         }
     }
-    b.vh[i] = v;
-    b.wh[i] = w;
+    if (MIX) {   // only the next step's gather reads the FP64 half-step velocities: past the L2
+        st_nt(&b.vh[i], v);
+        st_nt(&b.wh[i], w);
+    } else {
+        b.vh[i] = v;
+        b.wh[i] = w;
+    }
     if (MIX) {
         b.vsh[i] = make_float4((float)v.x, (float)v.y, (float)v.z, 0.0f);
         b.wsh[i] = make_float4((float)w.x, (float)w.y, (float)w.z, 0.0f);
@@ -1632,7 +1648,7 @@ __device__ __forceinline__ void gather_particle(const Bufs& b, const RepParams& 
     const R ai = (R)pi.w;
     // the half-step velocities for the one-body terms and the kicks (in mixed precision the
     // FP32 copies are these values rounded, so they are not read again)
-    const double4 vh = b.vh[i], wh = b.wh[i];
+    const double4 vh = MIX ? ld_nt(&b.vh[i]) : b.vh[i], wh = MIX ? ld_nt(&b.wh[i]) : b.wh[i];
     const R vi[3] = {(R)vh.x, (R)vh.y, (R)vh.z}, wi[3] = {(R)wh.x, (R)wh.y, (R)wh.z};
     Acc<R> F, T;
     const PairIdx pq = b.pidx[i];
